@@ -1,0 +1,183 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/lbm_oracle.cpp).
+
+Test infrastructure only: imported by tests/, by the package smoke check and by
+the CPU-baseline leg of bench.py. The product path never imports this module.
+
+Moment arrays use the layout [block][moment][node]; moments are
+(rho-1, ux, uy, uz, Sxx, Syy, Szz, Sxy, Sxz, Syz), node index x + 8y + 64z,
+blocks listed in increasing Morton order of their block coordinates.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm_oracle.so")
+
+PERIODIC, INFLOW, OUTFLOW, WALL = 0, 1, 2, 3
+R_INTERIOR, R_GHOST, R_IU, R_SOLID, R_INFLOW, R_OUTFLOW = range(6)
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3),
+        ("bc", ctypes.c_int32 * 6),
+        ("uin", ctypes.c_double * 3),
+        ("tau0", ctypes.c_double),
+        ("force", ctypes.c_double * 3),
+        ("rescale", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from oracle.build import build
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        L.oc_create.restype = vp
+        L.oc_create.argtypes = [ctypes.POINTER(_Cfg), vp, vp, i64]
+        L.oc_destroy.argtypes = [vp]
+        L.oc_last_error.restype = ctypes.c_char_p
+        L.oc_num_blocks.restype = i64
+        L.oc_num_blocks.argtypes = [vp, i32]
+        L.oc_block_keys.argtypes = [vp, i32, vp]
+        L.oc_set_block_moments.restype = i32
+        L.oc_set_block_moments.argtypes = [vp, i32, vp, vp, i64]
+        L.oc_get_block_moments.argtypes = [vp, i32, vp, vp]
+        L.oc_get_roles.argtypes = [vp, i32, vp]
+        L.oc_step.restype = i32
+        L.oc_step.argtypes = [vp, i32]
+        L.oc_remesh.restype = i32
+        L.oc_remesh.argtypes = [vp, vp, i64]
+        L.oc_advance_particles.argtypes = [vp, i64, vp]
+        L.oc_reduce.argtypes = [vp, i32, vp, vp, vp]
+        L.oc_level_params.argtypes = [vp, vp, vp, vp]
+        L.oc_lattice.argtypes = [vp, vp]
+        L.oc_reconstruct.argtypes = [vp, vp]
+        L.oc_collide.argtypes = [vp, ctypes.c_double, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class OracleSim:
+    """One simulation held by the oracle."""
+
+    def __init__(self, levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
+                 solid=None, particles=None, rescale="ce"):
+        c = _Cfg()
+        c.levels = levels
+        for a in range(3):
+            c.n[a] = int(n[a])
+            c.uin[a] = float(uin[a])
+            c.force[a] = float(force[a])
+        for f in range(6):
+            c.bc[f] = int(bc[f])
+        c.tau0 = float(tau0)
+        c.rescale = {"ce": 0, "printed": 1}[rescale]
+        self.levels = levels
+        self.n = tuple(int(v) for v in n)
+        self._solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
+        p = None if particles is None else np.ascontiguousarray(particles, dtype=np.float32)
+        np_ = 0 if p is None else p.shape[0]
+        h = lib().oc_create(ctypes.byref(c), _ptr(self._solid), _ptr(p), np_)
+        if not h:
+            raise ValueError(lib().oc_last_error().decode())
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().oc_destroy(self.h)
+            self.h = None
+
+    def num_blocks(self, level):
+        return int(lib().oc_num_blocks(self.h, level))
+
+    def block_keys(self, level):
+        k = np.empty(self.num_blocks(level), dtype=np.int64)
+        lib().oc_block_keys(self.h, level, _ptr(k))
+        return k
+
+    def set_block_moments(self, level, keys, vals):
+        keys = np.ascontiguousarray(keys, dtype=np.int64)
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        assert vals.shape == (keys.shape[0], 10, 512)
+        if lib().oc_set_block_moments(self.h, level, _ptr(keys), _ptr(vals), keys.shape[0]) != 0:
+            raise ValueError(lib().oc_last_error().decode())
+
+    def get_block_moments(self, level):
+        nb = self.num_blocks(level)
+        k = np.empty(nb, dtype=np.int64)
+        v = np.empty((nb, 10, 512), dtype=np.float64)
+        lib().oc_get_block_moments(self.h, level, _ptr(k), _ptr(v))
+        return k, v
+
+    def roles(self, level):
+        r = np.empty((self.num_blocks(level), 512), dtype=np.uint8)
+        lib().oc_get_roles(self.h, level, _ptr(r))
+        return r
+
+    def step(self, n=1):
+        if lib().oc_step(self.h, n) != 0:
+            raise RuntimeError(lib().oc_last_error().decode())
+
+    def remesh(self, particles):
+        p = np.ascontiguousarray(particles, dtype=np.float32)
+        if lib().oc_remesh(self.h, _ptr(p), p.shape[0]) != 0:
+            raise RuntimeError(lib().oc_last_error().decode())
+
+    def reduce(self, level, lo=(0, 0, 0), hi=None):
+        hi = self.n if hi is None else hi
+        lo_ = np.array(lo, dtype=np.int32)
+        hi_ = np.array(hi, dtype=np.int32)
+        out = np.empty(5, dtype=np.float64)
+        lib().oc_reduce(self.h, level, _ptr(lo_), _ptr(hi_), _ptr(out))
+        return out
+
+    def level_params(self):
+        t = np.empty(self.levels)
+        u = np.empty(self.levels)
+        d = np.empty(self.levels)
+        lib().oc_level_params(self.h, _ptr(t), _ptr(u), _ptr(d))
+        return t, u, d
+
+
+def advance_particles(p, d):
+    """p += d in float32 (in place), the same rounding as the GPU path."""
+    assert p.dtype == np.float32 and p.flags.c_contiguous
+    dd = np.asarray(d, dtype=np.float32)
+    lib().oc_advance_particles(_ptr(p), p.shape[0], _ptr(dd))
+
+
+def lattice():
+    c = np.empty((27, 3), dtype=np.int32)
+    w = np.empty(27)
+    lib().oc_lattice(_ptr(c), _ptr(w))
+    return c, w
+
+
+def reconstruct(q):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    f = np.empty(27)
+    lib().oc_reconstruct(_ptr(q), _ptr(f))
+    return f
+
+
+def collide(q, omega, force=(0.0, 0.0, 0.0)):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    F = np.ascontiguousarray(force, dtype=np.float64)
+    out = np.empty(10)
+    lib().oc_collide(_ptr(q), float(omega), _ptr(F), _ptr(out))
+    return out

@@ -1,0 +1,140 @@
+/*
+ * lbm.h - C ABI of the block-adaptive, moment-encoded D3Q27 lattice Boltzmann
+ * step for MI355X (gfx950), after arXiv 2603.14982 ("Adaptive GPU Kinetic
+ * Solver for Fluid-Granular Flows").
+ *
+ * The problem (Sec. 5.1-5.4 of the paper): a domain split into levels with
+ * spacing dx_l = 2^l dx_0 (level 0 finest), finest relaxation time tau_0 which
+ * fixes tau_l = tau_0/2^l + (2^l-1)/2^(l+1) (Sec. 5.2), a level-selection
+ * function Phi driven by particles or geometry (Sec. 5.4), initial moments
+ * {rho, u, S} per node (Sec. 3.1, Eq. rho_u_stress); the outputs are the
+ * moments per level after stepping.
+ *
+ * Conventions
+ *  - Every function returns an lbm_status; nothing throws across the ABI.
+ *  - All pointers marked "device" are HIP device pointers owned by the caller;
+ *    the context borrows them and never frees them. Host pointers are read
+ *    (or written) only during the call.
+ *  - Calls run asynchronously on cfg.stream unless marked "synchronises".
+ *  - Block keys are Morton codes of block coordinates (bx, by, bz), x in the
+ *    lowest bit of each 3-bit group; a level-l block covers level-l nodes
+ *    8*b .. 8*b+7 per axis, i.e. fine positions 2^l * (8*b + k).
+ *  - Moment arrays use [block][moment][node], node = x + 8y + 64z, moment order
+ *    (rho - 1, ux, uy, uz, Sxx, Syy, Szz, Sxy, Sxz, Syz), f32.
+ *  - Per-level block lists are in increasing key order.
+ *  - Arguments are validated on the host before any launch; on error the
+ *    context is unchanged and lbm_last_error() says why.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* bad argument or configuration */
+  LBM_ENOMEM = -2,     /* caller buffers smaller than lbm_pool_bytes / lbm_meta_bytes */
+  LBM_ECAPACITY = -3,  /* the block pool cannot hold the requested hierarchy */
+  LBM_EDEVICE = -4,    /* a HIP call failed */
+  LBM_ENAN = -5,       /* non-finite moments found */
+  LBM_ESTATE = -6      /* call not valid in the current state */
+} lbm_status;
+
+typedef enum { LBM_F32 = 0, LBM_BF16 = 1, LBM_F16 = 2 } lbm_storage;
+
+/* Per-face boundary kind. INFLOW holds nodes on the face at the equilibrium
+ * moments (1, inflow_u, inflow_u inflow_u); OUTFLOW copies the inward
+ * neighbour after each step (zero gradient); WALL is halfway bounce-back half a
+ * node outside the face. Faces of one axis are either both PERIODIC or neither. */
+typedef enum { LBM_PERIODIC = 0, LBM_INFLOW = 1, LBM_OUTFLOW = 2, LBM_WALL = 3 } lbm_bc;
+
+typedef struct {
+  int32_t levels;          /* L in 1..5; level 0 is the finest */
+  int32_t fine_extent[3];  /* fine-equivalent nodes per axis; each a multiple of 8*2^(L-1) */
+  int32_t bc[6];           /* lbm_bc for faces x-, x+, y-, y+, z-, z+ */
+  float inflow_u[3];       /* velocity held on INFLOW faces */
+  double tau0;             /* finest-level relaxation time, > 1/2 */
+  int32_t storage;         /* lbm_storage of the stored moments */
+  int32_t rescale;         /* 0: Chapman-Enskog S^neq factors (default); 1: factors as printed in Sec. 5.2-5.3 */
+  float scale[10];         /* per-moment power-of-two storage scales for BF16/F16 (ignored for F32) */
+  int64_t max_blocks;      /* block-pool capacity over all levels */
+  void* pool;              /* device, >= lbm_pool_bytes(cfg): moment storage, two time levels */
+  void* meta;              /* device, >= lbm_meta_bytes(cfg): hierarchy tables and scratch */
+  void* stream;            /* hipStream_t the context launches on (NULL = default stream) */
+} lbm_config;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Sizes of the caller-owned device buffers for a configuration (0 if invalid). */
+size_t lbm_pool_bytes(const lbm_config* cfg);
+size_t lbm_meta_bytes(const lbm_config* cfg);
+
+/* Builds the hierarchy H(Phi) (Sec. 5.4 Phi, Sec. 6.3): level-0 blocks hold every
+ * particle and every solid node; coarser levels follow with one block of overlap.
+ * solid_fine: device uint8 [Z][Y][X] over the fine extent (nonzero = solid), or
+ *   NULL; it must stay valid for the life of the context.
+ * particles: device float [n][3] in fine units, or NULL with n = 0.
+ * All nodes start at rest (rho = 1, u = 0, S = 0), INFLOW nodes at their state.
+ * Synchronises. */
+lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const float* particles,
+                      int64_t n, lbm_ctx** out);
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* Number of active blocks on a level. Host-side, no synchronisation. */
+lbm_status lbm_num_blocks(lbm_ctx* ctx, int32_t level, int64_t* out);
+
+/* Keys of the active blocks of a level into keys_out (device int64 [nb]). */
+lbm_status lbm_block_keys(lbm_ctx* ctx, int32_t level, int64_t* keys_out);
+
+/* Writes moments (layout above, device f32 [nb][10][512]) into the listed blocks
+ * (keys: device int64 [nb], each an active block of the level). SOLID nodes keep
+ * the rest state and INFLOW nodes their face state. */
+lbm_status lbm_set_block_moments(lbm_ctx* ctx, int32_t level, const int64_t* keys, const float* in,
+                                 int64_t nb);
+
+/* Advances n coarse steps: each is one call of AdvanceLBM(L-1, 1) of Alg. 1
+ * (Sec. 5.3): stream-collide per level with two fine substeps per coarser step,
+ * downward transfer (Eq. downward_rescale, with temporal interpolation) before
+ * each fine stream-collide, upward transfer (Eq. upload_S) after the second. */
+lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
+
+/* Moves particles by d (fine units) in f32: p[i] = p[i] + d, as a prescribed
+ * stand-in for the granular solver. particles: device float [n][3]. */
+lbm_status lbm_advance_particles(lbm_ctx* ctx, float* particles, int64_t n, const float d[3]);
+
+/* Grid update (Sec. 6.3) at a coarse-step boundary: rebuilds H(Phi) for the given
+ * particles; new nodes take the value of the old hierarchy (own level, else the
+ * finest coincident node transferred upward, else interpolated downward).
+ * Transactional: on LBM_ECAPACITY the context is unchanged. Synchronises once
+ * (block counts), twice when the block set changes. */
+lbm_status lbm_remesh(lbm_ctx* ctx, const float* particles, int64_t n);
+
+/* Current moments of a level (decoded to f32): keys_out device int64 [nb] (may be
+ * NULL), out device f32 [nb][10][512], blocks in key order. */
+lbm_status lbm_get_moments(lbm_ctx* ctx, int32_t level, int64_t* keys_out, float* out);
+
+/* Node roles of a level, device uint8 [nb][512]: 0 computed, 1 ghost (filled by
+ * the downward transfer), 2 upward-interface node, 3 solid, 4 inflow, 5 outflow. */
+lbm_status lbm_get_roles(lbm_ctx* ctx, int32_t level, uint8_t* out);
+
+/* FP64 sums over the owned (non-ghost, non-solid) nodes of one level whose fine
+ * position lies in [lo, hi): out = {sum rho, sum rho ux, sum rho uy, sum rho uz,
+ * 1/2 sum rho |u|^2} (host double[5]). Synchronises. */
+lbm_status lbm_reduce_f64(lbm_ctx* ctx, int32_t level, const int32_t lo[3], const int32_t hi[3],
+                          double out[5]);
+
+/* LBM_ENAN if any stored moment of an active block is not finite. Synchronises. */
+lbm_status lbm_check_finite(lbm_ctx* ctx);
+
+/* Message of the last failed call on this context (or of lbm_create, for NULL). */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

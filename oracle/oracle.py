@@ -98,9 +98,12 @@ class OracleSim:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().oc_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                lib().oc_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
 
     def num_blocks(self, level):
         return int(lib().oc_num_blocks(self.h, level))

@@ -1,0 +1,588 @@
+// Block hierarchy: level selection, refine/coarsen/delete flags, order-preserving
+// compaction, slot allocation, node roles, neighbour table and the
+// initialisation of new nodes (Sec. 5.4 Phi, Sec. 6.1-6.3).
+//
+// The target hierarchy H(Phi) is written as set algebra on dense per-level flag
+// grids (one byte per block position):
+//   T_0 = level-0 blocks holding a particle or a solid node       (Phi = 0 there)
+//   D_1 = parent(T_0),  B_l = N26(D_l) \ D_l,  D_{l+1} = parent(D_l u B_l)
+//   active_l = children(D_{l+1} u B_{l+1}) \ D_l   (top level: everything \ D_{L-1})
+// D_l are the blocks deleted because the finer level covers them; B_l is the
+// one-block overlap ring. The refine / coarsen / delete decisions of Sec. 6.3 are
+// the differences between the new and the current states of each position.
+// Lists are produced by wavefront ballots + a device prefix scan, visiting block
+// positions in Morton order so every list comes out sorted by key.
+#include "common.h"
+#include "kernels.h"
+
+namespace lbmx {
+namespace {
+
+constexpr uint8_t F_D = 1, F_B = 2;
+
+__device__ inline bool in_level(const LevelGeom& g, int x, int y, int z) {
+  return x >= 0 && y >= 0 && z >= 0 && x < g.nb[0] && y < g.nb[1] && z < g.nb[2];
+}
+
+// ---------------------------------------------------------------- level-0 targets
+__global__ void k_mark_static(Geom G, const uint8_t* solid, uint8_t* t0s) {
+  const LevelGeom& g = G.lv[0];
+  const int64_t cell = blockIdx.x;
+  const int bx = (int)(cell % g.nb[0]), by = (int)((cell / g.nb[0]) % g.nb[1]), bz = (int)(cell / ((int64_t)g.nb[0] * g.nb[1]));
+  int any = 0;
+  for (int n = threadIdx.x; n < kNodes; n += blockDim.x) {
+    const int64_t x = bx * kEdge + (n & 7), y = by * kEdge + ((n >> 3) & 7), z = bz * kEdge + (n >> 6);
+    any |= solid[x + (int64_t)G.N[0] * (y + (int64_t)G.N[1] * z)] != 0;
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) t0s[cell] = any ? 1 : 0;
+}
+
+__global__ void k_copy_or_clear(uint8_t* dst, const uint8_t* src, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src ? src[i] : 0;
+}
+
+__global__ void k_mark_particles(Geom G, const float* p, int64_t n, uint8_t* t0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const LevelGeom& g = G.lv[0];
+  int b[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float q = p[3 * i + a];
+    if (!G.periodic[a] && !(q >= 0.0f && q < (float)G.N[a])) return;
+    int v = (int)floorf(q * 0.125f);
+    if (G.periodic[a]) {
+      v %= g.nb[a];
+      if (v < 0) v += g.nb[a];
+    }
+    b[a] = v;
+  }
+  t0[cell_lin(g, b[0], b[1], b[2])] = 1;
+}
+
+// D_l from the finer level: any child flagged (T_0 for l = 1, D|B for l > 1)
+__global__ void k_deleted(Geom G, int l, const uint8_t* finer, uint8_t mask, uint8_t* flags_l) {
+  const LevelGeom& g = G.lv[l];
+  const LevelGeom& f = G.lv[l - 1];
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  const int bx = (int)(cell % g.nb[0]), by = (int)((cell / g.nb[0]) % g.nb[1]), bz = (int)(cell / ((int64_t)g.nb[0] * g.nb[1]));
+  uint8_t any = 0;
+  for (int c = 0; c < 8; ++c)
+    any |= finer[cell_lin(f, 2 * bx + (c & 1), 2 * by + ((c >> 1) & 1), 2 * bz + (c >> 2))] & mask;
+  flags_l[cell] = any ? F_D : 0;
+}
+
+// B_l = N26(D_l) \ D_l
+__global__ void k_ring(Geom G, int l, uint8_t* flags_l) {
+  const LevelGeom& g = G.lv[l];
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  const uint8_t own = flags_l[cell] & F_D;
+  if (own) return;
+  const int b[3] = {(int)(cell % g.nb[0]), (int)((cell / g.nb[0]) % g.nb[1]), (int)(cell / ((int64_t)g.nb[0] * g.nb[1]))};
+  bool ring = false;
+  for (int d = 0; d < 27 && !ring; ++d) {
+    if (d == 13) continue;
+    int h[3] = {b[0] + d % 3 - 1, b[1] + (d / 3) % 3 - 1, b[2] + d / 9 - 1};
+    bool ok = true;
+    for (int a = 0; a < 3; ++a) {
+      if (h[a] < 0 || h[a] >= g.nb[a]) {
+        if (!G.periodic[a]) { ok = false; break; }
+        h[a] = h[a] < 0 ? h[a] + g.nb[a] : h[a] - g.nb[a];
+      }
+    }
+    if (ok && (flags_l[cell_lin(g, h[0], h[1], h[2])] & F_D)) ring = true;
+  }
+  if (ring) flags_l[cell] = F_B;
+}
+
+__global__ void k_state(Geom G, int l, const uint8_t* flags_l, const uint8_t* flags_up, uint8_t* st_l) {
+  const LevelGeom& g = G.lv[l];
+  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  uint8_t s;
+  if (flags_l && (flags_l[cell] & F_D)) {
+    s = ST_DELETED;
+  } else if (l == G.L - 1) {
+    s = ST_ACTIVE;
+  } else {
+    const LevelGeom& u = G.lv[l + 1];
+    const int bx = (int)(cell % g.nb[0]), by = (int)((cell / g.nb[0]) % g.nb[1]), bz = (int)(cell / ((int64_t)g.nb[0] * g.nb[1]));
+    s = (flags_up[cell_lin(u, bx >> 1, by >> 1, bz >> 1)] & (F_D | F_B)) ? ST_ACTIVE : ST_ABSENT;
+  }
+  st_l[cell] = s;
+}
+
+// ---------------------------------------------------------------- compaction
+// Each wave evaluates up to three predicates on 64 consecutive items, counts
+// them with ballots, a single-workgroup scan turns the wave counts into offsets,
+// and the scatter pass writes every selected item at offset + rank-in-wave.
+__device__ inline void cell_preds(const Geom& G, int l, int64_t t, const uint8_t* st_new, const uint8_t* st_old,
+                                  uint32_t& bits, int32_t& lin) {
+  const LevelGeom& g = G.lv[l];
+  int x, y, z;
+  morton_decode3((uint64_t)t, x, y, z);
+  bits = 0;
+  lin = -1;
+  if (!in_level(g, x, y, z)) return;
+  lin = (int32_t)cell_lin(g, x, y, z);
+  const bool a = st_new[g.off + lin] == ST_ACTIVE;
+  const bool o = st_old[g.off + lin] == ST_ACTIVE;
+  bits = (a ? 1u : 0u) | ((a && !o) ? 2u : 0u) | ((o && !a) ? 4u : 0u);
+}
+
+__global__ void k_cells_count(Geom G, int l, const uint8_t* st_new, const uint8_t* st_old, int64_t nitems,
+                              int32_t* wcount) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t bits = 0;
+  int32_t lin;
+  if (t < nitems) cell_preds(G, l, t, st_new, st_old, bits, lin);
+  const int64_t wave = t >> 6;
+  const int64_t nw = (nitems + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint64_t m = __ballot((bits >> k) & 1u);
+    if ((threadIdx.x & 63) == 0 && wave < nw) wcount[k * nw + wave] = __popcll(m);
+  }
+}
+
+__global__ void k_cells_scatter(Geom G, int l, const uint8_t* st_new, const uint8_t* st_old, int64_t nitems,
+                                const int32_t* woff, CompactOut o) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t bits = 0;
+  int32_t lin = -1;
+  if (t < nitems) cell_preds(G, l, t, st_new, st_old, bits, lin);
+  const int64_t wave = t >> 6;
+  const int64_t nw = (nitems + 63) >> 6;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const bool p = (bits >> k) & 1u;
+    const uint64_t m = __ballot(p);
+    if (p && o.out[k]) o.out[k][woff[k * nw + wave] + __popcll(m & below)] = lin;
+  }
+}
+
+__global__ void k_summary_count(const int32_t* blocks, int32_t n, const uint8_t* summary, int32_t* wcount) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t bits = t < n ? summary[blocks[t]] : 0u;
+  const int64_t nw = ((int64_t)n + 63) >> 6;
+  const int64_t wave = t >> 6;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const uint64_t m = __ballot((bits >> k) & 1u);
+    if ((threadIdx.x & 63) == 0 && wave < nw) wcount[k * nw + wave] = __popcll(m);
+  }
+}
+
+__global__ void k_summary_scatter(const int32_t* blocks, int32_t n, const uint8_t* summary, const int32_t* woff,
+                                  CompactOut o) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t slot = t < n ? blocks[t] : -1;
+  const uint32_t bits = t < n ? summary[slot] : 0u;
+  const int64_t nw = ((int64_t)n + 63) >> 6;
+  const int64_t wave = t >> 6;
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const bool p = (bits >> k) & 1u;
+    const uint64_t m = __ballot(p);
+    if (p && o.out[k]) o.out[k][woff[k * nw + wave] + __popcll(m & below)] = slot;
+  }
+}
+
+// exclusive scan of three arrays of nw wave counts (in place), totals to count[3]
+__global__ __launch_bounds__(1024) void k_scan3(int32_t* w, int64_t nw, int32_t* count) {
+  __shared__ int32_t part[1024];
+  __shared__ int32_t carry;
+  for (int k = 0; k < 3; ++k) {
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nw; base += 1024) {
+      const int64_t i = base + threadIdx.x;
+      const int32_t v = i < nw ? w[k * nw + i] : 0;
+      part[threadIdx.x] = v;
+      __syncthreads();
+      for (int off = 1; off < 1024; off <<= 1) {
+        const int32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+      }
+      if (i < nw) w[k * nw + i] = carry + part[threadIdx.x] - v;
+      __syncthreads();
+      if (threadIdx.x == 1023) carry += part[1023];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) count[k] = carry;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- slots
+__global__ void k_alloc(AllocLaunch a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const LevelGeom& g = a.G.lv[a.level];
+  const int32_t cell = a.cells[i];
+  const int32_t slot = a.free_stack[a.free_top - 1 - i];
+  a.dir_new[g.off + cell] = slot;
+  const int bx = cell % g.nb[0], by = (cell / g.nb[0]) % g.nb[1], bz = cell / (g.nb[0] * g.nb[1]);
+  a.coord[slot] = make_int4(bx, by, bz, a.level);
+}
+
+__global__ void k_release(const int32_t* cells, int32_t n, int64_t off, const int32_t* dir_old, int32_t* free_stack,
+                          int32_t free_top, int32_t* dir_new) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t cell = cells[i];
+  free_stack[free_top + i] = dir_old[off + cell];
+  dir_new[off + cell] = NBR_NONE;
+}
+
+__global__ void k_copy_i32(const int32_t* src, int32_t* dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+__global__ void k_fill_i32(int32_t* dst, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+__global__ void k_fill_u8(uint8_t* dst, uint8_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = v;
+}
+
+// ---------------------------------------------------------------- roles + neighbours
+__device__ inline bool solid_at(const Geom& G, const uint8_t* solid, int l, int gx, int gy, int gz) {
+  if (!solid) return false;
+  const int64_t x = (int64_t)gx << l, y = (int64_t)gy << l, z = (int64_t)gz << l;
+  return solid[x + (int64_t)G.N[0] * (y + (int64_t)G.N[1] * z)] != 0;
+}
+
+__global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
+  __shared__ uint8_t s_st[27];    // state of the 27 surrounding block positions (255 = outside)
+  __shared__ uint8_t s_wall[27];  // outside the domain across wall faces only
+  const Geom& G = r.G;
+  const int l = r.level;
+  const LevelGeom& g = G.lv[l];
+  const int32_t cell = r.cells[blockIdx.x];
+  const int32_t slot = r.dir[g.off + cell];
+  if (slot < 0) return;  // every active cell holds a slot; never write out of bounds
+  const int b[3] = {cell % g.nb[0], (cell / g.nb[0]) % g.nb[1], cell / (g.nb[0] * g.nb[1])};
+  if (threadIdx.x < 27) {
+    const int d = threadIdx.x;
+    int h[3] = {b[0] + d % 3 - 1, b[1] + (d / 3) % 3 - 1, b[2] + d / 9 - 1};
+    bool inside = true, wall = true;
+    for (int a = 0; a < 3; ++a) {
+      if (h[a] < 0 || h[a] >= g.nb[a]) {
+        if (G.periodic[a]) {
+          h[a] = h[a] < 0 ? h[a] + g.nb[a] : h[a] - g.nb[a];
+        } else {
+          inside = false;
+          if (G.bc[2 * a + (h[a] < 0 ? 0 : 1)] != BC_WALL) wall = false;
+        }
+      }
+    }
+    int32_t ns = NBR_NONE;
+    uint8_t stv = 255;
+    if (inside) {
+      const int64_t hc = g.off + cell_lin(g, h[0], h[1], h[2]);
+      stv = r.st[hc];
+      if (stv == ST_ACTIVE) ns = r.dir[hc];
+    } else if (wall) {
+      ns = NBR_WALL;
+    }
+    s_st[d] = stv;
+    s_wall[d] = (!inside && wall) ? 1 : 0;
+    r.nbr[(size_t)slot * 27 + d] = ns;
+  }
+  if (threadIdx.x == 0) r.blocks[blockIdx.x] = slot;
+  __syncthreads();
+  uint8_t sum = 0;
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
+    const int gc[3] = {b[0] * kEdge + lc[0], b[1] * kEdge + lc[1], b[2] * kEdge + lc[2]};
+    uint8_t role = 255;
+    if (solid_at(G, r.solid, l, gc[0], gc[1], gc[2])) role = ROLE_SOLID;
+    if (role == 255) {
+      for (int a = 0; a < 3 && role == 255; ++a) {
+        if (G.periodic[a]) continue;
+        int kind = -1;
+        if (gc[a] == 0) kind = G.bc[2 * a];
+        else if (gc[a] == g.nn[a] - 1) kind = G.bc[2 * a + 1];
+        if (kind == BC_INFLOW) role = ROLE_INFLOW;
+        else if (kind == BC_OUTFLOW) role = ROLE_OUTFLOW;
+      }
+    }
+    if (role == 255) {
+      bool ghost = false, iu = false, bb = false;
+      for (int d = 0; d < 27; ++d) {
+        if (d == 13) continue;
+        const int dd[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+        int h[3], o[3];
+        bool outside = false;
+        for (int a = 0; a < 3; ++a) {
+          const int v = lc[a] + dd[a];
+          o[a] = v < 0 ? 0 : (v > 7 ? 2 : 1);
+          h[a] = gc[a] + dd[a];
+          if (h[a] < 0 || h[a] >= g.nn[a]) {
+            if (G.periodic[a]) h[a] = h[a] < 0 ? h[a] + g.nn[a] : h[a] - g.nn[a];
+            else outside = true;
+          }
+        }
+        const int nd = o[0] + 3 * o[1] + 9 * o[2];
+        if (outside) {
+          if (s_wall[nd]) bb = true;
+          continue;
+        }
+        const uint8_t stv = s_st[nd];
+        if (stv == ST_ABSENT) ghost = true;
+        else if (stv == ST_DELETED) iu = true;
+        if (solid_at(G, r.solid, l, h[0], h[1], h[2])) bb = true;
+      }
+      role = ghost ? ROLE_GHOST : (iu ? ROLE_IU : (uint8_t)(ROLE_COMPUTED | (bb ? ROLE_BB : 0)));
+    }
+    r.role[(size_t)slot * kNodes + node] = role;
+    const uint8_t rk = role & ROLE_MASK;
+    sum |= rk == ROLE_GHOST ? SUM_GHOST : (rk == ROLE_IU ? SUM_IU : (rk == ROLE_OUTFLOW ? SUM_OUTFLOW : 0));
+  }
+  const int any_g = __syncthreads_or(sum & SUM_GHOST);
+  const int any_i = __syncthreads_or(sum & SUM_IU);
+  const int any_o = __syncthreads_or(sum & SUM_OUTFLOW);
+  if (threadIdx.x == 0) r.summary[slot] = (any_g ? SUM_GHOST : 0) | (any_i ? SUM_IU : 0) | (any_o ? SUM_OUTFLOW : 0);
+}
+
+// ---------------------------------------------------------------- new-node initialisation
+// Value of level-l node g in the old hierarchy, accumulated linearly in
+// (rho-1, u, S^neq) with weight w and S^neq factor sf: the node's own value if
+// owned; else the nearest finer level owning the coincident node (upward, S^neq
+// times a_up per level); else trilinear from level l+1 (downward, times a_down).
+template <class S> struct Sampler {
+  const InitLaunch& a;
+  __device__ explicit Sampler(const InitLaunch& x) : a(x) {}
+
+  __device__ bool owned(int l, int gx, int gy, int gz, float q[kMom]) const {
+    const LevelGeom& g = a.G.lv[l];
+    const int64_t c = g.off + cell_lin(g, gx >> 3, gy >> 3, gz >> 3);
+    if (a.st_old[c] != ST_ACTIVE) return false;
+    const int32_t slot = a.dir_old[c];
+    if (slot < 0) return false;
+    const int node = (gx & 7) + 8 * (gy & 7) + 64 * (gz & 7);
+    const uint8_t r = a.role_old[(size_t)slot * kNodes + node] & ROLE_MASK;
+    if (!(r == ROLE_COMPUTED || r == ROLE_IU || r == ROLE_INFLOW || r == ROLE_OUTFLOW)) return false;
+    const typename S::type* p = static_cast<const typename S::type*>(a.cur[l]) + (size_t)slot * kBlockStride + node;
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(p[m * kNodes], a.sc.inv[m]);
+    return true;
+  }
+
+  __device__ bool upchain(int l, const int g[3], float w, float sf, float acc[kMom]) const {
+    float f = sf;
+    for (int k = l; k >= 0; --k) {
+      const int sh = l - k;
+      float q[kMom];
+      if (owned(k, g[0] << sh, g[1] << sh, g[2] << sh, q)) {
+        acc[0] += w * q[0];
+        acc[1] += w * q[1]; acc[2] += w * q[2]; acc[3] += w * q[3];
+        const float ws = w * f;
+        acc[4] += ws * (q[4] - q[1] * q[1]); acc[5] += ws * (q[5] - q[2] * q[2]); acc[6] += ws * (q[6] - q[3] * q[3]);
+        acc[7] += ws * (q[7] - q[1] * q[2]); acc[8] += ws * (q[8] - q[1] * q[3]); acc[9] += ws * (q[9] - q[2] * q[3]);
+        return true;
+      }
+      if (k > 0) f *= a.a_up[k - 1];
+    }
+    return false;
+  }
+
+  template <int D>
+  __device__ bool sample(int l, const int g[3], float w, float sf, float acc[kMom]) const {
+    if (upchain(l, g, w, sf, acc)) return true;
+    if constexpr (D == 0) {
+      return false;
+    } else {
+      if (l + 1 >= a.G.L) return false;
+      const LevelGeom& cg = a.G.lv[l + 1];
+      int cand[3][2], cnt[3];
+      float wv[3][2];
+      for (int ax = 0; ax < 3; ++ax) {
+        const int nc = cg.nn[ax];
+        if ((g[ax] & 1) == 0) { cand[ax][0] = g[ax] >> 1; wv[ax][0] = 1.0f; cnt[ax] = 1; }
+        else { cand[ax][0] = (g[ax] - 1) >> 1; cand[ax][1] = (g[ax] + 1) >> 1; wv[ax][0] = wv[ax][1] = 0.5f; cnt[ax] = 2; }
+        for (int k = 0; k < cnt[ax]; ++k) {
+          int v = cand[ax][k];
+          if (a.G.periodic[ax]) v = v < 0 ? v + nc : (v >= nc ? v - nc : v);
+          else v = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+          cand[ax][k] = v;
+        }
+      }
+      bool ok = true;
+      for (int kz = 0; kz < cnt[2]; ++kz)
+        for (int ky = 0; ky < cnt[1]; ++ky)
+          for (int kx = 0; kx < cnt[0]; ++kx) {
+            const int j[3] = {cand[0][kx], cand[1][ky], cand[2][kz]};
+            ok = sample<D - 1>(l + 1, j, w * wv[0][kx] * wv[1][ky] * wv[2][kz], sf * a.a_down[l], acc) && ok;
+          }
+      return ok;
+    }
+  }
+};
+
+template <class S>
+__global__ __launch_bounds__(256) void k_init(InitLaunch a) {
+  const LevelGeom& g = a.G.lv[a.level];
+  const int32_t cell = a.cells[blockIdx.x];
+  const int32_t slot = a.dir_new[g.off + cell];
+  if (slot < 0) return;  // every active cell holds a slot; never write out of bounds
+  const bool new_block = a.create || a.st_old[g.off + cell] != ST_ACTIVE;
+  const int b[3] = {cell % g.nb[0], (cell / g.nb[0]) % g.nb[1], cell / (g.nb[0] * g.nb[1])};
+  typedef typename S::type T;
+  T* cur = static_cast<T*>(a.dst_cur) + (size_t)slot * kBlockStride;
+  T* oth = static_cast<T*>(a.dst_other) + (size_t)slot * kBlockStride;
+  Sampler<S> smp(a);
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    const uint8_t rn = a.role_new[(size_t)slot * kNodes + node] & ROLE_MASK;
+    bool fresh = new_block;
+    if (!fresh) {
+      const uint8_t ro = a.role_old[(size_t)slot * kNodes + node] & ROLE_MASK;
+      const bool own_old = ro == ROLE_COMPUTED || ro == ROLE_IU || ro == ROLE_INFLOW || ro == ROLE_OUTFLOW;
+      const bool own_new = rn == ROLE_COMPUTED || rn == ROLE_IU || rn == ROLE_INFLOW || rn == ROLE_OUTFLOW;
+      fresh = !own_old && own_new;
+    }
+    if (!fresh) continue;
+    float q[kMom];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) q[m] = 0.0f;
+    if (rn == ROLE_INFLOW) {
+      q[1] = a.inflow[0]; q[2] = a.inflow[1]; q[3] = a.inflow[2];
+      q[4] = q[1] * q[1]; q[5] = q[2] * q[2]; q[6] = q[3] * q[3];
+      q[7] = q[1] * q[2]; q[8] = q[1] * q[3]; q[9] = q[2] * q[3];
+    } else if (rn != ROLE_SOLID && !a.create) {
+      const int gn[3] = {b[0] * kEdge + (node & 7), b[1] * kEdge + ((node >> 3) & 7), b[2] * kEdge + (node >> 6)};
+      float acc[kMom];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
+      smp.template sample<kMaxLevels - 1>(a.level, gn, 1.0f, 1.0f, acc);
+      q[0] = acc[0];
+      q[1] = acc[1]; q[2] = acc[2]; q[3] = acc[3];
+      q[4] = acc[4] + acc[1] * acc[1]; q[5] = acc[5] + acc[2] * acc[2]; q[6] = acc[6] + acc[3] * acc[3];
+      q[7] = acc[7] + acc[1] * acc[2]; q[8] = acc[8] + acc[1] * acc[3]; q[9] = acc[9] + acc[2] * acc[3];
+    }
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) {
+      const T v = Codec<S>::store(q[m], a.sc.s[m]);
+      cur[m * kNodes + node] = v;
+      oth[m * kNodes + node] = v;
+    }
+  }
+}
+
+inline unsigned grid1(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_mark_static(const Geom& G, const uint8_t* solid, uint8_t* t0s, hipStream_t s) {
+  if (!solid) {
+    hipLaunchKernelGGL(k_copy_or_clear, dim3(grid1(G.lv[0].ncell, 256)), dim3(256), 0, s, t0s, (const uint8_t*)nullptr,
+                       G.lv[0].ncell);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_mark_static, dim3((unsigned)G.lv[0].ncell), dim3(256), 0, s, G, solid, t0s);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const HierLaunch& h, const float* p, int64_t n, hipStream_t s) {
+  const int64_t n0 = h.G.lv[0].ncell;
+  hipLaunchKernelGGL(k_copy_or_clear, dim3(grid1(n0, 256)), dim3(256), 0, s, h.t0, h.t0_static, n0);
+  if (p && n > 0) hipLaunchKernelGGL(k_mark_particles, dim3(grid1(n, 256)), dim3(256), 0, s, h.G, p, n, h.t0);
+  return hipGetLastError();
+}
+
+hipError_t launch_states(const HierLaunch& h, hipStream_t s) {
+  const Geom& G = h.G;
+  for (int l = 1; l < G.L; ++l) {
+    const LevelGeom& g = G.lv[l];
+    const uint8_t* finer = (l == 1) ? h.t0 : h.flags + G.lv[l - 1].off;
+    const uint8_t mask = (l == 1) ? 1 : (F_D | F_B);
+    hipLaunchKernelGGL(k_deleted, dim3(grid1(g.ncell, 256)), dim3(256), 0, s, G, l, finer, mask, h.flags + g.off);
+    hipLaunchKernelGGL(k_ring, dim3(grid1(g.ncell, 256)), dim3(256), 0, s, G, l, h.flags + g.off);
+  }
+  for (int l = 0; l < G.L; ++l) {
+    const LevelGeom& g = G.lv[l];
+    const uint8_t* fl = (l >= 1) ? h.flags + g.off : nullptr;
+    const uint8_t* fu = (l + 1 < G.L) ? h.flags + G.lv[l + 1].off : nullptr;
+    hipLaunchKernelGGL(k_state, dim3(grid1(g.ncell, 256)), dim3(256), 0, s, G, l, fl, fu, h.st_new + g.off);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_cells(const Geom& G, int l, const uint8_t* st_new, const uint8_t* st_old,
+                                int32_t* wave_scratch, const CompactOut& o, hipStream_t s) {
+  const int64_t nitems = (int64_t)1 << (3 * G.lv[l].mbits);
+  const int64_t nw = (nitems + 63) >> 6;
+  hipLaunchKernelGGL(k_cells_count, dim3(grid1(nitems, 256)), dim3(256), 0, s, G, l, st_new, st_old, nitems, wave_scratch);
+  hipLaunchKernelGGL(k_scan3, dim3(1), dim3(1024), 0, s, wave_scratch, nw, o.count);
+  hipLaunchKernelGGL(k_cells_scatter, dim3(grid1(nitems, 256)), dim3(256), 0, s, G, l, st_new, st_old, nitems,
+                     (const int32_t*)wave_scratch, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_summary(const int32_t* blocks, int32_t n, const uint8_t* summary, int32_t* wave_scratch,
+                                  const CompactOut& o, hipStream_t s) {
+  const int64_t nw = ((int64_t)n + 63) >> 6;
+  if (n > 0) hipLaunchKernelGGL(k_summary_count, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, wave_scratch);
+  hipLaunchKernelGGL(k_scan3, dim3(1), dim3(1024), 0, s, wave_scratch, nw, o.count);
+  if (n > 0)
+    hipLaunchKernelGGL(k_summary_scatter, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary,
+                       (const int32_t*)wave_scratch, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_alloc(const AllocLaunch& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_alloc, dim3(grid1(a.n, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_release(const int32_t* cells, int32_t n, int64_t off, const int32_t* dir_old, int32_t* free_stack,
+                          int32_t free_top, int32_t* dir_new, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_release, dim3(grid1(n, 256)), dim3(256), 0, s, cells, n, off, dir_old, free_stack, free_top, dir_new);
+  return hipGetLastError();
+}
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_i32, dim3(grid1(n, 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t* dst, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid1(n, 256)), dim3(256), 0, s, dst, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u8(uint8_t* dst, uint8_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u8, dim3(grid1(n, 256)), dim3(256), 0, s, dst, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_roles(const RoleLaunch& r, hipStream_t s) {
+  if (r.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_roles, dim3(r.n), dim3(256), 0, s, r);
+  return hipGetLastError();
+}
+hipError_t launch_init(const InitLaunch& a, hipStream_t s) {
+  if (a.n <= 0) return hipSuccess;
+  switch (a.storage) {
+    case 0: hipLaunchKernelGGL(k_init<StoreF32>, dim3(a.n), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_init<StoreBF16>, dim3(a.n), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_init<StoreF16>, dim3(a.n), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbmx

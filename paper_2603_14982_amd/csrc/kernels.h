@@ -1,0 +1,161 @@
+// Host-side launchers of the HIP kernels (one translation unit per kernel family).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace lbmx {
+
+// ---- stream-collide (one level, one step) ----
+struct ScLaunch {
+  const void* in;            // pool time level read (storage type)
+  void* out;                 // pool time level written
+  const int32_t* blocks;     // slots of the level, key order
+  int32_t nblocks;
+  const int32_t* nbr;        // [slot][27]
+  const uint8_t* role;       // [slot][512]
+  float omega;
+  Scales sc;
+  int storage;
+};
+hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s);
+
+// ---- interface transfers and outflow ----
+struct TransferLaunch {
+  Geom G;
+  int level;                 // fine level l (down: l+1 -> l, up: l -> l+1)
+  const int32_t* blocks;     // blocks holding target nodes (level l for down, l+1 for up)
+  int32_t nblocks;
+  const int32_t* dir;        // all-level cell -> slot
+  const uint8_t* role;       // [slot][512]
+  const int4* coord;         // [slot] block coordinates and level
+  const void* src_a;         // source time level (down: coarse t; up: fine current)
+  const void* src_b;         // down only: coarse t+2 (same as src_a for s = 1)
+  void* dst;                 // target time level
+  float factor;              // S^neq rescaling factor
+  int midpoint;              // down only: 1 = average src_a and src_b
+  Scales sc;
+  int storage;
+};
+hipError_t launch_downward(const TransferLaunch& a, hipStream_t s);
+hipError_t launch_upward(const TransferLaunch& a, hipStream_t s);
+// outflow copy on the level's outflow blocks: dst = src_new (computed inward
+// neighbour) or the node's own old value
+struct OutflowLaunch {
+  Geom G;
+  int level;
+  const int32_t* blocks;
+  int32_t nblocks;
+  const uint8_t* role;
+  const int4* coord;
+  const void* old_buf;
+  void* new_buf;
+  int storage;
+};
+hipError_t launch_outflow(const OutflowLaunch& a, hipStream_t s);
+
+// ---- hierarchy (grid update) ----
+struct HierLaunch {
+  Geom G;
+  uint8_t* t0;               // level-0 target cells
+  const uint8_t* t0_static;  // level-0 cells holding solid nodes
+  uint8_t* flags;            // all-level cells: bit0 D (covered by finer), bit1 B (ring)
+  uint8_t* st_new;           // all-level cells: new state
+  const uint8_t* st_old;
+};
+hipError_t launch_mark_static(const Geom& G, const uint8_t* solid, uint8_t* t0_static, hipStream_t s);
+hipError_t launch_targets(const HierLaunch& h, const float* particles, int64_t n, hipStream_t s);
+hipError_t launch_states(const HierLaunch& h, hipStream_t s);
+
+// generic order-preserving compaction (ballot + device prefix scan) over up to
+// three predicates; items are cells visited in Morton order of a level, or the
+// entries of an int32 list
+struct CompactOut {
+  int32_t* out[3];           // compacted values per predicate (may be null)
+  int32_t* count;            // device: three totals
+};
+hipError_t launch_compact_cells(const Geom& G, int level, const uint8_t* st_new, const uint8_t* st_old,
+                                int32_t* wave_scratch, const CompactOut& o, hipStream_t s);
+hipError_t launch_compact_summary(const int32_t* blocks, int32_t n, const uint8_t* summary,
+                                  int32_t* wave_scratch, const CompactOut& o, hipStream_t s);
+
+struct AllocLaunch {
+  const int32_t* cells;      // new cells of one level
+  int32_t n;
+  int level;
+  Geom G;
+  const int32_t* free_stack;
+  int32_t free_top;          // stack top before this level's allocation
+  int32_t* dir_new;
+  int4* coord;
+};
+hipError_t launch_alloc(const AllocLaunch& a, hipStream_t s);
+hipError_t launch_release(const int32_t* cells, int32_t n, int64_t level_off, const int32_t* dir_old,
+                          int32_t* free_stack, int32_t free_top, int32_t* dir_new, hipStream_t s);
+hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* dst, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* dst, uint8_t v, int64_t n, hipStream_t s);
+
+struct RoleLaunch {
+  Geom G;
+  int level;
+  const int32_t* cells;      // active cells of the level (new hierarchy), Morton order
+  int32_t n;
+  const int32_t* dir;        // new directory
+  const uint8_t* st;         // new states
+  const uint8_t* solid;      // fine solid field or null
+  uint8_t* role;             // [slot][512] new roles
+  uint8_t* summary;          // [slot]
+  int32_t* blocks;           // out: slots in key order
+  int32_t* nbr;              // out: [slot][27]
+};
+hipError_t launch_roles(const RoleLaunch& r, hipStream_t s);
+
+struct InitLaunch {
+  Geom G;
+  int level;
+  const int32_t* cells;      // active cells of the level (new hierarchy)
+  int32_t n;
+  const int32_t* dir_new;
+  const uint8_t* st_old;
+  const int32_t* dir_old;
+  const uint8_t* role_old;
+  const uint8_t* role_new;
+  const void* cur[kMaxLevels];   // current time level of every level (old hierarchy)
+  void* dst_cur;             // current time level of this level
+  void* dst_other;           // other time level of this level
+  float a_up[kMaxLevels];
+  float a_down[kMaxLevels];
+  float inflow[3];
+  int create;                // 1: no old hierarchy, start at rest
+  Scales sc;
+  int storage;
+};
+hipError_t launch_init(const InitLaunch& a, hipStream_t s);
+
+// ---- data movement and reductions ----
+struct IoLaunch {
+  Geom G;
+  int level;
+  const int32_t* blocks;
+  int32_t nblocks;
+  const int4* coord;
+  const uint8_t* role;
+  void* buf;                 // current time level
+  void* other;               // other time level (set only)
+  Scales sc;
+  int storage;
+  float inflow[3];
+};
+hipError_t launch_get(const IoLaunch& a, int64_t* keys, float* out, hipStream_t s);
+hipError_t launch_get_roles(const IoLaunch& a, uint8_t* out, hipStream_t s);
+hipError_t launch_set(const IoLaunch& a, const int64_t* keys, const float* in, int64_t nb,
+                      const int32_t* dir, int32_t* err_flag, hipStream_t s);
+hipError_t launch_keys(const IoLaunch& a, int64_t* keys, hipStream_t s);
+hipError_t launch_reduce(const IoLaunch& a, const int32_t lo[3], const int32_t hi[3], double* partial,
+                         double* out, hipStream_t s);
+hipError_t launch_finite(const IoLaunch& a, int32_t* flag, hipStream_t s);
+hipError_t launch_advance_particles(float* p, int64_t n, float dx, float dy, float dz, hipStream_t s);
+
+}  // namespace lbmx

@@ -1,0 +1,605 @@
+// Host runtime behind the C ABI of include/lbm.h: configuration checks, the
+// layout of the caller-owned device buffers, the Alg. 1 driver (Sec. 5.3) and the
+// grid-update pipeline (Sec. 6.3).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "lbm.h"
+
+using namespace lbmx;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  size_t t0, t0s, flags, st[2], dir[2], lists, wave, counts, coord, nbr, role[2], summary, free_stack, blocks, gblocks,
+      iblocks, oblocks, red_partial, red_out, flag;
+  size_t total;
+  int64_t level_list_off[kMaxLevels];  // offset (elements) of each level's segment in blocks / g/i/o lists
+  int64_t level_list_cap[kMaxLevels];
+  int64_t wave_cap;                    // int32 entries per predicate in the wave scratch
+};
+
+bool make_geom(const lbm_config* c, Geom& G, std::string& err) {
+  if (!c) { err = "null configuration"; return false; }
+  if (c->levels < 1 || c->levels > kMaxLevels) { err = "levels must be in 1..5"; return false; }
+  std::memset(&G, 0, sizeof(G));
+  G.L = c->levels;
+  const int unit = kEdge << (c->levels - 1);
+  for (int a = 0; a < 3; ++a) {
+    if (c->fine_extent[a] <= 0 || c->fine_extent[a] % unit != 0) {
+      err = "fine_extent must be a positive multiple of 8*2^(levels-1)";
+      return false;
+    }
+    if (c->fine_extent[a] > (1 << 20)) { err = "fine_extent too large"; return false; }
+    G.N[a] = c->fine_extent[a];
+  }
+  for (int f = 0; f < 6; ++f) {
+    if (c->bc[f] < 0 || c->bc[f] > 3) { err = "unknown boundary kind"; return false; }
+    G.bc[f] = c->bc[f];
+  }
+  for (int a = 0; a < 3; ++a) {
+    const bool p0 = c->bc[2 * a] == LBM_PERIODIC, p1 = c->bc[2 * a + 1] == LBM_PERIODIC;
+    if (p0 != p1) { err = "periodic faces must come in pairs"; return false; }
+    G.periodic[a] = p0 ? 1 : 0;
+  }
+  int64_t off = 0;
+  for (int l = 0; l < G.L; ++l) {
+    LevelGeom& g = G.lv[l];
+    int mx = 0;
+    for (int a = 0; a < 3; ++a) {
+      g.nn[a] = G.N[a] >> l;
+      g.nb[a] = g.nn[a] / kEdge;
+      mx = g.nb[a] > mx ? g.nb[a] : mx;
+    }
+    g.mbits = 0;
+    while ((1 << g.mbits) < mx) ++g.mbits;
+    g.ncell = (int64_t)g.nb[0] * g.nb[1] * g.nb[2];
+    g.off = off;
+    off += g.ncell;
+  }
+  if (!(c->tau0 > 0.5) || !std::isfinite(c->tau0)) { err = "tau0 must be finite and exceed 1/2"; return false; }
+  if (c->storage < LBM_F32 || c->storage > LBM_F16) { err = "unknown storage format"; return false; }
+  if (c->rescale != 0 && c->rescale != 1) { err = "rescale must be 0 or 1"; return false; }
+  if (c->max_blocks < 1 || c->max_blocks > (int64_t(1) << 26)) { err = "max_blocks must be in 1..2^26"; return false; }
+  if (c->storage != LBM_F32)
+    for (int m = 0; m < kMom; ++m)
+      if (!(c->scale[m] > 0.0f) || !std::isfinite(c->scale[m])) { err = "storage scales must be positive"; return false; }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(c->inflow_u[a])) { err = "inflow_u must be finite"; return false; }
+  return true;
+}
+
+Layout make_layout(const lbm_config* c, const Geom& G) {
+  Layout L;
+  std::memset(&L, 0, sizeof(L));
+  const int64_t cap = c->max_blocks;
+  int64_t ncell = 0, nlist = 0, maxw = 0;
+  for (int l = 0; l < G.L; ++l) {
+    ncell += G.lv[l].ncell;
+    L.level_list_off[l] = nlist;
+    L.level_list_cap[l] = G.lv[l].ncell < cap ? G.lv[l].ncell : cap;
+    nlist += L.level_list_cap[l];
+    const int64_t nw = ((int64_t(1) << (3 * G.lv[l].mbits)) + 63) / 64;
+    maxw = nw > maxw ? nw : maxw;
+  }
+  const int64_t nwb = (cap + 63) / 64 + 1;
+  L.wave_cap = maxw > nwb ? maxw : nwb;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
+  L.t0 = take(G.lv[0].ncell);
+  L.t0s = take(G.lv[0].ncell);
+  L.flags = take(ncell);
+  L.st[0] = take(ncell);
+  L.st[1] = take(ncell);
+  L.dir[0] = take(ncell * 4);
+  L.dir[1] = take(ncell * 4);
+  L.lists = take(3 * ncell * 4);
+  L.wave = take(3 * L.wave_cap * 4);
+  L.counts = take(64 * 4);
+  L.coord = take(cap * 16);
+  L.nbr = take(cap * 27 * 4);
+  L.role[0] = take(cap * kNodes);
+  L.role[1] = take(cap * kNodes);
+  L.summary = take(cap);
+  L.free_stack = take(cap * 4);
+  L.blocks = take(nlist * 4);
+  L.gblocks = take(nlist * 4);
+  L.iblocks = take(nlist * 4);
+  L.oblocks = take(nlist * 4);
+  L.red_partial = take(cap * 5 * 8);
+  L.red_out = take(8 * 8);
+  L.flag = take(64);
+  L.total = o;
+  return L;
+}
+
+size_t elem_bytes(int storage) { return storage == LBM_F32 ? 4 : 2; }
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_config cfg;
+  Geom G;
+  Layout lay;
+  hipStream_t stream = nullptr;
+  int64_t cap = 0;
+  double tau[kMaxLevels], a_up[kMaxLevels], a_down[kMaxLevels];
+  int parity[kMaxLevels];
+  Scales sc;
+  size_t elem = 4;
+  char* pool = nullptr;
+  char* meta = nullptr;
+  int hier = 0;   // which of st/dir is current
+  int rcur = 0;   // which role array is current
+  const uint8_t* solid = nullptr;
+  int64_t nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels];
+  int32_t free_top = 0;
+  int32_t* host_counts = nullptr;  // pinned
+  std::string err;
+
+  template <class T> T* m(size_t off) const { return reinterpret_cast<T*>(meta + off); }
+  uint8_t* st(int k) const { return m<uint8_t>(lay.st[k]); }
+  int32_t* dir(int k) const { return m<int32_t>(lay.dir[k]); }
+  uint8_t* role(int k) const { return m<uint8_t>(lay.role[k]); }
+  int32_t* lists(int l, int k) const {
+    int64_t off = 0;
+    for (int j = 0; j < l; ++j) off += 3 * G.lv[j].ncell;
+    return m<int32_t>(lay.lists) + off + k * G.lv[l].ncell;
+  }
+  int32_t* blocks(int l) const { return m<int32_t>(lay.blocks) + lay.level_list_off[l]; }
+  int32_t* gblocks(int l) const { return m<int32_t>(lay.gblocks) + lay.level_list_off[l]; }
+  int32_t* iblocks(int l) const { return m<int32_t>(lay.iblocks) + lay.level_list_off[l]; }
+  int32_t* oblocks(int l) const { return m<int32_t>(lay.oblocks) + lay.level_list_off[l]; }
+  void* buf(int l, int p) const { return pool + (size_t)p * (size_t)cap * kBlockStride * elem; }
+  void* cur(int l) const { return buf(l, parity[l]); }
+  void* other(int l) const { return buf(l, 1 - parity[l]); }
+
+  lbm_status fail(lbm_status s, const std::string& msg) { err = msg; return s; }
+  lbm_status hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return LBM_OK;
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBM_EDEVICE;
+  }
+};
+
+#define HIPCHK(ctx, expr)                                        \
+  do {                                                           \
+    lbm_status _s = (ctx)->hip_check((expr), #expr);             \
+    if (_s != LBM_OK) return _s;                                 \
+  } while (0)
+
+namespace {
+
+IoLaunch io_of(const lbm_ctx* c, int level) {
+  IoLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  a.G = c->G;
+  a.level = level;
+  a.blocks = c->blocks(level);
+  a.nblocks = (int32_t)c->nblk[level];
+  a.coord = c->m<int4>(c->lay.coord);
+  a.role = c->role(c->rcur);
+  a.buf = c->cur(level);
+  a.other = c->other(level);
+  a.sc = c->sc;
+  a.storage = c->cfg.storage;
+  for (int k = 0; k < 3; ++k) a.inflow[k] = c->cfg.inflow_u[k];
+  return a;
+}
+
+// Grid update: H(Phi) for the particles (plus static solid blocks), new nodes
+// initialised from the old hierarchy (or at rest when creating).
+lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
+  const Geom& G = c->G;
+  hipStream_t s = c->stream;
+  const int L = G.L;
+  const int nh = 1 - c->hier;
+  HierLaunch h;
+  h.G = G;
+  h.t0 = c->m<uint8_t>(c->lay.t0);
+  h.t0_static = c->m<uint8_t>(c->lay.t0s);
+  h.flags = c->m<uint8_t>(c->lay.flags);
+  h.st_new = c->st(nh);
+  h.st_old = c->st(c->hier);
+  HIPCHK(c, launch_targets(h, particles, n, s));
+  HIPCHK(c, launch_states(h, s));
+  int32_t* counts = c->m<int32_t>(c->lay.counts);
+  int32_t* wave = c->m<int32_t>(c->lay.wave);
+  for (int l = 0; l < L; ++l) {
+    CompactOut o;
+    o.out[0] = c->lists(l, 0);
+    o.out[1] = c->lists(l, 1);
+    o.out[2] = c->lists(l, 2);
+    o.count = counts + 3 * l;
+    HIPCHK(c, launch_compact_cells(G, l, h.st_new, h.st_old, wave, o, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 3 * L * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  int64_t nact[kMaxLevels], nnew[kMaxLevels], nrem[kMaxLevels];
+  int64_t tot_new = 0, tot_rem = 0, tot_act = 0;
+  for (int l = 0; l < L; ++l) {
+    nact[l] = c->host_counts[3 * l];
+    nnew[l] = c->host_counts[3 * l + 1];
+    nrem[l] = c->host_counts[3 * l + 2];
+    tot_new += nnew[l];
+    tot_rem += nrem[l];
+    tot_act += nact[l];
+    if (nact[l] > c->lay.level_list_cap[l]) return c->fail(LBM_ECAPACITY, "level block count exceeds the pool capacity");
+  }
+  if (!create && tot_new == 0 && tot_rem == 0) return LBM_OK;
+  if (tot_new > c->free_top || tot_act > c->cap)
+    return c->fail(LBM_ECAPACITY, "block pool too small for the new hierarchy (" + std::to_string(tot_act) +
+                                      " blocks needed, max_blocks " + std::to_string(c->cap) + ")");
+  // ---- from here on the update commits
+  int64_t ncell = 0;
+  for (int l = 0; l < L; ++l) ncell += G.lv[l].ncell;
+  int32_t* dir_old = c->dir(c->hier);
+  int32_t* dir_new = c->dir(nh);
+  HIPCHK(c, launch_copy_i32(dir_old, dir_new, ncell, s));
+  int32_t top = c->free_top;
+  int4* coord = c->m<int4>(c->lay.coord);
+  int32_t* fstack = c->m<int32_t>(c->lay.free_stack);
+  for (int l = 0; l < L; ++l) {
+    AllocLaunch a;
+    a.cells = c->lists(l, 1);
+    a.n = (int32_t)nnew[l];
+    a.level = l;
+    a.G = G;
+    a.free_stack = fstack;
+    a.free_top = top;
+    a.dir_new = dir_new;
+    a.coord = coord;
+    HIPCHK(c, launch_alloc(a, s));
+    top -= (int32_t)nnew[l];
+  }
+  for (int l = 0; l < L; ++l) {
+    HIPCHK(c, launch_release(c->lists(l, 2), (int32_t)nrem[l], G.lv[l].off, dir_old, fstack, top, dir_new, s));
+    top += (int32_t)nrem[l];
+  }
+  uint8_t* role_old = c->role(c->rcur);
+  uint8_t* role_new = c->role(1 - c->rcur);
+  uint8_t* summary = c->m<uint8_t>(c->lay.summary);
+  for (int l = 0; l < L; ++l) {
+    RoleLaunch r;
+    r.G = G;
+    r.level = l;
+    r.cells = c->lists(l, 0);
+    r.n = (int32_t)nact[l];
+    r.dir = dir_new;
+    r.st = h.st_new;
+    r.solid = c->solid;
+    r.role = role_new;
+    r.summary = summary;
+    r.blocks = c->blocks(l);
+    r.nbr = c->m<int32_t>(c->lay.nbr);
+    HIPCHK(c, launch_roles(r, s));
+  }
+  for (int l = 0; l < L; ++l) {
+    InitLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.G = G;
+    a.level = l;
+    a.cells = c->lists(l, 0);
+    a.n = (int32_t)nact[l];
+    a.dir_new = dir_new;
+    a.st_old = h.st_old;
+    a.dir_old = dir_old;
+    a.role_old = role_old;
+    a.role_new = role_new;
+    for (int k = 0; k < L; ++k) a.cur[k] = c->cur(k);
+    a.dst_cur = c->cur(l);
+    a.dst_other = c->other(l);
+    for (int k = 0; k < L; ++k) {
+      a.a_up[k] = (float)c->a_up[k];
+      a.a_down[k] = (float)c->a_down[k];
+    }
+    for (int k = 0; k < 3; ++k) a.inflow[k] = c->cfg.inflow_u[k];
+    a.create = create ? 1 : 0;
+    a.sc = c->sc;
+    a.storage = c->cfg.storage;
+    HIPCHK(c, launch_init(a, s));
+  }
+  c->hier = nh;
+  c->rcur = 1 - c->rcur;
+  c->free_top = top;
+  for (int l = 0; l < L; ++l) {
+    CompactOut o;
+    o.out[0] = c->gblocks(l);
+    o.out[1] = c->iblocks(l);
+    o.out[2] = c->oblocks(l);
+    o.count = counts + 3 * l;
+    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, wave, o, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 3 * L * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int l = 0; l < L; ++l) {
+    c->nblk[l] = nact[l];
+    c->ngb[l] = c->host_counts[3 * l];
+    c->nib[l] = c->host_counts[3 * l + 1];
+    c->nob[l] = c->host_counts[3 * l + 2];
+  }
+  return LBM_OK;
+}
+
+// ---- Alg. 1 (Sec. 5.3) ----
+lbm_status sc_level(lbm_ctx* c, int l) {
+  ScLaunch a;
+  a.in = c->cur(l);
+  a.out = c->other(l);
+  a.blocks = c->blocks(l);
+  a.nblocks = (int32_t)c->nblk[l];
+  a.nbr = c->m<int32_t>(c->lay.nbr);
+  a.role = c->role(c->rcur);
+  a.omega = (float)(1.0 / c->tau[l]);
+  a.sc = c->sc;
+  a.storage = c->cfg.storage;
+  HIPCHK(c, launch_stream_collide(a, c->stream));
+  if (c->nob[l] > 0) {
+    OutflowLaunch o;
+    o.G = c->G;
+    o.level = l;
+    o.blocks = c->oblocks(l);
+    o.nblocks = (int32_t)c->nob[l];
+    o.role = c->role(c->rcur);
+    o.coord = c->m<int4>(c->lay.coord);
+    o.old_buf = c->cur(l);
+    o.new_buf = c->other(l);
+    o.storage = c->cfg.storage;
+    HIPCHK(c, launch_outflow(o, c->stream));
+  }
+  c->parity[l] ^= 1;
+  return LBM_OK;
+}
+
+TransferLaunch transfer_base(lbm_ctx* c, int l) {
+  TransferLaunch t;
+  std::memset(&t, 0, sizeof(t));
+  t.G = c->G;
+  t.level = l;
+  t.dir = c->dir(c->hier);
+  t.role = c->role(c->rcur);
+  t.coord = c->m<int4>(c->lay.coord);
+  t.sc = c->sc;
+  t.storage = c->cfg.storage;
+  return t;
+}
+
+// DownwardTransfer(l+1, s): ghosts of level l from level l+1 (old: t, current: t+2)
+lbm_status down_level(lbm_ctx* c, int l, int s) {
+  if (c->ngb[l] == 0) return LBM_OK;
+  TransferLaunch t = transfer_base(c, l);
+  t.blocks = c->gblocks(l);
+  t.nblocks = (int32_t)c->ngb[l];
+  t.src_a = c->other(l + 1);
+  t.src_b = c->cur(l + 1);
+  t.midpoint = (s == 2) ? 1 : 0;
+  t.dst = c->cur(l);
+  t.factor = (float)c->a_down[l];
+  HIPCHK(c, launch_downward(t, c->stream));
+  return LBM_OK;
+}
+
+// UpwardTransfer(l): interface nodes of level l+1 from level l
+lbm_status up_level(lbm_ctx* c, int l) {
+  if (c->nib[l + 1] == 0) return LBM_OK;
+  TransferLaunch t = transfer_base(c, l);
+  t.blocks = c->iblocks(l + 1);
+  t.nblocks = (int32_t)c->nib[l + 1];
+  t.src_a = c->cur(l);
+  t.dst = c->cur(l + 1);
+  t.factor = (float)c->a_up[l];
+  HIPCHK(c, launch_upward(t, c->stream));
+  return LBM_OK;
+}
+
+lbm_status advance(lbm_ctx* c, int l, int s) {
+  const int L = c->G.L;
+  lbm_status st;
+  if (l < L - 1 && (st = down_level(c, l, s)) != LBM_OK) return st;
+  if ((st = sc_level(c, l)) != LBM_OK) return st;
+  if (l < L - 1 && s == 2 && (st = up_level(c, l)) != LBM_OK) return st;
+  if (l > 0) {
+    if ((st = advance(c, l - 1, 1)) != LBM_OK) return st;
+    if ((st = advance(c, l - 1, 2)) != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
+bool level_ok(lbm_ctx* c, int level) { return c && level >= 0 && level < c->G.L; }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_pool_bytes(const lbm_config* cfg) {
+  Geom G;
+  std::string e;
+  if (!make_geom(cfg, G, e)) return 0;
+  return 2 * (size_t)cfg->max_blocks * kBlockStride * elem_bytes(cfg->storage);
+}
+
+size_t lbm_meta_bytes(const lbm_config* cfg) {
+  Geom G;
+  std::string e;
+  if (!make_geom(cfg, G, e)) return 0;
+  return make_layout(cfg, G).total;
+}
+
+lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const float* particles, int64_t n,
+                      lbm_ctx** out) {
+  if (!out) { g_create_error = "null output pointer"; return LBM_EINVAL; }
+  *out = nullptr;
+  Geom G;
+  if (!make_geom(cfg, G, g_create_error)) return LBM_EINVAL;
+  if (!cfg->pool || !cfg->meta) { g_create_error = "pool and meta buffers are required"; return LBM_EINVAL; }
+  if (n < 0 || (n > 0 && !particles)) { g_create_error = "bad particle array"; return LBM_EINVAL; }
+  lbm_ctx* c = new lbm_ctx();
+  c->cfg = *cfg;
+  c->G = G;
+  c->lay = make_layout(cfg, G);
+  c->stream = static_cast<hipStream_t>(cfg->stream);
+  c->cap = cfg->max_blocks;
+  c->elem = elem_bytes(cfg->storage);
+  c->pool = static_cast<char*>(cfg->pool);
+  c->meta = static_cast<char*>(cfg->meta);
+  c->solid = solid_fine;
+  for (int l = 0; l < G.L; ++l) {
+    const double k = std::ldexp(1.0, l);
+    c->tau[l] = cfg->tau0 / k + (k - 1.0) / (2.0 * k);  // tau_{l} from tau_0 (Sec. 5.2)
+    c->parity[l] = 0;
+    c->nblk[l] = c->ngb[l] = c->nib[l] = c->nob[l] = 0;
+  }
+  for (int l = 0; l < G.L; ++l) {
+    c->a_up[l] = c->a_down[l] = 1.0;
+    if (l + 1 < G.L) {
+      if (cfg->rescale == 0) {
+        // Chapman-Enskog: S^neq ~ -cs^2 tau_l dx_l (grad u + grad u^T)
+        c->a_up[l] = 2.0 * c->tau[l + 1] / c->tau[l];
+        c->a_down[l] = c->tau[l] / (2.0 * c->tau[l + 1]);
+      } else {
+        c->a_up[l] = c->tau[l + 1] / (2.0 * c->tau[l]);
+        c->a_down[l] = 2.0 * c->tau[l + 1] / c->tau[l];
+      }
+    }
+  }
+  for (int mm = 0; mm < kMom; ++mm) {
+    const float s = cfg->storage == LBM_F32 ? 1.0f : cfg->scale[mm];
+    c->sc.s[mm] = s;
+    c->sc.inv[mm] = 1.0f / s;
+  }
+  if (hipHostMalloc((void**)&c->host_counts, 64 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    g_create_error = "pinned host allocation failed";
+    delete c;
+    return LBM_EDEVICE;
+  }
+  int64_t ncell = 0;
+  for (int l = 0; l < G.L; ++l) ncell += G.lv[l].ncell;
+  lbm_status st = LBM_OK;
+  auto chk = [&](hipError_t e, const char* what) {
+    if (st == LBM_OK && e != hipSuccess) {
+      st = LBM_EDEVICE;
+      g_create_error = std::string(what) + ": " + hipGetErrorString(e);
+    }
+  };
+  chk(launch_fill_u8(c->st(0), ST_ABSENT, ncell, c->stream), "clear states");
+  chk(launch_fill_i32(c->dir(0), NBR_NONE, ncell, c->stream), "clear directory");
+  std::vector<int32_t> fs((size_t)c->cap);
+  for (int64_t i = 0; i < c->cap; ++i) fs[(size_t)i] = (int32_t)(c->cap - 1 - i);
+  chk(hipMemcpyAsync(c->m<int32_t>(c->lay.free_stack), fs.data(), fs.size() * 4, hipMemcpyHostToDevice, c->stream),
+      "free list");
+  c->free_top = (int32_t)c->cap;
+  chk(launch_mark_static(G, solid_fine, c->m<uint8_t>(c->lay.t0s), c->stream), "static targets");
+  chk(hipStreamSynchronize(c->stream), "synchronise");
+  if (st == LBM_OK) {
+    st = rebuild(c, particles, n, true);
+    if (st != LBM_OK) g_create_error = c->err;
+  }
+  if (st != LBM_OK) {
+    hipHostFree(c->host_counts);
+    delete c;
+    return st;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* ctx) {
+  if (!ctx) return LBM_EINVAL;
+  hipStreamSynchronize(ctx->stream);
+  hipHostFree(ctx->host_counts);
+  delete ctx;
+  return LBM_OK;
+}
+
+lbm_status lbm_num_blocks(lbm_ctx* ctx, int32_t level, int64_t* out) {
+  if (!level_ok(ctx, level) || !out) return ctx ? ctx->fail(LBM_EINVAL, "bad level or null output") : LBM_EINVAL;
+  *out = ctx->nblk[level];
+  return LBM_OK;
+}
+
+lbm_status lbm_block_keys(lbm_ctx* ctx, int32_t level, int64_t* keys) {
+  if (!level_ok(ctx, level) || !keys) return ctx ? ctx->fail(LBM_EINVAL, "bad level or null output") : LBM_EINVAL;
+  HIPCHK(ctx, launch_keys(io_of(ctx, level), keys, ctx->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_block_moments(lbm_ctx* ctx, int32_t level, const int64_t* keys, const float* in, int64_t nb) {
+  if (!level_ok(ctx, level)) return ctx ? ctx->fail(LBM_EINVAL, "bad level") : LBM_EINVAL;
+  if (nb < 0 || (nb > 0 && (!keys || !in))) return ctx->fail(LBM_EINVAL, "bad block arrays");
+  if (nb == 0) return LBM_OK;
+  int32_t* flag = ctx->m<int32_t>(ctx->lay.flag);
+  HIPCHK(ctx, launch_fill_i32(flag, 0, 1, ctx->stream));
+  HIPCHK(ctx, launch_set(io_of(ctx, level), keys, in, nb, ctx->dir(ctx->hier), flag, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, flag, 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->host_counts[0]) return ctx->fail(LBM_EINVAL, "a key is not an active block of this level");
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* ctx, int32_t n) {
+  if (!ctx) return LBM_EINVAL;
+  if (n < 0) return ctx->fail(LBM_EINVAL, "negative step count");
+  for (int32_t i = 0; i < n; ++i) {
+    lbm_status st = advance(ctx, ctx->G.L - 1, 1);
+    if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_advance_particles(lbm_ctx* ctx, float* particles, int64_t n, const float d[3]) {
+  if (!ctx) return LBM_EINVAL;
+  if (n < 0 || (n > 0 && (!particles || !d))) return ctx->fail(LBM_EINVAL, "bad particle arguments");
+  HIPCHK(ctx, launch_advance_particles(particles, n, d[0], d[1], d[2], ctx->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_remesh(lbm_ctx* ctx, const float* particles, int64_t n) {
+  if (!ctx) return LBM_EINVAL;
+  if (n < 0 || (n > 0 && !particles)) return ctx->fail(LBM_EINVAL, "bad particle array");
+  return rebuild(ctx, particles, n, false);
+}
+
+lbm_status lbm_get_moments(lbm_ctx* ctx, int32_t level, int64_t* keys_out, float* out) {
+  if (!level_ok(ctx, level) || !out) return ctx ? ctx->fail(LBM_EINVAL, "bad level or null output") : LBM_EINVAL;
+  HIPCHK(ctx, launch_get(io_of(ctx, level), keys_out, out, ctx->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_get_roles(lbm_ctx* ctx, int32_t level, uint8_t* out) {
+  if (!level_ok(ctx, level) || !out) return ctx ? ctx->fail(LBM_EINVAL, "bad level or null output") : LBM_EINVAL;
+  HIPCHK(ctx, launch_get_roles(io_of(ctx, level), out, ctx->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_reduce_f64(lbm_ctx* ctx, int32_t level, const int32_t lo[3], const int32_t hi[3], double out[5]) {
+  if (!level_ok(ctx, level) || !lo || !hi || !out) return ctx ? ctx->fail(LBM_EINVAL, "bad arguments") : LBM_EINVAL;
+  double* dev = ctx->m<double>(ctx->lay.red_out);
+  HIPCHK(ctx, launch_reduce(io_of(ctx, level), lo, hi, ctx->m<double>(ctx->lay.red_partial), dev, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(out, dev, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_check_finite(lbm_ctx* ctx) {
+  if (!ctx) return LBM_EINVAL;
+  int32_t* flag = ctx->m<int32_t>(ctx->lay.flag);
+  HIPCHK(ctx, launch_fill_i32(flag, 0, 1, ctx->stream));
+  for (int l = 0; l < ctx->G.L; ++l) HIPCHK(ctx, launch_finite(io_of(ctx, l), flag, ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, flag, 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->host_counts[0]) return ctx->fail(LBM_ENAN, "non-finite moments");
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,400 @@
+// Stream-collide of one level (Sec. 3.1 "Collision and Streaming", Eq. three_order_f).
+//
+// For every computed node x the step pulls the 27 populations reconstructed
+// (third-order Hermite, Eq. three_order_f) from the collided moments of the
+// neighbours x - c_i and takes their moments (Eq. rho_u_stress). Moments are
+// stored before collision; collision (S <- S + omega (u u - S)) is applied when
+// a node is read.
+//
+// Design for gfx950: one 64-lane wavefront per 8^3 block sweeps the block plane by
+// plane in z. The population field is never formed. Per source node the
+// reconstruction is written in a per-axis tensor basis (p0 = 1, p1 = c and a
+// quadratic p2; 17 nonzero coefficients); the stream + moment projection factorises
+// into three 1D passes (x, y, z), each: moment->population along the axis, shift
+// by one node, population->moment. The x and y passes exchange through LDS on a
+// 10x10 halo plane; the z pass runs in registers over a sliding window of three
+// planes. Every lane owns one (x, y) column. Bounce-back at solid neighbours is a
+// per-node correction on the few flagged nodes.
+//
+// Only the deviation rho - 1 enters the coefficients: the rest state maps to
+// itself exactly, so rho - 1 is produced without cancellation against 1.
+//
+// Exact arithmetic of the weights: the per-axis basis is p0 = 1, p1 = c,
+// p2' = 3c^2 - 1, and every 1D pass works on six times the populations, so the
+// lattice weights become the integers (1, 4, 1) and all basis constants are small
+// integers. Only additions round (to nearest, unbiased); the factor 6^3 = 216 is
+// removed by one correctly rounded division per output. Inexact weights such as
+// fl(1/6) would bias every step the same way and the error would grow linearly.
+#include "common.h"
+#include "kernels.h"
+
+namespace lbmx {
+namespace {
+
+template <class S> struct ScArgs {
+  const typename S::type* in;
+  typename S::type* out;
+  const int32_t* blocks;
+  const int32_t* nbr;
+  const uint8_t* role;
+  int32_t nblocks;
+  float omega;
+  Scales sc;
+};
+
+// x-direction populations (times 6) of the 8 (my, mz) coefficient groups of a
+// source node, three per group (P(+1), P(0), P(-1)):
+//   P(+-1) = a0 +- a1 + 2 a2,  P(0) = 4 (a0 - a2)
+// for the group's coefficients (a0, a1, a2) of p0, p1, p2' along x.
+__device__ __forceinline__ void source_pops(const float q[kMom], float omega, float p[24]) {
+  const float drho = q[0];
+  const float rho = 1.0f + drho;
+  const float ux = q[1], uy = q[2], uz = q[3];
+  // collision: S relaxes to u u
+  const float sxx = q[4] + omega * (ux * ux - q[4]);
+  const float syy = q[5] + omega * (uy * uy - q[5]);
+  const float szz = q[6] + omega * (uz * uz - q[6]);
+  const float sxy = q[7] + omega * (ux * uy - q[7]);
+  const float sxz = q[8] + omega * (ux * uz - q[8]);
+  const float syz = q[9] + omega * (uy * uz - q[9]);
+  // third-order terms Gamma_aab = S_aa u_b + 2 S_ab u_a - 2 u_a^2 u_b
+  const float gxxy = sxx * uy + 2.0f * sxy * ux - 2.0f * ux * ux * uy;
+  const float gyyx = syy * ux + 2.0f * sxy * uy - 2.0f * uy * uy * ux;
+  const float gxxz = sxx * uz + 2.0f * sxz * ux - 2.0f * ux * ux * uz;
+  const float gzzx = szz * ux + 2.0f * sxz * uz - 2.0f * uz * uz * ux;
+  const float gyyz = syy * uz + 2.0f * syz * uy - 2.0f * uy * uy * uz;
+  const float gzzy = szz * uy + 2.0f * syz * uz - 2.0f * uz * uz * uy;
+  const float gxyz = sxy * uz + sxz * uy + syz * ux - 2.0f * ux * uy * uz;
+  // tensor-basis coefficients (Eq. three_order_f in the p0/p1/p2' basis)
+  const float a100 = 3.0f * (rho * ux), a010 = 3.0f * (rho * uy), a001 = 3.0f * (rho * uz);
+  const float a200 = 1.5f * (rho * sxx), a020 = 1.5f * (rho * syy), a002 = 1.5f * (rho * szz);
+  const float a110 = 9.0f * (rho * sxy), a101 = 9.0f * (rho * sxz), a011 = 9.0f * (rho * syz);
+  const float a210 = 4.5f * (rho * gxxy), a120 = 4.5f * (rho * gyyx), a201 = 4.5f * (rho * gxxz);
+  const float a102 = 4.5f * (rho * gzzx), a021 = 4.5f * (rho * gyyz), a012 = 4.5f * (rho * gzzy);
+  const float a111 = 27.0f * (rho * gxyz);
+  float e;
+  // (my,mz) = (0,0): (a000, a100, a200)
+  e = drho + 2.0f * a200;  p[0] = e + a100;  p[1] = 4.0f * (drho - a200);  p[2] = e - a100;
+  // (1,0): (a010, a110, a210)
+  e = a010 + 2.0f * a210;  p[3] = e + a110;  p[4] = 4.0f * (a010 - a210);  p[5] = e - a110;
+  // (0,1): (a001, a101, a201)
+  e = a001 + 2.0f * a201;  p[6] = e + a101;  p[7] = 4.0f * (a001 - a201);  p[8] = e - a101;
+  // (2,0): (a020, a120, 0)
+  p[9] = a020 + a120;  p[10] = 4.0f * a020;  p[11] = a020 - a120;
+  // (0,2): (a002, a102, 0)
+  p[12] = a002 + a102;  p[13] = 4.0f * a002;  p[14] = a002 - a102;
+  // (1,1): (a011, a111, 0)
+  p[15] = a011 + a111;  p[16] = 4.0f * a011;  p[17] = a011 - a111;
+  // (2,1): (a021, 0, 0)
+  p[18] = a021;  p[19] = 4.0f * a021;  p[20] = a021;
+  // (1,2): (a012, 0, 0)
+  p[21] = a012;  p[22] = 4.0f * a012;  p[23] = a012;
+}
+
+// The 17 tensor-basis coefficients of a node (bounce-back path only), p2' basis.
+__device__ void node_coeffs(const float q[kMom], float omega, float a[17]) {
+  const float drho = q[0];
+  const float rho = 1.0f + drho;
+  const float ux = q[1], uy = q[2], uz = q[3];
+  const float sxx = q[4] + omega * (ux * ux - q[4]);
+  const float syy = q[5] + omega * (uy * uy - q[5]);
+  const float szz = q[6] + omega * (uz * uz - q[6]);
+  const float sxy = q[7] + omega * (ux * uy - q[7]);
+  const float sxz = q[8] + omega * (ux * uz - q[8]);
+  const float syz = q[9] + omega * (uy * uz - q[9]);
+  a[0] = drho;                      // 000
+  a[1] = 3.0f * (rho * ux);         // 100
+  a[2] = 3.0f * (rho * uy);         // 010
+  a[3] = 3.0f * (rho * uz);         // 001
+  a[4] = 1.5f * (rho * sxx);        // 200
+  a[5] = 1.5f * (rho * syy);        // 020
+  a[6] = 1.5f * (rho * szz);        // 002
+  a[7] = 9.0f * (rho * sxy);        // 110
+  a[8] = 9.0f * (rho * sxz);        // 101
+  a[9] = 9.0f * (rho * syz);        // 011
+  a[10] = 4.5f * (rho * (sxx * uy + 2.0f * sxy * ux - 2.0f * ux * ux * uy));  // 210
+  a[11] = 4.5f * (rho * (syy * ux + 2.0f * sxy * uy - 2.0f * uy * uy * ux));  // 120
+  a[12] = 4.5f * (rho * (sxx * uz + 2.0f * sxz * ux - 2.0f * ux * ux * uz));  // 201
+  a[13] = 4.5f * (rho * (szz * ux + 2.0f * sxz * uz - 2.0f * uz * uz * ux));  // 102
+  a[14] = 4.5f * (rho * (syy * uz + 2.0f * syz * uy - 2.0f * uy * uy * uz));  // 021
+  a[15] = 4.5f * (rho * (szz * uy + 2.0f * syz * uz - 2.0f * uz * uz * uy));  // 012
+  a[16] = 27.0f * (rho * (sxy * uz + sxz * uy + syz * ux - 2.0f * ux * uy * uz));  // 111
+}
+
+// 1D population->moment map after the shift (times 6 populations):
+// (P+, P0, P-) -> (m0, m1, m2') = (P+ + P0 + P-, P+ - P-, 2 (P+ + P-) - P0)
+__device__ __forceinline__ void back3(float pp, float p0, float pm, float& m0, float& m1, float& m2) {
+  const float s = pp + pm;
+  m0 = s + p0;
+  m1 = pp - pm;
+  m2 = 2.0f * s - p0;
+}
+// 1D moment->population map (times 6): (a0, a1, a2') -> (P+, P0, P-)
+__device__ __forceinline__ void fwd3(float a0, float a1, float a2, float& pp, float& p0, float& pm) {
+  const float e = a0 + 2.0f * a2;
+  pp = e + a1;
+  pm = e - a1;
+  p0 = 4.0f * (a0 - a2);
+}
+
+// halo-plane point (px, py) in [-1, 8]^2 of round r for a lane
+__device__ __forceinline__ bool plane_point(int lane, int r, int& px, int& py) {
+  if (r == 0) { px = lane & 7; py = lane >> 3; return true; }
+  if (lane < 10) { px = lane - 1; py = -1; return true; }
+  if (lane < 20) { px = lane - 11; py = 8; return true; }
+  if (lane < 28) { px = -1; py = lane - 20; return true; }
+  if (lane < 36) { px = 8; py = lane - 28; return true; }
+  return false;
+}
+
+template <class S>
+__device__ __forceinline__ void fetch_point(const ScArgs<S>& a, const int* s_nbr, int px, int py, int pz,
+                                            typename S::type raw[kMom], bool& present) {
+  const int ox = px < 0 ? -1 : (px > 7 ? 1 : 0);
+  const int oy = py < 0 ? -1 : (py > 7 ? 1 : 0);
+  const int oz = pz < 0 ? -1 : (pz > 7 ? 1 : 0);
+  const int ns = s_nbr[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
+  present = ns >= 0;
+  if (!present) return;
+  const int node = (px & 7) + 8 * (py & 7) + 64 * (pz & 7);
+  const typename S::type* src = a.in + (size_t)ns * kBlockStride + node;
+#pragma unroll
+  for (int m = 0; m < kMom; ++m) raw[m] = src[m * kNodes];
+}
+
+// bounce-back correction of one computed node: every direction c_i whose source
+// x - c_i is solid (or behind a wall) receives f_{-c_i}(x) instead.
+template <class S>
+__device__ void bounce_back(const ScArgs<S>& a, const int* s_nbr, int slot, int lx, int ly, int lz,
+                            float M[10]) {
+  float q[kMom];
+  const int node = lx + 8 * ly + 64 * lz;
+  const typename S::type* src = a.in + (size_t)slot * kBlockStride + node;
+  for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(src[m * kNodes], a.sc.inv[m]);
+  float c[17];
+  node_coeffs(q, a.omega, c);
+  for (int i = 0; i < 27; ++i) {
+    if (i == 13) continue;
+    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+    const int hx = lx - cx, hy = ly - cy, hz = lz - cz;
+    const int ox = hx < 0 ? -1 : (hx > 7 ? 1 : 0);
+    const int oy = hy < 0 ? -1 : (hy > 7 ? 1 : 0);
+    const int oz = hz < 0 ? -1 : (hz > 7 ? 1 : 0);
+    const int ns = s_nbr[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
+    bool solid = (ns == NBR_WALL);
+    if (ns >= 0) solid = (a.role[(size_t)ns * kNodes + (hx & 7) + 8 * (hy & 7) + 64 * (hz & 7)] & ROLE_MASK) == ROLE_SOLID;
+    if (!solid) continue;
+    // outgoing direction d = -c: basis values p1(d) = d, p2'(d) = 3 d^2 - 1
+    const float dx = -cx, dy = -cy, dz = -cz;
+    const float ex = 3.0f * dx * dx - 1.0f, ey = 3.0f * dy * dy - 1.0f, ez = 3.0f * dz * dz - 1.0f;
+    const float sum = c[0] + c[1] * dx + c[2] * dy + c[3] * dz + c[4] * ex + c[5] * ey + c[6] * ez
+                      + c[7] * dx * dy + c[8] * dx * dz + c[9] * dy * dz + c[10] * ex * dy + c[11] * dx * ey
+                      + c[12] * ex * dz + c[13] * dx * ez + c[14] * ey * dz + c[15] * dy * ez
+                      + c[16] * dx * dy * dz;
+    // 216 w_c = product of the integer per-axis weights (4 at rest, 1 moving)
+    const float w = (cx ? 1.0f : 4.0f) * (cy ? 1.0f : 4.0f) * (cz ? 1.0f : 4.0f);
+    const float f = w * sum;
+    const float fx = f * cx, fy = f * cy, fz = f * cz;
+    M[0] += f;
+    M[1] += fx; M[2] += fy; M[3] += fz;
+    M[4] += f * (3.0f * cx * cx - 1.0f); M[5] += f * (3.0f * cy * cy - 1.0f); M[6] += f * (3.0f * cz * cz - 1.0f);
+    M[7] += fx * cy; M[8] += fx * cz; M[9] += fy * cz;
+  }
+}
+
+// workgroup -> block with consecutive blocks on the same XCD (workgroups are
+// dealt to the 8 XCDs round-robin; neighbours in key order then share an L2)
+__device__ __forceinline__ int xcd_remap(int bid, int n) {
+  const int per = n >> 3, rem = n & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+template <class S>
+__global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
+  // LDS: x-pass input [24][100] (halo plane), reused as y-pass input [27][80]
+  __shared__ float lds[24 * 100];
+  __shared__ int s_nbr[27];
+  const int lane = threadIdx.x;
+  const int slot = a.blocks[xcd_remap(blockIdx.x, a.nblocks)];
+  if (lane < 27) s_nbr[lane] = a.nbr[(size_t)slot * 27 + lane];
+  __syncthreads();
+
+  int px[2], py[2];
+  bool has[2];
+  has[0] = plane_point(lane, 0, px[0], py[0]);
+  has[1] = plane_point(lane, 1, px[1], py[1]);
+  const int ox = lane & 7, oy = lane >> 3;   // owned column
+
+  typedef typename S::type T;
+  T nxt[2][kMom];
+  bool nxt_present[2] = {false, false};
+  for (int r = 0; r < 2; ++r)
+    if (has[r]) fetch_point<S>(a, s_nbr, px[r], py[r], -1, nxt[r], nxt_present[r]);
+
+  float zp1[6], zp2[6], z0[6];  // z-window: pop+ of planes z-1, z-2; pop0 of plane z-1
+#pragma unroll
+  for (int k = 0; k < 6; ++k) zp1[k] = zp2[k] = z0[k] = 0.0f;
+
+  for (int z = -1; z <= 8; ++z) {
+    // ---- pass 0: moments of plane z (+ halo) -> x-populations, into LDS
+    T cur[2][kMom];
+    bool present[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      present[r] = nxt_present[r];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) cur[r][m] = nxt[r][m];
+    }
+    if (z < 8) {
+      for (int r = 0; r < 2; ++r)
+        if (has[r]) fetch_point<S>(a, s_nbr, px[r], py[r], z + 1, nxt[r], nxt_present[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (!has[r]) continue;
+      float q[kMom];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) q[m] = present[r] ? Codec<S>::load(cur[r][m], a.sc.inv[m]) : 0.0f;
+      float p[24];
+      source_pops(q, a.omega, p);
+      const int pt = (px[r] + 1) + 10 * (py[r] + 1);
+#pragma unroll
+      for (int k = 0; k < 24; ++k) lds[k * 100 + pt] = p[k];
+    }
+    __syncthreads();
+
+    // ---- pass x: shift + back along x on the 8 x 10 plane, then y-forward
+    float yb[2][27];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int x = lane & 7;
+      const int y = (r == 0) ? (lane >> 3) - 1 : 7 + (lane >> 3);
+      if (r == 1 && lane >= 16) continue;
+      const int c = (x + 1) + 10 * (y + 1);
+      float B[3][3][3];  // [qx][my][mz]
+#pragma unroll
+      for (int g = 0; g < 8; ++g) {
+        float m0, m1, m2;
+        back3(lds[(3 * g + 0) * 100 + c - 1], lds[(3 * g + 1) * 100 + c], lds[(3 * g + 2) * 100 + c + 1], m0, m1, m2);
+        const int my = (g == 1 || g == 5 || g == 7) ? 1 : ((g == 3 || g == 6) ? 2 : 0);
+        const int mz = (g == 2 || g == 5 || g == 6) ? 1 : ((g == 4 || g == 7) ? 2 : 0);
+        B[0][my][mz] = m0; B[1][my][mz] = m1; B[2][my][mz] = m2;
+      }
+#pragma unroll
+      for (int qx = 0; qx < 3; ++qx)
+#pragma unroll
+        for (int mz = 0; mz < 3; ++mz) {
+          const float b2 = (mz == 2) ? 0.0f : B[qx][2][mz];
+          const int t = 3 * qx + mz;
+          fwd3(B[qx][0][mz], B[qx][1][mz], b2, yb[r][3 * t + 0], yb[r][3 * t + 1], yb[r][3 * t + 2]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (r == 1 && lane >= 16) continue;
+      const int x = lane & 7;
+      const int y = (r == 0) ? (lane >> 3) - 1 : 7 + (lane >> 3);
+      const int c = x + 8 * (y + 1);
+#pragma unroll
+      for (int k = 0; k < 27; ++k) lds[k * 80 + c] = yb[r][k];
+    }
+    __syncthreads();
+
+    // ---- pass y: shift + back along y for the owned column, then z-forward
+    float zpp[6], zpz[6], zpm[6];
+    {
+      const int cb = ox + 8 * oy;  // index of (x, y-1)
+      float C[3][3][3];            // [qx][qy][mz]
+#pragma unroll
+      for (int qx = 0; qx < 3; ++qx)
+#pragma unroll
+        for (int mz = 0; mz < 3; ++mz) {
+          const int t = 3 * qx + mz;
+          float m0, m1, m2;
+          back3(lds[(3 * t + 0) * 80 + cb], lds[(3 * t + 1) * 80 + cb + 8], lds[(3 * t + 2) * 80 + cb + 16], m0, m1, m2);
+          C[qx][0][mz] = m0; C[qx][1][mz] = m1; C[qx][2][mz] = m2;
+        }
+      // pairs (qx,qy): (0,0) (1,0) (0,1) (2,0) (0,2) (1,1); mz = 2 of qx/qy pairs is
+      // absent in the source basis only for (my, mz) = (2, 2), handled by zeros above
+      const int pqx[6] = {0, 1, 0, 2, 0, 1};
+      const int pqy[6] = {0, 0, 1, 0, 2, 1};
+#pragma unroll
+      for (int k = 0; k < 6; ++k) fwd3(C[pqx[k]][pqy[k]][0], C[pqx[k]][pqy[k]][1], C[pqx[k]][pqy[k]][2], zpp[k], zpz[k], zpm[k]);
+    }
+    __syncthreads();
+
+    // ---- pass z: output plane zo = z - 1 from planes z-2 (pop+), z-1 (pop0), z (pop-)
+    const int zo = z - 1;
+    if (zo >= 0) {
+      float M[10];
+      float m0, m1, m2;
+      back3(zp2[0], z0[0], zpm[0], m0, m1, m2);  // (0,0): M000, M001, M002
+      M[0] = m0; M[3] = m1; M[6] = m2;
+      back3(zp2[1], z0[1], zpm[1], m0, m1, m2);  // (1,0): M100, M101
+      M[1] = m0; M[8] = m1;
+      back3(zp2[2], z0[2], zpm[2], m0, m1, m2);  // (0,1): M010, M011
+      M[2] = m0; M[9] = m1;
+      back3(zp2[3], z0[3], zpm[3], m0, m1, m2);  // (2,0): M200
+      M[4] = m0;
+      back3(zp2[4], z0[4], zpm[4], m0, m1, m2);  // (0,2): M020
+      M[5] = m0;
+      back3(zp2[5], z0[5], zpm[5], m0, m1, m2);  // (1,1): M110
+      M[7] = m0;
+      const int node = ox + 8 * oy + 64 * zo;
+      const uint8_t role = a.role[(size_t)slot * kNodes + node];
+      typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
+      if ((role & ROLE_MASK) == ROLE_COMPUTED) {
+        if (role & ROLE_BB) bounce_back<S>(a, s_nbr, slot, ox, oy, zo, M);
+        // remove the 6^3 scale of the three passes with correctly rounded divisions
+        const float r216 = 216.0f + M[0];          // 216 rho'
+        const float r648 = 3.0f * r216;            // p2' = 3 p2 on the diagonal stresses
+        float v[kMom];
+        v[0] = M[0] / 216.0f;
+        v[1] = M[1] / r216; v[2] = M[2] / r216; v[3] = M[3] / r216;
+        v[4] = M[4] / r648; v[5] = M[5] / r648; v[6] = M[6] / r648;
+        v[7] = M[7] / r216; v[8] = M[8] / r216; v[9] = M[9] / r216;
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(v[m], a.sc.s[m]);
+      } else if ((role & ROLE_MASK) == ROLE_SOLID) {
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(0.0f, a.sc.s[m]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      zp2[k] = zp1[k];
+      zp1[k] = zpp[k];
+      z0[k] = zpz[k];
+    }
+  }
+}
+
+template <class S> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
+  if (l.nblocks <= 0) return hipSuccess;
+  ScArgs<S> a;
+  a.in = static_cast<const typename S::type*>(l.in);
+  a.out = static_cast<typename S::type*>(l.out);
+  a.blocks = l.blocks;
+  a.nbr = l.nbr;
+  a.role = l.role;
+  a.nblocks = l.nblocks;
+  a.omega = l.omega;
+  a.sc = l.sc;
+  hipLaunchKernelGGL(k_stream_collide<S>, dim3(l.nblocks), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s) {
+  switch (a.storage) {
+    case 0: return launch_sc_t<StoreF32>(a, s);
+    case 1: return launch_sc_t<StoreBF16>(a, s);
+    case 2: return launch_sc_t<StoreF16>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbmx

@@ -1,0 +1,194 @@
+// Interface transfers between levels (Sec. 5.3, Alg. 1) and the zero-gradient
+// outflow copy.
+//
+// DownwardTransfer(l+1, s): every ghost node of level l (the one-node outer shell
+// of the level's region) takes rho and u interpolated from its nearest 2^3 coarse
+// nodes (trilinear, node-centred: coarse node q sits on fine node 2q) and
+// S = a_down * sum_j w_j S^neq_j + u u (Eq. downward_rescale). For the second fine
+// substep (s = 2) the coarse rho, u and S^neq are first averaged between coarse
+// times t and t + 2 dt_l (temporal interpolation to the midpoint).
+//
+// UpwardTransfer(l): every upward-interface node q of level l+1 copies rho and u
+// of the coincident fine node 2q and rescales S^neq by a_up (Eq. upload_S).
+//
+// Threads: one 256-lane workgroup per interface block, two nodes per lane; only
+// lanes whose node has the target role do work.
+#include "common.h"
+#include "kernels.h"
+
+namespace lbmx {
+namespace {
+
+template <class S> struct Mom {
+  __device__ static inline void load(const void* base, int slot, int node, const Scales& sc, float q[kMom]) {
+    const typename S::type* p = static_cast<const typename S::type*>(base) + (size_t)slot * kBlockStride + node;
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(p[m * kNodes], sc.inv[m]);
+  }
+  __device__ static inline void store(void* base, int slot, int node, const Scales& sc, const float q[kMom]) {
+    typename S::type* p = static_cast<typename S::type*>(base) + (size_t)slot * kBlockStride + node;
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) p[m * kNodes] = Codec<S>::store(q[m], sc.s[m]);
+  }
+};
+
+// (rho-1, u, S) -> (rho-1, u, S^neq = S - u u), in place
+__device__ inline void to_neq(float q[kMom]) {
+  q[4] -= q[1] * q[1]; q[5] -= q[2] * q[2]; q[6] -= q[3] * q[3];
+  q[7] -= q[1] * q[2]; q[8] -= q[1] * q[3]; q[9] -= q[2] * q[3];
+}
+__device__ inline void from_neq(float q[kMom]) {
+  q[4] += q[1] * q[1]; q[5] += q[2] * q[2]; q[6] += q[3] * q[3];
+  q[7] += q[1] * q[2]; q[8] += q[1] * q[3]; q[9] += q[2] * q[3];
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
+  const int slot = a.blocks[blockIdx.x];
+  const int4 bc = a.coord[slot];
+  const int l = a.level;
+  const LevelGeom& cg = a.G.lv[l + 1];
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_GHOST) continue;
+    const int g[3] = {bc.x * kEdge + (node & 7), bc.y * kEdge + ((node >> 3) & 7), bc.z * kEdge + (node >> 6)};
+    int cand[3][2], cnt[3];
+    float wv[3][2];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int nc = cg.nn[ax];
+      if ((g[ax] & 1) == 0) {
+        cand[ax][0] = g[ax] >> 1; cand[ax][1] = cand[ax][0]; wv[ax][0] = 1.0f; wv[ax][1] = 0.0f; cnt[ax] = 1;
+      } else {
+        cand[ax][0] = (g[ax] - 1) >> 1; cand[ax][1] = (g[ax] + 1) >> 1; wv[ax][0] = 0.5f; wv[ax][1] = 0.5f; cnt[ax] = 2;
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        int v = cand[ax][k];
+        if (a.G.periodic[ax]) v = v < 0 ? v + nc : (v >= nc ? v - nc : v);
+        else v = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
+        cand[ax][k] = v;
+      }
+    }
+    float acc[kMom];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
+    for (int kz = 0; kz < cnt[2]; ++kz)
+      for (int ky = 0; ky < cnt[1]; ++ky)
+        for (int kx = 0; kx < cnt[0]; ++kx) {
+          const int j[3] = {cand[0][kx], cand[1][ky], cand[2][kz]};
+          const float w = wv[0][kx] * wv[1][ky] * wv[2][kz];
+          const int cs = a.dir[cg.off + cell_lin(cg, j[0] >> 3, j[1] >> 3, j[2] >> 3)];
+          if (cs < 0) continue;  // cannot happen for a valid hierarchy; never read out of bounds
+          const int cn = (j[0] & 7) + 8 * (j[1] & 7) + 64 * (j[2] & 7);
+          float q[kMom];
+          Mom<S>::load(a.src_a, cs, cn, a.sc, q);
+          to_neq(q);
+          if (a.midpoint) {
+            float r[kMom];
+            Mom<S>::load(a.src_b, cs, cn, a.sc, r);
+            to_neq(r);
+#pragma unroll
+            for (int m = 0; m < kMom; ++m) q[m] = 0.5f * (q[m] + r[m]);
+          }
+#pragma unroll
+          for (int m = 0; m < 4; ++m) acc[m] += w * q[m];
+#pragma unroll
+          for (int m = 4; m < kMom; ++m) acc[m] += (w * a.factor) * q[m];
+        }
+    from_neq(acc);
+    Mom<S>::store(a.dst, slot, node, a.sc, acc);
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_upward(TransferLaunch a) {
+  const int slot = a.blocks[blockIdx.x];
+  const int4 bc = a.coord[slot];
+  const int l = a.level;
+  const LevelGeom& fg = a.G.lv[l];
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_IU) continue;
+    const int f[3] = {2 * (bc.x * kEdge + (node & 7)), 2 * (bc.y * kEdge + ((node >> 3) & 7)), 2 * (bc.z * kEdge + (node >> 6))};
+    const int fs = a.dir[fg.off + cell_lin(fg, f[0] >> 3, f[1] >> 3, f[2] >> 3)];
+    if (fs < 0) continue;  // cannot happen for a valid hierarchy; never read out of bounds
+    const int fn = (f[0] & 7) + 8 * (f[1] & 7) + 64 * (f[2] & 7);
+    float q[kMom];
+    Mom<S>::load(a.src_a, fs, fn, a.sc, q);
+    to_neq(q);
+#pragma unroll
+    for (int m = 4; m < kMom; ++m) q[m] *= a.factor;
+    from_neq(q);
+    Mom<S>::store(a.dst, slot, node, a.sc, q);
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_outflow(OutflowLaunch a) {
+  const int slot = a.blocks[blockIdx.x];
+  const int4 bc = a.coord[slot];
+  const LevelGeom& lg = a.G.lv[a.level];
+  typedef typename S::type T;
+  const T* oldb = static_cast<const T*>(a.old_buf) + (size_t)slot * kBlockStride;
+  T* newb = static_cast<T*>(a.new_buf) + (size_t)slot * kBlockStride;
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_OUTFLOW) continue;
+    const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
+    const int g[3] = {bc.x * kEdge + lc[0], bc.y * kEdge + lc[1], bc.z * kEdge + lc[2]};
+    int step = 0;
+    for (int ax = 0; ax < 3 && step == 0; ++ax) {
+      if (a.G.periodic[ax]) continue;
+      const int stride = ax == 0 ? 1 : (ax == 1 ? 8 : 64);
+      if (g[ax] == 0 && a.G.bc[2 * ax] == BC_OUTFLOW) step = stride;              // inward is +axis
+      else if (g[ax] == lg.nn[ax] - 1 && a.G.bc[2 * ax + 1] == BC_OUTFLOW) step = -stride;
+    }
+    const int src = node + step;
+    const bool computed = step != 0 && (a.role[(size_t)slot * kNodes + src] & ROLE_MASK) == ROLE_COMPUTED;
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) newb[m * kNodes + node] = computed ? newb[m * kNodes + src] : oldb[m * kNodes + node];
+  }
+}
+
+template <class S> hipError_t down_t(const TransferLaunch& a, hipStream_t s) {
+  if (a.nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_downward<S>, dim3(a.nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <class S> hipError_t up_t(const TransferLaunch& a, hipStream_t s) {
+  if (a.nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_upward<S>, dim3(a.nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+template <class S> hipError_t out_t(const OutflowLaunch& a, hipStream_t s) {
+  if (a.nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_outflow<S>, dim3(a.nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_downward(const TransferLaunch& a, hipStream_t s) {
+  switch (a.storage) {
+    case 0: return down_t<StoreF32>(a, s);
+    case 1: return down_t<StoreBF16>(a, s);
+    case 2: return down_t<StoreF16>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+hipError_t launch_upward(const TransferLaunch& a, hipStream_t s) {
+  switch (a.storage) {
+    case 0: return up_t<StoreF32>(a, s);
+    case 1: return up_t<StoreBF16>(a, s);
+    case 2: return up_t<StoreF16>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+hipError_t launch_outflow(const OutflowLaunch& a, hipStream_t s) {
+  switch (a.storage) {
+    case 0: return out_t<StoreF32>(a, s);
+    case 1: return out_t<StoreBF16>(a, s);
+    case 2: return out_t<StoreF16>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lbmx

@@ -1,0 +1,229 @@
+"""Python binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Device memory comes from torch (the pool and table buffers, particles, solid
+field, moment arrays); every step of the method runs in the HIP kernels of
+liblbmx.so on torch's current stream. There is no CPU fallback: if the HIP
+library is missing this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblbmx.so")
+
+PERIODIC, INFLOW, OUTFLOW, WALL = 0, 1, 2, 3
+F32, BF16, F16 = 0, 1, 2
+STORAGE = {"f32": F32, "bf16": BF16, "f16": F16}
+ROLE_COMPUTED, ROLE_GHOST, ROLE_IU, ROLE_SOLID, ROLE_INFLOW, ROLE_OUTFLOW = range(6)
+
+_STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_ECAPACITY", -4: "LBM_EDEVICE",
+           -5: "LBM_ENAN", -6: "LBM_ESTATE"}
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class LBMConfig(ctypes.Structure):
+    _fields_ = [
+        ("levels", ctypes.c_int32),
+        ("fine_extent", ctypes.c_int32 * 3),
+        ("bc", ctypes.c_int32 * 6),
+        ("inflow_u", ctypes.c_float * 3),
+        ("tau0", ctypes.c_double),
+        ("storage", ctypes.c_int32),
+        ("rescale", ctypes.c_int32),
+        ("scale", ctypes.c_float * 10),
+        ("max_blocks", ctypes.c_int64),
+        ("pool", ctypes.c_void_p),
+        ("meta", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm_num_blocks", "lbm_block_keys",
+           "lbm_set_block_moments", "lbm_step", "lbm_advance_particles", "lbm_remesh", "lbm_get_moments",
+           "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Loads liblbmx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2603_14982_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        cfgp = ctypes.POINTER(LBMConfig)
+        L.lbm_pool_bytes.restype = sz
+        L.lbm_pool_bytes.argtypes = [cfgp]
+        L.lbm_meta_bytes.restype = sz
+        L.lbm_meta_bytes.argtypes = [cfgp]
+        L.lbm_create.argtypes = [cfgp, vp, vp, i64, ctypes.POINTER(vp)]
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_num_blocks.argtypes = [vp, i32, ctypes.POINTER(i64)]
+        L.lbm_block_keys.argtypes = [vp, i32, vp]
+        L.lbm_set_block_moments.argtypes = [vp, i32, vp, vp, i64]
+        L.lbm_step.argtypes = [vp, i32]
+        L.lbm_advance_particles.argtypes = [vp, vp, i64, vp]
+        L.lbm_remesh.argtypes = [vp, vp, i64]
+        L.lbm_get_moments.argtypes = [vp, i32, vp, vp]
+        L.lbm_get_roles.argtypes = [vp, i32, vp]
+        L.lbm_reduce_f64.argtypes = [vp, i32, vp, vp, vp]
+        L.lbm_check_finite.argtypes = [vp]
+        L.lbm_last_error.restype = ctypes.c_char_p
+        L.lbm_last_error.argtypes = [vp]
+        for name in EXPORTS:
+            if name not in ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def make_config(levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), storage="f32", scale=None, rescale="ce",
+                max_blocks=1):
+    c = LBMConfig()
+    c.levels = int(levels)
+    for a in range(3):
+        c.fine_extent[a] = int(n[a])
+        c.inflow_u[a] = float(uin[a])
+    for f in range(6):
+        c.bc[f] = int(bc[f])
+    c.tau0 = float(tau0)
+    c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    c.rescale = {"ce": 0, "printed": 1}[rescale]
+    sc = [1.0] * 10 if scale is None else list(scale)
+    for m in range(10):
+        c.scale[m] = float(sc[m])
+    c.max_blocks = int(max_blocks)
+    return c
+
+
+def _dptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Sim:
+    """One block-adaptive simulation on a GPU; buffers are torch tensors."""
+
+    def __init__(self, levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), storage="f32", scale=None, rescale="ce",
+                 max_blocks=None, solid=None, particles=None, device="cuda"):
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.levels = int(levels)
+        self.n = tuple(int(v) for v in n)
+        if max_blocks is None:
+            max_blocks = sum((n[0] >> l) // 8 * ((n[1] >> l) // 8) * ((n[2] >> l) // 8) for l in range(levels))
+            max_blocks = min(max_blocks, 1 << 16)
+        self.cfg = make_config(levels, n, bc, tau0, uin, storage, scale, rescale, max_blocks)
+        L = lib()
+        pool_bytes = L.lbm_pool_bytes(ctypes.byref(self.cfg))
+        meta_bytes = L.lbm_meta_bytes(ctypes.byref(self.cfg))
+        if pool_bytes == 0 or meta_bytes == 0:
+            raise LBMError(-1, "invalid configuration")
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=self.device)
+        self.meta = torch.empty(meta_bytes, dtype=torch.uint8, device=self.device)
+        self.cfg.pool = self.pool.data_ptr()
+        self.cfg.meta = self.meta.data_ptr()
+        self.cfg.stream = torch.cuda.current_stream(self.device).cuda_stream
+        self.solid = None
+        if solid is not None:
+            self.solid = torch.as_tensor(np.ascontiguousarray(solid, dtype=np.uint8)).to(self.device).contiguous()
+        p = self._particles(particles)
+        h = ctypes.c_void_p()
+        st = L.lbm_create(ctypes.byref(self.cfg), _dptr(self.solid), _dptr(p), 0 if p is None else p.shape[0],
+                          ctypes.byref(h))
+        if st != 0:
+            raise LBMError(st, L.lbm_last_error(None).decode())
+        self.h = h
+
+    def _particles(self, particles):
+        if particles is None:
+            return None
+        if isinstance(particles, torch.Tensor):
+            assert particles.dtype == torch.float32 and particles.is_contiguous() and particles.device == self.device
+            return particles
+        return torch.as_tensor(np.ascontiguousarray(particles, dtype=np.float32)).to(self.device)
+
+    def _check(self, st):
+        if st != 0:
+            raise LBMError(st, lib().lbm_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_blocks(self, level):
+        out = ctypes.c_int64()
+        self._check(lib().lbm_num_blocks(self.h, level, ctypes.byref(out)))
+        return int(out.value)
+
+    def block_keys(self, level):
+        k = torch.empty(self.num_blocks(level), dtype=torch.int64, device=self.device)
+        if k.numel():
+            self._check(lib().lbm_block_keys(self.h, level, _dptr(k)))
+        return k
+
+    def set_block_moments(self, level, keys, vals):
+        keys = torch.as_tensor(np.asarray(keys) if not isinstance(keys, torch.Tensor) else keys,
+                               dtype=torch.int64).to(self.device).contiguous()
+        vals = torch.as_tensor(vals if isinstance(vals, torch.Tensor) else np.asarray(vals),
+                               dtype=torch.float32).to(self.device).contiguous()
+        assert vals.shape == (keys.shape[0], 10, 512)
+        self._check(lib().lbm_set_block_moments(self.h, level, _dptr(keys), _dptr(vals), keys.shape[0]))
+
+    def step(self, n=1):
+        self._check(lib().lbm_step(self.h, int(n)))
+
+    def advance_particles(self, particles, d):
+        dd = (ctypes.c_float * 3)(*[float(v) for v in d])
+        self._check(lib().lbm_advance_particles(self.h, _dptr(particles), particles.shape[0], dd))
+
+    def remesh(self, particles):
+        p = self._particles(particles)
+        self._check(lib().lbm_remesh(self.h, _dptr(p), 0 if p is None else p.shape[0]))
+
+    def get_moments(self, level):
+        nb = self.num_blocks(level)
+        k = torch.empty(nb, dtype=torch.int64, device=self.device)
+        v = torch.empty((nb, 10, 512), dtype=torch.float32, device=self.device)
+        if nb:
+            self._check(lib().lbm_get_moments(self.h, level, _dptr(k), _dptr(v)))
+        return k, v
+
+    def roles(self, level):
+        nb = self.num_blocks(level)
+        r = torch.empty((nb, 512), dtype=torch.uint8, device=self.device)
+        if nb:
+            self._check(lib().lbm_get_roles(self.h, level, _dptr(r)))
+        return r
+
+    def reduce(self, level, lo=(0, 0, 0), hi=None):
+        hi = self.n if hi is None else hi
+        lo_ = (ctypes.c_int32 * 3)(*lo)
+        hi_ = (ctypes.c_int32 * 3)(*hi)
+        out = (ctypes.c_double * 5)()
+        self._check(lib().lbm_reduce_f64(self.h, level, lo_, hi_, out))
+        return np.array(list(out))
+
+    def check_finite(self):
+        st = lib().lbm_check_finite(self.h)
+        if st == -5:
+            return False
+        self._check(st)
+        return True

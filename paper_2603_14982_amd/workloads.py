@@ -68,9 +68,11 @@ def uniform_field(level, keys, rho=1.0, u=(0.0, 0.0, 0.0)):
     return moments_from_fields(r, uu)
 
 
-def tgv3d_field(level, keys, n, amp=0.05, wavelength=None):
+def tgv3d_field(level, keys, n, amp=0.05, wavelength=None, pressure=False):
     """3D Taylor-Green vortex: u = U sin kx cos ky cos kz, v = -U cos kx sin ky cos kz,
-    w = 0; rho = 1; S = u u. k = 2 pi / wavelength (fine units, default the x extent)."""
+    w = 0; S = u u; rho = 1, or with pressure=True rho = 1 + 3p with the vortex's
+    pressure p = U^2/16 (cos 2kx + cos 2ky)(cos 2kz + 2). k = 2 pi / wavelength (fine
+    units, default the x extent)."""
     lam = float(n[0] if wavelength is None else wavelength)
     k = 2.0 * np.pi / lam
     p = node_positions(level, keys).astype(np.float64)
@@ -78,7 +80,10 @@ def tgv3d_field(level, keys, n, amp=0.05, wavelength=None):
     ux = amp * np.sin(k * x) * np.cos(k * y) * np.cos(k * z)
     uy = -amp * np.cos(k * x) * np.sin(k * y) * np.cos(k * z)
     uz = np.zeros_like(ux)
-    return moments_from_fields(np.zeros_like(ux), [ux, uy, uz])
+    r = np.zeros_like(ux)
+    if pressure:
+        r = 3.0 * amp * amp / 16.0 * (np.cos(2 * k * x) + np.cos(2 * k * y)) * (np.cos(2 * k * z) + 2.0)
+    return moments_from_fields(r, [ux, uy, uz])
 
 
 def sample_dense(level, keys, dense):

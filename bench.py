@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the block-adaptive D3Q27 moment LBM step on one MI355X.
+
+Workload (the three-level adaptive configuration): 512^3 fine-equivalent
+periodic box, 3 levels of 8^3-node blocks, 2,000,000 seeded particles in the
+slab x, y in [64, 448), z in [352, 384) falling at 0.02 fine nodes per finest
+step, 3D Taylor-Green initial field (U = 0.05, wavelength 512, rho = 1,
+S = u u), tau_0 = 0.6, FP32 moments. One step = one coarse step of Alg. 1
+(4 finest substeps, 2 on level 1, 1 on level 2, downward/upward transfers),
+the particle advance and one grid update.
+
+Prints one JSON line. `value` is MLUPS (computed-node updates per second over
+the whole step, grid update included). The roofline object is the level-0
+stream-collide kernel: algorithmic bytes (80 B per node update: 10 f32 moments
+read and written) per launch over its HIP-event-timed average duration.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + achieved HBM GB/s per LBM step; adjoint/forward time ratio"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 80.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_slab512_traffic.json")
+
+
+def sc_source_hash():
+    with open(os.path.join(ROOT, "paper_2603_14982_amd", "csrc", "stream_collide.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def init_fields(sim, wl, W):
+    import numpy as np
+    for l in range(sim.levels):
+        keys = sim.block_keys(l).cpu().numpy()
+        for s in range(0, len(keys), 4096):
+            k = keys[s:s + 4096]
+            sim.set_block_moments(l, k, W.tgv3d_field(l, k, wl["n"], wl["amp"]).astype(np.float32))
+
+
+def computed_nodes(sim):
+    return [int((sim.roles(l) == 0).sum().item()) for l in range(sim.levels)]
+
+
+def cpu_baseline(W):
+    """The oracle on a bounded sample of the same workload: the three-level slab
+    case scaled to 128^3 (particles 2M/64 in the scaled slab), 2 coarse steps with
+    particle advance and grid update, after one warm-up step."""
+    import numpy as np
+    from oracle import oracle as O
+    n = (128, 128, 128)
+    p = W.slab_particles(2_000_000 // 64, 3, (16.0, 16.0, 88.0), (112.0, 112.0, 96.0))
+    sim = O.OracleSim(3, n, (W.PERIODIC,) * 6, 0.6, particles=p)
+    for l in range(3):
+        keys = sim.block_keys(l)
+        sim.set_block_moments(l, keys, W.tgv3d_field(l, keys, n, 0.05))
+    roles = [sim.roles(l) for l in range(3)]
+    updates = sum((roles[l] == 0).sum() * (1 << (2 - l)) for l in range(3))
+    d = np.array([0.0, 0.0, -0.08], dtype=np.float32)
+
+    def one():
+        sim.step(1)
+        O.advance_particles(p, d)
+        sim.remesh(p)
+
+    one()
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        one()
+    dt = (time.perf_counter() - t0) / reps
+    return {"value": round(float(updates) / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "FP64 oracle, same three-level slab workload scaled to 128^3 (31,250 particles), "
+                      f"{reps} coarse steps with grid update after 1 warm-up; {int(updates)} node updates per step"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the block hierarchy is not sharded across GPUs "
+              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2603_14982_amd import lbm, workloads as W
+
+    wl = W.workload("slab512")
+    print(f"[bench] workload slab512 n={wl['n']} levels={wl['levels']} particles={wl['particles']}",
+          file=sys.stderr, flush=True)
+    p_host = W.slab_particles(wl["particles"], wl["seed"], wl["lo"], wl["hi"])
+    particles = torch.as_tensor(p_host).cuda()
+    sim = lbm.Sim(wl["levels"], wl["n"], wl["bc"], wl["tau0"], particles=particles, max_blocks=48000)
+    init_fields(sim, wl, W)
+    torch.cuda.synchronize()
+    sub = 1 << (wl["levels"] - 1)
+    d = (wl["v_fine"][0] * sub, wl["v_fine"][1] * sub, wl["v_fine"][2] * sub)
+
+    def coarse_step():
+        sim.step(1)
+        sim.advance_particles(particles, d)
+        sim.remesh(particles)
+
+    for _ in range(args.warmup):
+        coarse_step()
+    torch.cuda.synchronize()
+    nodes_before = computed_nodes(sim)
+    blocks_before = [sim.num_blocks(l) for l in range(sim.levels)]
+    print(f"[bench] warm-up done; blocks {blocks_before}, computed nodes {nodes_before}", file=sys.stderr, flush=True)
+
+    sim.profile()
+    sim.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        coarse_step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sim.set_profiling(False)
+    prof = sim.profile()
+    nodes_after = computed_nodes(sim)
+    blocks_after = [sim.num_blocks(l) for l in range(sim.levels)]
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; blocks {blocks_after}", file=sys.stderr, flush=True)
+    assert sim.check_finite(), "non-finite moments"
+
+    per_level = [(a + b) / 2.0 for a, b in zip(nodes_before, nodes_after)]
+    updates = sum(per_level[l] * (1 << (sim.levels - 1 - l)) for l in range(sim.levels))
+    fine_equiv = float(np.prod(wl["n"])) * sub
+    ms_per_step = elapsed / args.steps * 1e3
+    mlups = updates * args.steps / elapsed / 1e6
+
+    sc_ms, sc_n = prof["sc0"]
+    sc_avg_s = sc_ms / sc_n / 1e3
+    alg_bytes = BYTES_PER_UPDATE * per_level[0]
+    achieved = alg_bytes / sc_avg_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_src_sha") == sc_source_hash():
+            traffic = tr.get("hbm_bytes_per_launch")
+    all_sc = sum(prof[f"sc{l}"][0] for l in range(sim.levels))
+    sc_updates = sum(per_level[l] * (1 << (sim.levels - 1 - l)) for l in range(sim.levels)) * args.steps
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "slab512: 512^3 fine-equivalent periodic, 3 levels of 8^3 blocks, 2M seeded particles "
+                        "falling at 0.02/finest step drive the grid update every coarse step, 3D Taylor-Green "
+                        "U=0.05, tau0=0.6, f32 moments",
+            "levels": sim.levels,
+            "fine_extent": list(wl["n"]),
+            "blocks_per_level": blocks_after,
+            "computed_nodes_per_level": [int(v) for v in per_level],
+            "node_updates_per_step": int(updates),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_stream_collide<StoreF32> on level 0",
+            "algorithmic_bytes_per_launch": int(alg_bytes),
+            "avg_launch_ms": round(sc_avg_s * 1e3, 5),
+            "launches": sc_n,
+        },
+        "effective_mlups": round(fine_equiv * args.steps / elapsed / 1e6, 1),
+        "stream_collide_mlups": round(sc_updates / (all_sc / 1e3) / 1e6, 1),
+        "adjoint_forward_ratio": None,
+        "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(W)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -91,9 +91,10 @@ lbm_status lbm_num_blocks(lbm_ctx* ctx, int32_t level, int64_t* out);
 /* Keys of the active blocks of a level into keys_out (device int64 [nb]). */
 lbm_status lbm_block_keys(lbm_ctx* ctx, int32_t level, int64_t* keys_out);
 
-/* Writes moments (layout above, device f32 [nb][10][512]) into the listed blocks
- * (keys: device int64 [nb], each an active block of the level). SOLID nodes keep
- * the rest state and INFLOW nodes their face state. */
+/* Writes moments (layout above, device f32 [nb][10][512]) into both time levels of
+ * the listed blocks (keys: device int64 [nb], each an active block of the level;
+ * LBM_EINVAL otherwise). SOLID nodes keep the rest state and INFLOW nodes their
+ * face state. Synchronises (to report unknown keys). */
 lbm_status lbm_set_block_moments(lbm_ctx* ctx, int32_t level, const int64_t* keys, const float* in,
                                  int64_t nb);
 
@@ -130,6 +131,23 @@ lbm_status lbm_reduce_f64(lbm_ctx* ctx, int32_t level, const int32_t lo[3], cons
 
 /* LBM_ENAN if any stored moment of an active block is not finite. Synchronises. */
 lbm_status lbm_check_finite(lbm_ctx* ctx);
+
+/* Phase timers. With profiling on, every launch of the listed phases is bracketed
+ * by HIP events on cfg.stream; lbm_get_profile synchronises, returns the summed
+ * milliseconds and launch counts per phase since the last call, and resets them.
+ * Phases: stream-collide of levels 0..4, downward transfers, upward transfers,
+ * outflow copies, whole grid updates (lbm_remesh, host time between its events
+ * included). */
+enum {
+  LBM_PROF_SC0 = 0,            /* + level */
+  LBM_PROF_DOWN = 5,
+  LBM_PROF_UP = 6,
+  LBM_PROF_OUTFLOW = 7,
+  LBM_PROF_REMESH = 8,
+  LBM_PROFILE_PHASES = 9
+};
+lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t on);
+lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t count[LBM_PROFILE_PHASES]);
 
 /* Message of the last failed call on this context (or of lbm_create, for NULL). */
 const char* lbm_last_error(const lbm_ctx* ctx);

@@ -43,6 +43,10 @@
 #include <string>
 #include <vector>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 namespace {
 
 constexpr int kBlock = 8;            // nodes per block edge
@@ -887,6 +891,14 @@ void oc_reduce(void* h, int level, const int32_t lo[3], const int32_t hi[3], dou
 void oc_level_params(void* h, double* tau, double* a_up, double* a_down) {
   auto* s = static_cast<OSim*>(h);
   for (int l = 0; l < s->L; ++l) { tau[l] = s->tau[l]; a_up[l] = s->a_up[l]; a_down[l] = s->a_down[l]; }
+}
+
+int oc_num_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 // Single-node pieces, exposed for the pinning tests.

@@ -64,6 +64,7 @@ def lib():
         L.oc_lattice.argtypes = [vp, vp]
         L.oc_reconstruct.argtypes = [vp, vp]
         L.oc_collide.argtypes = [vp, ctypes.c_double, vp, vp]
+        L.oc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -162,6 +163,11 @@ def advance_particles(p, d):
     assert p.dtype == np.float32 and p.flags.c_contiguous
     dd = np.asarray(d, dtype=np.float32)
     lib().oc_advance_particles(_ptr(p), p.shape[0], _ptr(dd))
+
+
+def num_threads():
+    """OpenMP threads the oracle runs with."""
+    return int(lib().oc_num_threads())
 
 
 def lattice():

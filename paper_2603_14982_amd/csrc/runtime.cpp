@@ -145,6 +145,13 @@ struct lbm_ctx {
   int32_t free_top = 0;
   int32_t* host_counts = nullptr;  // pinned
   std::string err;
+  // phase timers (HIP events around launches, enabled on request)
+  bool profiling = false;
+  struct Timed { int phase; hipEvent_t a, b; };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> spare;
+  double prof_ms[LBM_PROFILE_PHASES] = {0};
+  int64_t prof_n[LBM_PROFILE_PHASES] = {0};
 
   template <class T> T* m(size_t off) const { return reinterpret_cast<T*>(meta + off); }
   uint8_t* st(int k) const { return m<uint8_t>(lay.st[k]); }
@@ -164,6 +171,37 @@ struct lbm_ctx {
   void* other(int l) const { return buf(l, 1 - parity[l]); }
 
   lbm_status fail(lbm_status s, const std::string& msg) { err = msg; return s; }
+  hipEvent_t take_event() {
+    if (!spare.empty()) { hipEvent_t e = spare.back(); spare.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+  }
+  // open a timed region of a phase; returns its index or -1
+  int tic(int phase) {
+    if (!profiling) return -1;
+    Timed t{phase, take_event(), take_event()};
+    hipEventRecord(t.a, stream);
+    timed.push_back(t);
+    return (int)timed.size() - 1;
+  }
+  void toc(int k) {
+    if (k >= 0) hipEventRecord(timed[(size_t)k].b, stream);
+  }
+  void collect() {
+    if (timed.empty()) return;
+    hipStreamSynchronize(stream);
+    for (auto& t : timed) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+        prof_ms[t.phase] += ms;
+        prof_n[t.phase] += 1;
+      }
+      spare.push_back(t.a);
+      spare.push_back(t.b);
+    }
+    timed.clear();
+  }
   lbm_status hip_check(hipError_t e, const char* what) {
     if (e == hipSuccess) return LBM_OK;
     err = std::string(what) + ": " + hipGetErrorString(e);
@@ -342,7 +380,9 @@ lbm_status sc_level(lbm_ctx* c, int l) {
   a.omega = (float)(1.0 / c->tau[l]);
   a.sc = c->sc;
   a.storage = c->cfg.storage;
+  const int k = c->tic(LBM_PROF_SC0 + l);
   HIPCHK(c, launch_stream_collide(a, c->stream));
+  c->toc(k);
   if (c->nob[l] > 0) {
     OutflowLaunch o;
     o.G = c->G;
@@ -354,7 +394,9 @@ lbm_status sc_level(lbm_ctx* c, int l) {
     o.old_buf = c->cur(l);
     o.new_buf = c->other(l);
     o.storage = c->cfg.storage;
+    const int ko = c->tic(LBM_PROF_OUTFLOW);
     HIPCHK(c, launch_outflow(o, c->stream));
+    c->toc(ko);
   }
   c->parity[l] ^= 1;
   return LBM_OK;
@@ -384,7 +426,9 @@ lbm_status down_level(lbm_ctx* c, int l, int s) {
   t.midpoint = (s == 2) ? 1 : 0;
   t.dst = c->cur(l);
   t.factor = (float)c->a_down[l];
+  const int k = c->tic(LBM_PROF_DOWN);
   HIPCHK(c, launch_downward(t, c->stream));
+  c->toc(k);
   return LBM_OK;
 }
 
@@ -397,7 +441,9 @@ lbm_status up_level(lbm_ctx* c, int l) {
   t.src_a = c->cur(l);
   t.dst = c->cur(l + 1);
   t.factor = (float)c->a_up[l];
+  const int k = c->tic(LBM_PROF_UP);
   HIPCHK(c, launch_upward(t, c->stream));
+  c->toc(k);
   return LBM_OK;
 }
 
@@ -515,6 +561,8 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
 lbm_status lbm_destroy(lbm_ctx* ctx) {
   if (!ctx) return LBM_EINVAL;
   hipStreamSynchronize(ctx->stream);
+  ctx->collect();
+  for (hipEvent_t e : ctx->spare) hipEventDestroy(e);
   hipHostFree(ctx->host_counts);
   delete ctx;
   return LBM_OK;
@@ -565,7 +613,29 @@ lbm_status lbm_advance_particles(lbm_ctx* ctx, float* particles, int64_t n, cons
 lbm_status lbm_remesh(lbm_ctx* ctx, const float* particles, int64_t n) {
   if (!ctx) return LBM_EINVAL;
   if (n < 0 || (n > 0 && !particles)) return ctx->fail(LBM_EINVAL, "bad particle array");
-  return rebuild(ctx, particles, n, false);
+  const int k = ctx->tic(LBM_PROF_REMESH);
+  lbm_status st = rebuild(ctx, particles, n, false);
+  ctx->toc(k);
+  return st;
+}
+
+lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t on) {
+  if (!ctx) return LBM_EINVAL;
+  ctx->collect();
+  ctx->profiling = on != 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t count[LBM_PROFILE_PHASES]) {
+  if (!ctx || !ms || !count) return ctx ? ctx->fail(LBM_EINVAL, "null output") : LBM_EINVAL;
+  ctx->collect();
+  for (int k = 0; k < LBM_PROFILE_PHASES; ++k) {
+    ms[k] = ctx->prof_ms[k];
+    count[k] = ctx->prof_n[k];
+    ctx->prof_ms[k] = 0.0;
+    ctx->prof_n[k] = 0;
+  }
+  return LBM_OK;
 }
 
 lbm_status lbm_get_moments(lbm_ctx* ctx, int32_t level, int64_t* keys_out, float* out) {

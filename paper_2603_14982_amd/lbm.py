@@ -48,7 +48,9 @@ class LBMConfig(ctypes.Structure):
 
 EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm_num_blocks", "lbm_block_keys",
            "lbm_set_block_moments", "lbm_step", "lbm_advance_particles", "lbm_remesh", "lbm_get_moments",
-           "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_last_error"]
+           "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
+           "lbm_last_error"]
+PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh"]
 
 _lib = None
 
@@ -78,6 +80,8 @@ def lib():
         L.lbm_get_roles.argtypes = [vp, i32, vp]
         L.lbm_reduce_f64.argtypes = [vp, i32, vp, vp, vp]
         L.lbm_check_finite.argtypes = [vp]
+        L.lbm_set_profiling.argtypes = [vp, i32]
+        L.lbm_get_profile.argtypes = [vp, vp, vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_last_error.argtypes = [vp]
         for name in EXPORTS:
@@ -220,6 +224,16 @@ class Sim:
         out = (ctypes.c_double * 5)()
         self._check(lib().lbm_reduce_f64(self.h, level, lo_, hi_, out))
         return np.array(list(out))
+
+    def set_profiling(self, on=True):
+        self._check(lib().lbm_set_profiling(self.h, 1 if on else 0))
+
+    def profile(self):
+        """Summed ms and launch counts per phase since the last call (synchronises)."""
+        ms = (ctypes.c_double * len(PROFILE_PHASES))()
+        cnt = (ctypes.c_int64 * len(PROFILE_PHASES))()
+        self._check(lib().lbm_get_profile(self.h, ms, cnt))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROFILE_PHASES)}
 
     def check_finite(self):
         st = lib().lbm_check_finite(self.h)

@@ -66,12 +66,13 @@ __device__ __forceinline__ void source_pops(const float q[kMom], float omega, fl
   const float gzzy = szz * uy + 2.0f * syz * uz - 2.0f * uz * uz * uy;
   const float gxyz = sxy * uz + sxz * uy + syz * ux - 2.0f * ux * uy * uz;
   // tensor-basis coefficients (Eq. three_order_f in the p0/p1/p2' basis)
-  const float a100 = 3.0f * (rho * ux), a010 = 3.0f * (rho * uy), a001 = 3.0f * (rho * uz);
-  const float a200 = 1.5f * (rho * sxx), a020 = 1.5f * (rho * syy), a002 = 1.5f * (rho * szz);
-  const float a110 = 9.0f * (rho * sxy), a101 = 9.0f * (rho * sxz), a011 = 9.0f * (rho * syz);
-  const float a210 = 4.5f * (rho * gxxy), a120 = 4.5f * (rho * gyyx), a201 = 4.5f * (rho * gxxz);
-  const float a102 = 4.5f * (rho * gzzx), a021 = 4.5f * (rho * gyyz), a012 = 4.5f * (rho * gzzy);
-  const float a111 = 27.0f * (rho * gxyz);
+  const float r3 = 3.0f * rho, r15 = 1.5f * rho, r9 = 9.0f * rho, r45 = 4.5f * rho, r27 = 27.0f * rho;
+  const float a100 = r3 * ux, a010 = r3 * uy, a001 = r3 * uz;
+  const float a200 = r15 * sxx, a020 = r15 * syy, a002 = r15 * szz;
+  const float a110 = r9 * sxy, a101 = r9 * sxz, a011 = r9 * syz;
+  const float a210 = r45 * gxxy, a120 = r45 * gyyx, a201 = r45 * gxxz;
+  const float a102 = r45 * gzzx, a021 = r45 * gyyz, a012 = r45 * gzzy;
+  const float a111 = r27 * gxyz;
   float e;
   // (my,mz) = (0,0): (a000, a100, a200)
   e = drho + 2.0f * a200;  p[0] = e + a100;  p[1] = 4.0f * (drho - a200);  p[2] = e - a100;
@@ -173,6 +174,7 @@ __device__ void bounce_back(const ScArgs<S>& a, const int* s_nbr, int slot, int 
   for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(src[m * kNodes], a.sc.inv[m]);
   float c[17];
   node_coeffs(q, a.omega, c);
+#pragma unroll 1
   for (int i = 0; i < 27; ++i) {
     if (i == 13) continue;
     const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
@@ -210,10 +212,77 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
+// LDS plane buffer, row-major so that the x pass of a row only overwrites its
+// own row: row r (plane row y = r - 1) holds
+//   x-pass input:  [kind (P+, P0, P-)][col 0..9][group 0..7]        (240 floats)
+//   y-pass input:  [kind (P+, P0, P-)][col 0..7][triple 0..8, pad 10] (240 floats)
+// Components of one point are contiguous so a lane moves them with 128-bit
+// (x-pass input) and 64-bit (y-pass input) LDS accesses.
+constexpr int kRow = 240;
+__device__ __forceinline__ int a_off(int row, int kind, int col) { return row * kRow + kind * 80 + col * 8; }
+__device__ __forceinline__ int b_off(int row, int kind, int col) { return row * kRow + kind * 80 + col * 10; }
+
+__device__ __forceinline__ void st8(float* lds, int off, const float v[8]) {
+  float4* p = reinterpret_cast<float4*>(lds + off);
+  p[0] = make_float4(v[0], v[1], v[2], v[3]);
+  p[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+__device__ __forceinline__ void ld8(const float* lds, int off, float v[8]) {
+  const float4* p = reinterpret_cast<const float4*>(lds + off);
+  const float4 a = p[0], b = p[1];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+__device__ __forceinline__ void st9(float* lds, int off, const float v[9]) {
+  float2* p = reinterpret_cast<float2*>(lds + off);
+  p[0] = make_float2(v[0], v[1]);
+  p[1] = make_float2(v[2], v[3]);
+  p[2] = make_float2(v[4], v[5]);
+  p[3] = make_float2(v[6], v[7]);
+  lds[off + 8] = v[8];
+}
+__device__ __forceinline__ void ld9(const float* lds, int off, float v[9]) {
+  const float2* p = reinterpret_cast<const float2*>(lds + off);
+  const float2 a = p[0], b = p[1], c = p[2], d = p[3];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y; v[6] = d.x; v[7] = d.y;
+  v[8] = lds[off + 8];
+}
+
+// reciprocal to within about half an ulp: hardware estimate plus one Newton step
+__device__ __forceinline__ float recip(float r) {
+  float y = __builtin_amdgcn_rcpf(r);
+  const float e = __builtin_fmaf(-r, y, 1.0f);
+  return __builtin_fmaf(y, e, y);
+}
+
+// x pass for one row of the owned 8 columns: back-map the 8 groups after the
+// shift, then forward-map along y for the 9 (qx, mz) triples
+__device__ __forceinline__ void x_pass(const float* lds, int row, int x, float yb[27]) {
+  float pp[8], pz[8], pm[8];
+  ld8(lds, a_off(row, 0, x), pp);       // P+ of column x-1
+  ld8(lds, a_off(row, 1, x + 1), pz);   // P0 of column x
+  ld8(lds, a_off(row, 2, x + 2), pm);   // P- of column x+1
+  float B[3][3][3];  // [qx][my][mz]
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    float m0, m1, m2;
+    back3(pp[g], pz[g], pm[g], m0, m1, m2);
+    const int my = (g == 1 || g == 5 || g == 7) ? 1 : ((g == 3 || g == 6) ? 2 : 0);
+    const int mz = (g == 2 || g == 5 || g == 6) ? 1 : ((g == 4 || g == 7) ? 2 : 0);
+    B[0][my][mz] = m0; B[1][my][mz] = m1; B[2][my][mz] = m2;
+  }
+#pragma unroll
+  for (int qx = 0; qx < 3; ++qx)
+#pragma unroll
+    for (int mz = 0; mz < 3; ++mz) {
+      const float b2 = (mz == 2) ? 0.0f : B[qx][2][mz];  // no (my, mz) = (2, 2) coefficient
+      const int t = 3 * qx + mz;
+      fwd3(B[qx][0][mz], B[qx][1][mz], b2, yb[t], yb[9 + t], yb[18 + t]);
+    }
+}
+
 template <class S>
 __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
-  // LDS: x-pass input [24][100] (halo plane), reused as y-pass input [27][80]
-  __shared__ float lds[24 * 100];
+  __shared__ __align__(16) float lds[10 * kRow];
   __shared__ int s_nbr[27];
   const int lane = threadIdx.x;
   const int slot = a.blocks[xcd_remap(blockIdx.x, a.nblocks)];
@@ -225,10 +294,12 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   has[0] = plane_point(lane, 0, px[0], py[0]);
   has[1] = plane_point(lane, 1, px[1], py[1]);
   const int ox = lane & 7, oy = lane >> 3;   // owned column
+  const float c216 = 1.0f / 216.0f;
 
   typedef typename S::type T;
   T nxt[2][kMom];
   bool nxt_present[2] = {false, false};
+#pragma unroll
   for (int r = 0; r < 2; ++r)
     if (has[r]) fetch_point<S>(a, s_nbr, px[r], py[r], -1, nxt[r], nxt_present[r]);
 
@@ -247,6 +318,7 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
       for (int m = 0; m < kMom; ++m) cur[r][m] = nxt[r][m];
     }
     if (z < 8) {
+#pragma unroll
       for (int r = 0; r < 2; ++r)
         if (has[r]) fetch_point<S>(a, s_nbr, px[r], py[r], z + 1, nxt[r], nxt_present[r]);
     }
@@ -258,70 +330,65 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
       for (int m = 0; m < kMom; ++m) q[m] = present[r] ? Codec<S>::load(cur[r][m], a.sc.inv[m]) : 0.0f;
       float p[24];
       source_pops(q, a.omega, p);
-      const int pt = (px[r] + 1) + 10 * (py[r] + 1);
+      float v[8];
+      const int row = py[r] + 1, col = px[r] + 1;
 #pragma unroll
-      for (int k = 0; k < 24; ++k) lds[k * 100 + pt] = p[k];
+      for (int kind = 0; kind < 3; ++kind) {
+#pragma unroll
+        for (int g = 0; g < 8; ++g) v[g] = p[3 * g + kind];
+        st8(lds, a_off(row, kind, col), v);
+      }
     }
     __syncthreads();
 
-    // ---- pass x: shift + back along x on the 8 x 10 plane, then y-forward
-    float yb[2][27];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int x = lane & 7;
-      const int y = (r == 0) ? (lane >> 3) - 1 : 7 + (lane >> 3);
-      if (r == 1 && lane >= 16) continue;
-      const int c = (x + 1) + 10 * (y + 1);
-      float B[3][3][3];  // [qx][my][mz]
-#pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        float m0, m1, m2;
-        back3(lds[(3 * g + 0) * 100 + c - 1], lds[(3 * g + 1) * 100 + c], lds[(3 * g + 2) * 100 + c + 1], m0, m1, m2);
-        const int my = (g == 1 || g == 5 || g == 7) ? 1 : ((g == 3 || g == 6) ? 2 : 0);
-        const int mz = (g == 2 || g == 5 || g == 6) ? 1 : ((g == 4 || g == 7) ? 2 : 0);
-        B[0][my][mz] = m0; B[1][my][mz] = m1; B[2][my][mz] = m2;
-      }
-#pragma unroll
-      for (int qx = 0; qx < 3; ++qx)
-#pragma unroll
-        for (int mz = 0; mz < 3; ++mz) {
-          const float b2 = (mz == 2) ? 0.0f : B[qx][2][mz];
-          const int t = 3 * qx + mz;
-          fwd3(B[qx][0][mz], B[qx][1][mz], b2, yb[r][3 * t + 0], yb[r][3 * t + 1], yb[r][3 * t + 2]);
-        }
+    // ---- pass x on rows 0..7 (plane rows -1..6), then rows 8..9 (plane rows 7..8);
+    // each row is overwritten by its own y-pass input once all its reads are done
+    {
+      float yb[27];
+      x_pass(lds, oy, ox, yb);
+      __syncthreads();
+      st9(lds, b_off(oy, 0, ox), yb);
+      st9(lds, b_off(oy, 1, ox), yb + 9);
+      st9(lds, b_off(oy, 2, ox), yb + 18);
     }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      if (r == 1 && lane >= 16) continue;
-      const int x = lane & 7;
-      const int y = (r == 0) ? (lane >> 3) - 1 : 7 + (lane >> 3);
-      const int c = x + 8 * (y + 1);
-#pragma unroll
-      for (int k = 0; k < 27; ++k) lds[k * 80 + c] = yb[r][k];
+    {
+      float yb[27];
+      const int row = 8 + (oy & 1);  // lanes 16..63 repeat rows 8..9 and do not store
+      x_pass(lds, row, ox, yb);
+      __syncthreads();
+      if (lane < 16) {
+        st9(lds, b_off(row, 0, ox), yb);
+        st9(lds, b_off(row, 1, ox), yb + 9);
+        st9(lds, b_off(row, 2, ox), yb + 18);
+      }
     }
     __syncthreads();
 
     // ---- pass y: shift + back along y for the owned column, then z-forward
     float zpp[6], zpz[6], zpm[6];
     {
-      const int cb = ox + 8 * oy;  // index of (x, y-1)
-      float C[3][3][3];            // [qx][qy][mz]
+      float bp[9], bz[9], bm[9];
+      ld9(lds, b_off(oy, 0, ox), bp);       // P+ of row y-1
+      ld9(lds, b_off(oy + 1, 1, ox), bz);   // P0 of row y
+      ld9(lds, b_off(oy + 2, 2, ox), bm);   // P- of row y+1
+      float C[3][3][3];                     // [qx][qy][mz]
 #pragma unroll
       for (int qx = 0; qx < 3; ++qx)
 #pragma unroll
         for (int mz = 0; mz < 3; ++mz) {
           const int t = 3 * qx + mz;
           float m0, m1, m2;
-          back3(lds[(3 * t + 0) * 80 + cb], lds[(3 * t + 1) * 80 + cb + 8], lds[(3 * t + 2) * 80 + cb + 16], m0, m1, m2);
+          back3(bp[t], bz[t], bm[t], m0, m1, m2);
           C[qx][0][mz] = m0; C[qx][1][mz] = m1; C[qx][2][mz] = m2;
         }
-      // pairs (qx,qy): (0,0) (1,0) (0,1) (2,0) (0,2) (1,1); mz = 2 of qx/qy pairs is
-      // absent in the source basis only for (my, mz) = (2, 2), handled by zeros above
-      const int pqx[6] = {0, 1, 0, 2, 0, 1};
-      const int pqy[6] = {0, 0, 1, 0, 2, 1};
-#pragma unroll
-      for (int k = 0; k < 6; ++k) fwd3(C[pqx[k]][pqy[k]][0], C[pqx[k]][pqy[k]][1], C[pqx[k]][pqy[k]][2], zpp[k], zpz[k], zpm[k]);
+      // (qx, qy) pairs needed by the ten output moments:
+      // (0,0) (1,0) (0,1) (2,0) (0,2) (1,1)
+      fwd3(C[0][0][0], C[0][0][1], C[0][0][2], zpp[0], zpz[0], zpm[0]);
+      fwd3(C[1][0][0], C[1][0][1], C[1][0][2], zpp[1], zpz[1], zpm[1]);
+      fwd3(C[0][1][0], C[0][1][1], C[0][1][2], zpp[2], zpz[2], zpm[2]);
+      fwd3(C[2][0][0], C[2][0][1], C[2][0][2], zpp[3], zpz[3], zpm[3]);
+      fwd3(C[0][2][0], C[0][2][1], C[0][2][2], zpp[4], zpz[4], zpm[4]);
+      fwd3(C[1][1][0], C[1][1][1], C[1][1][2], zpp[5], zpz[5], zpm[5]);
     }
     __syncthreads();
 
@@ -347,14 +414,18 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
       typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
       if ((role & ROLE_MASK) == ROLE_COMPUTED) {
         if (role & ROLE_BB) bounce_back<S>(a, s_nbr, slot, ox, oy, zo, M);
-        // remove the 6^3 scale of the three passes with correctly rounded divisions
+        // remove the 6^3 scale of the three passes; no constant reciprocal of
+        // 216 or 3 multiplies a result (it would bias every step the same way)
+        const float q0 = M[0] * c216;
+        const float drho = __builtin_fmaf(__builtin_fmaf(-q0, 216.0f, M[0]), c216, q0);  // M0 / 216
         const float r216 = 216.0f + M[0];          // 216 rho'
-        const float r648 = 3.0f * r216;            // p2' = 3 p2 on the diagonal stresses
+        const float inv = recip(r216);
+        const float inv3 = recip(3.0f * r216);     // p2' = 3 p2 on the diagonal stresses
         float v[kMom];
-        v[0] = M[0] / 216.0f;
-        v[1] = M[1] / r216; v[2] = M[2] / r216; v[3] = M[3] / r216;
-        v[4] = M[4] / r648; v[5] = M[5] / r648; v[6] = M[6] / r648;
-        v[7] = M[7] / r216; v[8] = M[8] / r216; v[9] = M[9] / r216;
+        v[0] = drho;
+        v[1] = M[1] * inv; v[2] = M[2] * inv; v[3] = M[3] * inv;
+        v[4] = M[4] * inv3; v[5] = M[5] * inv3; v[6] = M[6] * inv3;
+        v[7] = M[7] * inv; v[8] = M[8] * inv; v[9] = M[9] * inv;
 #pragma unroll
         for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(v[m], a.sc.s[m]);
       } else if ((role & ROLE_MASK) == ROLE_SOLID) {

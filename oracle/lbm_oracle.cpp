@@ -147,6 +147,36 @@ template <class T> T reconstruct(const Mom<T>& p, int i) {
   return p.rho() * LAT.w[i] * (1.0 + cu / CS2 + h2 / (2.0 * CS2 * CS2) + h3);
 }
 
+// Storage rounding of one stored value v (already shifted: rho-1 for the first
+// moment) with scale s: v*s rounded to f32 (nearest even), then to bf16 or f16
+// (nearest even), divided by s again.
+inline double round_bf16(float f) {
+  uint32_t b;
+  std::memcpy(&b, &f, 4);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  b &= 0xffff0000u;
+  float r;
+  std::memcpy(&r, &b, 4);
+  return double(r);
+}
+inline double round_f16(float f) {
+  // nearest-even rounding to IEEE binary16 (normal and subnormal ranges, overflow to infinity)
+  double a = std::fabs(double(f));
+  if (a == 0.0) return double(f);
+  int e;
+  std::frexp(a, &e);                 // a = m 2^e, m in [0.5, 1)
+  int ulp_exp = std::max(e - 11, -24);  // 11 significant bits; subnormal spacing 2^-24
+  double q = std::ldexp(std::nearbyint(std::ldexp(a, -ulp_exp)), ulp_exp);
+  if (q >= 65536.0) q = HUGE_VAL;  // beyond the largest finite binary16 (65504)
+  return f < 0 ? -q : q;
+}
+inline double store_round(double v, int storage, double scale) {
+  if (storage == 0) return v;
+  float f = float(v * scale);
+  double r = storage == 1 ? round_bf16(f) : round_f16(f);
+  return r / scale;
+}
+
 inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   uint64_t k = 0;
   for (int bit = 0; bit < 21; ++bit) {
@@ -174,11 +204,21 @@ struct oc_config {
   double tau0;         // finest-level relaxation time
   double force[3];     // body force on level 0 (oracle-only physics checks)
   int32_t rescale;     // 0: Chapman-Enskog S^neq factors; 1: factors as printed
-  int32_t pad_;
+  int32_t storage;     // 0: exact; 1: bf16, 2: f16 storage emulation (rho-1 shift, scales)
+  double scale[10];    // per-moment power-of-two storage scales
 };
 }
 
 namespace {
+
+template <class T> Mom<T> quantize(const Mom<T>& q, const oc_config&) { return q; }
+template <> Mom<double> quantize(const Mom<double>& q, const oc_config& c) {
+  if (c.storage == 0) return q;
+  Mom<double> r = q;
+  r.v[0] = 1.0 + store_round(q.v[0] - 1.0, c.storage, c.scale[0]);
+  for (int m = 1; m < kMom; ++m) r.v[m] = store_round(q.v[m], c.storage, c.scale[m]);
+  return r;
+}
 
 template <class T> struct Blk {
   int lvl = 0;
@@ -317,6 +357,9 @@ template <class T> struct Sim {
     return R_INTERIOR;
   }
   static bool owned(uint8_t r) { return r == R_INTERIOR || r == R_IU || r == R_INFLOW || r == R_OUTFLOW; }
+
+  // storage emulation of the GPU's 16-bit formats (identity for exact storage)
+  Mom<T> stored(const Mom<T>& q) const { return quantize(q, cfg); }
 
   void link_level(int l) {
     for (auto& kv : lv[l]) {
@@ -524,7 +567,7 @@ template <class T> struct Sim {
         }
         lin_axpy(acc, ws[k], src, ad);
       }
-      B->cur[n] = mom_of(acc);
+      B->cur[n] = stored(mom_of(acc));
     }
     if (!local_err.empty()) throw std::runtime_error(local_err);
   }
@@ -552,7 +595,7 @@ template <class T> struct Sim {
       }
       Lin acc = lin_zero();
       lin_axpy(acc, 1.0, lin_of(F->cur[node]), au);
-      B->cur[n] = mom_of(acc);
+      B->cur[n] = stored(mom_of(acc));
     }
     if (!local_err.empty()) throw std::runtime_error(local_err);
   }
@@ -626,7 +669,7 @@ template <class T> struct Sim {
         for (int a = 0; a < 3; ++a) q.v[1 + a] = (j[a] + 0.5 * F[a]) / rho;
         for (int a = 0; a < 3; ++a)
           for (int b = a; b < 3; ++b) q.S(a, b) = pi[a][b] / rho - (a == b ? CS2 : 0.0);
-        next[k][n] = q;
+        next[k][n] = stored(q);
       }
     }
     if (!local_err.empty()) throw std::runtime_error(local_err);
@@ -720,10 +763,10 @@ template <class T> struct Sim {
           bool fresh = (O == nullptr) || (!owned(O->role[n]) && owned(r));
           if (!fresh) { B->cur[n] = O->cur[n]; continue; }
           if (r == R_SOLID) { B->cur[n] = rest_state(); continue; }
-          if (r == R_INFLOW) { B->cur[n] = inflow_state(); continue; }
+          if (r == R_INFLOW) { B->cur[n] = stored(inflow_state()); continue; }
           int g[3] = {B->b[0] * kBlock + n % kBlock, B->b[1] * kBlock + (n / kBlock) % kBlock, B->b[2] * kBlock + n / (kBlock * kBlock)};
           try {
-            B->cur[n] = mom_of(sample_old(l, g));
+            B->cur[n] = stored(mom_of(sample_old(l, g)));
           } catch (const std::exception& e) {
 #pragma omp critical
             local_err = e.what();
@@ -751,6 +794,10 @@ void validate(const oc_config& c) {
   for (int f = 0; f < 6; ++f)
     if (c.bc[f] < 0 || c.bc[f] > 3) throw std::runtime_error("bad boundary kind");
   if (!(c.tau0 > 0.5)) throw std::runtime_error("tau0 must exceed 1/2");
+  if (c.storage < 0 || c.storage > 2) throw std::runtime_error("bad storage emulation");
+  if (c.storage != 0)
+    for (int m = 0; m < kMom; ++m)
+      if (!(c.scale[m] > 0.0)) throw std::runtime_error("storage scales must be positive");
 }
 
 template <class T> Sim<T>* create(const oc_config* cfg, const uint8_t* solid, const float* p, int64_t np) {
@@ -767,7 +814,7 @@ template <class T> Sim<T>* create(const oc_config* cfg, const uint8_t* solid, co
   for (int l = 0; l < s->L; ++l)
     for (auto& kv : s->lv[l])
       for (int n = 0; n < kNodes; ++n) {
-        if (kv.second.role[n] == R_INFLOW) kv.second.cur[n] = s->inflow_state();
+        if (kv.second.role[n] == R_INFLOW) kv.second.cur[n] = s->stored(s->inflow_state());
         kv.second.prev[n] = kv.second.cur[n];
       }
   return s;
@@ -816,6 +863,7 @@ int oc_set_block_moments(void* h, int level, const int64_t* keys, const double* 
       q.v[0] += 1.0;
       if (B.role[n] == R_SOLID) q = s->rest_state();
       if (B.role[n] == R_INFLOW) q = s->inflow_state();
+      q = s->stored(q);
       B.cur[n] = q;
       B.prev[n] = q;
     }
@@ -892,6 +940,8 @@ void oc_level_params(void* h, double* tau, double* a_up, double* a_down) {
   auto* s = static_cast<OSim*>(h);
   for (int l = 0; l < s->L; ++l) { tau[l] = s->tau[l]; a_up[l] = s->a_up[l]; a_down[l] = s->a_down[l]; }
 }
+
+double oc_store_round(double v, int storage, double scale) { return store_round(v, storage, scale); }
 
 int oc_num_threads() {
 #ifdef _OPENMP

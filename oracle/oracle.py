@@ -28,7 +28,8 @@ class _Cfg(ctypes.Structure):
         ("tau0", ctypes.c_double),
         ("force", ctypes.c_double * 3),
         ("rescale", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("scale", ctypes.c_double * 10),
     ]
 
 
@@ -65,6 +66,8 @@ def lib():
         L.oc_reconstruct.argtypes = [vp, vp]
         L.oc_collide.argtypes = [vp, ctypes.c_double, vp, vp]
         L.oc_num_threads.restype = ctypes.c_int
+        L.oc_store_round.restype = ctypes.c_double
+        L.oc_store_round.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
         _lib = L
     return _lib
 
@@ -77,7 +80,7 @@ class OracleSim:
     """One simulation held by the oracle."""
 
     def __init__(self, levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
-                 solid=None, particles=None, rescale="ce"):
+                 solid=None, particles=None, rescale="ce", storage="exact", scale=None):
         c = _Cfg()
         c.levels = levels
         for a in range(3):
@@ -88,6 +91,10 @@ class OracleSim:
             c.bc[f] = int(bc[f])
         c.tau0 = float(tau0)
         c.rescale = {"ce": 0, "printed": 1}[rescale]
+        c.storage = {"exact": 0, "bf16": 1, "f16": 2}[storage]
+        sc = [1.0] * 10 if scale is None else list(scale)
+        for m in range(10):
+            c.scale[m] = float(sc[m])
         self.levels = levels
         self.n = tuple(int(v) for v in n)
         self._solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
@@ -163,6 +170,11 @@ def advance_particles(p, d):
     assert p.dtype == np.float32 and p.flags.c_contiguous
     dd = np.asarray(d, dtype=np.float32)
     lib().oc_advance_particles(_ptr(p), p.shape[0], _ptr(dd))
+
+
+def store_round(v, storage, scale):
+    """The oracle's emulation of one 16-bit stored value ('bf16' or 'f16')."""
+    return float(lib().oc_store_round(float(v), {"bf16": 1, "f16": 2}[storage], float(scale)))
 
 
 def num_threads():

@@ -116,6 +116,13 @@ __global__ void k_state(Geom G, int l, const uint8_t* flags_l, const uint8_t* fl
   st_l[cell] = s;
 }
 
+// any block position of any level whose state changes -> flag = 1
+__global__ void k_diff(const uint8_t* st_new, const uint8_t* st_old, int64_t n, int32_t* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool d = i < n && st_new[i] != st_old[i];
+  if (__ballot(d) != 0ull && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
 // ---------------------------------------------------------------- compaction
 // Each wave evaluates up to three predicates on 64 consecutive items, counts
 // them with ballots, a single-workgroup scan turns the wave counts into offsets,
@@ -518,6 +525,12 @@ hipError_t launch_states(const HierLaunch& h, hipStream_t s) {
     const uint8_t* fu = (l + 1 < G.L) ? h.flags + G.lv[l + 1].off : nullptr;
     hipLaunchKernelGGL(k_state, dim3(grid1(g.ncell, 256)), dim3(256), 0, s, G, l, fl, fu, h.st_new + g.off);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_diff_flag(const uint8_t* st_new, const uint8_t* st_old, int64_t n, int32_t* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, flag, 0, (int64_t)1);
+  if (n > 0) hipLaunchKernelGGL(k_diff, dim3(grid1(n, 256)), dim3(256), 0, s, st_new, st_old, n, flag);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@ struct ScLaunch {
   int32_t nblocks;
   const int32_t* nbr;        // [slot][27]
   const uint8_t* role;       // [slot][512]
+  int32_t zero_slot;         // all-zero block read in place of missing neighbours
   float omega;
   Scales sc;
   int storage;
@@ -67,6 +68,8 @@ struct HierLaunch {
 hipError_t launch_mark_static(const Geom& G, const uint8_t* solid, uint8_t* t0_static, hipStream_t s);
 hipError_t launch_targets(const HierLaunch& h, const float* particles, int64_t n, hipStream_t s);
 hipError_t launch_states(const HierLaunch& h, hipStream_t s);
+// flag = 1 if any of the n all-level block states differ
+hipError_t launch_diff_flag(const uint8_t* st_new, const uint8_t* st_old, int64_t n, int32_t* flag, hipStream_t s);
 
 // generic order-preserving compaction (ballot + device prefix scan) over up to
 // three predicates; items are cells visited in Morton order of a level, or the

@@ -166,7 +166,8 @@ struct lbm_ctx {
   int32_t* gblocks(int l) const { return m<int32_t>(lay.gblocks) + lay.level_list_off[l]; }
   int32_t* iblocks(int l) const { return m<int32_t>(lay.iblocks) + lay.level_list_off[l]; }
   int32_t* oblocks(int l) const { return m<int32_t>(lay.oblocks) + lay.level_list_off[l]; }
-  void* buf(int l, int p) const { return pool + (size_t)p * (size_t)cap * kBlockStride * elem; }
+  // time level p of the pool: cap block slots plus one all-zero slot (index cap)
+  void* buf(int l, int p) const { return pool + (size_t)p * (size_t)(cap + 1) * kBlockStride * elem; }
   void* cur(int l) const { return buf(l, parity[l]); }
   void* other(int l) const { return buf(l, 1 - parity[l]); }
 
@@ -252,6 +253,15 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
   HIPCHK(c, launch_states(h, s));
   int32_t* counts = c->m<int32_t>(c->lay.counts);
   int32_t* wave = c->m<int32_t>(c->lay.wave);
+  int64_t ncell = 0;
+  for (int l = 0; l < L; ++l) ncell += G.lv[l].ncell;
+  if (!create) {
+    // fast path: one flag tells whether any block state changed
+    HIPCHK(c, launch_diff_flag(h.st_new, h.st_old, ncell, counts + 63, s));
+    HIPCHK(c, hipMemcpyAsync(c->host_counts, counts + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (c->host_counts[0] == 0) return LBM_OK;
+  }
   for (int l = 0; l < L; ++l) {
     CompactOut o;
     o.out[0] = c->lists(l, 0);
@@ -273,13 +283,10 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     tot_act += nact[l];
     if (nact[l] > c->lay.level_list_cap[l]) return c->fail(LBM_ECAPACITY, "level block count exceeds the pool capacity");
   }
-  if (!create && tot_new == 0 && tot_rem == 0) return LBM_OK;
   if (tot_new > c->free_top || tot_act > c->cap)
     return c->fail(LBM_ECAPACITY, "block pool too small for the new hierarchy (" + std::to_string(tot_act) +
                                       " blocks needed, max_blocks " + std::to_string(c->cap) + ")");
   // ---- from here on the update commits
-  int64_t ncell = 0;
-  for (int l = 0; l < L; ++l) ncell += G.lv[l].ncell;
   int32_t* dir_old = c->dir(c->hier);
   int32_t* dir_new = c->dir(nh);
   HIPCHK(c, launch_copy_i32(dir_old, dir_new, ncell, s));
@@ -377,6 +384,7 @@ lbm_status sc_level(lbm_ctx* c, int l) {
   a.nblocks = (int32_t)c->nblk[l];
   a.nbr = c->m<int32_t>(c->lay.nbr);
   a.role = c->role(c->rcur);
+  a.zero_slot = (int32_t)c->cap;
   a.omega = (float)(1.0 / c->tau[l]);
   a.sc = c->sc;
   a.storage = c->cfg.storage;
@@ -470,7 +478,7 @@ size_t lbm_pool_bytes(const lbm_config* cfg) {
   Geom G;
   std::string e;
   if (!make_geom(cfg, G, e)) return 0;
-  return 2 * (size_t)cfg->max_blocks * kBlockStride * elem_bytes(cfg->storage);
+  return 2 * (size_t)(cfg->max_blocks + 1) * kBlockStride * elem_bytes(cfg->storage);
 }
 
 size_t lbm_meta_bytes(const lbm_config* cfg) {
@@ -537,6 +545,10 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
     }
   };
   chk(launch_fill_u8(c->st(0), ST_ABSENT, ncell, c->stream), "clear states");
+  for (int p = 0; p < 2; ++p)  // the all-zero slot of each time level
+    chk(launch_fill_u8(static_cast<uint8_t*>(c->buf(0, p)) + (size_t)c->cap * kBlockStride * c->elem, 0,
+                       (int64_t)kBlockStride * (int64_t)c->elem, c->stream),
+        "zero slot");
   chk(launch_fill_i32(c->dir(0), NBR_NONE, ncell, c->stream), "clear directory");
   std::vector<int32_t> fs((size_t)c->cap);
   for (int64_t i = 0; i < c->cap; ++i) fs[(size_t)i] = (int32_t)(c->cap - 1 - i);

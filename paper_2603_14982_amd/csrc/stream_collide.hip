@@ -38,6 +38,7 @@ template <class S> struct ScArgs {
   const int32_t* nbr;
   const uint8_t* role;
   int32_t nblocks;
+  int32_t zero_slot;
   float omega;
   Scales sc;
 };
@@ -58,13 +59,16 @@ __device__ __forceinline__ void source_pops(const float q[kMom], float omega, fl
   const float sxz = q[8] + omega * (ux * uz - q[8]);
   const float syz = q[9] + omega * (uy * uz - q[9]);
   // third-order terms Gamma_aab = S_aa u_b + 2 S_ab u_a - 2 u_a^2 u_b
-  const float gxxy = sxx * uy + 2.0f * sxy * ux - 2.0f * ux * ux * uy;
-  const float gyyx = syy * ux + 2.0f * sxy * uy - 2.0f * uy * uy * ux;
-  const float gxxz = sxx * uz + 2.0f * sxz * ux - 2.0f * ux * ux * uz;
-  const float gzzx = szz * ux + 2.0f * sxz * uz - 2.0f * uz * uz * ux;
-  const float gyyz = syy * uz + 2.0f * syz * uy - 2.0f * uy * uy * uz;
-  const float gzzy = szz * uy + 2.0f * syz * uz - 2.0f * uz * uz * uy;
-  const float gxyz = sxy * uz + sxz * uy + syz * ux - 2.0f * ux * uy * uz;
+  //                             = u_b (S_aa - 2 u_a^2) + 2 S_ab u_a
+  const float tx = sxx - 2.0f * (ux * ux), ty = syy - 2.0f * (uy * uy), tz = szz - 2.0f * (uz * uz);
+  const float s2xy = 2.0f * sxy, s2xz = 2.0f * sxz, s2yz = 2.0f * syz;
+  const float gxxy = uy * tx + s2xy * ux;
+  const float gyyx = ux * ty + s2xy * uy;
+  const float gxxz = uz * tx + s2xz * ux;
+  const float gzzx = ux * tz + s2xz * uz;
+  const float gyyz = uz * ty + s2yz * uy;
+  const float gzzy = uy * tz + s2yz * uz;
+  const float gxyz = sxy * uz + sxz * uy + syz * ux - 2.0f * (ux * uy) * uz;
   // tensor-basis coefficients (Eq. three_order_f in the p0/p1/p2' basis)
   const float r3 = 3.0f * rho, r15 = 1.5f * rho, r9 = 9.0f * rho, r45 = 4.5f * rho, r27 = 27.0f * rho;
   const float a100 = r3 * ux, a010 = r3 * uy, a001 = r3 * uz;
@@ -148,15 +152,15 @@ __device__ __forceinline__ bool plane_point(int lane, int r, int& px, int& py) {
   return false;
 }
 
+// Missing neighbours (no block, wall) read the pool's all-zero slot: zero
+// moments give zero coefficients, the same as a solid node.
 template <class S>
-__device__ __forceinline__ void fetch_point(const ScArgs<S>& a, const int* s_nbr, int px, int py, int pz,
-                                            typename S::type raw[kMom], bool& present) {
+__device__ __forceinline__ void fetch_point(const ScArgs<S>& a, const int* s_src, int px, int py, int pz,
+                                            typename S::type raw[kMom]) {
   const int ox = px < 0 ? -1 : (px > 7 ? 1 : 0);
   const int oy = py < 0 ? -1 : (py > 7 ? 1 : 0);
   const int oz = pz < 0 ? -1 : (pz > 7 ? 1 : 0);
-  const int ns = s_nbr[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
-  present = ns >= 0;
-  if (!present) return;
+  const int ns = s_src[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
   const int node = (px & 7) + 8 * (py & 7) + 64 * (pz & 7);
   const typename S::type* src = a.in + (size_t)ns * kBlockStride + node;
 #pragma unroll
@@ -166,8 +170,8 @@ __device__ __forceinline__ void fetch_point(const ScArgs<S>& a, const int* s_nbr
 // bounce-back correction of one computed node: every direction c_i whose source
 // x - c_i is solid (or behind a wall) receives f_{-c_i}(x) instead.
 template <class S>
-__device__ void bounce_back(const ScArgs<S>& a, const int* s_nbr, int slot, int lx, int ly, int lz,
-                            float M[10]) {
+__device__ void bounce_back(const ScArgs<S>& a, int slot, int lx, int ly, int lz, float M[10]) {
+  const int32_t* nbr = a.nbr + (size_t)slot * 27;
   float q[kMom];
   const int node = lx + 8 * ly + 64 * lz;
   const typename S::type* src = a.in + (size_t)slot * kBlockStride + node;
@@ -182,7 +186,7 @@ __device__ void bounce_back(const ScArgs<S>& a, const int* s_nbr, int slot, int 
     const int ox = hx < 0 ? -1 : (hx > 7 ? 1 : 0);
     const int oy = hy < 0 ? -1 : (hy > 7 ? 1 : 0);
     const int oz = hz < 0 ? -1 : (hz > 7 ? 1 : 0);
-    const int ns = s_nbr[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
+    const int ns = nbr[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
     bool solid = (ns == NBR_WALL);
     if (ns >= 0) solid = (a.role[(size_t)ns * kNodes + (hx & 7) + 8 * (hy & 7) + 64 * (hz & 7)] & ROLE_MASK) == ROLE_SOLID;
     if (!solid) continue;
@@ -218,18 +222,23 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
 //   y-pass input:  [kind (P+, P0, P-)][col 0..7][triple 0..8, pad 10] (240 floats)
 // Components of one point are contiguous so a lane moves them with 128-bit
 // (x-pass input) and 64-bit (y-pass input) LDS accesses.
+// The two 4-float halves of an x-pass entry swap places on odd rows, so that the
+// 128-bit accesses of two neighbouring rows fall on disjoint LDS banks.
 constexpr int kRow = 240;
 __device__ __forceinline__ int a_off(int row, int kind, int col) { return row * kRow + kind * 80 + col * 8; }
 __device__ __forceinline__ int b_off(int row, int kind, int col) { return row * kRow + kind * 80 + col * 10; }
 
-__device__ __forceinline__ void st8(float* lds, int off, const float v[8]) {
-  float4* p = reinterpret_cast<float4*>(lds + off);
-  p[0] = make_float4(v[0], v[1], v[2], v[3]);
-  p[1] = make_float4(v[4], v[5], v[6], v[7]);
+__device__ __forceinline__ void st8(float* lds, int row, int kind, int col, const float v[8]) {
+  const int off = a_off(row, kind, col);
+  const int sw = (row & 1) << 2;
+  *reinterpret_cast<float4*>(lds + off + sw) = make_float4(v[0], v[1], v[2], v[3]);
+  *reinterpret_cast<float4*>(lds + off + (4 ^ sw)) = make_float4(v[4], v[5], v[6], v[7]);
 }
-__device__ __forceinline__ void ld8(const float* lds, int off, float v[8]) {
-  const float4* p = reinterpret_cast<const float4*>(lds + off);
-  const float4 a = p[0], b = p[1];
+__device__ __forceinline__ void ld8(const float* lds, int row, int kind, int col, float v[8]) {
+  const int off = a_off(row, kind, col);
+  const int sw = (row & 1) << 2;
+  const float4 a = *reinterpret_cast<const float4*>(lds + off + sw);
+  const float4 b = *reinterpret_cast<const float4*>(lds + off + (4 ^ sw));
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 __device__ __forceinline__ void st9(float* lds, int off, const float v[9]) {
@@ -258,9 +267,9 @@ __device__ __forceinline__ float recip(float r) {
 // shift, then forward-map along y for the 9 (qx, mz) triples
 __device__ __forceinline__ void x_pass(const float* lds, int row, int x, float yb[27]) {
   float pp[8], pz[8], pm[8];
-  ld8(lds, a_off(row, 0, x), pp);       // P+ of column x-1
-  ld8(lds, a_off(row, 1, x + 1), pz);   // P0 of column x
-  ld8(lds, a_off(row, 2, x + 2), pm);   // P- of column x+1
+  ld8(lds, row, 0, x, pp);       // P+ of column x-1
+  ld8(lds, row, 1, x + 1, pz);   // P0 of column x
+  ld8(lds, row, 2, x + 2, pm);   // P- of column x+1
   float B[3][3][3];  // [qx][my][mz]
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
@@ -283,10 +292,13 @@ __device__ __forceinline__ void x_pass(const float* lds, int row, int x, float y
 template <class S>
 __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   __shared__ __align__(16) float lds[10 * kRow];
-  __shared__ int s_nbr[27];
+  __shared__ int s_src[27];
   const int lane = threadIdx.x;
   const int slot = a.blocks[xcd_remap(blockIdx.x, a.nblocks)];
-  if (lane < 27) s_nbr[lane] = a.nbr[(size_t)slot * 27 + lane];
+  if (lane < 27) {
+    const int ns = a.nbr[(size_t)slot * 27 + lane];
+    s_src[lane] = ns >= 0 ? ns : a.zero_slot;
+  }
   __syncthreads();
 
   int px[2], py[2];
@@ -296,12 +308,20 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   const int ox = lane & 7, oy = lane >> 3;   // owned column
   const float c216 = 1.0f / 216.0f;
 
+  // roles of the owned column, loaded before the sweep so that no wait inside
+  // the plane loop has to drain the prefetch of the next plane
+  uint64_t col_roles = 0;
+  {
+    const uint8_t* rp = a.role + (size_t)slot * kNodes + ox + 8 * oy;
+#pragma unroll
+    for (int zz = 0; zz < 8; ++zz) col_roles |= (uint64_t)rp[64 * zz] << (8 * zz);
+  }
+
   typedef typename S::type T;
   T nxt[2][kMom];
-  bool nxt_present[2] = {false, false};
 #pragma unroll
   for (int r = 0; r < 2; ++r)
-    if (has[r]) fetch_point<S>(a, s_nbr, px[r], py[r], -1, nxt[r], nxt_present[r]);
+    if (has[r]) fetch_point<S>(a, s_src, px[r], py[r], -1, nxt[r]);
 
   float zp1[6], zp2[6], z0[6];  // z-window: pop+ of planes z-1, z-2; pop0 of plane z-1
 #pragma unroll
@@ -310,24 +330,21 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   for (int z = -1; z <= 8; ++z) {
     // ---- pass 0: moments of plane z (+ halo) -> x-populations, into LDS
     T cur[2][kMom];
-    bool present[2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      present[r] = nxt_present[r];
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int m = 0; m < kMom; ++m) cur[r][m] = nxt[r][m];
-    }
     if (z < 8) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
-        if (has[r]) fetch_point<S>(a, s_nbr, px[r], py[r], z + 1, nxt[r], nxt_present[r]);
+        if (has[r]) fetch_point<S>(a, s_src, px[r], py[r], z + 1, nxt[r]);
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       if (!has[r]) continue;
       float q[kMom];
 #pragma unroll
-      for (int m = 0; m < kMom; ++m) q[m] = present[r] ? Codec<S>::load(cur[r][m], a.sc.inv[m]) : 0.0f;
+      for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(cur[r][m], a.sc.inv[m]);
       float p[24];
       source_pops(q, a.omega, p);
       float v[8];
@@ -336,7 +353,7 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
       for (int kind = 0; kind < 3; ++kind) {
 #pragma unroll
         for (int g = 0; g < 8; ++g) v[g] = p[3 * g + kind];
-        st8(lds, a_off(row, kind, col), v);
+        st8(lds, row, kind, col, v);
       }
     }
     __syncthreads();
@@ -410,10 +427,10 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
       back3(zp2[5], z0[5], zpm[5], m0, m1, m2);  // (1,1): M110
       M[7] = m0;
       const int node = ox + 8 * oy + 64 * zo;
-      const uint8_t role = a.role[(size_t)slot * kNodes + node];
+      const uint8_t role = (uint8_t)(col_roles >> (8 * zo));
       typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
       if ((role & ROLE_MASK) == ROLE_COMPUTED) {
-        if (role & ROLE_BB) bounce_back<S>(a, s_nbr, slot, ox, oy, zo, M);
+        if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, zo, M);
         // remove the 6^3 scale of the three passes; no constant reciprocal of
         // 216 or 3 multiplies a result (it would bias every step the same way)
         const float q0 = M[0] * c216;
@@ -451,6 +468,7 @@ template <class S> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
   a.nbr = l.nbr;
   a.role = l.role;
   a.nblocks = l.nblocks;
+  a.zero_slot = l.zero_slot;
   a.omega = l.omega;
   a.sc = l.sc;
   hipLaunchKernelGGL(k_stream_collide<S>, dim3(l.nblocks), dim3(64), 0, s, a);

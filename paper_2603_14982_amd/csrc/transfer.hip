@@ -42,59 +42,75 @@ __device__ inline void from_neq(float q[kMom]) {
   q[7] += q[1] * q[2]; q[8] += q[1] * q[3]; q[9] += q[2] * q[3];
 }
 
+// One workgroup per fine block holding ghost nodes. The 5^3 coarse nodes under the
+// block's footprint (coarse indices 4b .. 4b+4 per axis) are staged once in LDS as
+// (rho-1, u, S^neq), already averaged in time for the midpoint substep; each ghost
+// node then combines its 1, 2, 4 or 8 trilinear sources from LDS. Staged positions
+// in blocks that hold no coarse data (covered by the fine level) read as zero; no
+// ghost node of a valid hierarchy uses them.
 template <class S>
 __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
+  __shared__ float cq[kMom][125];
   const int slot = a.blocks[blockIdx.x];
   const int4 bc = a.coord[slot];
   const int l = a.level;
   const LevelGeom& cg = a.G.lv[l + 1];
-  for (int node = threadIdx.x; node < kNodes; node += 256) {
-    if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_GHOST) continue;
-    const int g[3] = {bc.x * kEdge + (node & 7), bc.y * kEdge + ((node >> 3) & 7), bc.z * kEdge + (node >> 6)};
-    int cand[3][2], cnt[3];
-    float wv[3][2];
+  const int base[3] = {4 * bc.x, 4 * bc.y, 4 * bc.z};
+  for (int t = threadIdx.x; t < 125; t += 256) {
+    int j[3] = {base[0] + t % 5, base[1] + (t / 5) % 5, base[2] + t / 25};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const int nc = cg.nn[ax];
-      if ((g[ax] & 1) == 0) {
-        cand[ax][0] = g[ax] >> 1; cand[ax][1] = cand[ax][0]; wv[ax][0] = 1.0f; wv[ax][1] = 0.0f; cnt[ax] = 1;
-      } else {
-        cand[ax][0] = (g[ax] - 1) >> 1; cand[ax][1] = (g[ax] + 1) >> 1; wv[ax][0] = 0.5f; wv[ax][1] = 0.5f; cnt[ax] = 2;
-      }
+      if (a.G.periodic[ax]) j[ax] = j[ax] >= nc ? j[ax] - nc : j[ax];
+      else j[ax] = j[ax] >= nc ? nc - 1 : j[ax];
+    }
+    const int cs = a.dir[cg.off + cell_lin(cg, j[0] >> 3, j[1] >> 3, j[2] >> 3)];
+    float q[kMom];
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
-        int v = cand[ax][k];
-        if (a.G.periodic[ax]) v = v < 0 ? v + nc : (v >= nc ? v - nc : v);
-        else v = v < 0 ? 0 : (v >= nc ? nc - 1 : v);
-        cand[ax][k] = v;
+    for (int m = 0; m < kMom; ++m) q[m] = 0.0f;
+    if (cs >= 0) {
+      const int cn = (j[0] & 7) + 8 * (j[1] & 7) + 64 * (j[2] & 7);
+      Mom<S>::load(a.src_a, cs, cn, a.sc, q);
+      to_neq(q);
+      if (a.midpoint) {
+        float r[kMom];
+        Mom<S>::load(a.src_b, cs, cn, a.sc, r);
+        to_neq(r);
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) q[m] = 0.5f * (q[m] + r[m]);
       }
+    }
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) cq[m][t] = q[m];
+  }
+  __syncthreads();
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_GHOST) continue;
+    const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
+    int i0[3], i1[3];
+    float w1[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      // fine node 8b + lc sits on coarse 4b + lc/2 (even) or between the two neighbours (odd)
+      i0[ax] = lc[ax] >> 1;
+      i1[ax] = (lc[ax] + 1) >> 1;
+      w1[ax] = (lc[ax] & 1) ? 0.5f : 0.0f;
     }
     float acc[kMom];
 #pragma unroll
     for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
-    for (int kz = 0; kz < cnt[2]; ++kz)
-      for (int ky = 0; ky < cnt[1]; ++ky)
-        for (int kx = 0; kx < cnt[0]; ++kx) {
-          const int j[3] = {cand[0][kx], cand[1][ky], cand[2][kz]};
-          const float w = wv[0][kx] * wv[1][ky] * wv[2][kz];
-          const int cs = a.dir[cg.off + cell_lin(cg, j[0] >> 3, j[1] >> 3, j[2] >> 3)];
-          if (cs < 0) continue;  // cannot happen for a valid hierarchy; never read out of bounds
-          const int cn = (j[0] & 7) + 8 * (j[1] & 7) + 64 * (j[2] & 7);
-          float q[kMom];
-          Mom<S>::load(a.src_a, cs, cn, a.sc, q);
-          to_neq(q);
-          if (a.midpoint) {
-            float r[kMom];
-            Mom<S>::load(a.src_b, cs, cn, a.sc, r);
-            to_neq(r);
 #pragma unroll
-            for (int m = 0; m < kMom; ++m) q[m] = 0.5f * (q[m] + r[m]);
-          }
+    for (int c = 0; c < 8; ++c) {
+      const int kx = c & 1, ky = (c >> 1) & 1, kz = c >> 2;
+      const float w = (kx ? w1[0] : 1.0f - w1[0]) * (ky ? w1[1] : 1.0f - w1[1]) * (kz ? w1[2] : 1.0f - w1[2]);
+      if (w == 0.0f) continue;
+      const int t = (kx ? i1[0] : i0[0]) + 5 * (ky ? i1[1] : i0[1]) + 25 * (kz ? i1[2] : i0[2]);
 #pragma unroll
-          for (int m = 0; m < 4; ++m) acc[m] += w * q[m];
+      for (int m = 0; m < 4; ++m) acc[m] += w * cq[m][t];
+      const float ws = w * a.factor;
 #pragma unroll
-          for (int m = 4; m < kMom; ++m) acc[m] += (w * a.factor) * q[m];
-        }
+      for (int m = 4; m < kMom; ++m) acc[m] += ws * cq[m][t];
+    }
     from_neq(acc);
     Mom<S>::store(a.dst, slot, node, a.sc, acc);
   }

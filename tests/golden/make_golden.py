@@ -1,0 +1,89 @@
+"""Writes the stored expected values of the full-size parity tests.
+
+Calls only the FP64 oracle (oracle/) and the seeded input generators; no value
+here comes from the GPU path. Each output holds a seeded sample of owned nodes
+(level, block key, node index, 10 moments) of the oracle's state.
+
+  python tests/golden/make_golden.py sphere128   # 500 coarse steps
+  python tests/golden/make_golden.py slab512     # 20 coarse steps with grid updates
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2603_14982_amd import workloads as W  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def sample_state(sim, per_level, seed):
+    rng = np.random.default_rng(seed)
+    out = {"level": [], "key": [], "node": [], "values": []}
+    counts = []
+    for l in range(sim.levels):
+        keys, vals = sim.get_block_moments(l)
+        roles = sim.roles(l)
+        counts.append(len(keys))
+        own = np.argwhere(roles != O.R_GHOST)
+        if len(own) == 0:
+            continue
+        pick = own[rng.choice(len(own), size=min(per_level, len(own)), replace=False)]
+        out["level"].append(np.full(len(pick), l, dtype=np.int32))
+        out["key"].append(keys[pick[:, 0]])
+        out["node"].append(pick[:, 1].astype(np.int32))
+        out["values"].append(vals[pick[:, 0], :, pick[:, 1]])
+    res = {k: np.concatenate(v) for k, v in out.items()}
+    res["blocks_per_level"] = np.array(counts, dtype=np.int64)
+    return res
+
+
+def sphere128(steps=500):
+    wl = W.workload("sphere128")
+    c, r = wl["sphere"]
+    solid = W.sphere_solid(wl["n"], c, r)
+    sim = O.OracleSim(2, wl["n"], wl["bc"], wl["tau0"], uin=wl["uin"], solid=solid)
+    for l in range(2):
+        keys = sim.block_keys(l)
+        sim.set_block_moments(l, keys, W.uniform_field(l, keys))
+    t = time.time()
+    for i in range(steps):
+        sim.step(1)
+        if i % 50 == 49:
+            print(f"sphere128 step {i + 1} ({time.time() - t:.0f} s)", flush=True)
+    res = sample_state(sim, 4096, seed=128)
+    res["steps"] = np.array(steps)
+    np.savez_compressed(os.path.join(HERE, "sphere128_oracle_sample.npz"), **res)
+
+
+def slab512(coarse_steps=20):
+    wl = W.workload("slab512")
+    p = W.slab_particles(wl["particles"], wl["seed"], wl["lo"], wl["hi"])
+    t = time.time()
+    sim = O.OracleSim(3, wl["n"], wl["bc"], wl["tau0"], particles=p)
+    print(f"slab512 hierarchy built ({time.time() - t:.0f} s)", flush=True)
+    for l in range(3):
+        keys = sim.block_keys(l)
+        for s in range(0, len(keys), 2048):
+            k = keys[s:s + 2048]
+            sim.set_block_moments(l, k, W.tgv3d_field(l, k, wl["n"], wl["amp"]))
+    sub = 1 << (wl["levels"] - 1)
+    d = np.array([v * sub for v in wl["v_fine"]], dtype=np.float32)
+    for i in range(coarse_steps):
+        sim.step(1)
+        O.advance_particles(p, d)
+        sim.remesh(p)
+        print(f"slab512 coarse step {i + 1} ({time.time() - t:.0f} s)", flush=True)
+    res = sample_state(sim, 8192, seed=512)
+    res["steps"] = np.array(coarse_steps)
+    np.savez_compressed(os.path.join(HERE, "slab512_oracle_sample.npz"), **res)
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:]:
+        {"sphere128": sphere128, "slab512": slab512}[name]()

@@ -36,7 +36,7 @@ def test_buffer_sizes():
     L = lbm.lib()
     c = _cfg()
     pool = L.lbm_pool_bytes(ctypes.byref(c))
-    assert pool == 2 * 600 * 10 * 512 * 4
+    assert pool == 2 * 601 * 10 * 512 * 4  # 600 slots + the all-zero slot
     c16 = _cfg(storage="bf16", scale=[64.0] * 10)
     assert L.lbm_pool_bytes(ctypes.byref(c16)) == pool // 2
     assert L.lbm_meta_bytes(ctypes.byref(c)) > 600 * (27 * 4 + 2 * 512)

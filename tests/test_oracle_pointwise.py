@@ -114,3 +114,19 @@ def test_forced_collision_moments():
     u = q[1:4]
     expect = _S(q) + om * (np.outer(u, u) - _S(q)) + (1 - om / 2) * (np.outer(u, F) + np.outer(F, u)) / q[0]
     assert np.allclose(_S(p), expect, atol=1e-18)
+
+
+def test_storage_rounding_matches_ieee_half_and_bfloat16():
+    # the oracle's 16-bit storage emulation against numpy's float16 and torch's
+    # bfloat16 conversions (both round to nearest even), after the f32 rounding
+    import torch
+    rng = np.random.default_rng(7)
+    vals = np.concatenate([rng.standard_normal(2000) * 10.0 ** rng.integers(-9, 2, 2000),
+                           [0.0, 1e-8, -3e-6, 2.0 ** -24, 2.0 ** -15, 0.5, 65000.0]])
+    for scale in (1.0, 64.0, 8.0):
+        for v in vals:
+            f = np.float32(v * scale)
+            e16 = float(np.float16(f)) / scale
+            eb = float(torch.tensor(float(f), dtype=torch.float32).to(torch.bfloat16).float()) / scale
+            assert O.store_round(v, "f16", scale) == e16, (v, scale)
+            assert O.store_round(v, "bf16", scale) == eb, (v, scale)

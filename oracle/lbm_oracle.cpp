@@ -732,6 +732,27 @@ template <class T> struct Sim {
     return acc;
   }
 
+  // 1/2 sum rho |u|^2 over the owned nodes of one level inside the fine box [lo, hi)
+  // (no conjugation: the analytic continuation used by complex-step derivatives)
+  T kinetic_energy(int level, const int32_t lo[3], const int32_t hi[3]) const {
+    T sum = T(0);
+    for (auto& kv : lv[level])
+      for (int n = 0; n < kNodes; ++n) {
+        if (!owned(kv.second.role[n])) continue;
+        const int g[3] = {kv.second.b[0] * kBlock + n % kBlock, kv.second.b[1] * kBlock + (n / kBlock) % kBlock,
+                          kv.second.b[2] * kBlock + n / (kBlock * kBlock)};
+        bool in = true;
+        for (int a = 0; a < 3; ++a) {
+          const int64_t f = int64_t(g[a]) << level;
+          if (f < lo[a] || f >= hi[a]) in = false;
+        }
+        if (!in) continue;
+        const Mom<T>& q = kv.second.cur[n];
+        sum = sum + 0.5 * q.rho() * (q.u(0) * q.u(0) + q.u(1) * q.u(1) + q.u(2) * q.u(2));
+      }
+    return sum;
+  }
+
   int remesh(const float* p, int64_t np) {
     BSet T0 = mark_T0(p, np);
     auto states = hierarchy_states(T0);
@@ -904,6 +925,53 @@ int oc_remesh(void* h, const float* particles, int64_t np) {
   try { return s->remesh(particles, np); }
   catch (const std::exception& e) { g_err = e.what(); return -1; }
 }
+double oc_loss_ke(void* h, int level, const int32_t lo[3], const int32_t hi[3]) {
+  return static_cast<OSim*>(h)->kinetic_energy(level, lo, hi);
+}
+
+// ---- complex-step instance: the same templated code on std::complex<double> ----
+typedef Sim<std::complex<double>> CSim;
+void* occ_create(const oc_config* cfg, const uint8_t* solid, const float* particles, int64_t np) {
+  try {
+    if (cfg->storage != 0) throw std::runtime_error("complex-step runs need exact storage");
+    return create<std::complex<double>>(cfg, solid, particles, np);
+  } catch (const std::exception& e) { g_err = e.what(); return nullptr; }
+}
+void occ_destroy(void* h) { delete static_cast<CSim*>(h); }
+int occ_set_block_moments(void* h, int level, const int64_t* keys, const double* re, const double* im, int64_t nb) {
+  auto* s = static_cast<CSim*>(h);
+  for (int64_t k = 0; k < nb; ++k) {
+    auto it = s->lv[level].find(uint64_t(keys[k]));
+    if (it == s->lv[level].end()) { g_err = "set_block_moments: unknown block"; return -1; }
+    auto& B = it->second;
+    for (int n = 0; n < kNodes; ++n) {
+      Mom<std::complex<double>> q;
+      for (int m = 0; m < kMom; ++m) {
+        const size_t i = size_t((k * kMom + m) * kNodes + n);
+        q.v[m] = std::complex<double>(re[i], im ? im[i] : 0.0);
+      }
+      q.v[0] += 1.0;
+      if (B.role[n] == R_SOLID) q = s->rest_state();
+      if (B.role[n] == R_INFLOW) q = s->inflow_state();
+      B.cur[n] = q;
+      B.prev[n] = q;
+    }
+  }
+  return 0;
+}
+int occ_step(void* h, int n) {
+  auto* s = static_cast<CSim*>(h);
+  try {
+    for (int i = 0; i < n; ++i) s->advance(s->L - 1, 1);
+  } catch (const std::exception& e) { g_err = e.what(); return -1; }
+  return 0;
+}
+void occ_loss_ke(void* h, int level, const int32_t lo[3], const int32_t hi[3], double out[2]) {
+  const std::complex<double> v = static_cast<CSim*>(h)->kinetic_energy(level, lo, hi);
+  out[0] = v.real();
+  out[1] = v.imag();
+}
+
 // FP32 particle advance p += d (no contraction), as the GPU path does it.
 void oc_advance_particles(float* p, int64_t np, const float d[3]) {
   for (int64_t i = 0; i < np; ++i)

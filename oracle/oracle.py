@@ -66,6 +66,16 @@ def lib():
         L.oc_reconstruct.argtypes = [vp, vp]
         L.oc_collide.argtypes = [vp, ctypes.c_double, vp, vp]
         L.oc_num_threads.restype = ctypes.c_int
+        L.oc_loss_ke.restype = ctypes.c_double
+        L.oc_loss_ke.argtypes = [vp, i32, vp, vp]
+        L.occ_create.restype = vp
+        L.occ_create.argtypes = [ctypes.POINTER(_Cfg), vp, vp, i64]
+        L.occ_destroy.argtypes = [vp]
+        L.occ_set_block_moments.restype = i32
+        L.occ_set_block_moments.argtypes = [vp, i32, vp, vp, vp, i64]
+        L.occ_step.restype = i32
+        L.occ_step.argtypes = [vp, i32]
+        L.occ_loss_ke.argtypes = [vp, i32, vp, vp, vp]
         L.oc_store_round.restype = ctypes.c_double
         L.oc_store_round.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
         _lib = L
@@ -157,12 +167,70 @@ class OracleSim:
         lib().oc_reduce(self.h, level, _ptr(lo_), _ptr(hi_), _ptr(out))
         return out
 
+    def kinetic_energy(self, level, lo, hi):
+        lo_ = np.array(lo, dtype=np.int32)
+        hi_ = np.array(hi, dtype=np.int32)
+        return float(lib().oc_loss_ke(self.h, level, _ptr(lo_), _ptr(hi_)))
+
     def level_params(self):
         t = np.empty(self.levels)
         u = np.empty(self.levels)
         d = np.empty(self.levels)
         lib().oc_level_params(self.h, _ptr(t), _ptr(u), _ptr(d))
         return t, u, d
+
+
+class OracleSimComplex:
+    """The same oracle on std::complex<double>, for complex-step derivatives: set
+    moments with an imaginary part h*d, step, read the imaginary part of the loss."""
+
+    def __init__(self, levels, n, bc, tau0, particles=None, solid=None, uin=(0.0, 0.0, 0.0), rescale="ce"):
+        self._real = OracleSim(levels, n, bc, tau0, uin=uin, solid=solid, particles=particles, rescale=rescale)
+        c = _Cfg()
+        c.levels = levels
+        for a in range(3):
+            c.n[a] = int(n[a])
+            c.uin[a] = float(uin[a])
+        for f in range(6):
+            c.bc[f] = int(bc[f])
+        c.tau0 = float(tau0)
+        c.rescale = {"ce": 0, "printed": 1}[rescale]
+        self.levels = levels
+        p = None if particles is None else np.ascontiguousarray(particles, dtype=np.float32)
+        self._solid = None if solid is None else np.ascontiguousarray(solid, dtype=np.uint8)
+        h = lib().occ_create(ctypes.byref(c), _ptr(self._solid), _ptr(p), 0 if p is None else p.shape[0])
+        if not h:
+            raise ValueError(lib().oc_last_error().decode())
+        self.h = h
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().occ_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def block_keys(self, level):
+        return self._real.block_keys(level)
+
+    def set_block_moments(self, level, keys, re, im=None):
+        keys = np.ascontiguousarray(keys, dtype=np.int64)
+        re = np.ascontiguousarray(re, dtype=np.float64)
+        im = None if im is None else np.ascontiguousarray(im, dtype=np.float64)
+        if lib().occ_set_block_moments(self.h, level, _ptr(keys), _ptr(re), _ptr(im), keys.shape[0]) != 0:
+            raise ValueError(lib().oc_last_error().decode())
+
+    def step(self, n=1):
+        if lib().occ_step(self.h, n) != 0:
+            raise RuntimeError(lib().oc_last_error().decode())
+
+    def kinetic_energy(self, level, lo, hi):
+        lo_ = np.array(lo, dtype=np.int32)
+        hi_ = np.array(hi, dtype=np.int32)
+        out = np.empty(2)
+        lib().occ_loss_ke(self.h, level, _ptr(lo_), _ptr(hi_), _ptr(out))
+        return complex(out[0], out[1])
 
 
 def advance_particles(p, d):

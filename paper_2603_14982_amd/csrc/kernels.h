@@ -19,8 +19,12 @@ struct ScLaunch {
   float omega;
   Scales sc;
   int storage;
+  const float* lam_y = nullptr;  // adjoint epilogue: adjoint of the outputs (f32 pool layout)
+  float* mu = nullptr;           // adjoint epilogue: adjoint of the scaled moments M
 };
 hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s);
+// the stream-collide sweep with the adjoint epilogue (writes mu instead of moments)
+hipError_t launch_stream_collide_mu(const ScLaunch& a, hipStream_t s);
 
 // ---- interface transfers and outflow ----
 struct TransferLaunch {

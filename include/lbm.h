@@ -149,6 +149,53 @@ enum {
 lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t on);
 lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t count[LBM_PROFILE_PHASES]);
 
+/* ---- states and the adjoint (gradient of a loss of the final moments with
+ * respect to the initial moments; Sec. 7 differentiates the solver) ----
+ *
+ * A state is the current time level of every block of every level, in level
+ * order and key order, behind a 256-byte header that names the block hierarchy
+ * it belongs to. The hierarchy must not change between saving and loading.
+ *
+ * lbm_state_bytes: size of a state under the current hierarchy (0 for NULL).
+ * lbm_save: writes the state to dst (device, >= lbm_state_bytes bytes); async.
+ * lbm_load: makes a saved state current. Synchronises (reads the header).
+ *   LBM_ESTATE if src holds no state of this context or was saved under another
+ *   hierarchy (a grid update that changed blocks happened since). */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+lbm_status lbm_save(lbm_ctx* ctx, void* dst, size_t bytes);
+lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes);
+
+/* One reverse-mode step (Sec. 7: the gradient is the transposed Jacobian of the
+ * update applied to the adjoint, coarse step by coarse step, backwards).
+ *   state      device, a state saved at the start of the coarse step (lbm_save);
+ *   lam_next   device f32 [sum over levels of nb_l][10][512], levels in order and
+ *              blocks in key order (the layout of lbm_get_moments, concatenated):
+ *              dLoss/d(moments after the step). Only nodes that carry state
+ *              (computed, upward-interface and outflow nodes) are read; ghost,
+ *              solid and inflow entries are ignored.
+ *   lam_out    device f32, same layout: dLoss/d(moments of `state`), i.e. with
+ *              respect to the values lbm_set_block_moments would write (zero at
+ *              ghost, solid and inflow nodes, which do not influence the step).
+ *              May alias lam_next.
+ *   work       device scratch of >= lbm_adjoint_work_bytes bytes (caller-owned):
+ *              the adjoint of both time levels, the adjoint of the per-node
+ *              moment sums, and the undo log of the replayed step.
+ * The call loads `state` (synchronises once), replays the coarse step while
+ * logging every block it overwrites, then walks the log backwards: adjoint of
+ * each operation, then its undo. On return the simulation is at `state`.
+ * The adjoint is that of the f32 arithmetic; with 16-bit storage the rounding
+ * of stored values is passed through unchanged. Grid updates are not part of
+ * the step and are not differentiated. */
+size_t lbm_adjoint_work_bytes(const lbm_ctx* ctx);
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes, const float* lam_next,
+                            float* lam_out, void* work, size_t work_bytes);
+
+/* Adjoint seed of the kinetic energy 1/2 sum rho |u|^2 over the owned nodes of
+ * `level` whose fine position lies in [lo, hi): writes lam (device f32, the
+ * all-level layout of lbm_adjoint_step) with d(loss)/d(moments) of the current
+ * state, zero outside the level's owned state nodes in the box. */
+lbm_status lbm_loss_ke_grad(lbm_ctx* ctx, int32_t level, const int32_t lo[3], const int32_t hi[3], float* lam);
+
 /* Message of the last failed call on this context (or of lbm_create, for NULL). */
 const char* lbm_last_error(const lbm_ctx* ctx);
 

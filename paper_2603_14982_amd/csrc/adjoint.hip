@@ -1,0 +1,749 @@
+// Hand-written adjoint of one coarse step (reverse mode, transposed Jacobians).
+//
+// Stream-collide: Y = F(M), M = L a(X) with L the (linear, integer) stream +
+// projection operator and a the per-node coefficient map (collision included).
+// The adjoint is computed in two sweeps over a level:
+//   1. the forward sweep recomputes M and writes mu = (dF/dM)^T lambda_Y
+//      (k_stream_collide with the adjoint epilogue);
+//   2. this file's k_sc_transpose applies L^T to mu (the same three 1D passes,
+//      transposed: back-maps and shifts swap roles, x and y through LDS on a halo
+//      plane, z over a register window) and adds (da/dX)^T (L^T mu) to lambda_X.
+// Bounce-back adds, at a flagged computed node, populations built from the node's
+// own coefficients; its transpose is a per-node term of the same sweep. Solid and
+// inflow nodes hold fixed values and collect no adjoint.
+// Interface transfers: the downward transfer is transposed as a gather per coarse
+// node (every ghost whose trilinear stencil contains the node), the upward
+// transfer as a one-to-one scatter; both use the forward values they depend on.
+// Every kernel is deterministic: no atomics, each output written by one lane.
+#include "common.h"
+#include "kernels.h"
+
+namespace lbmx {
+namespace {
+
+// transposes of the 1D maps of the forward sweep (times-6 populations, p2' basis)
+// back3: (P+,P0,P-) -> (P+ + P0 + P-, P+ - P-, 2(P+ + P-) - P0)
+__device__ __forceinline__ void back3_t(float m0, float m1, float m2, float& pp, float& p0, float& pm) {
+  pp = m0 + m1 + 2.0f * m2;
+  p0 = m0 - m2;
+  pm = m0 - m1 + 2.0f * m2;
+}
+// fwd3: (a0,a1,a2) -> (a0 + a1 + 2a2, 4(a0 - a2), a0 - a1 + 2a2)
+__device__ __forceinline__ void fwd3_t(float pp, float p0, float pm, float& a0, float& a1, float& a2) {
+  a0 = pp + 4.0f * p0 + pm;
+  a1 = pp - pm;
+  a2 = 2.0f * (pp + pm) - 4.0f * p0;
+}
+
+template <class S> struct TrArgs {
+  const typename S::type* x;  // forward input time level
+  const float* mu;            // adjoint of M (one f32 time level, all-zero slot at zero_slot)
+  float* lam_x;               // adjoint of the input time level (accumulated)
+  const int32_t* blocks;
+  const int32_t* nbr;
+  const uint8_t* role;
+  int32_t nblocks;
+  int32_t zero_slot;
+  float omega;
+  Scales sc;
+};
+
+// lambda_X += (da/dX)^T nu for one source node; nu[m] indexed [mx][my][mz]
+__device__ inline void coeff_jacobian_t(const float q[kMom], float omega, const float nu[3][3][3], float lam[kMom]) {
+  const float drho = q[0];
+  const float rho = 1.0f + drho;
+  const float u[3] = {q[1], q[2], q[3]};
+  const float w1 = 1.0f - omega;
+  float sp[3][3];
+  sp[0][0] = q[4] + omega * (u[0] * u[0] - q[4]);
+  sp[1][1] = q[5] + omega * (u[1] * u[1] - q[5]);
+  sp[2][2] = q[6] + omega * (u[2] * u[2] - q[6]);
+  sp[0][1] = sp[1][0] = q[7] + omega * (u[0] * u[1] - q[7]);
+  sp[0][2] = sp[2][0] = q[8] + omega * (u[0] * u[2] - q[8]);
+  sp[1][2] = sp[2][1] = q[9] + omega * (u[1] * u[2] - q[9]);
+  // unit vectors of the per-axis index for the coefficient (a, a, b) of Gamma_aab:
+  // index 2 on axis a, 1 on axis b
+  float ub[3], spb[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  float drb = nu[0][0][0];
+  // first-order coefficients 3 rho u_a
+  const float n1[3] = {nu[1][0][0], nu[0][1][0], nu[0][0][1]};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ub[a] = 3.0f * rho * n1[a];
+    drb += 3.0f * u[a] * n1[a];
+  }
+  // diagonal second-order 1.5 rho Sp_aa
+  const float n2[3] = {nu[2][0][0], nu[0][2][0], nu[0][0][2]};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    spb[a][a] += 1.5f * rho * n2[a];
+    drb += 1.5f * sp[a][a] * n2[a];
+  }
+  // off-diagonal second-order 9 rho Sp_ab
+  const float n11[3] = {nu[1][1][0], nu[1][0][1], nu[0][1][1]};
+  const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    spb[pa[k]][pb[k]] += 9.0f * rho * n11[k];
+    drb += 9.0f * sp[pa[k]][pb[k]] * n11[k];
+  }
+  // third order 4.5 rho Gamma_aab, Gamma_aab = Sp_aa u_b + 2 Sp_ab u_a - 2 u_a^2 u_b
+  const int ga[6] = {0, 1, 0, 2, 1, 2}, gb[6] = {1, 0, 2, 0, 2, 1};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int a = ga[k], b = gb[k];
+    int idx[3] = {0, 0, 0};
+    idx[a] = 2;
+    idx[b] = 1;
+    const float n3 = nu[idx[0]][idx[1]][idx[2]];
+    const float gam = sp[a][a] * u[b] + 2.0f * sp[a][b] * u[a] - 2.0f * u[a] * u[a] * u[b];
+    drb += 4.5f * gam * n3;
+    const float gbar = 4.5f * rho * n3;
+    spb[a][a] += gbar * u[b];
+    ub[b] += gbar * (sp[a][a] - 2.0f * u[a] * u[a]);
+    spb[a < b ? a : b][a < b ? b : a] += 2.0f * gbar * u[a];
+    ub[a] += gbar * (2.0f * sp[a][b] - 4.0f * u[a] * u[b]);
+  }
+  // 27 rho Gamma_xyz, Gamma_xyz = Sp_xy u_z + Sp_xz u_y + Sp_yz u_x - 2 u_x u_y u_z
+  {
+    const float n3 = nu[1][1][1];
+    const float gam = sp[0][1] * u[2] + sp[0][2] * u[1] + sp[1][2] * u[0] - 2.0f * u[0] * u[1] * u[2];
+    drb += 27.0f * gam * n3;
+    const float gbar = 27.0f * rho * n3;
+    spb[0][1] += gbar * u[2];
+    spb[0][2] += gbar * u[1];
+    spb[1][2] += gbar * u[0];
+    ub[2] += gbar * (sp[0][1] - 2.0f * u[0] * u[1]);
+    ub[1] += gbar * (sp[0][2] - 2.0f * u[0] * u[2]);
+    ub[0] += gbar * (sp[1][2] - 2.0f * u[1] * u[2]);
+  }
+  // collision Sp = (1 - omega) S + omega u u
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ub[a] += 2.0f * omega * u[a] * spb[a][a];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float g = spb[pa[k]][pb[k]];
+    ub[pa[k]] += omega * u[pb[k]] * g;
+    ub[pb[k]] += omega * u[pa[k]] * g;
+  }
+  lam[0] += drb;
+  lam[1] += ub[0]; lam[2] += ub[1]; lam[3] += ub[2];
+  lam[4] += w1 * spb[0][0]; lam[5] += w1 * spb[1][1]; lam[6] += w1 * spb[2][2];
+  lam[7] += w1 * spb[0][1]; lam[8] += w1 * spb[0][2]; lam[9] += w1 * spb[1][2];
+}
+
+// transpose of the bounce-back correction of one computed node: the node's own
+// coefficients receive, for every direction c whose source x - c is solid (or
+// behind a wall), w_c (mu . e(c)) times the basis values at the outgoing -c
+template <class S>
+__device__ void bounce_back_t(const TrArgs<S>& a, int slot, int lx, int ly, int lz, float nu[3][3][3]) {
+  const int32_t* nbr = a.nbr + (size_t)slot * 27;
+  const int node = lx + 8 * ly + 64 * lz;
+  const float* mp = a.mu + (size_t)slot * kBlockStride + node;
+  float g[kMom];
+#pragma unroll
+  for (int m = 0; m < kMom; ++m) g[m] = mp[m * kNodes];
+#pragma unroll 1
+  for (int i = 0; i < 27; ++i) {
+    if (i == 13) continue;
+    const int cx = i % 3 - 1, cy = (i / 3) % 3 - 1, cz = i / 9 - 1;
+    const int hx = lx - cx, hy = ly - cy, hz = lz - cz;
+    const int ox = hx < 0 ? -1 : (hx > 7 ? 1 : 0);
+    const int oy = hy < 0 ? -1 : (hy > 7 ? 1 : 0);
+    const int oz = hz < 0 ? -1 : (hz > 7 ? 1 : 0);
+    const int ns = nbr[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)];
+    bool solid = (ns == NBR_WALL);
+    if (ns >= 0) solid = (a.role[(size_t)ns * kNodes + (hx & 7) + 8 * (hy & 7) + 64 * (hz & 7)] & ROLE_MASK) == ROLE_SOLID;
+    if (!solid) continue;
+    const float fx = (float)cx, fy = (float)cy, fz = (float)cz;
+    const float pe = g[0] + g[1] * fx + g[2] * fy + g[3] * fz + g[4] * (3.0f * fx * fx - 1.0f)
+                     + g[5] * (3.0f * fy * fy - 1.0f) + g[6] * (3.0f * fz * fz - 1.0f) + g[7] * fx * fy
+                     + g[8] * fx * fz + g[9] * fy * fz;
+    const float w = (cx ? 1.0f : 4.0f) * (cy ? 1.0f : 4.0f) * (cz ? 1.0f : 4.0f);
+    const float fb = w * pe;
+    const float px[3] = {1.0f, -fx, 3.0f * fx * fx - 1.0f};
+    const float py[3] = {1.0f, -fy, 3.0f * fy * fy - 1.0f};
+    const float pz[3] = {1.0f, -fz, 3.0f * fz * fz - 1.0f};
+#pragma unroll
+    for (int mx = 0; mx < 3; ++mx)
+#pragma unroll
+      for (int my = 0; my < 3; ++my)
+#pragma unroll
+        for (int mz = 0; mz < 3; ++mz) nu[mx][my][mz] += fb * px[mx] * py[my] * pz[mz];
+  }
+}
+
+// LDS plane rows as in the forward sweep: row r = plane row y + 1
+//   x-pass input: [kind][col 0..9][group 0..5]   (180 floats)
+//   y-pass input: [kind][col 0..7][triple 0..8, pad 10] (240 floats)
+constexpr int kRowT = 240;
+__device__ __forceinline__ int ta_off(int row, int kind, int col) { return row * kRowT + kind * 60 + col * 6; }
+__device__ __forceinline__ int tb_off(int row, int kind, int col) { return row * kRowT + kind * 80 + col * 10; }
+
+__device__ __forceinline__ bool plane_point_t(int lane, int r, int& px, int& py) {
+  if (r == 0) { px = lane & 7; py = lane >> 3; return true; }
+  if (lane < 10) { px = lane - 1; py = -1; return true; }
+  if (lane < 20) { px = lane - 11; py = 8; return true; }
+  if (lane < 28) { px = -1; py = lane - 20; return true; }
+  if (lane < 36) { px = 8; py = lane - 28; return true; }
+  return false;
+}
+
+__device__ __forceinline__ void x_pass_t(const float* lds, int row, int x, float yb[27]) {
+  float E[3][6];
+#pragma unroll
+  for (int g = 0; g < 6; ++g) {
+    const float pp = lds[ta_off(row, 0, x + 2) + g];  // P+ of column x+1
+    const float pz = lds[ta_off(row, 1, x + 1) + g];  // P0 of column x
+    const float pm = lds[ta_off(row, 2, x) + g];      // P- of column x-1
+    fwd3_t(pp, pz, pm, E[0][g], E[1][g], E[2][g]);
+  }
+  // (qy, qz) groups: 0 (0,0), 1 (1,0), 2 (0,1), 3 (2,0), 4 (0,2), 5 (1,1)
+#pragma unroll
+  for (int mx = 0; mx < 3; ++mx) {
+    float pp, pz, pm;
+    back3_t(E[mx][0], E[mx][1], E[mx][3], pp, pz, pm);  // qz = 0, qy = 0,1,2
+    yb[3 * mx + 0] = pp; yb[9 + 3 * mx + 0] = pz; yb[18 + 3 * mx + 0] = pm;
+    back3_t(E[mx][2], E[mx][5], 0.0f, pp, pz, pm);      // qz = 1, qy = 0,1
+    yb[3 * mx + 1] = pp; yb[9 + 3 * mx + 1] = pz; yb[18 + 3 * mx + 1] = pm;
+    back3_t(E[mx][4], 0.0f, 0.0f, pp, pz, pm);          // qz = 2, qy = 0
+    yb[3 * mx + 2] = pp; yb[9 + 3 * mx + 2] = pz; yb[18 + 3 * mx + 2] = pm;
+  }
+}
+
+__device__ __forceinline__ int xcd_remap_t(int bid, int n) {
+  const int per = n >> 3, rem = n & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+template <class S>
+__global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
+  __shared__ __align__(16) float lds[10 * kRowT];
+  __shared__ int s_src[27];
+  const int lane = threadIdx.x;
+  const int slot = a.blocks[xcd_remap_t(blockIdx.x, a.nblocks)];
+  if (lane < 27) {
+    const int ns = a.nbr[(size_t)slot * 27 + lane];
+    s_src[lane] = ns >= 0 ? ns : a.zero_slot;
+  }
+  __syncthreads();
+  int px[2], py[2];
+  bool has[2];
+  has[0] = plane_point_t(lane, 0, px[0], py[0]);
+  has[1] = plane_point_t(lane, 1, px[1], py[1]);
+  const int ox = lane & 7, oy = lane >> 3;
+
+  // z window over the 8 (mx, my) pairs: P0 of plane z-1, P- of planes z-1 and z-2
+  float w0[8], wm1[8], wm2[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) w0[k] = wm1[k] = wm2[k] = 0.0f;
+  const int pmx[8] = {0, 1, 2, 0, 1, 2, 0, 1};
+  const int pmy[8] = {0, 0, 0, 1, 1, 1, 2, 2};
+
+  for (int z = -1; z <= 8; ++z) {
+    // ---- mu of plane z (+ halo) -> transposed x back-map per (qy, qz) group
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (!has[r]) continue;
+      const int ox_ = px[r] < 0 ? -1 : (px[r] > 7 ? 1 : 0);
+      const int oy_ = py[r] < 0 ? -1 : (py[r] > 7 ? 1 : 0);
+      const int oz_ = z < 0 ? -1 : (z > 7 ? 1 : 0);
+      const int ns = s_src[(ox_ + 1) + 3 * (oy_ + 1) + 9 * (oz_ + 1)];
+      const float* src = a.mu + (size_t)ns * kBlockStride + (px[r] & 7) + 8 * (py[r] & 7) + 64 * (z & 7);
+      float m[kMom];
+#pragma unroll
+      for (int k = 0; k < kMom; ++k) m[k] = src[k * kNodes];
+      float P[3][6];
+      back3_t(m[0], m[1], m[4], P[0][0], P[1][0], P[2][0]);  // (qy,qz) = (0,0): mu000, mu100, mu200
+      back3_t(m[2], m[7], 0.0f, P[0][1], P[1][1], P[2][1]);  // (1,0): mu010, mu110
+      back3_t(m[3], m[8], 0.0f, P[0][2], P[1][2], P[2][2]);  // (0,1): mu001, mu101
+      back3_t(m[5], 0.0f, 0.0f, P[0][3], P[1][3], P[2][3]);  // (2,0): mu020
+      back3_t(m[6], 0.0f, 0.0f, P[0][4], P[1][4], P[2][4]);  // (0,2): mu002
+      back3_t(m[9], 0.0f, 0.0f, P[0][5], P[1][5], P[2][5]);  // (1,1): mu011
+      const int row = py[r] + 1, col = px[r] + 1;
+#pragma unroll
+      for (int kind = 0; kind < 3; ++kind)
+#pragma unroll
+        for (int g = 0; g < 6; ++g) lds[ta_off(row, kind, col) + g] = P[kind][g];
+    }
+    __syncthreads();
+    // ---- x pass (rows 0..7, then 8..9), each row overwritten by its own y-pass input
+    {
+      float yb[27];
+      x_pass_t(lds, oy, ox, yb);
+      __syncthreads();
+#pragma unroll
+      for (int kind = 0; kind < 3; ++kind)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) lds[tb_off(oy, kind, ox) + t] = yb[9 * kind + t];
+    }
+    {
+      float yb[27];
+      const int row = 8 + (oy & 1);
+      x_pass_t(lds, row, ox, yb);
+      __syncthreads();
+      if (lane < 16) {
+#pragma unroll
+        for (int kind = 0; kind < 3; ++kind)
+#pragma unroll
+          for (int t = 0; t < 9; ++t) lds[tb_off(row, kind, ox) + t] = yb[9 * kind + t];
+      }
+    }
+    __syncthreads();
+    // ---- y pass for the owned column, then transposed z back-map per (mx, my)
+    float cp[8], cz[8], cm[8];
+    {
+      float F[3][3][3];  // [mx][my][qz]
+#pragma unroll
+      for (int mx = 0; mx < 3; ++mx)
+#pragma unroll
+        for (int qz = 0; qz < 3; ++qz) {
+          const int t = 3 * mx + qz;
+          const float pp = lds[tb_off(oy + 2, 0, ox) + t];  // P+ of row y+1
+          const float pz = lds[tb_off(oy + 1, 1, ox) + t];  // P0 of row y
+          const float pm = lds[tb_off(oy, 2, ox) + t];      // P- of row y-1
+          fwd3_t(pp, pz, pm, F[mx][0][qz], F[mx][1][qz], F[mx][2][qz]);
+        }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) back3_t(F[pmx[k]][pmy[k]][0], F[pmx[k]][pmy[k]][1], F[pmx[k]][pmy[k]][2], cp[k], cz[k], cm[k]);
+    }
+    __syncthreads();
+    // ---- z pass: source plane zo = z - 1 takes P+ of plane z, P0 of z-1, P- of z-2
+    const int zo = z - 1;
+    if (zo >= 0) {
+      const int node = ox + 8 * oy + 64 * zo;
+      const uint8_t role = a.role[(size_t)slot * kNodes + node];
+      const uint8_t rm = role & ROLE_MASK;
+      if (rm != ROLE_SOLID && rm != ROLE_INFLOW) {
+        float nu[3][3][3];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) fwd3_t(cp[k], w0[k], wm2[k], nu[pmx[k]][pmy[k]][0], nu[pmx[k]][pmy[k]][1], nu[pmx[k]][pmy[k]][2]);
+        nu[2][2][0] = nu[2][2][1] = nu[2][2][2] = 0.0f;
+        if (rm == ROLE_COMPUTED && (role & ROLE_BB)) bounce_back_t<S>(a, slot, ox, oy, zo, nu);
+        const typename S::type* xs = a.x + (size_t)slot * kBlockStride + node;
+        float q[kMom];
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(xs[m * kNodes], a.sc.inv[m]);
+        float* lam = a.lam_x + (size_t)slot * kBlockStride + node;
+        float L[kMom];
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) L[m] = lam[m * kNodes];
+        coeff_jacobian_t(q, a.omega, nu, L);
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) lam[m * kNodes] = L[m];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      wm2[k] = wm1[k];
+      wm1[k] = cm[k];
+      w0[k] = cz[k];
+    }
+  }
+}
+
+// ---- downward transfer, transposed --------------------------------------------
+// (a) per ghost node: adjoint of the ghost moments -> adjoint of its interpolated
+//     (rho-1, u, S^neq) (the u u term needs the interpolated u); ghost adjoint cleared
+template <class S>
+__global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
+  __shared__ float cu[3][125];
+  const int slot = a.blocks[blockIdx.x];
+  const int4 bc = a.coord[slot];
+  const int l = a.level;
+  const LevelGeom& cg = a.G.lv[l + 1];
+  const int base[3] = {4 * bc.x, 4 * bc.y, 4 * bc.z};
+  typedef typename S::type T;
+  for (int t = threadIdx.x; t < 125; t += 256) {
+    int j[3] = {base[0] + t % 5, base[1] + (t / 5) % 5, base[2] + t / 25};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int nc = cg.nn[ax];
+      if (a.G.periodic[ax]) j[ax] = j[ax] >= nc ? j[ax] - nc : j[ax];
+      else j[ax] = j[ax] >= nc ? nc - 1 : j[ax];
+    }
+    const int cs = a.dir[cg.off + cell_lin(cg, j[0] >> 3, j[1] >> 3, j[2] >> 3)];
+    float u[3] = {0.0f, 0.0f, 0.0f};
+    if (cs >= 0) {
+      const int cn = (j[0] & 7) + 8 * (j[1] & 7) + 64 * (j[2] & 7);
+      const T* pa = static_cast<const T*>(a.src_a) + (size_t)cs * kBlockStride + cn;
+      const T* pb = static_cast<const T*>(a.src_b) + (size_t)cs * kBlockStride + cn;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        u[k] = Codec<S>::load(pa[(1 + k) * kNodes], a.sc.inv[1 + k]);
+        if (a.midpoint) u[k] = 0.5f * (u[k] + Codec<S>::load(pb[(1 + k) * kNodes], a.sc.inv[1 + k]));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) cu[k][t] = u[k];
+  }
+  __syncthreads();
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_GHOST) continue;
+    const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
+    float ug[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int kx = c & 1, ky = (c >> 1) & 1, kz = c >> 2;
+      const float wx = (lc[0] & 1) ? 0.5f : (kx ? 0.0f : 1.0f);
+      const float wy = (lc[1] & 1) ? 0.5f : (ky ? 0.0f : 1.0f);
+      const float wz = (lc[2] & 1) ? 0.5f : (kz ? 0.0f : 1.0f);
+      const float w = wx * wy * wz;
+      if (w == 0.0f) continue;
+      const int t = ((lc[0] + kx) >> 1) + 5 * ((lc[1] + ky) >> 1) + 25 * ((lc[2] + kz) >> 1);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ug[k] += w * cu[k][t];
+    }
+    float* lam = a.lam_fine + (size_t)slot * kBlockStride + node;
+    float L[kMom];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) L[m] = lam[m * kNodes];
+    float* out = a.scratch + (size_t)slot * kBlockStride + node;
+    out[0] = L[0];
+    out[kNodes * 1] = L[1] + 2.0f * L[4] * ug[0] + L[7] * ug[1] + L[8] * ug[2];
+    out[kNodes * 2] = L[2] + 2.0f * L[5] * ug[1] + L[7] * ug[0] + L[9] * ug[2];
+    out[kNodes * 3] = L[3] + 2.0f * L[6] * ug[2] + L[8] * ug[0] + L[9] * ug[1];
+#pragma unroll
+    for (int m = 4; m < kMom; ++m) out[m * kNodes] = a.factor * L[m];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) lam[m * kNodes] = 0.0f;
+  }
+}
+
+// (b) per coarse node: gather the lin-adjoints of every ghost whose stencil holds it
+template <class S>
+__global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
+  const int cslot = a.blocks[blockIdx.x];
+  const int4 bc = a.coord[cslot];
+  const int l = a.level;
+  const LevelGeom& fg = a.G.lv[l];
+  const LevelGeom& cg = a.G.lv[l + 1];
+  typedef typename S::type T;
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    const int j[3] = {bc.x * kEdge + (node & 7), bc.y * kEdge + ((node >> 3) & 7), bc.z * kEdge + (node >> 6)};
+    float acc[kMom];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
+    bool any = false;
+    for (int d = 0; d < 27; ++d) {
+      int p[3] = {2 * j[0] + d % 3 - 1, 2 * j[1] + (d / 3) % 3 - 1, 2 * j[2] + d / 9 - 1};
+      bool ok = true;
+      float w = 1.0f;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const int nf = fg.nn[ax], nc = cg.nn[ax];
+        if (p[ax] < 0 || p[ax] >= nf) {
+          if (!a.G.periodic[ax]) { ok = false; break; }
+          p[ax] = p[ax] < 0 ? p[ax] + nf : p[ax] - nf;
+        }
+        // the forward stencil of fine p along this axis and the weight it gives j
+        int c0, c1;
+        float w0, w1;
+        if ((p[ax] & 1) == 0) { c0 = c1 = p[ax] >> 1; w0 = 1.0f; w1 = 0.0f; }
+        else { c0 = (p[ax] - 1) >> 1; c1 = (p[ax] + 1) >> 1; w0 = w1 = 0.5f; }
+        if (a.G.periodic[ax]) { c1 = c1 >= nc ? c1 - nc : c1; }
+        else { c1 = c1 >= nc ? nc - 1 : c1; }
+        const float wa = (c0 == j[ax] ? w0 : 0.0f) + (c1 == j[ax] ? w1 : 0.0f);
+        w *= wa;
+      }
+      if (!ok || w == 0.0f) continue;
+      const int fs = a.dir[fg.off + cell_lin(fg, p[0] >> 3, p[1] >> 3, p[2] >> 3)];
+      if (fs < 0) continue;
+      const int fn = (p[0] & 7) + 8 * (p[1] & 7) + 64 * (p[2] & 7);
+      if ((a.role[(size_t)fs * kNodes + fn] & ROLE_MASK) != ROLE_GHOST) continue;
+      const float* src = a.scratch + (size_t)fs * kBlockStride + fn;
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) acc[m] += w * src[m * kNodes];
+      any = true;
+    }
+    if (!any) continue;
+    // time levels: s = 1 uses coarse t only; s = 2 averages t and t + 2
+    for (int tl = 0; tl < (a.midpoint ? 2 : 1); ++tl) {
+      const float c = a.midpoint ? 0.5f : 1.0f;
+      const T* qs = static_cast<const T*>(tl == 0 ? a.src_a : a.src_b) + (size_t)cslot * kBlockStride + node;
+      float* lam = (tl == 0 ? a.lam_coarse_a : a.lam_coarse_b) + (size_t)cslot * kBlockStride + node;
+      float u[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) u[k] = Codec<S>::load(qs[(1 + k) * kNodes], a.sc.inv[1 + k]);
+      // lin = (rho-1, u, S - u u)
+      float g[kMom];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) g[m] = c * acc[m];
+      const float gu0 = g[1] - (2.0f * g[4] * u[0] + g[7] * u[1] + g[8] * u[2]);
+      const float gu1 = g[2] - (2.0f * g[5] * u[1] + g[7] * u[0] + g[9] * u[2]);
+      const float gu2 = g[3] - (2.0f * g[6] * u[2] + g[8] * u[0] + g[9] * u[1]);
+      lam[0] += g[0];
+      lam[kNodes] += gu0;
+      lam[2 * kNodes] += gu1;
+      lam[3 * kNodes] += gu2;
+#pragma unroll
+      for (int m = 4; m < kMom; ++m) lam[m * kNodes] += g[m];
+    }
+  }
+}
+
+// ---- upward transfer, transposed ------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(256) void k_up_adj(AdjTransferLaunch a) {
+  const int slot = a.blocks[blockIdx.x];
+  const int4 bc = a.coord[slot];
+  const LevelGeom& fg = a.G.lv[a.level];
+  typedef typename S::type T;
+  const float f = a.factor;
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_IU) continue;
+    const int p[3] = {2 * (bc.x * kEdge + (node & 7)), 2 * (bc.y * kEdge + ((node >> 3) & 7)), 2 * (bc.z * kEdge + (node >> 6))};
+    const int fs = a.dir[fg.off + cell_lin(fg, p[0] >> 3, p[1] >> 3, p[2] >> 3)];
+    if (fs < 0) continue;
+    const int fn = (p[0] & 7) + 8 * (p[1] & 7) + 64 * (p[2] & 7);
+    float* lq = a.lam_coarse_a + (size_t)slot * kBlockStride + node;
+    float L[kMom];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) { L[m] = lq[m * kNodes]; lq[m * kNodes] = 0.0f; }
+    const T* qs = static_cast<const T*>(a.src_a) + (size_t)fs * kBlockStride + fn;
+    float u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = Codec<S>::load(qs[(1 + k) * kNodes], a.sc.inv[1 + k]);
+    // S_q = f S_f + (1 - f) u_f u_f
+    const float h = 1.0f - f;
+    float* lf = a.lam_fine + (size_t)fs * kBlockStride + fn;
+    lf[0] += L[0];
+    lf[kNodes] += L[1] + h * (2.0f * L[4] * u[0] + L[7] * u[1] + L[8] * u[2]);
+    lf[2 * kNodes] += L[2] + h * (2.0f * L[5] * u[1] + L[7] * u[0] + L[9] * u[2]);
+    lf[3 * kNodes] += L[3] + h * (2.0f * L[6] * u[2] + L[8] * u[0] + L[9] * u[1]);
+#pragma unroll
+    for (int m = 4; m < kMom; ++m) lf[m * kNodes] += f * L[m];
+  }
+}
+
+// ---- zero-gradient outflow copy, transposed -----------------------------------
+// Phase 1: every outflow node hands its adjoint either to its inward computed
+// neighbour (through LDS) or to its own old value. Phase 2: every computed node
+// collects from the outflow nodes that copied it (at most one per face).
+__device__ inline int outflow_src(const Geom& G, const LevelGeom& lg, const int4 bc, const uint8_t* role, int node) {
+  const int g[3] = {bc.x * kEdge + (node & 7), bc.y * kEdge + ((node >> 3) & 7), bc.z * kEdge + (node >> 6)};
+  int step = 0;
+  for (int ax = 0; ax < 3 && step == 0; ++ax) {
+    if (G.periodic[ax]) continue;
+    const int stride = ax == 0 ? 1 : (ax == 1 ? 8 : 64);
+    if (g[ax] == 0 && G.bc[2 * ax] == BC_OUTFLOW) step = stride;
+    else if (g[ax] == lg.nn[ax] - 1 && G.bc[2 * ax + 1] == BC_OUTFLOW) step = -stride;
+  }
+  if (step == 0) return -1;
+  const int src = node + step;
+  return (role[src] & ROLE_MASK) == ROLE_COMPUTED ? src : -1;
+}
+
+__global__ __launch_bounds__(256) void k_outflow_adj(AdjTransferLaunch a) {
+  __shared__ float sv[kMom][kNodes];
+  __shared__ int16_t sdst[kNodes];
+  const int slot = a.blocks[blockIdx.x];
+  const int4 bc = a.coord[slot];
+  const LevelGeom& lg = a.G.lv[a.level];
+  const uint8_t* role = a.role + (size_t)slot * kNodes;
+  float* ly = a.lam_coarse_a + (size_t)slot * kBlockStride;  // adjoint of the new time level
+  float* lx = a.lam_fine + (size_t)slot * kBlockStride;      // adjoint of the old time level
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    int dst = -1;
+    if ((role[node] & ROLE_MASK) == ROLE_OUTFLOW) {
+      dst = outflow_src(a.G, lg, bc, role, node);
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) {
+        const float v = ly[m * kNodes + node];
+        ly[m * kNodes + node] = 0.0f;
+        sv[m][node] = v;
+        if (dst < 0) lx[m * kNodes + node] += v;
+      }
+    }
+    sdst[node] = (int16_t)dst;
+  }
+  __syncthreads();
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    if ((role[node] & ROLE_MASK) != ROLE_COMPUTED) continue;
+    const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
+    float acc[kMom];
+    bool any = false;
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int ax = f >> 1, sgn = (f & 1) ? 1 : -1;
+      const int c = lc[ax] + sgn;
+      if (c < 0 || c > 7) continue;
+      const int nb = node + sgn * (ax == 0 ? 1 : (ax == 1 ? 8 : 64));
+      if (sdst[nb] != node) continue;
+      any = true;
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) acc[m] += sv[m][nb];
+    }
+    if (any) {
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) ly[m * kNodes + node] += acc[m];
+    }
+  }
+}
+
+// ---- loss L = 1/2 sum rho |u|^2 over owned nodes in a fine-unit box: dL/dQ ------
+// Inflow nodes count in the loss but hold fixed values: their entry stays zero.
+template <class S>
+__global__ __launch_bounds__(256) void k_loss_ke_grad(AdjTransferLaunch a, float* out, int lx, int ly, int lz, int hx,
+                                                      int hy, int hz) {
+  const int slot = a.blocks[blockIdx.x];
+  const int4 c = a.coord[slot];
+  typedef typename S::type T;
+  const T* q = static_cast<const T*>(a.src_a) + (size_t)slot * kBlockStride;
+  float* lam = out + (size_t)blockIdx.x * kBlockStride;
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    const uint8_t r = a.role[(size_t)slot * kNodes + node] & ROLE_MASK;
+    const int64_t fx = (int64_t)(c.x * kEdge + (node & 7)) << a.level;
+    const int64_t fy = (int64_t)(c.y * kEdge + ((node >> 3) & 7)) << a.level;
+    const int64_t fz = (int64_t)(c.z * kEdge + (node >> 6)) << a.level;
+    const bool in = fx >= lx && fx < hx && fy >= ly && fy < hy && fz >= lz && fz < hz;
+    const bool st = r == ROLE_COMPUTED || r == ROLE_IU || r == ROLE_OUTFLOW;
+    float g[kMom];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) g[m] = 0.0f;
+    if (in && st) {
+      const float rho = 1.0f + Codec<S>::load(q[node], a.sc.inv[0]);
+      float u[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) u[k] = Codec<S>::load(q[(1 + k) * kNodes + node], a.sc.inv[1 + k]);
+      g[0] = 0.5f * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) g[1 + k] = rho * u[k];
+    }
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) lam[m * kNodes + node] = g[m];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lam_scatter(const float* in, float* lam, const int32_t* blocks,
+                                                     const uint8_t* role) {
+  const int32_t slot = blocks[blockIdx.x];
+  const float* src = in + (size_t)blockIdx.x * kBlockStride;
+  float* dst = lam + (size_t)slot * kBlockStride;
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    const uint8_t r = role[(size_t)slot * kNodes + node] & ROLE_MASK;
+    const bool st = r == ROLE_COMPUTED || r == ROLE_IU || r == ROLE_OUTFLOW;
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) dst[m * kNodes + node] = st ? src[m * kNodes + node] : 0.0f;
+  }
+}
+
+__global__ void k_zero_blocks(float* buf, const int32_t* blocks, int32_t n) {
+  const int32_t slot = blocks[blockIdx.x];
+  float* p = buf + (size_t)slot * kBlockStride;
+  for (int i = threadIdx.x; i < kBlockStride; i += blockDim.x) p[i] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_gather_blocks(const uint4* src, uint4* dst, const int32_t* blocks,
+                                                       int32_t per_block) {
+  const uint4* s = src + (size_t)blocks[blockIdx.x] * per_block;
+  uint4* d = dst + (size_t)blockIdx.x * per_block;
+  for (int i = threadIdx.x; i < per_block; i += 256) d[i] = s[i];
+}
+__global__ __launch_bounds__(256) void k_scatter_blocks(const uint4* src, uint4* dst, const int32_t* blocks,
+                                                        int32_t per_block) {
+  const uint4* s = src + (size_t)blockIdx.x * per_block;
+  uint4* d = dst + (size_t)blocks[blockIdx.x] * per_block;
+  for (int i = threadIdx.x; i < per_block; i += 256) d[i] = s[i];
+}
+__global__ void k_write_words(uint64_t* dst, Words8 w) {
+  if (threadIdx.x < 8) dst[threadIdx.x] = w.v[threadIdx.x];
+}
+
+template <class S> hipError_t tr_t(const AdjScLaunch& l, hipStream_t s) {
+  if (l.nblocks <= 0) return hipSuccess;
+  TrArgs<S> a;
+  a.x = static_cast<const typename S::type*>(l.x);
+  a.mu = l.mu;
+  a.lam_x = l.lam_x;
+  a.blocks = l.blocks;
+  a.nbr = l.nbr;
+  a.role = l.role;
+  a.nblocks = l.nblocks;
+  a.zero_slot = l.zero_slot;
+  a.omega = l.omega;
+  a.sc = l.sc;
+  hipLaunchKernelGGL(k_sc_transpose<S>, dim3(l.nblocks), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+template <template <class> class K>
+hipError_t dispatch_adj(const AdjTransferLaunch& a, hipStream_t s) {
+  if (a.nblocks <= 0) return hipSuccess;
+  switch (a.storage) {
+    case 0: hipLaunchKernelGGL(K<StoreF32>::fn, dim3(a.nblocks), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(K<StoreBF16>::fn, dim3(a.nblocks), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(K<StoreF16>::fn, dim3(a.nblocks), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+template <class S> struct DownLinK { static constexpr auto fn = k_down_adj_lin<S>; };
+template <class S> struct DownGatherK { static constexpr auto fn = k_down_adj_gather<S>; };
+template <class S> struct UpAdjK { static constexpr auto fn = k_up_adj<S>; };
+
+}  // namespace
+
+hipError_t launch_sc_transpose(const AdjScLaunch& l, hipStream_t s) {
+  switch (l.storage) {
+    case 0: return tr_t<StoreF32>(l, s);
+    case 1: return tr_t<StoreBF16>(l, s);
+    case 2: return tr_t<StoreF16>(l, s);
+  }
+  return hipErrorInvalidValue;
+}
+hipError_t launch_down_adj_lin(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<DownLinK>(a, s); }
+hipError_t launch_down_adj_gather(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<DownGatherK>(a, s); }
+hipError_t launch_up_adj(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<UpAdjK>(a, s); }
+hipError_t launch_outflow_adj(const AdjTransferLaunch& a, hipStream_t s) {
+  if (a.nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_outflow_adj, dim3(a.nblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_loss_ke_grad(const AdjTransferLaunch& a, float* out, const int32_t lo[3], const int32_t hi[3],
+                               hipStream_t s) {
+  if (a.nblocks <= 0) return hipSuccess;
+  switch (a.storage) {
+    case 0: hipLaunchKernelGGL(k_loss_ke_grad<StoreF32>, dim3(a.nblocks), dim3(256), 0, s, a, out, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]); break;
+    case 1: hipLaunchKernelGGL(k_loss_ke_grad<StoreBF16>, dim3(a.nblocks), dim3(256), 0, s, a, out, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]); break;
+    case 2: hipLaunchKernelGGL(k_loss_ke_grad<StoreF16>, dim3(a.nblocks), dim3(256), 0, s, a, out, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+hipError_t launch_lam_scatter(const float* in, float* lam, const int32_t* blocks, const uint8_t* role, int32_t n,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lam_scatter, dim3(n), dim3(256), 0, s, in, lam, blocks, role);
+  return hipGetLastError();
+}
+hipError_t launch_zero_blocks(float* buf, const int32_t* blocks, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_blocks, dim3(n), dim3(256), 0, s, buf, blocks, n);
+  return hipGetLastError();
+}
+hipError_t launch_gather_blocks(const void* src, void* dst, const int32_t* blocks, int32_t n, size_t block_bytes,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (block_bytes % 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather_blocks, dim3(n), dim3(256), 0, s, static_cast<const uint4*>(src),
+                     static_cast<uint4*>(dst), blocks, (int32_t)(block_bytes / 16));
+  return hipGetLastError();
+}
+hipError_t launch_scatter_blocks(const void* src, void* dst, const int32_t* blocks, int32_t n, size_t block_bytes,
+                                 hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (block_bytes % 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scatter_blocks, dim3(n), dim3(256), 0, s, static_cast<const uint4*>(src),
+                     static_cast<uint4*>(dst), blocks, (int32_t)(block_bytes / 16));
+  return hipGetLastError();
+}
+hipError_t launch_write_words(uint64_t* dst, Words8 w, hipStream_t s) {
+  hipLaunchKernelGGL(k_write_words, dim3(1), dim3(64), 0, s, dst, w);
+  return hipGetLastError();
+}
+
+}  // namespace lbmx

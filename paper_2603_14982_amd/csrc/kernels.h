@@ -19,7 +19,7 @@ struct ScLaunch {
   float omega;
   Scales sc;
   int storage;
-  const float* lam_y = nullptr;  // adjoint epilogue: adjoint of the outputs (f32 pool layout)
+  float* lam_y = nullptr;        // adjoint epilogue: adjoint of the outputs (f32 pool layout)
   float* mu = nullptr;           // adjoint epilogue: adjoint of the scaled moments M
 };
 hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s);
@@ -164,5 +164,67 @@ hipError_t launch_reduce(const IoLaunch& a, const int32_t lo[3], const int32_t h
                          double* out, hipStream_t s);
 hipError_t launch_finite(const IoLaunch& a, int32_t* flag, hipStream_t s);
 hipError_t launch_advance_particles(float* p, int64_t n, float dx, float dy, float dz, hipStream_t s);
+
+// ---- adjoint (reverse mode) ----
+// transposed stream + projection of one level: lam_x += (da/dX)^T L^T mu
+struct AdjScLaunch {
+  const void* x;             // forward input time level (storage type)
+  const float* mu;           // adjoint of the scaled moments M (f32 pool layout, zero at zero_slot)
+  float* lam_x;              // adjoint of the input time level (f32 pool layout), accumulated
+  const int32_t* blocks;
+  int32_t nblocks;
+  const int32_t* nbr;
+  const uint8_t* role;
+  int32_t zero_slot;
+  float omega;
+  Scales sc;
+  int storage;
+};
+hipError_t launch_sc_transpose(const AdjScLaunch& a, hipStream_t s);
+
+struct AdjTransferLaunch {
+  Geom G;
+  int level;                 // fine level l
+  const int32_t* blocks;     // blocks visited (see each launcher)
+  int32_t nblocks;
+  const int32_t* dir;
+  const uint8_t* role;
+  const int4* coord;
+  const void* src_a;         // forward sources (down: coarse t and t + 2; up: fine current)
+  const void* src_b;
+  float factor;
+  int midpoint;
+  Scales sc;
+  int storage;
+  float* lam_fine;           // adjoint of the level-l time level involved
+  float* lam_coarse_a;       // adjoint of the level-(l+1) time level src_a (up: the target)
+  float* lam_coarse_b;       // adjoint of the level-(l+1) time level src_b
+  float* scratch;            // per-ghost adjoint of the interpolated quantities (pool layout)
+};
+// downward transfer: (a) over the ghost blocks of level l, (b) over the blocks of level l+1
+hipError_t launch_down_adj_lin(const AdjTransferLaunch& a, hipStream_t s);
+hipError_t launch_down_adj_gather(const AdjTransferLaunch& a, hipStream_t s);
+// upward transfer over the interface blocks of level l+1
+hipError_t launch_up_adj(const AdjTransferLaunch& a, hipStream_t s);
+// outflow copy over the outflow blocks of a level: lam_coarse_a = adjoint of the new
+// time level, lam_fine = adjoint of the old one
+hipError_t launch_outflow_adj(const AdjTransferLaunch& a, hipStream_t s);
+// d(1/2 sum rho |u|^2)/d(moments) over the owned nodes of the level inside a fine-unit
+// box, written per block in key order (out[i] for blocks[i]) from the time level src_a
+hipError_t launch_loss_ke_grad(const AdjTransferLaunch& a, float* out, const int32_t lo[3], const int32_t hi[3],
+                               hipStream_t s);
+// adjoint given per block in key order -> pool layout at the state nodes (computed,
+// interface, outflow), zero elsewhere
+hipError_t launch_lam_scatter(const float* in, float* lam, const int32_t* blocks, const uint8_t* role, int32_t n,
+                              hipStream_t s);
+hipError_t launch_zero_blocks(float* buf, const int32_t* blocks, int32_t n, hipStream_t s);
+// dst[i] = src[blocks[i]] / dst[blocks[i]] = src[i], whole blocks of block_bytes (multiple of 16)
+hipError_t launch_gather_blocks(const void* src, void* dst, const int32_t* blocks, int32_t n, size_t block_bytes,
+                                hipStream_t s);
+hipError_t launch_scatter_blocks(const void* src, void* dst, const int32_t* blocks, int32_t n, size_t block_bytes,
+                                 hipStream_t s);
+// eight 64-bit words written by a kernel (kernel arguments: no host buffer to keep alive)
+struct Words8 { uint64_t v[8]; };
+hipError_t launch_write_words(uint64_t* dst, Words8 w, hipStream_t s);
 
 }  // namespace lbmx

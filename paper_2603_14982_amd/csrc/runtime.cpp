@@ -152,6 +152,15 @@ struct lbm_ctx {
   std::vector<hipEvent_t> spare;
   double prof_ms[LBM_PROFILE_PHASES] = {0};
   int64_t prof_n[LBM_PROFILE_PHASES] = {0};
+  uint64_t generation = 0;  // bumped by every grid update that changes the hierarchy
+  // undo log of one coarse step replayed for the adjoint: before every operation
+  // the blocks it is about to overwrite are copied to the tape
+  enum { OP_SC = 0, OP_DOWN = 1, OP_UP = 2 };
+  struct TapeOp { int kind, level, s, pf, pc; size_t off; };
+  bool recording = false;
+  char* tape = nullptr;
+  size_t tape_cap = 0, tape_used = 0;
+  std::vector<TapeOp> ops;
 
   template <class T> T* m(size_t off) const { return reinterpret_cast<T*>(meta + off); }
   uint8_t* st(int k) const { return m<uint8_t>(lay.st[k]); }
@@ -356,6 +365,7 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
   c->hier = nh;
   c->rcur = 1 - c->rcur;
   c->free_top = top;
+  c->generation++;
   for (int l = 0; l < L; ++l) {
     CompactOut o;
     o.out[0] = c->gblocks(l);
@@ -375,6 +385,25 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
   return LBM_OK;
 }
 
+size_t block_bytes(const lbm_ctx* c) { return (size_t)kBlockStride * c->elem; }
+
+// undo-log entry: the n blocks of `blocks` in time level `buf`, before operation op
+lbm_status record(lbm_ctx* c, int kind, int l, int s, const int32_t* blocks, int64_t n, const void* buf) {
+  const size_t bytes = (size_t)n * block_bytes(c);
+  if (c->tape_used + bytes > c->tape_cap) return c->fail(LBM_ECAPACITY, "adjoint tape too small");
+  lbm_ctx::TapeOp op;
+  op.kind = kind;
+  op.level = l;
+  op.s = s;
+  op.pf = c->parity[l];
+  op.pc = l + 1 < c->G.L ? c->parity[l + 1] : 0;
+  op.off = c->tape_used;
+  HIPCHK(c, launch_gather_blocks(buf, c->tape + c->tape_used, blocks, (int32_t)n, block_bytes(c), c->stream));
+  c->tape_used += bytes;
+  c->ops.push_back(op);
+  return LBM_OK;
+}
+
 // ---- Alg. 1 (Sec. 5.3) ----
 lbm_status sc_level(lbm_ctx* c, int l) {
   ScLaunch a;
@@ -388,6 +417,10 @@ lbm_status sc_level(lbm_ctx* c, int l) {
   a.omega = (float)(1.0 / c->tau[l]);
   a.sc = c->sc;
   a.storage = c->cfg.storage;
+  if (c->recording) {
+    lbm_status st = record(c, lbm_ctx::OP_SC, l, 0, c->blocks(l), c->nblk[l], c->other(l));
+    if (st != LBM_OK) return st;
+  }
   const int k = c->tic(LBM_PROF_SC0 + l);
   HIPCHK(c, launch_stream_collide(a, c->stream));
   c->toc(k);
@@ -434,6 +467,10 @@ lbm_status down_level(lbm_ctx* c, int l, int s) {
   t.midpoint = (s == 2) ? 1 : 0;
   t.dst = c->cur(l);
   t.factor = (float)c->a_down[l];
+  if (c->recording) {
+    lbm_status st = record(c, lbm_ctx::OP_DOWN, l, s, c->gblocks(l), c->ngb[l], c->cur(l));
+    if (st != LBM_OK) return st;
+  }
   const int k = c->tic(LBM_PROF_DOWN);
   HIPCHK(c, launch_downward(t, c->stream));
   c->toc(k);
@@ -449,6 +486,10 @@ lbm_status up_level(lbm_ctx* c, int l) {
   t.src_a = c->cur(l);
   t.dst = c->cur(l + 1);
   t.factor = (float)c->a_up[l];
+  if (c->recording) {
+    lbm_status st = record(c, lbm_ctx::OP_UP, l, 0, c->iblocks(l + 1), c->nib[l + 1], c->cur(l + 1));
+    if (st != LBM_OK) return st;
+  }
   const int k = c->tic(LBM_PROF_UP);
   HIPCHK(c, launch_upward(t, c->stream));
   c->toc(k);
@@ -469,6 +510,122 @@ lbm_status advance(lbm_ctx* c, int l, int s) {
 }
 
 bool level_ok(lbm_ctx* c, int level) { return c && level >= 0 && level < c->G.L; }
+
+// ---- adjoint of one coarse step: reverse sweep over the undo log ----
+constexpr uint64_t kStateMagic = 0x4554415453424c4dull;  // "MLBSTATE"
+constexpr size_t kStateHeader = 256;
+
+struct AdjBufs {
+  float* lam[2];  // adjoint of the pool's two time levels (f32, slot layout)
+  float* mu;      // adjoint of the scaled moments M; per-ghost scratch of the downward transfer
+};
+
+size_t slot_floats(const lbm_ctx* c) { return (size_t)(c->cap + 1) * kBlockStride; }
+
+size_t tape_bytes(const lbm_ctx* c) {
+  const int L = c->G.L;
+  int64_t nb = 0;
+  for (int l = 0; l < L; ++l) {
+    const int64_t calls = int64_t(1) << (L - 1 - l);  // advance(l, s) calls per coarse step
+    nb += calls * c->nblk[l];
+    if (l + 1 < L) nb += calls * c->ngb[l] + (calls / 2) * c->nib[l + 1];
+  }
+  return (size_t)nb * block_bytes(c);
+}
+
+int64_t total_blocks(const lbm_ctx* c) {
+  int64_t nb = 0;
+  for (int l = 0; l < c->G.L; ++l) nb += c->nblk[l];
+  return nb;
+}
+
+AdjTransferLaunch adj_base(lbm_ctx* c, int l) {
+  AdjTransferLaunch t;
+  std::memset(&t, 0, sizeof(t));
+  t.G = c->G;
+  t.level = l;
+  t.dir = c->dir(c->hier);
+  t.role = c->role(c->rcur);
+  t.coord = c->m<int4>(c->lay.coord);
+  t.sc = c->sc;
+  t.storage = c->cfg.storage;
+  return t;
+}
+
+// adjoint of one recorded operation in the state right after it, then its undo
+lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
+  const int l = op.level;
+  hipStream_t s = c->stream;
+  const size_t bb = block_bytes(c);
+  if (op.kind == lbm_ctx::OP_SC) {
+    const int p = op.pf;  // input time level; the sweep wrote 1 - p
+    if (c->nob[l] > 0) {
+      AdjTransferLaunch t = adj_base(c, l);
+      t.blocks = c->oblocks(l);
+      t.nblocks = (int32_t)c->nob[l];
+      t.lam_coarse_a = b.lam[1 - p];
+      t.lam_fine = b.lam[p];
+      HIPCHK(c, launch_outflow_adj(t, s));
+    }
+    ScLaunch a;
+    a.in = c->buf(l, p);
+    a.out = nullptr;
+    a.blocks = c->blocks(l);
+    a.nblocks = (int32_t)c->nblk[l];
+    a.nbr = c->m<int32_t>(c->lay.nbr);
+    a.role = c->role(c->rcur);
+    a.zero_slot = (int32_t)c->cap;
+    a.omega = (float)(1.0 / c->tau[l]);
+    a.sc = c->sc;
+    a.storage = c->cfg.storage;
+    a.lam_y = b.lam[1 - p];
+    a.mu = b.mu;
+    HIPCHK(c, launch_stream_collide_mu(a, s));
+    AdjScLaunch t;
+    t.x = c->buf(l, p);
+    t.mu = b.mu;
+    t.lam_x = b.lam[p];
+    t.blocks = c->blocks(l);
+    t.nblocks = (int32_t)c->nblk[l];
+    t.nbr = a.nbr;
+    t.role = a.role;
+    t.zero_slot = (int32_t)c->cap;
+    t.omega = a.omega;
+    t.sc = c->sc;
+    t.storage = c->cfg.storage;
+    HIPCHK(c, launch_sc_transpose(t, s));
+    HIPCHK(c, launch_scatter_blocks(c->tape + op.off, c->buf(l, 1 - p), c->blocks(l), (int32_t)c->nblk[l], bb, s));
+  } else if (op.kind == lbm_ctx::OP_DOWN) {
+    AdjTransferLaunch t = adj_base(c, l);
+    t.blocks = c->gblocks(l);
+    t.nblocks = (int32_t)c->ngb[l];
+    t.src_a = c->buf(l + 1, 1 - op.pc);
+    t.src_b = c->buf(l + 1, op.pc);
+    t.midpoint = op.s == 2 ? 1 : 0;
+    t.factor = (float)c->a_down[l];
+    t.lam_fine = b.lam[op.pf];
+    t.lam_coarse_a = b.lam[1 - op.pc];
+    t.lam_coarse_b = b.lam[op.pc];
+    t.scratch = b.mu;
+    HIPCHK(c, launch_down_adj_lin(t, s));
+    t.blocks = c->blocks(l + 1);
+    t.nblocks = (int32_t)c->nblk[l + 1];
+    HIPCHK(c, launch_down_adj_gather(t, s));
+    HIPCHK(c, launch_scatter_blocks(c->tape + op.off, c->buf(l, op.pf), c->gblocks(l), (int32_t)c->ngb[l], bb, s));
+  } else {
+    AdjTransferLaunch t = adj_base(c, l);
+    t.blocks = c->iblocks(l + 1);
+    t.nblocks = (int32_t)c->nib[l + 1];
+    t.src_a = c->buf(l, op.pf);
+    t.factor = (float)c->a_up[l];
+    t.lam_fine = b.lam[op.pf];
+    t.lam_coarse_a = b.lam[op.pc];
+    HIPCHK(c, launch_up_adj(t, s));
+    HIPCHK(c, launch_scatter_blocks(c->tape + op.off, c->buf(l + 1, op.pc), c->iblocks(l + 1), (int32_t)c->nib[l + 1],
+                                    bb, s));
+  }
+  return LBM_OK;
+}
 
 }  // namespace
 
@@ -679,6 +836,140 @@ lbm_status lbm_check_finite(lbm_ctx* ctx) {
   HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, flag, 4, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   if (ctx->host_counts[0]) return ctx->fail(LBM_ENAN, "non-finite moments");
+  return LBM_OK;
+}
+
+size_t lbm_state_bytes(const lbm_ctx* ctx) {
+  if (!ctx) return 0;
+  return kStateHeader + (size_t)total_blocks(ctx) * block_bytes(ctx);
+}
+
+lbm_status lbm_save(lbm_ctx* ctx, void* dst, size_t bytes) {
+  if (!ctx) return LBM_EINVAL;
+  if (!dst || bytes < lbm_state_bytes(ctx)) return ctx->fail(LBM_EINVAL, "state buffer missing or too small");
+  Words8 w;
+  std::memset(&w, 0, sizeof(w));
+  w.v[0] = kStateMagic;
+  w.v[1] = ctx->generation;
+  w.v[2] = (uint64_t)ctx->G.L;
+  w.v[3] = (uint64_t)total_blocks(ctx);
+  w.v[4] = (uint64_t)ctx->elem;
+  HIPCHK(ctx, launch_write_words(static_cast<uint64_t*>(dst), w, ctx->stream));
+  char* p = static_cast<char*>(dst) + kStateHeader;
+  for (int l = 0; l < ctx->G.L; ++l) {
+    HIPCHK(ctx, launch_gather_blocks(ctx->cur(l), p, ctx->blocks(l), (int32_t)ctx->nblk[l], block_bytes(ctx),
+                                     ctx->stream));
+    p += (size_t)ctx->nblk[l] * block_bytes(ctx);
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes) {
+  if (!ctx) return LBM_EINVAL;
+  if (!src || bytes < lbm_state_bytes(ctx)) return ctx->fail(LBM_EINVAL, "state buffer missing or too small");
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, src, 64, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  const uint64_t* w = reinterpret_cast<const uint64_t*>(ctx->host_counts);
+  if (w[0] != kStateMagic || w[2] != (uint64_t)ctx->G.L || w[4] != (uint64_t)ctx->elem)
+    return ctx->fail(LBM_ESTATE, "not a state of this simulation");
+  if (w[1] != ctx->generation || w[3] != (uint64_t)total_blocks(ctx))
+    return ctx->fail(LBM_ESTATE, "state was saved under another block hierarchy");
+  const char* p = static_cast<const char*>(src) + kStateHeader;
+  for (int l = 0; l < ctx->G.L; ++l) {
+    HIPCHK(ctx, launch_scatter_blocks(p, ctx->cur(l), ctx->blocks(l), (int32_t)ctx->nblk[l], block_bytes(ctx),
+                                      ctx->stream));
+    p += (size_t)ctx->nblk[l] * block_bytes(ctx);
+  }
+  return LBM_OK;
+}
+
+size_t lbm_adjoint_work_bytes(const lbm_ctx* ctx) {
+  if (!ctx) return 0;
+  return 3 * slot_floats(ctx) * sizeof(float) + tape_bytes(ctx);
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes, const float* lam_next, float* lam_out,
+                            void* work, size_t work_bytes) {
+  if (!ctx) return LBM_EINVAL;
+  if (!lam_next || !lam_out || !work) return ctx->fail(LBM_EINVAL, "null adjoint buffer");
+  if (work_bytes < lbm_adjoint_work_bytes(ctx)) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
+  lbm_status st = lbm_load(ctx, state, state_bytes);
+  if (st != LBM_OK) return st;
+  hipStream_t s = ctx->stream;
+  const int L = ctx->G.L;
+  const size_t sf = slot_floats(ctx);
+  AdjBufs b;
+  b.lam[0] = static_cast<float*>(work);
+  b.lam[1] = b.lam[0] + sf;
+  b.mu = b.lam[1] + sf;
+  ctx->tape = reinterpret_cast<char*>(b.mu + sf);
+  ctx->tape_cap = work_bytes - 3 * sf * sizeof(float);
+  ctx->tape_used = 0;
+  ctx->ops.clear();
+  int p0[kMaxLevels];
+  for (int l = 0; l < L; ++l) p0[l] = ctx->parity[l];
+  // forward replay of the coarse step from the loaded state, recording the undo log
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;
+  ctx->recording = true;
+  st = advance(ctx, L - 1, 1);
+  ctx->recording = false;
+  ctx->profiling = prof;
+  if (st == LBM_OK) {
+    // adjoint of the state after the step: lam_next at the state nodes of the current time level
+    HIPCHK(ctx, launch_fill_i32(reinterpret_cast<int32_t*>(b.mu + (size_t)ctx->cap * kBlockStride), 0, kBlockStride, s));
+    size_t off = 0;
+    for (int l = 0; l < L; ++l) {
+      const int32_t n = (int32_t)ctx->nblk[l];
+      HIPCHK(ctx, launch_zero_blocks(b.lam[1 - ctx->parity[l]], ctx->blocks(l), n, s));
+      HIPCHK(ctx, launch_lam_scatter(lam_next + off, b.lam[ctx->parity[l]], ctx->blocks(l), ctx->role(ctx->rcur), n, s));
+      off += (size_t)n * kBlockStride;
+    }
+  }
+  // reverse sweep; on a failed replay only the undo runs
+  for (size_t i = ctx->ops.size(); i-- > 0;) {
+    const lbm_ctx::TapeOp& op = ctx->ops[i];
+    if (st == LBM_OK) {
+      lbm_status e = adjoint_op(ctx, op, b);
+      if (e != LBM_OK) st = e;
+    }
+    if (st != LBM_OK) {
+      // restore what the operation overwrote so the simulation is left at the loaded state
+      const int l = op.level;
+      const size_t bb = block_bytes(ctx);
+      if (op.kind == lbm_ctx::OP_SC)
+        launch_scatter_blocks(ctx->tape + op.off, ctx->buf(l, 1 - op.pf), ctx->blocks(l), (int32_t)ctx->nblk[l], bb, s);
+      else if (op.kind == lbm_ctx::OP_DOWN)
+        launch_scatter_blocks(ctx->tape + op.off, ctx->buf(l, op.pf), ctx->gblocks(l), (int32_t)ctx->ngb[l], bb, s);
+      else
+        launch_scatter_blocks(ctx->tape + op.off, ctx->buf(l + 1, op.pc), ctx->iblocks(l + 1), (int32_t)ctx->nib[l + 1],
+                              bb, s);
+    }
+  }
+  for (int l = 0; l < L; ++l) ctx->parity[l] = p0[l];
+  ctx->ops.clear();
+  ctx->tape = nullptr;
+  ctx->tape_cap = 0;
+  if (st != LBM_OK) return st;
+  size_t off = 0;
+  for (int l = 0; l < L; ++l) {
+    const int32_t n = (int32_t)ctx->nblk[l];
+    HIPCHK(ctx, launch_gather_blocks(b.lam[p0[l]], lam_out + off, ctx->blocks(l), n, kBlockStride * sizeof(float), s));
+    off += (size_t)n * kBlockStride;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_loss_ke_grad(lbm_ctx* ctx, int32_t level, const int32_t lo[3], const int32_t hi[3], float* lam) {
+  if (!level_ok(ctx, level) || !lo || !hi || !lam) return ctx ? ctx->fail(LBM_EINVAL, "bad arguments") : LBM_EINVAL;
+  HIPCHK(ctx, launch_fill_i32(reinterpret_cast<int32_t*>(lam), 0, total_blocks(ctx) * kBlockStride, ctx->stream));
+  size_t off = 0;
+  for (int l = 0; l < level; ++l) off += (size_t)ctx->nblk[l] * kBlockStride;
+  AdjTransferLaunch t = adj_base(ctx, level);
+  t.blocks = ctx->blocks(level);
+  t.nblocks = (int32_t)ctx->nblk[level];
+  t.src_a = ctx->cur(level);
+  HIPCHK(ctx, launch_loss_ke_grad(t, lam + off, lo, hi, ctx->stream));
   return LBM_OK;
 }
 

@@ -41,8 +41,9 @@ template <class S> struct ScArgs {
   int32_t zero_slot;
   float omega;
   Scales sc;
-  // adjoint epilogue only: adjoint of the outputs in, adjoint of M out (f32, pool layout)
-  const float* lam_y;
+  // adjoint epilogue only: adjoint of the outputs in (cleared where the sweep
+  // overwrites them), adjoint of M out (f32, pool layout)
+  float* lam_y;
   float* mu;
 };
 
@@ -293,8 +294,9 @@ __device__ __forceinline__ void x_pass(const float* lds, int row, int x, float y
 }
 
 // ADJ = false: the stream-collide. ADJ = true: the same sweep recomputes the
-// scaled moments M of every computed node and, instead of the new moments, writes
-// mu = (dY/dM)^T lambda_Y for the adjoint (zero for nodes that are not computed).
+// scaled moments M of every computed node (bounce-back included) and, instead of
+// the new moments, writes mu = (dY/dM)^T lambda_Y for the adjoint (zero for nodes
+// that are not computed); lambda_Y is cleared at the nodes the sweep writes.
 template <class S, bool ADJ>
 __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   __shared__ __align__(16) float lds[10 * kRow];
@@ -436,11 +438,16 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
       const uint8_t role = (uint8_t)(col_roles >> (8 * zo));
       if constexpr (ADJ) {
         float* mu = a.mu + (size_t)slot * kBlockStride + node;
+        float* lam = a.lam_y + (size_t)slot * kBlockStride + node;
         if ((role & ROLE_MASK) == ROLE_COMPUTED) {
-          const float* lam = a.lam_y + (size_t)slot * kBlockStride + node;
+          if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, zo, M);
+          // the outputs are overwritten: their adjoint is consumed here
           float L[kMom];
 #pragma unroll
-          for (int m = 0; m < kMom; ++m) L[m] = lam[m * kNodes];
+          for (int m = 0; m < kMom; ++m) {
+            L[m] = lam[m * kNodes];
+            lam[m * kNodes] = 0.0f;
+          }
           // Y0 = M0/216, Y_i = M_i/r (off-diagonal, u), Y_i = M_i/(3r) (diagonal S), r = 216 + M0
           const float r216 = 216.0f + M[0];
           const float inv = recip(r216);
@@ -454,8 +461,12 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
           }
           mu[0] = L[0] * (1.0f / 216.0f) - dot * inv;
         } else {
+          const bool solid = (role & ROLE_MASK) == ROLE_SOLID;  // written with zeros
 #pragma unroll
-          for (int m = 0; m < kMom; ++m) mu[m * kNodes] = 0.0f;
+          for (int m = 0; m < kMom; ++m) {
+            mu[m * kNodes] = 0.0f;
+            if (solid) lam[m * kNodes] = 0.0f;
+          }
         }
       } else {
         typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;

@@ -49,7 +49,9 @@ class LBMConfig(ctypes.Structure):
 EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm_num_blocks", "lbm_block_keys",
            "lbm_set_block_moments", "lbm_step", "lbm_advance_particles", "lbm_remesh", "lbm_get_moments",
            "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
-           "lbm_last_error"]
+           "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step",
+           "lbm_loss_ke_grad", "lbm_last_error"]
+_SIZE_QUERIES = ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_state_bytes", "lbm_adjoint_work_bytes", "lbm_last_error")
 PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh"]
 
 _lib = None
@@ -82,10 +84,18 @@ def lib():
         L.lbm_check_finite.argtypes = [vp]
         L.lbm_set_profiling.argtypes = [vp, i32]
         L.lbm_get_profile.argtypes = [vp, vp, vp]
+        L.lbm_state_bytes.restype = sz
+        L.lbm_state_bytes.argtypes = [vp]
+        L.lbm_save.argtypes = [vp, vp, sz]
+        L.lbm_load.argtypes = [vp, vp, sz]
+        L.lbm_adjoint_work_bytes.restype = sz
+        L.lbm_adjoint_work_bytes.argtypes = [vp]
+        L.lbm_adjoint_step.argtypes = [vp, vp, sz, vp, vp, vp, sz]
+        L.lbm_loss_ke_grad.argtypes = [vp, i32, vp, vp, vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_last_error.argtypes = [vp]
         for name in EXPORTS:
-            if name not in ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_last_error"):
+            if name not in _SIZE_QUERIES:
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -241,3 +251,100 @@ class Sim:
             return False
         self._check(st)
         return True
+
+    # ---- states and the adjoint ----
+    def total_blocks(self):
+        return sum(self.num_blocks(l) for l in range(self.levels))
+
+    def state_bytes(self):
+        return int(lib().lbm_state_bytes(self.h))
+
+    def save(self, out=None):
+        """The current state (all levels' current time level) as a device uint8 tensor."""
+        n = self.state_bytes()
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self._check(lib().lbm_save(self.h, _dptr(out), out.numel()))
+        return out
+
+    def load(self, state):
+        self._check(lib().lbm_load(self.h, _dptr(state), state.numel()))
+
+    def get_all_moments(self):
+        """Moments of every level, concatenated in level order: [sum nb, 10, 512]."""
+        return torch.cat([self.get_moments(l)[1] for l in range(self.levels)])
+
+    def set_all_moments(self, x):
+        off = 0
+        for l in range(self.levels):
+            keys = self.block_keys(l)
+            n = keys.shape[0]
+            if n:
+                self.set_block_moments(l, keys, x[off:off + n])
+            off += n
+        assert off == x.shape[0]
+
+    def adjoint_work(self):
+        return torch.empty(int(lib().lbm_adjoint_work_bytes(self.h)), dtype=torch.uint8, device=self.device)
+
+    def adjoint_step(self, state, lam_next, lam_out=None, work=None):
+        """dLoss/d(state) from dLoss/d(state one coarse step later); leaves the simulation at `state`."""
+        if lam_out is None:
+            lam_out = torch.empty_like(lam_next)
+        if work is None:
+            work = self.adjoint_work()
+        assert lam_next.dtype == torch.float32 and lam_next.is_contiguous()
+        assert lam_next.shape == (self.total_blocks(), 10, 512) and lam_out.shape == lam_next.shape
+        self._check(lib().lbm_adjoint_step(self.h, _dptr(state), state.numel(), _dptr(lam_next), _dptr(lam_out),
+                                           _dptr(work), work.numel()))
+        return lam_out
+
+    def loss_ke_grad(self, level, lo, hi):
+        """d(1/2 sum rho |u|^2 over the level's owned nodes in [lo, hi))/d(moments), all-level layout."""
+        lam = torch.empty((self.total_blocks(), 10, 512), dtype=torch.float32, device=self.device)
+        lo_ = (ctypes.c_int32 * 3)(*lo)
+        hi_ = (ctypes.c_int32 * 3)(*hi)
+        self._check(lib().lbm_loss_ke_grad(self.h, level, lo_, hi_, _dptr(lam)))
+        return lam
+
+
+class _Rollout(torch.autograd.Function):
+    """x0 (all-level moments) -> moments after `steps` coarse steps. The backward
+    pass replays each segment of `every` steps from its checkpoint, keeps the
+    segment's states, and runs the adjoint step backwards over them."""
+
+    @staticmethod
+    def forward(ctx, x0, sim, steps, every):
+        sim.set_all_moments(x0.detach())
+        ckpts = []
+        for k in range(steps):
+            if k % every == 0:
+                ckpts.append((k, sim.save()))
+            sim.step(1)
+        out = sim.get_all_moments()
+        ctx.sim, ctx.steps, ctx.every, ctx.ckpts = sim, steps, every, ckpts
+        ctx.final = sim.save()
+        return out
+
+    @staticmethod
+    def backward(ctx, grad):
+        sim = ctx.sim
+        lam = grad.detach().to(torch.float32).contiguous().clone()
+        work = sim.adjoint_work()
+        for k0, ck in reversed(ctx.ckpts):
+            k1 = min(k0 + ctx.every, ctx.steps)
+            sim.load(ck)
+            states = [ck]
+            for _ in range(k0 + 1, k1):
+                sim.step(1)
+                states.append(sim.save())
+            for st in reversed(states):
+                sim.adjoint_step(st, lam, lam, work)
+        sim.load(ctx.final)
+        return lam, None, None, None
+
+
+def rollout(sim, x0, steps, checkpoint_every=20):
+    """Differentiable `steps` coarse steps from the all-level moments x0 ([sum nb, 10, 512],
+    device f32); returns the all-level moments after them. The hierarchy stays fixed."""
+    return _Rollout.apply(x0, sim, int(steps), int(checkpoint_every))

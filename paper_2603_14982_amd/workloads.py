@@ -135,6 +135,31 @@ def smooth_random_velocity(n, seed, kmax=6.0, rms=0.03):
     return u
 
 
+def block_centre_markers(blocks):
+    """Particles (float32 [k^3, 3]) at the centres of the level-0 blocks b x b x b, b in `blocks`."""
+    c = [8.0 * b + 4.0 for b in blocks]
+    pts = [(x, y, z) for z in c for y in c for x in c]
+    return np.ascontiguousarray(np.array(pts, dtype=np.float32))
+
+
+def velocity_moments(level, keys, u_dense):
+    """Moments (rho = 1, u sampled from the dense fine field [3, Z, Y, X] at every node's
+    fine position, S = u u) of the given blocks: [nb, 10, 512] float64."""
+    u = sample_dense(level, keys, u_dense)
+    nb = u.shape[0]
+    return moments_from_fields(np.zeros((nb, 512)), [u[:, 0], u[:, 1], u[:, 2]])
+
+
+def unit_directions(n, seeds, kmax=6.0):
+    """Divergence-free directions with the spectrum of smooth_random_velocity, each of
+    unit L2 norm over all 3 n^3 components: [len(seeds), 3, Z, Y, X] float64."""
+    out = []
+    for s in seeds:
+        d = smooth_random_velocity(n, s, kmax=kmax, rms=1.0)
+        out.append(d / np.linalg.norm(d))
+    return np.stack(out)
+
+
 # --- the five workloads ------------------------------------------------------
 def workload(name):
     """Static description of a named workload (sizes, boundaries, parameters)."""
@@ -149,6 +174,9 @@ def workload(name):
                     particles=2_000_000, seed=3, lo=(64.0, 64.0, 352.0), hi=(448.0, 448.0, 384.0),
                     v_fine=(0.0, 0.0, -0.02))
     if name == "adjoint128":
+        # level 0 over [32, 96)^3: the two-level block set of the sphere case, fixed by
+        # eight marker particles at the centres of the level-0 blocks 7..8 per axis
         return dict(levels=2, n=(128, 128, 128), bc=(P,) * 6, tau0=0.6, steps=200, seed=5,
-                    kmax=6.0, rms=0.03, box=((48, 48, 48), (80, 80, 80)))
+                    kmax=6.0, rms=0.03, box=((48, 48, 48), (80, 80, 80)), checkpoint_every=20,
+                    markers=block_centre_markers((7, 8)), direction_seeds=tuple(range(5000, 5016)))
     raise KeyError(name)

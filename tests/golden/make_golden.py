@@ -6,6 +6,11 @@ here comes from the GPU path. Each output holds a seeded sample of owned nodes
 
   python tests/golden/make_golden.py sphere128   # 500 coarse steps
   python tests/golden/make_golden.py slab512     # 20 coarse steps with grid updates
+  python tests/golden/make_golden.py adjoint128  # loss and 16 directional derivatives
+
+The adjoint file holds the kinetic-energy loss after 200 coarse steps of the
+two-level 128^3 case and its derivatives along 16 unit directions of the initial
+velocity, by the complex step (step 1e-30) in the complex instance of the oracle.
 """
 import os
 import sys
@@ -84,6 +89,56 @@ def slab512(coarse_steps=20):
     np.savez_compressed(os.path.join(HERE, "slab512_oracle_sample.npz"), **res)
 
 
+def adjoint_setup(wl):
+    """The oracle's initial moments of the two-level adjoint case: real part from the
+    velocity u0, imaginary part (per direction) the moments' derivative along d."""
+    u0 = W.smooth_random_velocity(wl["n"], wl["seed"], wl["kmax"], wl["rms"])
+    return u0, W.unit_directions(wl["n"], wl["direction_seeds"], wl["kmax"])
+
+
+def moment_tangent(level, keys, u0, d):
+    """d/dh of the moments (rho = 1, u = u0 + h d, S = u u) at h = 0: (0, d, u0 d + d u0)."""
+    a = W.sample_dense(level, keys, u0)
+    b = W.sample_dense(level, keys, d)
+    nb = a.shape[0]
+    out = np.zeros((nb, 10, 512))
+    out[:, 1:4] = b
+    pairs = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    for k, (i, j) in enumerate(pairs):
+        out[:, 4 + k] = a[:, i] * b[:, j] + b[:, i] * a[:, j]
+    return out
+
+
+def adjoint128(steps=None):
+    wl = W.workload("adjoint128")
+    steps = wl["steps"] if steps is None else steps
+    u0, dirs = adjoint_setup(wl)
+    lo, hi = wl["box"]
+    h = 1e-30
+    t = time.time()
+    real = O.OracleSim(2, wl["n"], wl["bc"], wl["tau0"], particles=wl["markers"])
+    for l in range(2):
+        keys = real.block_keys(l)
+        real.set_block_moments(l, keys, W.velocity_moments(l, keys, u0))
+    real.step(steps)
+    loss = real.kinetic_energy(0, lo, hi)
+    print(f"adjoint128 loss {loss!r} ({time.time() - t:.0f} s)", flush=True)
+    deriv = []
+    for k, d in enumerate(dirs):
+        sim = O.OracleSimComplex(2, wl["n"], wl["bc"], wl["tau0"], particles=wl["markers"])
+        for l in range(2):
+            keys = sim.block_keys(l)
+            sim.set_block_moments(l, keys, W.velocity_moments(l, keys, u0), h * moment_tangent(l, keys, u0, d))
+        sim.step(steps)
+        v = sim.kinetic_energy(0, lo, hi)
+        deriv.append(v.imag / h)
+        print(f"direction {k}: loss {v.real!r} derivative {deriv[-1]!r} ({time.time() - t:.0f} s)", flush=True)
+        del sim
+    np.savez(os.path.join(HERE, "adjoint128_oracle_derivatives.npz"), loss=np.array(loss),
+             derivatives=np.array(deriv), steps=np.array(steps), h=np.array(h),
+             seeds=np.array(wl["direction_seeds"]))
+
+
 if __name__ == "__main__":
     for name in sys.argv[1:]:
-        {"sphere128": sphere128, "slab512": slab512}[name]()
+        {"sphere128": sphere128, "slab512": slab512, "adjoint128": adjoint128}[name]()

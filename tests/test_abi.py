@@ -79,3 +79,14 @@ def test_null_context_calls_fail_cleanly():
     assert L.lbm_destroy(None) == -1
     out = ctypes.c_int64()
     assert L.lbm_num_blocks(None, 0, ctypes.byref(out)) == -1
+
+
+def test_null_context_state_and_adjoint_calls_fail_cleanly():
+    L = lbm.lib()
+    assert L.lbm_state_bytes(None) == 0
+    assert L.lbm_adjoint_work_bytes(None) == 0
+    assert L.lbm_save(None, None, 0) == -1
+    assert L.lbm_load(None, None, 0) == -1
+    assert L.lbm_adjoint_step(None, None, 0, None, None, None, 0) == -1
+    lo = (ctypes.c_int32 * 3)(0, 0, 0)
+    assert L.lbm_loss_ke_grad(None, 0, lo, lo, None) == -1

@@ -74,6 +74,19 @@ def test_tgv64_single_level():
     compare(gpu, ora, label="tgv64")
 
 
+def test_walls_two_level_channel():
+    # no-slip walls (bounce-back at z faces, level 0 and level 1), periodic x and y,
+    # smooth random start; two levels from marker particles, 20 coarse steps
+    n = (80, 80, 80)
+    bc = (P, P, P, P, W.WALL, W.WALL)
+    u0 = W.smooth_random_velocity(n, 9, kmax=4.0, rms=0.03)
+    gpu, ora = setup_pair(2, n, bc, 0.6, lambda l, k: W.velocity_moments(l, k, u0),
+                          particles=W.block_centre_markers((4, 5)))
+    gpu.step(20)
+    ora.step(20)
+    compare(gpu, ora, label="walls")
+
+
 def test_single_level_conservation_fp64_sums():
     n = (32, 32, 32)
     gpu, ora = setup_pair(1, n, (P,) * 6, 0.55, lambda l, k: W.tgv3d_field(l, k, n, 0.04))

@@ -1,0 +1,89 @@
+"""Pins of the complex-step derivative of the oracle, the reference of every
+gradient check: the complex instance runs the same templated FP64 code on
+std::complex<double>, so its imaginary part along a direction must equal the
+central finite difference of the real oracle, and its real part the real run.
+
+Configurations (two coarse steps each):
+- two levels, 80^3 periodic, level 0 over [16, 64)^3 fixed by marker particles
+  (stream-collide on both levels, downward and upward transfers);
+- the same block set from a solid sphere (r = 3 at the centre) with an inflow
+  face at x- and an outflow face at x+ (bounce-back, inflow, outflow copy).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_14982_amd import workloads as W
+
+P, INF, OUT = W.PERIODIC, W.INFLOW, W.OUTFLOW
+N = (80, 80, 80)
+BOX = ((16, 16, 16), (64, 64, 64))
+
+
+def _config(kind):
+    if kind == "periodic":
+        return dict(bc=(P,) * 6, particles=W.block_centre_markers((4, 5)), solid=None, uin=(0.0, 0.0, 0.0))
+    solid = W.sphere_solid(N, (40.0, 40.0, 40.0), 3.0)
+    return dict(bc=(INF, OUT, P, P, P, P), particles=None, solid=solid, uin=(0.03, 0.0, 0.0))
+
+
+def _fields(sim, seed):
+    """Initial moments (smooth velocity with a density and stress perturbation) and a
+    random direction over every moment of every node, per level."""
+    u0 = W.smooth_random_velocity(N, seed, kmax=4.0, rms=0.03)
+    rng = np.random.default_rng(seed + 1)
+    x, v = [], []
+    for l in range(2):
+        keys = sim.block_keys(l)
+        q = W.velocity_moments(l, keys, u0)
+        q[:, 0] += 1e-3 * rng.standard_normal(q[:, 0].shape)
+        q[:, 4:] += 1e-4 * rng.standard_normal(q[:, 4:].shape)
+        x.append(q)
+        v.append(rng.standard_normal(q.shape))
+    return x, v
+
+
+def _real_loss(kind, x, steps):
+    c = _config(kind)
+    sim = O.OracleSim(2, N, c["bc"], 0.6, uin=c["uin"], solid=c["solid"], particles=c["particles"])
+    for l in range(2):
+        sim.set_block_moments(l, sim.block_keys(l), x[l])
+    sim.step(steps)
+    return sim.kinetic_energy(0, *BOX) + sim.kinetic_energy(1, *BOX)
+
+
+def _complex_loss(kind, x, v, h, steps):
+    c = _config(kind)
+    sim = O.OracleSimComplex(2, N, c["bc"], 0.6, uin=c["uin"], solid=c["solid"], particles=c["particles"])
+    for l in range(2):
+        sim.set_block_moments(l, sim.block_keys(l), x[l], h * v[l])
+    sim.step(steps)
+    return sim.kinetic_energy(0, *BOX) + sim.kinetic_energy(1, *BOX)
+
+
+@pytest.mark.parametrize("kind", ["periodic", "sphere"])
+def test_complex_step_matches_central_difference(kind):
+    c = _config(kind)
+    probe = O.OracleSim(2, N, c["bc"], 0.6, uin=c["uin"], solid=c["solid"], particles=c["particles"])
+    assert probe.num_blocks(0) == 216 and probe.num_blocks(1) == 124
+    roles0 = probe.roles(0)
+    assert (roles0 == O.R_GHOST).any()
+    if kind == "sphere":
+        assert (roles0 == O.R_SOLID).any()
+        assert (probe.roles(1) == O.R_OUTFLOW).any() and (probe.roles(1) == O.R_INFLOW).any()
+    x, v = _fields(probe, 11)
+    steps = 2
+    base = _real_loss(kind, x, steps)
+    cs = _complex_loss(kind, x, v, 1e-30, steps)
+    # the real part of the complex run is the real run
+    assert abs(cs.real - base) <= 1e-13 * abs(base)
+    d_cs = cs.imag / 1e-30
+    # central differences: truncation O(eps^2), rounding O(1e-16 L / eps)
+    fd = []
+    for eps in (1e-5, 1e-6):
+        xp = [a + eps * b for a, b in zip(x, v)]
+        xm = [a - eps * b for a, b in zip(x, v)]
+        fd.append((_real_loss(kind, xp, steps) - _real_loss(kind, xm, steps)) / (2 * eps))
+    print(f"{kind}: loss {base:.6e}, complex step {d_cs:.10e}, central differences {fd}")
+    assert abs(fd[0] - fd[1]) <= 1e-6 * abs(d_cs)
+    assert abs(d_cs - fd[1]) <= 1e-6 * abs(d_cs)

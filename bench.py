@@ -81,12 +81,43 @@ def cpu_baseline(W):
                       f"{reps} coarse steps with grid update after 1 warm-up; {int(updates)} node updates per step"}
 
 
+def adjoint_ratio(lbm, W, torch):
+    """Two-level 128^3 adjoint case: time of the plain forward of its 200 coarse steps
+    vs the backward pass of the checkpointed rollout (checkpoints every 20 steps:
+    segment replay, per-step replay with the undo log, reverse sweep)."""
+    wl = W.workload("adjoint128")
+    sim = lbm.Sim(2, wl["n"], wl["bc"], wl["tau0"], particles=wl["markers"])
+    u0 = W.smooth_random_velocity(wl["n"], wl["seed"], wl["kmax"], wl["rms"])
+    for l in range(2):
+        keys = sim.block_keys(l).cpu().numpy()
+        sim.set_block_moments(l, keys, W.velocity_moments(l, keys, u0).astype("float32"))
+    x0 = sim.get_all_moments().clone()
+    steps = wl["steps"]
+    sim.step(5)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    x = x0.clone().requires_grad_(True)
+    xt = lbm.rollout(sim, x, steps, checkpoint_every=wl["checkpoint_every"])
+    seed = sim.loss_ke_grad(0, *wl["box"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xt.backward(seed)
+    torch.cuda.synchronize()
+    bwd = time.perf_counter() - t0
+    return {"value": round(bwd / fwd, 3), "forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
+            "workload": "adjoint128: 128^3, 2 levels (512 + 504 blocks), 200 coarse steps, checkpoints every 20"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -193,7 +224,7 @@ def main():
         },
         "effective_mlups": round(fine_equiv * args.steps / elapsed / 1e6, 1),
         "stream_collide_mlups": round(sc_updates / (sc_ms / 1e3) / 1e6, 1),
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": None,  # filled below
         "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]},
     }
     if args.calibrate_copy_mib > 0:
@@ -204,6 +235,9 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = args.calibrate_copy_mib << 20
+    if not args.no_adjoint:
+        print("[bench] adjoint/forward ratio (adjoint128)", file=sys.stderr, flush=True)
+        out["adjoint_forward_ratio"] = adjoint_ratio(lbm, W, torch)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W)

@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="print only the adjoint/forward measurement (for profiling the adjoint kernels)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -130,6 +132,9 @@ def main():
     import torch
     from paper_2603_14982_amd import lbm, workloads as W
 
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_forward_ratio": adjoint_ratio(lbm, W, torch)}), flush=True)
+        return
     wl = W.workload("slab512")
     print(f"[bench] workload slab512 n={wl['n']} levels={wl['levels']} particles={wl['particles']}",
           file=sys.stderr, flush=True)

@@ -177,7 +177,7 @@ lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes);
  *              respect to the values lbm_set_block_moments would write (zero at
  *              ghost, solid and inflow nodes, which do not influence the step).
  *              May alias lam_next.
- *   work       device scratch of >= lbm_adjoint_work_bytes bytes (caller-owned):
+ *   work       device scratch of >= lbm_adjoint_work_bytes(ctx, 1) bytes (caller-owned):
  *              the adjoint of both time levels, the adjoint of the per-node
  *              moment sums, and the undo log of the replayed step.
  * The call loads `state` (synchronises once), replays the coarse step while
@@ -186,9 +186,17 @@ lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes);
  * The adjoint is that of the f32 arithmetic; with 16-bit storage the rounding
  * of stored values is passed through unchanged. Grid updates are not part of
  * the step and are not differentiated. */
-size_t lbm_adjoint_work_bytes(const lbm_ctx* ctx);
+size_t lbm_adjoint_work_bytes(const lbm_ctx* ctx, int32_t n_steps);
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes, const float* lam_next,
                             float* lam_out, void* work, size_t work_bytes);
+
+/* The same over n_steps coarse steps at once (a checkpoint segment): one load, one
+ * replay of the n steps with the undo log, one reverse sweep. lam_next is the
+ * adjoint of the state n_steps after `state`; work >= lbm_adjoint_work_bytes(ctx,
+ * n_steps) (the undo log grows linearly with n_steps). lbm_adjoint_step is this
+ * call with n_steps = 1. */
+lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes, int32_t n_steps,
+                             const float* lam_next, float* lam_out, void* work, size_t work_bytes);
 
 /* Adjoint seed of the kinetic energy 1/2 sum rho |u|^2 over the owned nodes of
  * `level` whose fine position lies in [lo, hi): writes lam (device f32, the

@@ -883,16 +883,22 @@ lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes) {
   return LBM_OK;
 }
 
-size_t lbm_adjoint_work_bytes(const lbm_ctx* ctx) {
-  if (!ctx) return 0;
-  return 3 * slot_floats(ctx) * sizeof(float) + tape_bytes(ctx);
+size_t lbm_adjoint_work_bytes(const lbm_ctx* ctx, int32_t n_steps) {
+  if (!ctx || n_steps < 1) return 0;
+  return 3 * slot_floats(ctx) * sizeof(float) + (size_t)n_steps * tape_bytes(ctx);
 }
 
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes, const float* lam_next, float* lam_out,
                             void* work, size_t work_bytes) {
+  return lbm_adjoint_steps(ctx, state, state_bytes, 1, lam_next, lam_out, work, work_bytes);
+}
+
+lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes, int32_t n_steps,
+                             const float* lam_next, float* lam_out, void* work, size_t work_bytes) {
   if (!ctx) return LBM_EINVAL;
+  if (n_steps < 1) return ctx->fail(LBM_EINVAL, "step count must be positive");
   if (!lam_next || !lam_out || !work) return ctx->fail(LBM_EINVAL, "null adjoint buffer");
-  if (work_bytes < lbm_adjoint_work_bytes(ctx)) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
+  if (work_bytes < lbm_adjoint_work_bytes(ctx, n_steps)) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
   lbm_status st = lbm_load(ctx, state, state_bytes);
   if (st != LBM_OK) return st;
   hipStream_t s = ctx->stream;
@@ -908,15 +914,15 @@ lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes,
   ctx->ops.clear();
   int p0[kMaxLevels];
   for (int l = 0; l < L; ++l) p0[l] = ctx->parity[l];
-  // forward replay of the coarse step from the loaded state, recording the undo log
+  // forward replay of the coarse steps from the loaded state, recording the undo log
   const bool prof = ctx->profiling;
   ctx->profiling = false;
   ctx->recording = true;
-  st = advance(ctx, L - 1, 1);
+  for (int32_t i = 0; i < n_steps && st == LBM_OK; ++i) st = advance(ctx, L - 1, 1);
   ctx->recording = false;
   ctx->profiling = prof;
   if (st == LBM_OK) {
-    // adjoint of the state after the step: lam_next at the state nodes of the current time level
+    // adjoint of the state after the steps: lam_next at the state nodes of the current time level
     HIPCHK(ctx, launch_fill_i32(reinterpret_cast<int32_t*>(b.mu + (size_t)ctx->cap * kBlockStride), 0, kBlockStride, s));
     size_t off = 0;
     for (int l = 0; l < L; ++l) {
@@ -926,7 +932,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes,
       off += (size_t)n * kBlockStride;
     }
   }
-  // reverse sweep; on a failed replay only the undo runs
+  // reverse sweep over every logged operation of every step; on a failure only the undo runs
   for (size_t i = ctx->ops.size(); i-- > 0;) {
     const lbm_ctx::TapeOp& op = ctx->ops[i];
     if (st == LBM_OK) {

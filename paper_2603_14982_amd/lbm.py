@@ -49,7 +49,7 @@ class LBMConfig(ctypes.Structure):
 EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm_num_blocks", "lbm_block_keys",
            "lbm_set_block_moments", "lbm_step", "lbm_advance_particles", "lbm_remesh", "lbm_get_moments",
            "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
-           "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step",
+           "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
            "lbm_loss_ke_grad", "lbm_last_error"]
 _SIZE_QUERIES = ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_state_bytes", "lbm_adjoint_work_bytes", "lbm_last_error")
 PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh"]
@@ -89,8 +89,9 @@ def lib():
         L.lbm_save.argtypes = [vp, vp, sz]
         L.lbm_load.argtypes = [vp, vp, sz]
         L.lbm_adjoint_work_bytes.restype = sz
-        L.lbm_adjoint_work_bytes.argtypes = [vp]
+        L.lbm_adjoint_work_bytes.argtypes = [vp, i32]
         L.lbm_adjoint_step.argtypes = [vp, vp, sz, vp, vp, vp, sz]
+        L.lbm_adjoint_steps.argtypes = [vp, vp, sz, i32, vp, vp, vp, sz]
         L.lbm_loss_ke_grad.argtypes = [vp, i32, vp, vp, vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_last_error.argtypes = [vp]
@@ -284,19 +285,21 @@ class Sim:
             off += n
         assert off == x.shape[0]
 
-    def adjoint_work(self):
-        return torch.empty(int(lib().lbm_adjoint_work_bytes(self.h)), dtype=torch.uint8, device=self.device)
+    def adjoint_work(self, n_steps=1):
+        n = int(lib().lbm_adjoint_work_bytes(self.h, int(n_steps)))
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
 
-    def adjoint_step(self, state, lam_next, lam_out=None, work=None):
-        """dLoss/d(state) from dLoss/d(state one coarse step later); leaves the simulation at `state`."""
+    def adjoint_step(self, state, lam_next, lam_out=None, work=None, n_steps=1):
+        """dLoss/d(state) from dLoss/d(state n_steps coarse steps later); leaves the
+        simulation at `state`."""
         if lam_out is None:
             lam_out = torch.empty_like(lam_next)
         if work is None:
-            work = self.adjoint_work()
+            work = self.adjoint_work(n_steps)
         assert lam_next.dtype == torch.float32 and lam_next.is_contiguous()
         assert lam_next.shape == (self.total_blocks(), 10, 512) and lam_out.shape == lam_next.shape
-        self._check(lib().lbm_adjoint_step(self.h, _dptr(state), state.numel(), _dptr(lam_next), _dptr(lam_out),
-                                           _dptr(work), work.numel()))
+        self._check(lib().lbm_adjoint_steps(self.h, _dptr(state), state.numel(), int(n_steps), _dptr(lam_next),
+                                            _dptr(lam_out), _dptr(work), work.numel()))
         return lam_out
 
     def loss_ke_grad(self, level, lo, hi):
@@ -309,9 +312,9 @@ class Sim:
 
 
 class _Rollout(torch.autograd.Function):
-    """x0 (all-level moments) -> moments after `steps` coarse steps. The backward
-    pass replays each segment of `every` steps from its checkpoint, keeps the
-    segment's states, and runs the adjoint step backwards over them."""
+    """x0 (all-level moments) -> moments after `steps` coarse steps. Checkpoints
+    every `every` steps; the backward pass hands each segment, last first, to the
+    library's multi-step adjoint (one replay with the undo log, one reverse sweep)."""
 
     @staticmethod
     def forward(ctx, x0, sim, steps, every):
@@ -330,16 +333,10 @@ class _Rollout(torch.autograd.Function):
     def backward(ctx, grad):
         sim = ctx.sim
         lam = grad.detach().to(torch.float32).contiguous().clone()
-        work = sim.adjoint_work()
+        work = sim.adjoint_work(min(ctx.every, ctx.steps))
         for k0, ck in reversed(ctx.ckpts):
             k1 = min(k0 + ctx.every, ctx.steps)
-            sim.load(ck)
-            states = [ck]
-            for _ in range(k0 + 1, k1):
-                sim.step(1)
-                states.append(sim.save())
-            for st in reversed(states):
-                sim.adjoint_step(st, lam, lam, work)
+            sim.adjoint_step(ck, lam, lam, work, n_steps=k1 - k0)
         sim.load(ctx.final)
         return lam, None, None, None
 

@@ -179,10 +179,13 @@ lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes);
  *              May alias lam_next.
  *   work       device scratch of >= lbm_adjoint_work_bytes(ctx, 1) bytes (caller-owned):
  *              the adjoint of both time levels, the adjoint of the per-node
- *              moment sums, and the undo log of the replayed step.
- * The call loads `state` (synchronises once), replays the coarse step while
- * logging every block it overwrites, then walks the log backwards: adjoint of
- * each operation, then its undo. On return the simulation is at `state`.
+ *              moment sums, one flag byte per block slot, and the undo log of
+ *              the replayed step.
+ * The call loads `state` (synchronises once), replays the coarse step while the
+ * forward kernels keep the old value of every node they overwrite (the undo log),
+ * then walks the log backwards: adjoint of each operation, whose kernels also put
+ * back what the operation overwrote. On return the simulation is at `state`; after
+ * a failed call its state is undefined (load a saved state).
  * The adjoint is that of the f32 arithmetic; with 16-bit storage the rounding
  * of stored values is passed through unchanged. Grid updates are not part of
  * the step and are not differentiated. */

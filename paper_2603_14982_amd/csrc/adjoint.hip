@@ -2,12 +2,15 @@
 //
 // Stream-collide: Y = F(M), M = L a(X) with L the (linear, integer) stream +
 // projection operator and a the per-node coefficient map (collision included).
-// The adjoint is computed in two sweeps over a level:
-//   1. the forward sweep recomputes M and writes mu = (dF/dM)^T lambda_Y
-//      (k_stream_collide with the adjoint epilogue);
-//   2. this file's k_sc_transpose applies L^T to mu (the same three 1D passes,
-//      transposed: back-maps and shifts swap roles, x and y through LDS on a halo
-//      plane, z over a register window) and adds (da/dX)^T (L^T mu) to lambda_X.
+// The adjoint is computed in two passes over a level:
+//   1. k_sc_mu: mu = (dF/dM)^T lambda_Y per computed node. F only divides by
+//      216 rho' = 216 (1 + Y0), so mu needs the outputs Y, not the stencil;
+//   2. k_sc_transpose applies L^T to mu (the same three 1D passes, transposed:
+//      back-maps and shifts swap roles, x and y through LDS on a halo plane, z
+//      over a register window) and adds (da/dX)^T (L^T mu) to lambda_X.
+// The undo of every forward operation (the old values it overwrote, kept on a
+// tape during the replay) is folded into the first adjoint kernel that runs after
+// the values were last needed.
 // Bounce-back adds, at a flagged computed node, populations built from the node's
 // own coefficients; its transpose is a per-node term of the same sweep. Solid and
 // inflow nodes hold fixed values and collect no adjoint.
@@ -343,12 +346,71 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
   }
 }
 
+// ---- adjoint of the division by 216 rho' (per computed node) -------------------
+// Y0 = M0 / 216, Y_m = M_m / (216 + M0) (u and off-diagonal S; a further / 3 on
+// the diagonal S): mu_m = lambda_m dY_m/dM_m, mu_0 = lambda_0 / 216 - sum_m
+// lambda_m Y_m / (216 + M0). The outputs are then restored from the tape.
+template <class S>
+__global__ __launch_bounds__(256) void k_sc_mu(AdjScLaunch a) {
+  typedef typename S::type T;
+  const int slot = a.blocks[blockIdx.x];
+  T* y = static_cast<T*>(a.y) + (size_t)slot * kBlockStride;
+  const T* tp = static_cast<const T*>(a.tape) + (size_t)blockIdx.x * kBlockStride;
+  float* lam = a.lam_y + (size_t)slot * kBlockStride;
+  float* mu = a.mu + (size_t)slot * kBlockStride;
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    const uint8_t r = a.role[(size_t)slot * kNodes + node] & ROLE_MASK;
+    float g[kMom];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) g[m] = 0.0f;
+    if (r == ROLE_COMPUTED) {
+      float Y[kMom], L[kMom];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) {
+        Y[m] = Codec<S>::load(y[m * kNodes + node], a.sc.inv[m]);
+        L[m] = lam[m * kNodes + node];
+      }
+      const float inv = 1.0f / (216.0f * (1.0f + Y[0]));
+      float dot = 0.0f;
+#pragma unroll
+      for (int m = 1; m < kMom; ++m) {
+        g[m] = L[m] * ((m >= 4 && m <= 6) ? inv * (1.0f / 3.0f) : inv);
+        dot += L[m] * Y[m];
+      }
+      g[0] = L[0] * (1.0f / 216.0f) - dot * inv;
+    }
+    if (r == ROLE_COMPUTED || r == ROLE_SOLID) {
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) {
+        lam[m * kNodes + node] = 0.0f;
+        y[m * kNodes + node] = tp[m * kNodes + node];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) mu[m * kNodes + node] = g[m];
+  }
+}
+
+// restore the node's pre-operation value from the tape entry of list index idx
+template <class S>
+__device__ inline void undo_node(void* buf, const void* tape, int slot, int idx, int node) {
+  typename S::type* p = static_cast<typename S::type*>(buf) + (size_t)slot * kBlockStride + node;
+  const typename S::type* t = static_cast<const typename S::type*>(tape) + (size_t)idx * kBlockStride + node;
+#pragma unroll
+  for (int m = 0; m < kMom; ++m) p[m * kNodes] = t[m * kNodes];
+}
+
 // ---- downward transfer, transposed --------------------------------------------
-// (a) per ghost node: adjoint of the ghost moments -> adjoint of its interpolated
-//     (rho-1, u, S^neq) (the u u term needs the interpolated u); ghost adjoint cleared
+// (a) one workgroup per ghost block of level l: adjoint of every ghost's moments ->
+//     adjoint of its interpolated (rho-1, u, S^neq) (the u u term needs the
+//     interpolated u), kept in LDS; ghost adjoint cleared and ghost values restored;
+//     then the block's contribution to each of the 5^3 coarse nodes under it (the
+//     transposed trilinear weights, a fixed-order sum over <= 27 ghosts), written
+//     to the block's partial [list index][10][125].
 template <class S>
 __global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
   __shared__ float cu[3][125];
+  __shared__ float gl[kMom][kNodes];
   const int slot = a.blocks[blockIdx.x];
   const int4 bc = a.coord[slot];
   const int l = a.level;
@@ -379,42 +441,89 @@ __global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
     for (int k = 0; k < 3; ++k) cu[k][t] = u[k];
   }
   __syncthreads();
+  float* lamb = a.lam_fine + (size_t)slot * kBlockStride;
+  T* dstb = static_cast<T*>(a.undo_dst) + (size_t)slot * kBlockStride;
+  const T* tapeb = static_cast<const T*>(a.undo_tape) + (size_t)blockIdx.x * kBlockStride;
   for (int node = threadIdx.x; node < kNodes; node += 256) {
-    if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_GHOST) continue;
-    const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
-    float ug[3] = {0.0f, 0.0f, 0.0f};
+    float g[kMom];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int kx = c & 1, ky = (c >> 1) & 1, kz = c >> 2;
-      const float wx = (lc[0] & 1) ? 0.5f : (kx ? 0.0f : 1.0f);
-      const float wy = (lc[1] & 1) ? 0.5f : (ky ? 0.0f : 1.0f);
-      const float wz = (lc[2] & 1) ? 0.5f : (kz ? 0.0f : 1.0f);
-      const float w = wx * wy * wz;
-      if (w == 0.0f) continue;
-      const int t = ((lc[0] + kx) >> 1) + 5 * ((lc[1] + ky) >> 1) + 25 * ((lc[2] + kz) >> 1);
+    for (int m = 0; m < kMom; ++m) g[m] = 0.0f;
+    if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) == ROLE_GHOST) {
+      float L[kMom];
+      T old[kMom];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) ug[k] += w * cu[k][t];
+      for (int m = 0; m < kMom; ++m) {
+        L[m] = lamb[m * kNodes + node];
+        old[m] = tapeb[m * kNodes + node];
+      }
+      const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
+      float ug[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int kx = c & 1, ky = (c >> 1) & 1, kz = c >> 2;
+        const float wx = (lc[0] & 1) ? 0.5f : (kx ? 0.0f : 1.0f);
+        const float wy = (lc[1] & 1) ? 0.5f : (ky ? 0.0f : 1.0f);
+        const float wz = (lc[2] & 1) ? 0.5f : (kz ? 0.0f : 1.0f);
+        const float w = wx * wy * wz;
+        if (w == 0.0f) continue;
+        const int t = ((lc[0] + kx) >> 1) + 5 * ((lc[1] + ky) >> 1) + 25 * ((lc[2] + kz) >> 1);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ug[k] += w * cu[k][t];
+      }
+      g[0] = L[0];
+      g[1] = L[1] + 2.0f * L[4] * ug[0] + L[7] * ug[1] + L[8] * ug[2];
+      g[2] = L[2] + 2.0f * L[5] * ug[1] + L[7] * ug[0] + L[9] * ug[2];
+      g[3] = L[3] + 2.0f * L[6] * ug[2] + L[8] * ug[0] + L[9] * ug[1];
+#pragma unroll
+      for (int m = 4; m < kMom; ++m) g[m] = a.factor * L[m];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) {
+        lamb[m * kNodes + node] = 0.0f;
+        dstb[m * kNodes + node] = old[m];
+      }
     }
-    float* lam = a.lam_fine + (size_t)slot * kBlockStride + node;
-    float L[kMom];
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) L[m] = lam[m * kNodes];
-    float* out = a.scratch + (size_t)slot * kBlockStride + node;
-    out[0] = L[0];
-    out[kNodes * 1] = L[1] + 2.0f * L[4] * ug[0] + L[7] * ug[1] + L[8] * ug[2];
-    out[kNodes * 2] = L[2] + 2.0f * L[5] * ug[1] + L[7] * ug[0] + L[9] * ug[2];
-    out[kNodes * 3] = L[3] + 2.0f * L[6] * ug[2] + L[8] * ug[0] + L[9] * ug[1];
+    for (int m = 0; m < kMom; ++m) gl[m][node] = g[m];
+  }
+  __syncthreads();
+  // footprint node t (coarse 4b + t per axis) collects fine local 2t-1, 2t, 2t+1
+  // (weights 1/2, 1, 1/2) that lie inside the block
+  float* part = a.scratch + (size_t)blockIdx.x * (kMom * 125);
+  for (int t = threadIdx.x; t < 125; t += 256) {
+    const int tt[3] = {t % 5, (t / 5) % 5, t / 25};
+    float acc[kMom];
 #pragma unroll
-    for (int m = 4; m < kMom; ++m) out[m * kNodes] = a.factor * L[m];
+    for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
+    for (int dz = -1; dz <= 1; ++dz) {
+      const int z = 2 * tt[2] + dz;
+      if (z < 0 || z > 7) continue;
+      const float wz = dz ? 0.5f : 1.0f;
+      for (int dy = -1; dy <= 1; ++dy) {
+        const int y = 2 * tt[1] + dy;
+        if (y < 0 || y > 7) continue;
+        const float wy = dy ? 0.5f : 1.0f;
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int x = 2 * tt[0] + dx;
+          if (x < 0 || x > 7) continue;
+          const float w = wz * wy * (dx ? 0.5f : 1.0f);
+          const int n = x + 8 * y + 64 * z;
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) lam[m * kNodes] = 0.0f;
+          for (int m = 0; m < kMom; ++m) acc[m] += w * gl[m][n];
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) part[m * 125 + t] = acc[m];
   }
 }
 
-// (b) per coarse node: gather the lin-adjoints of every ghost whose stencil holds it
+// (b) per coarse node of a flagged level-(l+1) block: sum of the partials of the
+//     <= 2 x 2 x 2 ghost blocks whose footprint holds it (fixed order), then the
+//     split over the two coarse time levels through lin = (rho-1, u, S - u u)
 template <class S>
 __global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
   const int cslot = a.blocks[blockIdx.x];
+  if (!a.flags[cslot]) return;  // no ghost of level l interpolates from this block
   const int4 bc = a.coord[cslot];
   const int l = a.level;
   const LevelGeom& fg = a.G.lv[l];
@@ -422,41 +531,38 @@ __global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
   typedef typename S::type T;
   for (int node = threadIdx.x; node < kNodes; node += 256) {
     const int j[3] = {bc.x * kEdge + (node & 7), bc.y * kEdge + ((node >> 3) & 7), bc.z * kEdge + (node >> 6)};
+    // per axis: (fine block, footprint index) pairs whose staged coarse index is j
+    int nb[3], fb[3][2], ft[3][2];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int nbf = fg.nb[ax], nc = cg.nn[ax];
+      int k = 0;
+      fb[ax][k] = j[ax] >> 2; ft[ax][k] = j[ax] & 3; ++k;
+      if ((j[ax] & 3) == 0) {
+        const int b = (j[ax] >> 2) - 1;
+        if (b >= 0) { fb[ax][k] = b; ft[ax][k] = 4; ++k; }
+        else if (a.G.periodic[ax]) { fb[ax][k] = nbf - 1; ft[ax][k] = 4; ++k; }
+      }
+      if (!a.G.periodic[ax] && j[ax] == nc - 1) { fb[ax][k] = nbf - 1; ft[ax][k] = 4; ++k; }
+      nb[ax] = k;
+    }
     float acc[kMom];
 #pragma unroll
     for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
     bool any = false;
-    for (int d = 0; d < 27; ++d) {
-      int p[3] = {2 * j[0] + d % 3 - 1, 2 * j[1] + (d / 3) % 3 - 1, 2 * j[2] + d / 9 - 1};
-      bool ok = true;
-      float w = 1.0f;
+    for (int iz = 0; iz < nb[2]; ++iz)
+      for (int iy = 0; iy < nb[1]; ++iy)
+        for (int ix = 0; ix < nb[0]; ++ix) {
+          const int fs = a.dir[fg.off + cell_lin(fg, fb[0][ix], fb[1][iy], fb[2][iz])];
+          if (fs < 0) continue;
+          const int gi = a.gidx[fs];
+          if (gi < 0) continue;
+          const int t = ft[0][ix] + 5 * ft[1][iy] + 25 * ft[2][iz];
+          const float* src = a.scratch + (size_t)gi * (kMom * 125) + t;
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const int nf = fg.nn[ax], nc = cg.nn[ax];
-        if (p[ax] < 0 || p[ax] >= nf) {
-          if (!a.G.periodic[ax]) { ok = false; break; }
-          p[ax] = p[ax] < 0 ? p[ax] + nf : p[ax] - nf;
+          for (int m = 0; m < kMom; ++m) acc[m] += src[m * 125];
+          any = true;
         }
-        // the forward stencil of fine p along this axis and the weight it gives j
-        int c0, c1;
-        float w0, w1;
-        if ((p[ax] & 1) == 0) { c0 = c1 = p[ax] >> 1; w0 = 1.0f; w1 = 0.0f; }
-        else { c0 = (p[ax] - 1) >> 1; c1 = (p[ax] + 1) >> 1; w0 = w1 = 0.5f; }
-        if (a.G.periodic[ax]) { c1 = c1 >= nc ? c1 - nc : c1; }
-        else { c1 = c1 >= nc ? nc - 1 : c1; }
-        const float wa = (c0 == j[ax] ? w0 : 0.0f) + (c1 == j[ax] ? w1 : 0.0f);
-        w *= wa;
-      }
-      if (!ok || w == 0.0f) continue;
-      const int fs = a.dir[fg.off + cell_lin(fg, p[0] >> 3, p[1] >> 3, p[2] >> 3)];
-      if (fs < 0) continue;
-      const int fn = (p[0] & 7) + 8 * (p[1] & 7) + 64 * (p[2] & 7);
-      if ((a.role[(size_t)fs * kNodes + fn] & ROLE_MASK) != ROLE_GHOST) continue;
-      const float* src = a.scratch + (size_t)fs * kBlockStride + fn;
-#pragma unroll
-      for (int m = 0; m < kMom; ++m) acc[m] += w * src[m * kNodes];
-      any = true;
-    }
     if (!any) continue;
     // time levels: s = 1 uses coarse t only; s = 2 averages t and t + 2
     for (int tl = 0; tl < (a.midpoint ? 2 : 1); ++tl) {
@@ -466,7 +572,6 @@ __global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
       float u[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) u[k] = Codec<S>::load(qs[(1 + k) * kNodes], a.sc.inv[1 + k]);
-      // lin = (rho-1, u, S - u u)
       float g[kMom];
 #pragma unroll
       for (int m = 0; m < kMom; ++m) g[m] = c * acc[m];
@@ -481,6 +586,31 @@ __global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
       for (int m = 4; m < kMom; ++m) lam[m * kNodes] += g[m];
     }
   }
+}
+
+// ghost-list index of every ghost block of a level (gidx[slot]; -1 elsewhere)
+__global__ void k_ghost_index(const int32_t* blocks, int32_t n, int32_t* gidx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) gidx[blocks[i]] = i;
+}
+
+// flags the level-(l+1) blocks under the 5^3 coarse-node footprint of every ghost
+// block of level l (the nodes its ghosts interpolate from); every writer stores 1
+__global__ void k_mark_gather(AdjTransferLaunch a) {
+  const int slot = a.blocks[blockIdx.x];
+  const int4 bc = a.coord[slot];
+  const LevelGeom& cg = a.G.lv[a.level + 1];
+  const int t = threadIdx.x;
+  if (t >= 8) return;
+  int j[3] = {4 * bc.x + 4 * (t & 1), 4 * bc.y + 4 * ((t >> 1) & 1), 4 * bc.z + 4 * (t >> 2)};
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const int nc = cg.nn[ax];
+    if (a.G.periodic[ax]) j[ax] = j[ax] >= nc ? j[ax] - nc : j[ax];
+    else j[ax] = j[ax] >= nc ? nc - 1 : j[ax];
+  }
+  const int cs = a.dir[cg.off + cell_lin(cg, j[0] >> 3, j[1] >> 3, j[2] >> 3)];
+  if (cs >= 0) a.flags[cs] = 1;
 }
 
 // ---- upward transfer, transposed ------------------------------------------------
@@ -501,6 +631,7 @@ __global__ __launch_bounds__(256) void k_up_adj(AdjTransferLaunch a) {
     float L[kMom];
 #pragma unroll
     for (int m = 0; m < kMom; ++m) { L[m] = lq[m * kNodes]; lq[m * kNodes] = 0.0f; }
+    undo_node<S>(a.undo_dst, a.undo_tape, slot, blockIdx.x, node);
     const T* qs = static_cast<const T*>(a.src_a) + (size_t)fs * kBlockStride + fn;
     float u[3];
 #pragma unroll
@@ -535,6 +666,7 @@ __device__ inline int outflow_src(const Geom& G, const LevelGeom& lg, const int4
   return (role[src] & ROLE_MASK) == ROLE_COMPUTED ? src : -1;
 }
 
+template <class S>
 __global__ __launch_bounds__(256) void k_outflow_adj(AdjTransferLaunch a) {
   __shared__ float sv[kMom][kNodes];
   __shared__ int16_t sdst[kNodes];
@@ -555,6 +687,7 @@ __global__ __launch_bounds__(256) void k_outflow_adj(AdjTransferLaunch a) {
         sv[m][node] = v;
         if (dst < 0) lx[m * kNodes + node] += v;
       }
+      undo_node<S>(a.undo_dst, a.undo_tape, slot, blockIdx.x, node);
     }
     sdst[node] = (int16_t)dst;
   }
@@ -684,6 +817,7 @@ hipError_t dispatch_adj(const AdjTransferLaunch& a, hipStream_t s) {
 template <class S> struct DownLinK { static constexpr auto fn = k_down_adj_lin<S>; };
 template <class S> struct DownGatherK { static constexpr auto fn = k_down_adj_gather<S>; };
 template <class S> struct UpAdjK { static constexpr auto fn = k_up_adj<S>; };
+template <class S> struct OutflowAdjK { static constexpr auto fn = k_outflow_adj<S>; };
 
 }  // namespace
 
@@ -698,9 +832,25 @@ hipError_t launch_sc_transpose(const AdjScLaunch& l, hipStream_t s) {
 hipError_t launch_down_adj_lin(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<DownLinK>(a, s); }
 hipError_t launch_down_adj_gather(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<DownGatherK>(a, s); }
 hipError_t launch_up_adj(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<UpAdjK>(a, s); }
-hipError_t launch_outflow_adj(const AdjTransferLaunch& a, hipStream_t s) {
+hipError_t launch_outflow_adj(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<OutflowAdjK>(a, s); }
+hipError_t launch_ghost_index(const int32_t* blocks, int32_t n, int32_t* gidx, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ghost_index, dim3((n + 255) / 256), dim3(256), 0, s, blocks, n, gidx);
+  return hipGetLastError();
+}
+hipError_t launch_mark_gather(const AdjTransferLaunch& a, hipStream_t s) {
   if (a.nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_outflow_adj, dim3(a.nblocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mark_gather, dim3(a.nblocks), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_sc_mu(const AdjScLaunch& l, hipStream_t s) {
+  if (l.nblocks <= 0) return hipSuccess;
+  switch (l.storage) {
+    case 0: hipLaunchKernelGGL(k_sc_mu<StoreF32>, dim3(l.nblocks), dim3(256), 0, s, l); break;
+    case 1: hipLaunchKernelGGL(k_sc_mu<StoreBF16>, dim3(l.nblocks), dim3(256), 0, s, l); break;
+    case 2: hipLaunchKernelGGL(k_sc_mu<StoreF16>, dim3(l.nblocks), dim3(256), 0, s, l); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 hipError_t launch_loss_ke_grad(const AdjTransferLaunch& a, float* out, const int32_t lo[3], const int32_t hi[3],

@@ -19,12 +19,8 @@ struct ScLaunch {
   float omega;
   Scales sc;
   int storage;
-  float* lam_y = nullptr;        // adjoint epilogue: adjoint of the outputs (f32 pool layout)
-  float* mu = nullptr;           // adjoint epilogue: adjoint of the scaled moments M
 };
 hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s);
-// the stream-collide sweep with the adjoint epilogue (writes mu instead of moments)
-hipError_t launch_stream_collide_mu(const ScLaunch& a, hipStream_t s);
 
 // ---- interface transfers and outflow ----
 struct TransferLaunch {
@@ -42,6 +38,7 @@ struct TransferLaunch {
   int midpoint;              // down only: 1 = average src_a and src_b
   Scales sc;
   int storage;
+  void* tape;                // adjoint replay: old values of the written nodes, [list index][10][512]
 };
 hipError_t launch_downward(const TransferLaunch& a, hipStream_t s);
 hipError_t launch_upward(const TransferLaunch& a, hipStream_t s);
@@ -57,6 +54,7 @@ struct OutflowLaunch {
   const void* old_buf;
   void* new_buf;
   int storage;
+  void* tape = nullptr;      // adjoint replay: old values of the written nodes, [list index][10][512]
 };
 hipError_t launch_outflow(const OutflowLaunch& a, hipStream_t s);
 
@@ -166,11 +164,17 @@ hipError_t launch_finite(const IoLaunch& a, int32_t* flag, hipStream_t s);
 hipError_t launch_advance_particles(float* p, int64_t n, float dx, float dy, float dz, hipStream_t s);
 
 // ---- adjoint (reverse mode) ----
-// transposed stream + projection of one level: lam_x += (da/dX)^T L^T mu
+// adjoint of one level's stream-collide, two passes:
+//   launch_sc_mu: mu = (dY/dM)^T lambda_Y at computed nodes (zero elsewhere), lambda_Y
+//     cleared and the outputs y restored from the tape at computed and solid nodes;
+//   launch_sc_transpose: lam_x += (da/dX)^T L^T mu over the level's blocks.
 struct AdjScLaunch {
   const void* x;             // forward input time level (storage type)
-  const float* mu;           // adjoint of the scaled moments M (f32 pool layout, zero at zero_slot)
+  void* y;                   // forward output time level (restored from the tape)
+  const void* tape;          // old values of y, [list index][10][512]
+  float* mu;                 // adjoint of the scaled moments M (f32 pool layout, zero at zero_slot)
   float* lam_x;              // adjoint of the input time level (f32 pool layout), accumulated
+  float* lam_y;              // adjoint of the output time level
   const int32_t* blocks;
   int32_t nblocks;
   const int32_t* nbr;
@@ -180,6 +184,7 @@ struct AdjScLaunch {
   Scales sc;
   int storage;
 };
+hipError_t launch_sc_mu(const AdjScLaunch& a, hipStream_t s);
 hipError_t launch_sc_transpose(const AdjScLaunch& a, hipStream_t s);
 
 struct AdjTransferLaunch {
@@ -199,11 +204,19 @@ struct AdjTransferLaunch {
   float* lam_fine;           // adjoint of the level-l time level involved
   float* lam_coarse_a;       // adjoint of the level-(l+1) time level src_a (up: the target)
   float* lam_coarse_b;       // adjoint of the level-(l+1) time level src_b
-  float* scratch;            // per-ghost adjoint of the interpolated quantities (pool layout)
+  float* scratch;            // down: per ghost block [list index][10][125] coarse-footprint partials
+  const int32_t* gidx;       // down: ghost-list index per slot (-1 if not a ghost block of level l)
+  void* undo_dst;            // time level the forward operation wrote (restored from undo_tape)
+  const void* undo_tape;     // its old values, [list index][10][512]
+  uint8_t* flags;            // per slot: level-(l+1) block read by a level-l ghost
 };
 // downward transfer: (a) over the ghost blocks of level l, (b) over the blocks of level l+1
 hipError_t launch_down_adj_lin(const AdjTransferLaunch& a, hipStream_t s);
 hipError_t launch_down_adj_gather(const AdjTransferLaunch& a, hipStream_t s);
+// sets flags[slot] = 1 for the level-(l+1) blocks the ghosts of the level-l ghost blocks read
+hipError_t launch_mark_gather(const AdjTransferLaunch& a, hipStream_t s);
+// gidx[blocks[i]] = i
+hipError_t launch_ghost_index(const int32_t* blocks, int32_t n, int32_t* gidx, hipStream_t s);
 // upward transfer over the interface blocks of level l+1
 hipError_t launch_up_adj(const AdjTransferLaunch& a, hipStream_t s);
 // outflow copy over the outflow blocks of a level: lam_coarse_a = adjoint of the new

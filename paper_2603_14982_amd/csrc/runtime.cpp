@@ -156,7 +156,7 @@ struct lbm_ctx {
   // undo log of one coarse step replayed for the adjoint: before every operation
   // the blocks it is about to overwrite are copied to the tape
   enum { OP_SC = 0, OP_DOWN = 1, OP_UP = 2 };
-  struct TapeOp { int kind, level, s, pf, pc; size_t off; };
+  struct TapeOp { int kind, level, s, pf, pc; size_t off, off2; };
   bool recording = false;
   char* tape = nullptr;
   size_t tape_cap = 0, tape_used = 0;
@@ -387,9 +387,11 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
 
 size_t block_bytes(const lbm_ctx* c) { return (size_t)kBlockStride * c->elem; }
 
-// undo-log entry: the n blocks of `blocks` in time level `buf`, before operation op
-lbm_status record(lbm_ctx* c, int kind, int l, int s, const int32_t* blocks, int64_t n, const void* buf) {
-  const size_t bytes = (size_t)n * block_bytes(c);
+// undo-log entry of the next operation: room for the old values of the n blocks it
+// writes (and of the n2 outflow blocks of a stream-collide); the forward kernels
+// fill it while they run
+lbm_status record(lbm_ctx* c, int kind, int l, int s, int64_t n, int64_t n2, void** tape, void** tape2) {
+  const size_t bytes = (size_t)(n + n2) * block_bytes(c);
   if (c->tape_used + bytes > c->tape_cap) return c->fail(LBM_ECAPACITY, "adjoint tape too small");
   lbm_ctx::TapeOp op;
   op.kind = kind;
@@ -398,7 +400,9 @@ lbm_status record(lbm_ctx* c, int kind, int l, int s, const int32_t* blocks, int
   op.pf = c->parity[l];
   op.pc = l + 1 < c->G.L ? c->parity[l + 1] : 0;
   op.off = c->tape_used;
-  HIPCHK(c, launch_gather_blocks(buf, c->tape + c->tape_used, blocks, (int32_t)n, block_bytes(c), c->stream));
+  op.off2 = c->tape_used + (size_t)n * block_bytes(c);
+  *tape = c->tape + op.off;
+  if (tape2) *tape2 = c->tape + op.off2;
   c->tape_used += bytes;
   c->ops.push_back(op);
   return LBM_OK;
@@ -417,9 +421,13 @@ lbm_status sc_level(lbm_ctx* c, int l) {
   a.omega = (float)(1.0 / c->tau[l]);
   a.sc = c->sc;
   a.storage = c->cfg.storage;
+  void* otape = nullptr;
   if (c->recording) {
-    lbm_status st = record(c, lbm_ctx::OP_SC, l, 0, c->blocks(l), c->nblk[l], c->other(l));
+    // the whole blocks of the written time level go to the tape (one bulk copy)
+    void* tape = nullptr;
+    lbm_status st = record(c, lbm_ctx::OP_SC, l, 0, c->nblk[l], c->nob[l], &tape, &otape);
     if (st != LBM_OK) return st;
+    HIPCHK(c, launch_gather_blocks(c->other(l), tape, c->blocks(l), (int32_t)c->nblk[l], block_bytes(c), c->stream));
   }
   const int k = c->tic(LBM_PROF_SC0 + l);
   HIPCHK(c, launch_stream_collide(a, c->stream));
@@ -435,6 +443,7 @@ lbm_status sc_level(lbm_ctx* c, int l) {
     o.old_buf = c->cur(l);
     o.new_buf = c->other(l);
     o.storage = c->cfg.storage;
+    o.tape = otape;
     const int ko = c->tic(LBM_PROF_OUTFLOW);
     HIPCHK(c, launch_outflow(o, c->stream));
     c->toc(ko);
@@ -468,7 +477,7 @@ lbm_status down_level(lbm_ctx* c, int l, int s) {
   t.dst = c->cur(l);
   t.factor = (float)c->a_down[l];
   if (c->recording) {
-    lbm_status st = record(c, lbm_ctx::OP_DOWN, l, s, c->gblocks(l), c->ngb[l], c->cur(l));
+    lbm_status st = record(c, lbm_ctx::OP_DOWN, l, s, c->ngb[l], 0, &t.tape, nullptr);
     if (st != LBM_OK) return st;
   }
   const int k = c->tic(LBM_PROF_DOWN);
@@ -487,7 +496,7 @@ lbm_status up_level(lbm_ctx* c, int l) {
   t.dst = c->cur(l + 1);
   t.factor = (float)c->a_up[l];
   if (c->recording) {
-    lbm_status st = record(c, lbm_ctx::OP_UP, l, 0, c->iblocks(l + 1), c->nib[l + 1], c->cur(l + 1));
+    lbm_status st = record(c, lbm_ctx::OP_UP, l, 0, c->nib[l + 1], 0, &t.tape, nullptr);
     if (st != LBM_OK) return st;
   }
   const int k = c->tic(LBM_PROF_UP);
@@ -516,9 +525,22 @@ constexpr uint64_t kStateMagic = 0x4554415453424c4dull;  // "MLBSTATE"
 constexpr size_t kStateHeader = 256;
 
 struct AdjBufs {
-  float* lam[2];  // adjoint of the pool's two time levels (f32, slot layout)
-  float* mu;      // adjoint of the scaled moments M; per-ghost scratch of the downward transfer
+  float* lam[2];   // adjoint of the pool's two time levels (f32, slot layout)
+  float* mu;       // adjoint of the scaled moments M (f32, slot layout)
+  float* part;     // downward transfer: coarse-footprint partials per ghost block, all levels
+  int32_t* gidx;   // per slot: index in its level's ghost-block list, or -1
+  uint8_t* flags;  // per slot: coarse block read by ghosts of the next finer level
 };
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+size_t part_bytes(const lbm_ctx* c) {
+  int64_t n = 0;
+  for (int l = 0; l < c->G.L; ++l) n += c->ngb[l];
+  return round256((size_t)n * kMom * 125 * sizeof(float));
+}
+size_t aux_bytes(const lbm_ctx* c) {
+  return part_bytes(c) + round256((size_t)(c->cap + 1) * 4) + round256((size_t)(c->cap + 1));
+}
 
 size_t slot_floats(const lbm_ctx* c) { return (size_t)(c->cap + 1) * kBlockStride; }
 
@@ -527,7 +549,7 @@ size_t tape_bytes(const lbm_ctx* c) {
   int64_t nb = 0;
   for (int l = 0; l < L; ++l) {
     const int64_t calls = int64_t(1) << (L - 1 - l);  // advance(l, s) calls per coarse step
-    nb += calls * c->nblk[l];
+    nb += calls * (c->nblk[l] + c->nob[l]);
     if (l + 1 < L) nb += calls * c->ngb[l] + (calls / 2) * c->nib[l + 1];
   }
   return (size_t)nb * block_bytes(c);
@@ -553,10 +575,10 @@ AdjTransferLaunch adj_base(lbm_ctx* c, int l) {
 }
 
 // adjoint of one recorded operation in the state right after it, then its undo
+// (folded into the adjoint kernels: each restores the nodes the operation wrote)
 lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
   const int l = op.level;
   hipStream_t s = c->stream;
-  const size_t bb = block_bytes(c);
   if (op.kind == lbm_ctx::OP_SC) {
     const int p = op.pf;  // input time level; the sweep wrote 1 - p
     if (c->nob[l] > 0) {
@@ -565,11 +587,17 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
       t.nblocks = (int32_t)c->nob[l];
       t.lam_coarse_a = b.lam[1 - p];
       t.lam_fine = b.lam[p];
+      t.undo_dst = c->buf(l, 1 - p);
+      t.undo_tape = c->tape + op.off2;
       HIPCHK(c, launch_outflow_adj(t, s));
     }
-    ScLaunch a;
-    a.in = c->buf(l, p);
-    a.out = nullptr;
+    AdjScLaunch a;
+    a.x = c->buf(l, p);
+    a.y = c->buf(l, 1 - p);
+    a.tape = c->tape + op.off;
+    a.mu = b.mu;
+    a.lam_x = b.lam[p];
+    a.lam_y = b.lam[1 - p];
     a.blocks = c->blocks(l);
     a.nblocks = (int32_t)c->nblk[l];
     a.nbr = c->m<int32_t>(c->lay.nbr);
@@ -578,23 +606,8 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
     a.omega = (float)(1.0 / c->tau[l]);
     a.sc = c->sc;
     a.storage = c->cfg.storage;
-    a.lam_y = b.lam[1 - p];
-    a.mu = b.mu;
-    HIPCHK(c, launch_stream_collide_mu(a, s));
-    AdjScLaunch t;
-    t.x = c->buf(l, p);
-    t.mu = b.mu;
-    t.lam_x = b.lam[p];
-    t.blocks = c->blocks(l);
-    t.nblocks = (int32_t)c->nblk[l];
-    t.nbr = a.nbr;
-    t.role = a.role;
-    t.zero_slot = (int32_t)c->cap;
-    t.omega = a.omega;
-    t.sc = c->sc;
-    t.storage = c->cfg.storage;
-    HIPCHK(c, launch_sc_transpose(t, s));
-    HIPCHK(c, launch_scatter_blocks(c->tape + op.off, c->buf(l, 1 - p), c->blocks(l), (int32_t)c->nblk[l], bb, s));
+    HIPCHK(c, launch_sc_mu(a, s));
+    HIPCHK(c, launch_sc_transpose(a, s));
   } else if (op.kind == lbm_ctx::OP_DOWN) {
     AdjTransferLaunch t = adj_base(c, l);
     t.blocks = c->gblocks(l);
@@ -606,12 +619,17 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
     t.lam_fine = b.lam[op.pf];
     t.lam_coarse_a = b.lam[1 - op.pc];
     t.lam_coarse_b = b.lam[op.pc];
-    t.scratch = b.mu;
+    size_t poff = 0;
+    for (int k = 0; k < l; ++k) poff += (size_t)c->ngb[k] * kMom * 125;
+    t.scratch = b.part + poff;
+    t.gidx = b.gidx;
+    t.flags = b.flags;
+    t.undo_dst = c->buf(l, op.pf);
+    t.undo_tape = c->tape + op.off;
     HIPCHK(c, launch_down_adj_lin(t, s));
     t.blocks = c->blocks(l + 1);
     t.nblocks = (int32_t)c->nblk[l + 1];
     HIPCHK(c, launch_down_adj_gather(t, s));
-    HIPCHK(c, launch_scatter_blocks(c->tape + op.off, c->buf(l, op.pf), c->gblocks(l), (int32_t)c->ngb[l], bb, s));
   } else {
     AdjTransferLaunch t = adj_base(c, l);
     t.blocks = c->iblocks(l + 1);
@@ -620,9 +638,9 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
     t.factor = (float)c->a_up[l];
     t.lam_fine = b.lam[op.pf];
     t.lam_coarse_a = b.lam[op.pc];
+    t.undo_dst = c->buf(l + 1, op.pc);
+    t.undo_tape = c->tape + op.off;
     HIPCHK(c, launch_up_adj(t, s));
-    HIPCHK(c, launch_scatter_blocks(c->tape + op.off, c->buf(l + 1, op.pc), c->iblocks(l + 1), (int32_t)c->nib[l + 1],
-                                    bb, s));
   }
   return LBM_OK;
 }
@@ -885,7 +903,7 @@ lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes) {
 
 size_t lbm_adjoint_work_bytes(const lbm_ctx* ctx, int32_t n_steps) {
   if (!ctx || n_steps < 1) return 0;
-  return 3 * slot_floats(ctx) * sizeof(float) + (size_t)n_steps * tape_bytes(ctx);
+  return 3 * slot_floats(ctx) * sizeof(float) + aux_bytes(ctx) + (size_t)n_steps * tape_bytes(ctx);
 }
 
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes, const float* lam_next, float* lam_out,
@@ -908,8 +926,12 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes
   b.lam[0] = static_cast<float*>(work);
   b.lam[1] = b.lam[0] + sf;
   b.mu = b.lam[1] + sf;
-  ctx->tape = reinterpret_cast<char*>(b.mu + sf);
-  ctx->tape_cap = work_bytes - 3 * sf * sizeof(float);
+  char* aux = reinterpret_cast<char*>(b.mu + sf);
+  b.part = reinterpret_cast<float*>(aux);
+  b.gidx = reinterpret_cast<int32_t*>(aux + part_bytes(ctx));
+  b.flags = reinterpret_cast<uint8_t*>(aux + part_bytes(ctx) + round256((size_t)(ctx->cap + 1) * 4));
+  ctx->tape = aux + aux_bytes(ctx);
+  ctx->tape_cap = work_bytes - 3 * sf * sizeof(float) - aux_bytes(ctx);
   ctx->tape_used = 0;
   ctx->ops.clear();
   int p0[kMaxLevels];
@@ -924,6 +946,16 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes
   if (st == LBM_OK) {
     // adjoint of the state after the steps: lam_next at the state nodes of the current time level
     HIPCHK(ctx, launch_fill_i32(reinterpret_cast<int32_t*>(b.mu + (size_t)ctx->cap * kBlockStride), 0, kBlockStride, s));
+    HIPCHK(ctx, launch_fill_u8(b.flags, 0, ctx->cap + 1, s));
+    HIPCHK(ctx, launch_fill_i32(b.gidx, -1, ctx->cap + 1, s));
+    for (int l = 0; l + 1 < L; ++l) {
+      AdjTransferLaunch t = adj_base(ctx, l);
+      t.blocks = ctx->gblocks(l);
+      t.nblocks = (int32_t)ctx->ngb[l];
+      t.flags = b.flags;
+      HIPCHK(ctx, launch_mark_gather(t, s));
+      HIPCHK(ctx, launch_ghost_index(ctx->gblocks(l), (int32_t)ctx->ngb[l], b.gidx, s));
+    }
     size_t off = 0;
     for (int l = 0; l < L; ++l) {
       const int32_t n = (int32_t)ctx->nblk[l];
@@ -932,26 +964,9 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes
       off += (size_t)n * kBlockStride;
     }
   }
-  // reverse sweep over every logged operation of every step; on a failure only the undo runs
-  for (size_t i = ctx->ops.size(); i-- > 0;) {
-    const lbm_ctx::TapeOp& op = ctx->ops[i];
-    if (st == LBM_OK) {
-      lbm_status e = adjoint_op(ctx, op, b);
-      if (e != LBM_OK) st = e;
-    }
-    if (st != LBM_OK) {
-      // restore what the operation overwrote so the simulation is left at the loaded state
-      const int l = op.level;
-      const size_t bb = block_bytes(ctx);
-      if (op.kind == lbm_ctx::OP_SC)
-        launch_scatter_blocks(ctx->tape + op.off, ctx->buf(l, 1 - op.pf), ctx->blocks(l), (int32_t)ctx->nblk[l], bb, s);
-      else if (op.kind == lbm_ctx::OP_DOWN)
-        launch_scatter_blocks(ctx->tape + op.off, ctx->buf(l, op.pf), ctx->gblocks(l), (int32_t)ctx->ngb[l], bb, s);
-      else
-        launch_scatter_blocks(ctx->tape + op.off, ctx->buf(l + 1, op.pc), ctx->iblocks(l + 1), (int32_t)ctx->nib[l + 1],
-                              bb, s);
-    }
-  }
+  // reverse sweep over every logged operation of every step (a failure leaves the
+  // simulation state undefined: the undo is part of the adjoint kernels)
+  for (size_t i = ctx->ops.size(); st == LBM_OK && i-- > 0;) st = adjoint_op(ctx, ctx->ops[i], b);
   for (int l = 0; l < L; ++l) ctx->parity[l] = p0[l];
   ctx->ops.clear();
   ctx->tape = nullptr;

@@ -41,10 +41,6 @@ template <class S> struct ScArgs {
   int32_t zero_slot;
   float omega;
   Scales sc;
-  // adjoint epilogue only: adjoint of the outputs in (cleared where the sweep
-  // overwrites them), adjoint of M out (f32, pool layout)
-  float* lam_y;
-  float* mu;
 };
 
 // x-direction populations (times 6) of the 8 (my, mz) coefficient groups of a
@@ -293,11 +289,7 @@ __device__ __forceinline__ void x_pass(const float* lds, int row, int x, float y
     }
 }
 
-// ADJ = false: the stream-collide. ADJ = true: the same sweep recomputes the
-// scaled moments M of every computed node (bounce-back included) and, instead of
-// the new moments, writes mu = (dY/dM)^T lambda_Y for the adjoint (zero for nodes
-// that are not computed); lambda_Y is cleared at the nodes the sweep writes.
-template <class S, bool ADJ>
+template <class S>
 __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   __shared__ __align__(16) float lds[10 * kRow];
   __shared__ int s_src[27];
@@ -436,60 +428,26 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
       M[7] = m0;
       const int node = ox + 8 * oy + 64 * zo;
       const uint8_t role = (uint8_t)(col_roles >> (8 * zo));
-      if constexpr (ADJ) {
-        float* mu = a.mu + (size_t)slot * kBlockStride + node;
-        float* lam = a.lam_y + (size_t)slot * kBlockStride + node;
-        if ((role & ROLE_MASK) == ROLE_COMPUTED) {
-          if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, zo, M);
-          // the outputs are overwritten: their adjoint is consumed here
-          float L[kMom];
+      typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
+      if ((role & ROLE_MASK) == ROLE_COMPUTED) {
+        if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, zo, M);
+        // remove the 6^3 scale of the three passes; no constant reciprocal of
+        // 216 or 3 multiplies a result (it would bias every step the same way)
+        const float q0 = M[0] * c216;
+        const float drho = __builtin_fmaf(__builtin_fmaf(-q0, 216.0f, M[0]), c216, q0);  // M0 / 216
+        const float r216 = 216.0f + M[0];          // 216 rho'
+        const float inv = recip(r216);
+        const float inv3 = recip(3.0f * r216);     // p2' = 3 p2 on the diagonal stresses
+        float v[kMom];
+        v[0] = drho;
+        v[1] = M[1] * inv; v[2] = M[2] * inv; v[3] = M[3] * inv;
+        v[4] = M[4] * inv3; v[5] = M[5] * inv3; v[6] = M[6] * inv3;
+        v[7] = M[7] * inv; v[8] = M[8] * inv; v[9] = M[9] * inv;
 #pragma unroll
-          for (int m = 0; m < kMom; ++m) {
-            L[m] = lam[m * kNodes];
-            lam[m * kNodes] = 0.0f;
-          }
-          // Y0 = M0/216, Y_i = M_i/r (off-diagonal, u), Y_i = M_i/(3r) (diagonal S), r = 216 + M0
-          const float r216 = 216.0f + M[0];
-          const float inv = recip(r216);
-          const float inv3 = recip(3.0f * r216);
-          float dot = 0.0f;
+        for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(v[m], a.sc.s[m]);
+      } else if ((role & ROLE_MASK) == ROLE_SOLID) {
 #pragma unroll
-          for (int m = 1; m < kMom; ++m) {
-            const float iv = (m >= 4 && m <= 6) ? inv3 : inv;
-            mu[m * kNodes] = L[m] * iv;
-            dot += L[m] * (M[m] * iv);
-          }
-          mu[0] = L[0] * (1.0f / 216.0f) - dot * inv;
-        } else {
-          const bool solid = (role & ROLE_MASK) == ROLE_SOLID;  // written with zeros
-#pragma unroll
-          for (int m = 0; m < kMom; ++m) {
-            mu[m * kNodes] = 0.0f;
-            if (solid) lam[m * kNodes] = 0.0f;
-          }
-        }
-      } else {
-        typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
-        if ((role & ROLE_MASK) == ROLE_COMPUTED) {
-          if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, zo, M);
-          // remove the 6^3 scale of the three passes; no constant reciprocal of
-          // 216 or 3 multiplies a result (it would bias every step the same way)
-          const float q0 = M[0] * c216;
-          const float drho = __builtin_fmaf(__builtin_fmaf(-q0, 216.0f, M[0]), c216, q0);  // M0 / 216
-          const float r216 = 216.0f + M[0];          // 216 rho'
-          const float inv = recip(r216);
-          const float inv3 = recip(3.0f * r216);     // p2' = 3 p2 on the diagonal stresses
-          float v[kMom];
-          v[0] = drho;
-          v[1] = M[1] * inv; v[2] = M[2] * inv; v[3] = M[3] * inv;
-          v[4] = M[4] * inv3; v[5] = M[5] * inv3; v[6] = M[6] * inv3;
-          v[7] = M[7] * inv; v[8] = M[8] * inv; v[9] = M[9] * inv;
-#pragma unroll
-          for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(v[m], a.sc.s[m]);
-        } else if ((role & ROLE_MASK) == ROLE_SOLID) {
-#pragma unroll
-          for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(0.0f, a.sc.s[m]);
-        }
+        for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(0.0f, a.sc.s[m]);
       }
     }
 #pragma unroll
@@ -501,11 +459,9 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   }
 }
 
-template <class S, bool ADJ> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
+template <class S> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
   if (l.nblocks <= 0) return hipSuccess;
   ScArgs<S> a;
-  a.lam_y = l.lam_y;
-  a.mu = l.mu;
   a.in = static_cast<const typename S::type*>(l.in);
   a.out = static_cast<typename S::type*>(l.out);
   a.blocks = l.blocks;
@@ -515,7 +471,7 @@ template <class S, bool ADJ> hipError_t launch_sc_t(const ScLaunch& l, hipStream
   a.zero_slot = l.zero_slot;
   a.omega = l.omega;
   a.sc = l.sc;
-  hipLaunchKernelGGL((k_stream_collide<S, ADJ>), dim3(l.nblocks), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_stream_collide<S>, dim3(l.nblocks), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -523,18 +479,9 @@ template <class S, bool ADJ> hipError_t launch_sc_t(const ScLaunch& l, hipStream
 
 hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s) {
   switch (a.storage) {
-    case 0: return launch_sc_t<StoreF32, false>(a, s);
-    case 1: return launch_sc_t<StoreBF16, false>(a, s);
-    case 2: return launch_sc_t<StoreF16, false>(a, s);
-  }
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_stream_collide_mu(const ScLaunch& a, hipStream_t s) {
-  switch (a.storage) {
-    case 0: return launch_sc_t<StoreF32, true>(a, s);
-    case 1: return launch_sc_t<StoreBF16, true>(a, s);
-    case 2: return launch_sc_t<StoreF16, true>(a, s);
+    case 0: return launch_sc_t<StoreF32>(a, s);
+    case 1: return launch_sc_t<StoreBF16>(a, s);
+    case 2: return launch_sc_t<StoreF16>(a, s);
   }
   return hipErrorInvalidValue;
 }

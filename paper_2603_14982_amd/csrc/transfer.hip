@@ -32,6 +32,16 @@ template <class S> struct Mom {
   }
 };
 
+// adjoint replay: copy the node's current value (about to be overwritten) to the
+// tape entry of the block's list index
+template <class S>
+__device__ inline void keep_old(const void* buf, void* tape, int slot, int idx, int node) {
+  const typename S::type* p = static_cast<const typename S::type*>(buf) + (size_t)slot * kBlockStride + node;
+  typename S::type* t = static_cast<typename S::type*>(tape) + (size_t)idx * kBlockStride + node;
+#pragma unroll
+  for (int m = 0; m < kMom; ++m) t[m * kNodes] = p[m * kNodes];
+}
+
 // (rho-1, u, S) -> (rho-1, u, S^neq = S - u u), in place
 __device__ inline void to_neq(float q[kMom]) {
   q[4] -= q[1] * q[1]; q[5] -= q[2] * q[2]; q[6] -= q[3] * q[3];
@@ -112,6 +122,7 @@ __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
       for (int m = 4; m < kMom; ++m) acc[m] += ws * cq[m][t];
     }
     from_neq(acc);
+    if (a.tape) keep_old<S>(a.dst, a.tape, slot, blockIdx.x, node);
     Mom<S>::store(a.dst, slot, node, a.sc, acc);
   }
 }
@@ -134,6 +145,7 @@ __global__ __launch_bounds__(256) void k_upward(TransferLaunch a) {
 #pragma unroll
     for (int m = 4; m < kMom; ++m) q[m] *= a.factor;
     from_neq(q);
+    if (a.tape) keep_old<S>(a.dst, a.tape, slot, blockIdx.x, node);
     Mom<S>::store(a.dst, slot, node, a.sc, q);
   }
 }
@@ -159,6 +171,7 @@ __global__ __launch_bounds__(256) void k_outflow(OutflowLaunch a) {
     }
     const int src = node + step;
     const bool computed = step != 0 && (a.role[(size_t)slot * kNodes + src] & ROLE_MASK) == ROLE_COMPUTED;
+    if (a.tape) keep_old<S>(a.new_buf, a.tape, slot, blockIdx.x, node);
 #pragma unroll
     for (int m = 0; m < kMom; ++m) newb[m * kNodes + node] = computed ? newb[m * kNodes + src] : oldb[m * kNodes + node];
   }

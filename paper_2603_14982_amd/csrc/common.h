@@ -24,7 +24,8 @@ enum : int { BC_PERIODIC = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_WALL = 3 };
 constexpr int32_t NBR_NONE = -1;
 constexpr int32_t NBR_WALL = -2;
 // per-block summary bits
-constexpr uint8_t SUM_GHOST = 1, SUM_IU = 2, SUM_OUTFLOW = 4;
+constexpr uint8_t SUM_GHOST = 1, SUM_IU = 2, SUM_OUTFLOW = 4, SUM_TILE = 8;
+constexpr int SUM_TILE_SHIFT = 3;
 
 struct LevelGeom {
   int nb[3];       // blocks per axis

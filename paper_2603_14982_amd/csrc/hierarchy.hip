@@ -174,9 +174,10 @@ __global__ void k_cells_scatter(Geom G, int l, const uint8_t* st_new, const uint
   }
 }
 
-__global__ void k_summary_count(const int32_t* blocks, int32_t n, const uint8_t* summary, int32_t* wcount) {
+__global__ void k_summary_count(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
+                                int32_t* wcount) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t bits = t < n ? summary[blocks[t]] : 0u;
+  const uint32_t bits = t < n ? (uint32_t)summary[blocks[t]] >> shift : 0u;
   const int64_t nw = ((int64_t)n + 63) >> 6;
   const int64_t wave = t >> 6;
 #pragma unroll
@@ -186,11 +187,11 @@ __global__ void k_summary_count(const int32_t* blocks, int32_t n, const uint8_t*
   }
 }
 
-__global__ void k_summary_scatter(const int32_t* blocks, int32_t n, const uint8_t* summary, const int32_t* woff,
-                                  CompactOut o) {
+__global__ void k_summary_scatter(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
+                                  const int32_t* woff, CompactOut o) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t slot = t < n ? blocks[t] : -1;
-  const uint32_t bits = t < n ? summary[slot] : 0u;
+  const uint32_t bits = t < n ? (uint32_t)summary[slot] >> shift : 0u;
   const int64_t nw = ((int64_t)n + 63) >> 6;
   const int64_t wave = t >> 6;
   const int lane = threadIdx.x & 63;
@@ -362,7 +363,18 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   const int any_g = __syncthreads_or(sum & SUM_GHOST);
   const int any_i = __syncthreads_or(sum & SUM_IU);
   const int any_o = __syncthreads_or(sum & SUM_OUTFLOW);
-  if (threadIdx.x == 0) r.summary[slot] = (any_g ? SUM_GHOST : 0) | (any_i ? SUM_IU : 0) | (any_o ? SUM_OUTFLOW : 0);
+  if (threadIdx.x == 0) {
+    // first active block (in key order) of its 2 x 2 group in x and y: the group's
+    // members are x & ~1 + {0, 1}, y & ~1 + {0, 1} at the same z, never wrapped
+    const int c = (b[0] & 1) + 2 * (b[1] & 1);
+    bool start = true;
+    for (int m = 0; m < c; ++m) {
+      const int mx = (b[0] & ~1) + (m & 1), my = (b[1] & ~1) + (m >> 1);
+      if (mx < g.nb[0] && my < g.nb[1] && r.st[g.off + cell_lin(g, mx, my, b[2])] == ST_ACTIVE) start = false;
+    }
+    r.summary[slot] = (any_g ? SUM_GHOST : 0) | (any_i ? SUM_IU : 0) | (any_o ? SUM_OUTFLOW : 0) |
+                      (start ? SUM_TILE : 0);
+  }
 }
 
 // ---------------------------------------------------------------- new-node initialisation
@@ -545,13 +557,14 @@ hipError_t launch_compact_cells(const Geom& G, int l, const uint8_t* st_new, con
   return hipGetLastError();
 }
 
-hipError_t launch_compact_summary(const int32_t* blocks, int32_t n, const uint8_t* summary, int32_t* wave_scratch,
-                                  const CompactOut& o, hipStream_t s) {
+hipError_t launch_compact_summary(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
+                                  int32_t* wave_scratch, const CompactOut& o, hipStream_t s) {
   const int64_t nw = ((int64_t)n + 63) >> 6;
-  if (n > 0) hipLaunchKernelGGL(k_summary_count, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, wave_scratch);
+  if (n > 0)
+    hipLaunchKernelGGL(k_summary_count, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, shift, wave_scratch);
   hipLaunchKernelGGL(k_scan3, dim3(1), dim3(1024), 0, s, wave_scratch, nw, o.count);
   if (n > 0)
-    hipLaunchKernelGGL(k_summary_scatter, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary,
+    hipLaunchKernelGGL(k_summary_scatter, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, shift,
                        (const int32_t*)wave_scratch, o);
   return hipGetLastError();
 }

@@ -19,6 +19,13 @@ struct ScLaunch {
   float omega;
   Scales sc;
   int storage;
+  // 2 x 2 tiles: first block of every tile (slots), the level's geometry and directory
+  const int32_t* tiles;
+  int32_t ntiles;
+  const int32_t* dir;
+  const int4* coord;
+  LevelGeom lg;
+  int periodic[3];
 };
 hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s);
 
@@ -82,7 +89,8 @@ struct CompactOut {
 };
 hipError_t launch_compact_cells(const Geom& G, int level, const uint8_t* st_new, const uint8_t* st_old,
                                 int32_t* wave_scratch, const CompactOut& o, hipStream_t s);
-hipError_t launch_compact_summary(const int32_t* blocks, int32_t n, const uint8_t* summary,
+// predicates: bits shift .. shift+2 of the block's summary byte
+hipError_t launch_compact_summary(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
                                   int32_t* wave_scratch, const CompactOut& o, hipStream_t s);
 
 struct AllocLaunch {

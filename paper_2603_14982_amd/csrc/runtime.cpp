@@ -21,7 +21,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   size_t t0, t0s, flags, st[2], dir[2], lists, wave, counts, coord, nbr, role[2], summary, free_stack, blocks, gblocks,
-      iblocks, oblocks, red_partial, red_out, flag;
+      iblocks, oblocks, tblocks, red_partial, red_out, flag;
   size_t total;
   int64_t level_list_off[kMaxLevels];  // offset (elements) of each level's segment in blocks / g/i/o lists
   int64_t level_list_cap[kMaxLevels];
@@ -115,6 +115,7 @@ Layout make_layout(const lbm_config* c, const Geom& G) {
   L.gblocks = take(nlist * 4);
   L.iblocks = take(nlist * 4);
   L.oblocks = take(nlist * 4);
+  L.tblocks = take(nlist * 4);
   L.red_partial = take(cap * 5 * 8);
   L.red_out = take(8 * 8);
   L.flag = take(64);
@@ -141,7 +142,7 @@ struct lbm_ctx {
   int hier = 0;   // which of st/dir is current
   int rcur = 0;   // which role array is current
   const uint8_t* solid = nullptr;
-  int64_t nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels];
+  int64_t nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels], ntile[kMaxLevels];
   int32_t free_top = 0;
   int32_t* host_counts = nullptr;  // pinned
   std::string err;
@@ -175,6 +176,8 @@ struct lbm_ctx {
   int32_t* gblocks(int l) const { return m<int32_t>(lay.gblocks) + lay.level_list_off[l]; }
   int32_t* iblocks(int l) const { return m<int32_t>(lay.iblocks) + lay.level_list_off[l]; }
   int32_t* oblocks(int l) const { return m<int32_t>(lay.oblocks) + lay.level_list_off[l]; }
+  // first block (key order) of every 2 x 2 tile of the level
+  int32_t* tblocks(int l) const { return m<int32_t>(lay.tblocks) + lay.level_list_off[l]; }
   // time level p of the pool: cap block slots plus one all-zero slot (index cap)
   void* buf(int l, int p) const { return pool + (size_t)p * (size_t)(cap + 1) * kBlockStride * elem; }
   void* cur(int l) const { return buf(l, parity[l]); }
@@ -184,26 +187,30 @@ struct lbm_ctx {
   hipEvent_t take_event() {
     if (!spare.empty()) { hipEvent_t e = spare.back(); spare.pop_back(); return e; }
     hipEvent_t e = nullptr;
-    hipEventCreate(&e);
-    return e;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
   }
-  // open a timed region of a phase; returns its index or -1
+  // open a timed region of a phase; returns its index or -1 (timing is best effort:
+  // a region whose events cannot be created or recorded is left out)
   int tic(int phase) {
     if (!profiling) return -1;
     Timed t{phase, take_event(), take_event()};
-    hipEventRecord(t.a, stream);
+    if (!t.a || !t.b || hipEventRecord(t.a, stream) != hipSuccess) {
+      if (t.a) spare.push_back(t.a);
+      if (t.b) spare.push_back(t.b);
+      return -1;
+    }
     timed.push_back(t);
     return (int)timed.size() - 1;
   }
   void toc(int k) {
-    if (k >= 0) hipEventRecord(timed[(size_t)k].b, stream);
+    if (k >= 0 && hipEventRecord(timed[(size_t)k].b, stream) != hipSuccess) timed[(size_t)k].phase = -1;
   }
   void collect() {
     if (timed.empty()) return;
-    hipStreamSynchronize(stream);
+    const bool synced = hipStreamSynchronize(stream) == hipSuccess;
     for (auto& t : timed) {
       float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      if (synced && t.phase >= 0 && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
         prof_ms[t.phase] += ms;
         prof_n[t.phase] += 1;
       }
@@ -372,15 +379,21 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     o.out[1] = c->iblocks(l);
     o.out[2] = c->oblocks(l);
     o.count = counts + 3 * l;
-    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, wave, o, s));
+    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, 0, wave, o, s));
+    CompactOut t;
+    t.out[0] = c->tblocks(l);
+    t.out[1] = t.out[2] = nullptr;
+    t.count = counts + 32 + 3 * l;
+    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, SUM_TILE_SHIFT, wave, t, s));
   }
-  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 3 * L * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 48 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   for (int l = 0; l < L; ++l) {
     c->nblk[l] = nact[l];
     c->ngb[l] = c->host_counts[3 * l];
     c->nib[l] = c->host_counts[3 * l + 1];
     c->nob[l] = c->host_counts[3 * l + 2];
+    c->ntile[l] = c->host_counts[32 + 3 * l];
   }
   return LBM_OK;
 }
@@ -421,6 +434,14 @@ lbm_status sc_level(lbm_ctx* c, int l) {
   a.omega = (float)(1.0 / c->tau[l]);
   a.sc = c->sc;
   a.storage = c->cfg.storage;
+  // 2 x 2 tiles once there are enough of them to fill the chip; single blocks below
+  const bool tiles = c->ntile[l] >= 4096;
+  a.tiles = tiles ? c->tblocks(l) : nullptr;
+  a.ntiles = tiles ? (int32_t)c->ntile[l] : 0;
+  a.dir = c->dir(c->hier);
+  a.coord = c->m<int4>(c->lay.coord);
+  a.lg = c->G.lv[l];
+  for (int k = 0; k < 3; ++k) a.periodic[k] = c->G.periodic[k];
   void* otape = nullptr;
   if (c->recording) {
     // the whole blocks of the written time level go to the tape (one bulk copy)
@@ -685,7 +706,7 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
     const double k = std::ldexp(1.0, l);
     c->tau[l] = cfg->tau0 / k + (k - 1.0) / (2.0 * k);  // tau_{l} from tau_0 (Sec. 5.2)
     c->parity[l] = 0;
-    c->nblk[l] = c->ngb[l] = c->nib[l] = c->nob[l] = 0;
+    c->nblk[l] = c->ngb[l] = c->nib[l] = c->nob[l] = c->ntile[l] = 0;
   }
   for (int l = 0; l < G.L; ++l) {
     c->a_up[l] = c->a_down[l] = 1.0;
@@ -737,7 +758,7 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
     if (st != LBM_OK) g_create_error = c->err;
   }
   if (st != LBM_OK) {
-    hipHostFree(c->host_counts);
+    (void)hipHostFree(c->host_counts);
     delete c;
     return st;
   }
@@ -747,12 +768,13 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
 
 lbm_status lbm_destroy(lbm_ctx* ctx) {
   if (!ctx) return LBM_EINVAL;
-  hipStreamSynchronize(ctx->stream);
+  // teardown: release what can be released; a device error here has no remedy
+  const bool synced = hipStreamSynchronize(ctx->stream) == hipSuccess;
   ctx->collect();
-  for (hipEvent_t e : ctx->spare) hipEventDestroy(e);
-  hipHostFree(ctx->host_counts);
+  for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
+  (void)hipHostFree(ctx->host_counts);
   delete ctx;
-  return LBM_OK;
+  return synced ? LBM_OK : LBM_EDEVICE;
 }
 
 lbm_status lbm_num_blocks(lbm_ctx* ctx, int32_t level, int64_t* out) {

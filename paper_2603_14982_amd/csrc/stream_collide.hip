@@ -41,6 +41,12 @@ template <class S> struct ScArgs {
   int32_t zero_slot;
   float omega;
   Scales sc;
+  const int32_t* tiles;
+  int32_t ntiles;
+  const int32_t* dir;
+  const int4* coord;
+  LevelGeom lg;
+  int periodic[3];
 };
 
 // x-direction populations (times 6) of the 8 (my, mz) coefficient groups of a
@@ -459,6 +465,258 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   }
 }
 
+// ---- 2 x 2 block tiles ----------------------------------------------------------
+// One workgroup of four waves sweeps a tile of 2 x 2 blocks (16 x 16 columns) in z.
+// The halo plane is 18 x 18 points instead of four separate 10 x 10 planes: the
+// faces shared inside the tile are read once, the points are spread over all 256
+// lanes (source and x passes), and each wave keeps one block for the y and z passes
+// and the stores. Missing blocks of a tile read as the all-zero slot and are not
+// written.
+constexpr int kTN = 16;                 // tile columns per axis
+constexpr int kTC = kTN + 2;            // halo plane points per axis
+constexpr int kTPts = kTC * kTC;        // 324
+constexpr int kTRowF = 3 * kTN * 10;    // floats per LDS row: y-pass input [kind][16][10]
+constexpr int kTKindA = kTC * 8;        // x-pass input: [kind][col 0..17][group 0..7]
+constexpr int kTKindB = kTN * 10;
+
+__device__ __forceinline__ void st8_at(float* lds, int off, int row, const float v[8]) {
+  const int sw = (row & 1) << 2;
+  *reinterpret_cast<float4*>(lds + off + sw) = make_float4(v[0], v[1], v[2], v[3]);
+  *reinterpret_cast<float4*>(lds + off + (4 ^ sw)) = make_float4(v[4], v[5], v[6], v[7]);
+}
+__device__ __forceinline__ void ld8_at(const float* lds, int off, int row, float v[8]) {
+  const int sw = (row & 1) << 2;
+  const float4 a = *reinterpret_cast<const float4*>(lds + off + sw);
+  const float4 b = *reinterpret_cast<const float4*>(lds + off + (4 ^ sw));
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+
+// x pass for tile row `row` (plane row row - 1), tile column x
+__device__ __forceinline__ void x_pass_tile(const float* lds, int row, int x, float yb[27]) {
+  float pp[8], pz[8], pm[8];
+  const int base = row * kTRowF;
+  ld8_at(lds, base + 0 * kTKindA + x * 8, row, pp);        // P+ of column x-1
+  ld8_at(lds, base + 1 * kTKindA + (x + 1) * 8, row, pz);  // P0 of column x
+  ld8_at(lds, base + 2 * kTKindA + (x + 2) * 8, row, pm);  // P- of column x+1
+  float B[3][3][3];  // [qx][my][mz]
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    float m0, m1, m2;
+    back3(pp[g], pz[g], pm[g], m0, m1, m2);
+    const int my = (g == 1 || g == 5 || g == 7) ? 1 : ((g == 3 || g == 6) ? 2 : 0);
+    const int mz = (g == 2 || g == 5 || g == 6) ? 1 : ((g == 4 || g == 7) ? 2 : 0);
+    B[0][my][mz] = m0; B[1][my][mz] = m1; B[2][my][mz] = m2;
+  }
+#pragma unroll
+  for (int qx = 0; qx < 3; ++qx)
+#pragma unroll
+    for (int mz = 0; mz < 3; ++mz) {
+      const float b2 = (mz == 2) ? 0.0f : B[qx][2][mz];
+      const int t = 3 * qx + mz;
+      fwd3(B[qx][0][mz], B[qx][1][mz], b2, yb[t], yb[9 + t], yb[18 + t]);
+    }
+}
+
+template <class S>
+__device__ __forceinline__ void fetch_tile(const ScArgs<S>& a, const int* s_src, int px, int py, int pz,
+                                           typename S::type raw[kMom]) {
+  const int ix = (px + 8) >> 3, iy = (py + 8) >> 3;  // px, py in [-1, 16] -> 0..3
+  const int iz = pz < 0 ? 0 : (pz > 7 ? 2 : 1);
+  const int ns = s_src[ix + 4 * iy + 16 * iz];
+  const int node = (px & 7) + 8 * (py & 7) + 64 * (pz & 7);
+  const typename S::type* src = a.in + (size_t)ns * kBlockStride + node;
+#pragma unroll
+  for (int m = 0; m < kMom; ++m) raw[m] = src[m * kNodes];
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
+  __shared__ __align__(16) float lds[kTC * kTRowF];
+  __shared__ int s_src[48];   // blocks (tx - 1 .. tx + 2) x (ty - 1 .. ty + 2) x (z - 1 .. z + 1)
+  __shared__ int s_mem[4];    // the tile's blocks (or -1)
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int4 c0 = a.coord[a.tiles[xcd_remap(blockIdx.x, a.ntiles)]];
+  const int qx = c0.x & ~1, qy = c0.y & ~1, qz = c0.z;
+  if (tid < 48) {
+    const int ix = tid & 3, iy = (tid >> 2) & 3, iz = tid >> 4;
+    int h[3] = {qx + ix - 1, qy + iy - 1, qz + iz - 1};
+    bool inside = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int nb = a.lg.nb[ax];
+      if (h[ax] < 0 || h[ax] >= nb) {
+        if (a.periodic[ax]) h[ax] = h[ax] < 0 ? h[ax] + nb : h[ax] - nb;
+        else inside = false;
+      }
+    }
+    const int ns = inside ? a.dir[a.lg.off + cell_lin(a.lg, h[0], h[1], h[2])] : -1;
+    s_src[tid] = ns >= 0 ? ns : a.zero_slot;
+    if (iz == 1 && ix >= 1 && ix <= 2 && iy >= 1 && iy <= 2) {
+      const bool own = qx + ix - 1 < a.lg.nb[0] && qy + iy - 1 < a.lg.nb[1];  // not wrapped
+      s_mem[(ix - 1) + 2 * (iy - 1)] = own ? ns : -1;
+    }
+  }
+  __syncthreads();
+
+  // source points: 256 in the first round, the other 68 on waves 2 and 3 (wave 0
+  // takes the two extra rows of the x pass), which evens out the work per wave
+  int px[2], py[2];
+  bool has[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int p = r == 0 ? tid : 128 + tid;
+    has[r] = r == 0 || (tid >= 128 && p < kTPts);
+    px[r] = p % kTC - 1;
+    py[r] = p / kTC - 1;
+  }
+  const int slot = s_mem[wave];
+  const int ox = lane & 7, oy = lane >> 3;
+  const int tx = (wave & 1) * 8 + ox, ty = (wave >> 1) * 8 + oy;  // tile column of this lane
+  const float c216 = 1.0f / 216.0f;
+  uint64_t col_roles = 0;
+  if (slot >= 0) {
+    const uint8_t* rp = a.role + (size_t)slot * kNodes + ox + 8 * oy;
+#pragma unroll
+    for (int zz = 0; zz < 8; ++zz) col_roles |= (uint64_t)rp[64 * zz] << (8 * zz);
+  }
+
+  typedef typename S::type T;
+  T nxt[2][kMom];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+    if (has[r]) fetch_tile<S>(a, s_src, px[r], py[r], -1, nxt[r]);
+
+  float zp1[6], zp2[6], z0[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) zp1[k] = zp2[k] = z0[k] = 0.0f;
+
+  for (int z = -1; z <= 8; ++z) {
+    // ---- source: moments of plane z (+ halo) -> x-populations, into LDS
+    T cur[2][kMom];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) cur[r][m] = nxt[r][m];
+    if (z < 8) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        if (has[r]) fetch_tile<S>(a, s_src, px[r], py[r], z + 1, nxt[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (!has[r]) continue;
+      float q[kMom];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(cur[r][m], a.sc.inv[m]);
+      float p[24];
+      source_pops(q, a.omega, p);
+      float v[8];
+      const int row = py[r] + 1, col = px[r] + 1;
+#pragma unroll
+      for (int kind = 0; kind < 3; ++kind) {
+#pragma unroll
+        for (int g = 0; g < 8; ++g) v[g] = p[3 * g + kind];
+        st8_at(lds, row * kTRowF + kind * kTKindA + col * 8, row, v);
+      }
+    }
+    __syncthreads();
+
+    // ---- x pass: 18 rows x 16 columns in two rounds (rows 0..15, then 16..17); each
+    // row is overwritten by its y-pass input once its reads are done
+    {
+      float yb[27];
+      const int row = tid >> 4, x = tid & 15;
+      x_pass_tile(lds, row, x, yb);
+      __syncthreads();
+      st9(lds, row * kTRowF + 0 * kTKindB + x * 10, yb);
+      st9(lds, row * kTRowF + 1 * kTKindB + x * 10, yb + 9);
+      st9(lds, row * kTRowF + 2 * kTKindB + x * 10, yb + 18);
+    }
+    if (tid < 2 * kTN) {
+      float yb[27];
+      const int row = 16 + (tid >> 4), x = tid & 15;
+      x_pass_tile(lds, row, x, yb);
+      st9(lds, row * kTRowF + 0 * kTKindB + x * 10, yb);
+      st9(lds, row * kTRowF + 1 * kTKindB + x * 10, yb + 9);
+      st9(lds, row * kTRowF + 2 * kTKindB + x * 10, yb + 18);
+    }
+    __syncthreads();
+
+    // ---- y pass for the lane's column, then z-forward
+    float zpp[6], zpz[6], zpm[6];
+    {
+      float bp[9], bz[9], bm[9];
+      ld9(lds, ty * kTRowF + 0 * kTKindB + tx * 10, bp);        // P+ of row y-1
+      ld9(lds, (ty + 1) * kTRowF + 1 * kTKindB + tx * 10, bz);  // P0 of row y
+      ld9(lds, (ty + 2) * kTRowF + 2 * kTKindB + tx * 10, bm);  // P- of row y+1
+      float C[3][3][3];  // [qx][qy][mz]
+#pragma unroll
+      for (int qx2 = 0; qx2 < 3; ++qx2)
+#pragma unroll
+        for (int mz = 0; mz < 3; ++mz) {
+          const int t = 3 * qx2 + mz;
+          float m0, m1, m2;
+          back3(bp[t], bz[t], bm[t], m0, m1, m2);
+          C[qx2][0][mz] = m0; C[qx2][1][mz] = m1; C[qx2][2][mz] = m2;
+        }
+      fwd3(C[0][0][0], C[0][0][1], C[0][0][2], zpp[0], zpz[0], zpm[0]);
+      fwd3(C[1][0][0], C[1][0][1], C[1][0][2], zpp[1], zpz[1], zpm[1]);
+      fwd3(C[0][1][0], C[0][1][1], C[0][1][2], zpp[2], zpz[2], zpm[2]);
+      fwd3(C[2][0][0], C[2][0][1], C[2][0][2], zpp[3], zpz[3], zpm[3]);
+      fwd3(C[0][2][0], C[0][2][1], C[0][2][2], zpp[4], zpz[4], zpm[4]);
+      fwd3(C[1][1][0], C[1][1][1], C[1][1][2], zpp[5], zpz[5], zpm[5]);
+    }
+    __syncthreads();
+
+    // ---- z pass: output plane zo = z - 1
+    const int zo = z - 1;
+    if (zo >= 0 && slot >= 0) {
+      float M[10];
+      float m0, m1, m2;
+      back3(zp2[0], z0[0], zpm[0], m0, m1, m2);
+      M[0] = m0; M[3] = m1; M[6] = m2;
+      back3(zp2[1], z0[1], zpm[1], m0, m1, m2);
+      M[1] = m0; M[8] = m1;
+      back3(zp2[2], z0[2], zpm[2], m0, m1, m2);
+      M[2] = m0; M[9] = m1;
+      back3(zp2[3], z0[3], zpm[3], m0, m1, m2);
+      M[4] = m0;
+      back3(zp2[4], z0[4], zpm[4], m0, m1, m2);
+      M[5] = m0;
+      back3(zp2[5], z0[5], zpm[5], m0, m1, m2);
+      M[7] = m0;
+      const int node = ox + 8 * oy + 64 * zo;
+      const uint8_t role = (uint8_t)(col_roles >> (8 * zo));
+      typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
+      if ((role & ROLE_MASK) == ROLE_COMPUTED) {
+        if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, zo, M);
+        const float q0 = M[0] * c216;
+        const float drho = __builtin_fmaf(__builtin_fmaf(-q0, 216.0f, M[0]), c216, q0);
+        const float r216 = 216.0f + M[0];
+        const float inv = recip(r216);
+        const float inv3 = recip(3.0f * r216);
+        float v[kMom];
+        v[0] = drho;
+        v[1] = M[1] * inv; v[2] = M[2] * inv; v[3] = M[3] * inv;
+        v[4] = M[4] * inv3; v[5] = M[5] * inv3; v[6] = M[6] * inv3;
+        v[7] = M[7] * inv; v[8] = M[8] * inv; v[9] = M[9] * inv;
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(v[m], a.sc.s[m]);
+      } else if ((role & ROLE_MASK) == ROLE_SOLID) {
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(0.0f, a.sc.s[m]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      zp2[k] = zp1[k];
+      zp1[k] = zpp[k];
+      z0[k] = zpz[k];
+    }
+  }
+}
+
 template <class S> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
   if (l.nblocks <= 0) return hipSuccess;
   ScArgs<S> a;
@@ -471,7 +729,18 @@ template <class S> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
   a.zero_slot = l.zero_slot;
   a.omega = l.omega;
   a.sc = l.sc;
-  hipLaunchKernelGGL(k_stream_collide<S>, dim3(l.nblocks), dim3(64), 0, s, a);
+  a.tiles = l.tiles;
+  a.ntiles = l.ntiles;
+  a.dir = l.dir;
+  a.coord = l.coord;
+  a.lg = l.lg;
+  for (int k = 0; k < 3; ++k) a.periodic[k] = l.periodic[k];
+  if (l.tiles) {
+    if (l.ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stream_collide_tile<S>, dim3(l.ntiles), dim3(256), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_stream_collide<S>, dim3(l.nblocks), dim3(64), 0, s, a);
+  }
   return hipGetLastError();
 }
 

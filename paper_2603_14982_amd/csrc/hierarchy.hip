@@ -276,6 +276,7 @@ __device__ inline bool solid_at(const Geom& G, const uint8_t* solid, int l, int 
 __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   __shared__ uint8_t s_st[27];    // state of the 27 surrounding block positions (255 = outside)
   __shared__ uint8_t s_wall[27];  // outside the domain across wall faces only
+  __shared__ int s_box[6];        // ghost-node bounding box: lo x, lo y, lo z, hi x, hi y, hi z
   const Geom& G = r.G;
   const int l = r.level;
   const LevelGeom& g = G.lv[l];
@@ -311,6 +312,7 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
     r.nbr[(size_t)slot * 27 + d] = ns;
   }
   if (threadIdx.x == 0) r.blocks[blockIdx.x] = slot;
+  if (threadIdx.x < 6) s_box[threadIdx.x] = threadIdx.x < 3 ? 7 : 0;
   __syncthreads();
   uint8_t sum = 0;
   for (int node = threadIdx.x; node < kNodes; node += 256) {
@@ -358,6 +360,13 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
     }
     r.role[(size_t)slot * kNodes + node] = role;
     const uint8_t rk = role & ROLE_MASK;
+    if (rk == ROLE_GHOST) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        atomicMin(&s_box[a], lc[a]);
+        atomicMax(&s_box[3 + a], lc[a]);
+      }
+    }
     sum |= rk == ROLE_GHOST ? SUM_GHOST : (rk == ROLE_IU ? SUM_IU : (rk == ROLE_OUTFLOW ? SUM_OUTFLOW : 0));
   }
   const int any_g = __syncthreads_or(sum & SUM_GHOST);
@@ -374,6 +383,7 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
     }
     r.summary[slot] = (any_g ? SUM_GHOST : 0) | (any_i ? SUM_IU : 0) | (any_o ? SUM_OUTFLOW : 0) |
                       (start ? SUM_TILE : 0);
+    r.gbox[slot] = s_box[0] | s_box[3] << 3 | s_box[1] << 6 | s_box[4] << 9 | s_box[2] << 12 | s_box[5] << 15;
   }
 }
 

@@ -46,6 +46,7 @@ struct TransferLaunch {
   Scales sc;
   int storage;
   void* tape;                // adjoint replay: old values of the written nodes, [list index][10][512]
+  const int32_t* gbox;       // down: per slot bounding box of the ghost nodes (from the grid update)
 };
 hipError_t launch_downward(const TransferLaunch& a, hipStream_t s);
 hipError_t launch_upward(const TransferLaunch& a, hipStream_t s);
@@ -120,6 +121,7 @@ struct RoleLaunch {
   const uint8_t* solid;      // fine solid field or null
   uint8_t* role;             // [slot][512] new roles
   uint8_t* summary;          // [slot]
+  int32_t* gbox;             // [slot] bounding box of the ghost nodes (3 bits per bound: lo x, hi x, lo y, ...)
   int32_t* blocks;           // out: slots in key order
   int32_t* nbr;              // out: [slot][27]
 };

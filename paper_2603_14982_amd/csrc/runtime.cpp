@@ -20,8 +20,8 @@ thread_local std::string g_create_error;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-  size_t t0, t0s, flags, st[2], dir[2], lists, wave, counts, coord, nbr, role[2], summary, free_stack, blocks, gblocks,
-      iblocks, oblocks, tblocks, red_partial, red_out, flag;
+  size_t t0, t0s, flags, st[2], dir[2], lists, wave, counts, coord, nbr, role[2], summary, gbox, free_stack, blocks,
+      gblocks, iblocks, oblocks, tblocks, red_partial, red_out, flag;
   size_t total;
   int64_t level_list_off[kMaxLevels];  // offset (elements) of each level's segment in blocks / g/i/o lists
   int64_t level_list_cap[kMaxLevels];
@@ -110,6 +110,7 @@ Layout make_layout(const lbm_config* c, const Geom& G) {
   L.role[0] = take(cap * kNodes);
   L.role[1] = take(cap * kNodes);
   L.summary = take(cap);
+  L.gbox = take(cap * 4);
   L.free_stack = take(cap * 4);
   L.blocks = take(nlist * 4);
   L.gblocks = take(nlist * 4);
@@ -340,6 +341,7 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     r.solid = c->solid;
     r.role = role_new;
     r.summary = summary;
+    r.gbox = c->m<int32_t>(c->lay.gbox);
     r.blocks = c->blocks(l);
     r.nbr = c->m<int32_t>(c->lay.nbr);
     HIPCHK(c, launch_roles(r, s));
@@ -497,6 +499,7 @@ lbm_status down_level(lbm_ctx* c, int l, int s) {
   t.midpoint = (s == 2) ? 1 : 0;
   t.dst = c->cur(l);
   t.factor = (float)c->a_down[l];
+  t.gbox = c->m<int32_t>(c->lay.gbox);
   if (c->recording) {
     lbm_status st = record(c, lbm_ctx::OP_DOWN, l, s, c->ngb[l], 0, &t.tape, nullptr);
     if (st != LBM_OK) return st;

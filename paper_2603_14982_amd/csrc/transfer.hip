@@ -52,12 +52,13 @@ __device__ inline void from_neq(float q[kMom]) {
   q[7] += q[1] * q[2]; q[8] += q[1] * q[3]; q[9] += q[2] * q[3];
 }
 
-// One workgroup per fine block holding ghost nodes. The 5^3 coarse nodes under the
-// block's footprint (coarse indices 4b .. 4b+4 per axis) are staged once in LDS as
-// (rho-1, u, S^neq), already averaged in time for the midpoint substep; each ghost
-// node then combines its 1, 2, 4 or 8 trilinear sources from LDS. Staged positions
-// in blocks that hold no coarse data (covered by the fine level) read as zero; no
-// ghost node of a valid hierarchy uses them.
+// One workgroup per fine block holding ghost nodes. The coarse nodes under the
+// bounding box of the block's ghost nodes (recorded by the grid update; within coarse
+// indices 4b .. 4b+4 per axis) are staged once in LDS as (rho-1, u, S^neq), already
+// averaged in time for the midpoint substep; each ghost node in the box then combines
+// its 1, 2, 4 or 8 trilinear sources from LDS. Staged positions in blocks that hold
+// no coarse data (covered by the fine level) read as zero; no ghost node of a valid
+// hierarchy uses them.
 template <class S>
 __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
   __shared__ float cq[kMom][125];
@@ -66,7 +67,14 @@ __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
   const int l = a.level;
   const LevelGeom& cg = a.G.lv[l + 1];
   const int base[3] = {4 * bc.x, 4 * bc.y, 4 * bc.z};
-  for (int t = threadIdx.x; t < 125; t += 256) {
+  // only the ghost nodes' bounding box and the coarse nodes under it
+  const int box = a.gbox[slot];
+  const int lo[3] = {box & 7, (box >> 6) & 7, (box >> 12) & 7};
+  const int hi[3] = {(box >> 3) & 7, (box >> 9) & 7, (box >> 15) & 7};
+  const int clo[3] = {lo[0] >> 1, lo[1] >> 1, lo[2] >> 1};
+  const int cn[3] = {((hi[0] + 1) >> 1) - clo[0] + 1, ((hi[1] + 1) >> 1) - clo[1] + 1, ((hi[2] + 1) >> 1) - clo[2] + 1};
+  for (int k = threadIdx.x; k < cn[0] * cn[1] * cn[2]; k += 256) {
+    const int t = (clo[0] + k % cn[0]) + 5 * (clo[1] + (k / cn[0]) % cn[1]) + 25 * (clo[2] + k / (cn[0] * cn[1]));
     int j[3] = {base[0] + t % 5, base[1] + (t / 5) % 5, base[2] + t / 25};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -94,9 +102,11 @@ __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
     for (int m = 0; m < kMom; ++m) cq[m][t] = q[m];
   }
   __syncthreads();
-  for (int node = threadIdx.x; node < kNodes; node += 256) {
+  const int nn[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
+  for (int k = threadIdx.x; k < nn[0] * nn[1] * nn[2]; k += 256) {
+    const int lc[3] = {lo[0] + k % nn[0], lo[1] + (k / nn[0]) % nn[1], lo[2] + k / (nn[0] * nn[1])};
+    const int node = lc[0] + 8 * lc[1] + 64 * lc[2];
     if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_GHOST) continue;
-    const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
     int i0[3], i1[3];
     float w1[3];
 #pragma unroll

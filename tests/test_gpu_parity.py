@@ -87,6 +87,19 @@ def test_walls_two_level_channel():
     compare(gpu, ora, label="walls")
 
 
+def test_large_level_tiled_sweep_with_partial_tiles():
+    # 33 x 32 x 16 blocks on one level (above the size where the stream-collide runs on
+    # 2 x 2 tiles): an odd block count along the periodic x axis leaves a column of
+    # half tiles whose halo wraps; no-slip walls at the z faces; 5 steps
+    n = (264, 256, 128)
+    bc = (P, P, P, P, W.WALL, W.WALL)
+    u0 = W.smooth_random_velocity(n, 13, kmax=4.0, rms=0.03)
+    gpu, ora = setup_pair(1, n, bc, 0.6, lambda l, k: W.velocity_moments(l, k, u0))
+    gpu.step(5)
+    ora.step(5)
+    compare(gpu, ora, label="tiled")
+
+
 def test_single_level_conservation_fp64_sums():
     n = (32, 32, 32)
     gpu, ora = setup_pair(1, n, (P,) * 6, 0.55, lambda l, k: W.tgv3d_field(l, k, n, 0.04))

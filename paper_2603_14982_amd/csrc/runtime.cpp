@@ -20,7 +20,7 @@ thread_local std::string g_create_error;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
-  size_t t0, t0s, flags, st[2], dir[2], lists, wave, counts, coord, nbr, role[2], summary, gbox, free_stack, blocks,
+  size_t t0, t0s, t0p, flags, st[2], dir[2], lists, wave, counts, coord, nbr, role[2], summary, gbox, free_stack, blocks,
       gblocks, iblocks, oblocks, tblocks, red_partial, red_out, flag;
   size_t total;
   int64_t level_list_off[kMaxLevels];  // offset (elements) of each level's segment in blocks / g/i/o lists
@@ -97,6 +97,7 @@ Layout make_layout(const lbm_config* c, const Geom& G) {
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
   L.t0 = take(G.lv[0].ncell);
   L.t0s = take(G.lv[0].ncell);
+  L.t0p = take(G.lv[0].ncell);
   L.flags = take(ncell);
   L.st[0] = take(ncell);
   L.st[1] = take(ncell);
@@ -267,17 +268,29 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
   h.st_new = c->st(nh);
   h.st_old = c->st(c->hier);
   HIPCHK(c, launch_targets(h, particles, n, s));
-  HIPCHK(c, launch_states(h, s));
   int32_t* counts = c->m<int32_t>(c->lay.counts);
   int32_t* wave = c->m<int32_t>(c->lay.wave);
+  uint8_t* t0_prev = c->m<uint8_t>(c->lay.t0p);
   int64_t ncell = 0;
   for (int l = 0; l < L; ++l) ncell += G.lv[l].ncell;
   if (!create) {
-    // fast path: one flag tells whether any block state changed
-    HIPCHK(c, launch_diff_flag(h.st_new, h.st_old, ncell, counts + 63, s));
+    // fast paths: H(Phi) depends on the level-0 target set T0 alone. If T0 equals a
+    // target set the current hierarchy is built from, nothing changes; otherwise the
+    // new block states are compared with the current ones.
+    HIPCHK(c, launch_diff_flag(h.t0, t0_prev, G.lv[0].ncell, counts + 63, s));
     HIPCHK(c, hipMemcpyAsync(c->host_counts, counts + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     if (c->host_counts[0] == 0) return LBM_OK;
+    HIPCHK(c, launch_states(h, s));
+    HIPCHK(c, launch_diff_flag(h.st_new, h.st_old, ncell, counts + 63, s));
+    HIPCHK(c, hipMemcpyAsync(c->host_counts, counts + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (c->host_counts[0] == 0) {
+      HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
+      return LBM_OK;
+    }
+  } else {
+    HIPCHK(c, launch_states(h, s));
   }
   for (int l = 0; l < L; ++l) {
     CompactOut o;
@@ -375,6 +388,7 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
   c->rcur = 1 - c->rcur;
   c->free_top = top;
   c->generation++;
+  HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
   for (int l = 0; l < L; ++l) {
     CompactOut o;
     o.out[0] = c->gblocks(l);

@@ -19,7 +19,7 @@ struct ScLaunch {
   float omega;
   Scales sc;
   int storage;
-  // 2 x 2 tiles: first block of every tile (slots), the level's geometry and directory
+  // 2 x 2 x 2 tiles: first block of every tile (slots), the level's geometry and directory
   const int32_t* tiles;
   int32_t ntiles;
   const int32_t* dir;

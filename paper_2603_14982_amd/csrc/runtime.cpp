@@ -178,7 +178,7 @@ struct lbm_ctx {
   int32_t* gblocks(int l) const { return m<int32_t>(lay.gblocks) + lay.level_list_off[l]; }
   int32_t* iblocks(int l) const { return m<int32_t>(lay.iblocks) + lay.level_list_off[l]; }
   int32_t* oblocks(int l) const { return m<int32_t>(lay.oblocks) + lay.level_list_off[l]; }
-  // first block (key order) of every 2 x 2 tile of the level
+  // first block (key order) of every 2 x 2 x 2 tile of the level
   int32_t* tblocks(int l) const { return m<int32_t>(lay.tblocks) + lay.level_list_off[l]; }
   // time level p of the pool: cap block slots plus one all-zero slot (index cap)
   void* buf(int l, int p) const { return pool + (size_t)p * (size_t)(cap + 1) * kBlockStride * elem; }
@@ -450,8 +450,9 @@ lbm_status sc_level(lbm_ctx* c, int l) {
   a.omega = (float)(1.0 / c->tau[l]);
   a.sc = c->sc;
   a.storage = c->cfg.storage;
-  // 2 x 2 tiles once there are enough of them to fill the chip; single blocks below
-  const bool tiles = c->ntile[l] >= 4096;
+  // 2 x 2 x 2 tiles once there are enough of them to fill the chip several times;
+  // single blocks below
+  const bool tiles = c->ntile[l] >= 2048;
   a.tiles = tiles ? c->tblocks(l) : nullptr;
   a.ntiles = tiles ? (int32_t)c->ntile[l] : 0;
   a.dir = c->dir(c->hier);

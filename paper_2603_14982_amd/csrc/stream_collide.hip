@@ -465,13 +465,14 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   }
 }
 
-// ---- 2 x 2 block tiles ----------------------------------------------------------
-// One workgroup of four waves sweeps a tile of 2 x 2 blocks (16 x 16 columns) in z.
-// The halo plane is 18 x 18 points instead of four separate 10 x 10 planes: the
-// faces shared inside the tile are read once, the points are spread over all 256
-// lanes (source and x passes), and each wave keeps one block for the y and z passes
-// and the stores. Missing blocks of a tile read as the all-zero slot and are not
-// written.
+// ---- 2 x 2 x 2 block tiles ------------------------------------------------------
+// One workgroup of four waves sweeps a tile of 2 x 2 x 2 blocks (16 x 16 columns,
+// 16 planes) in z. The halo plane is 18 x 18 points instead of four separate 10 x 10
+// planes and the sweep crosses the two blocks in z without re-reading halo planes:
+// the faces shared inside the tile are read once, the points are spread over all
+// 256 lanes (source and x passes), and each wave keeps one column of blocks for the
+// y and z passes and the stores. Missing blocks of a tile read as the all-zero slot
+// and are not written.
 constexpr int kTN = 16;                 // tile columns per axis
 constexpr int kTC = kTN + 2;            // halo plane points per axis
 constexpr int kTPts = kTC * kTC;        // 324
@@ -520,9 +521,8 @@ __device__ __forceinline__ void x_pass_tile(const float* lds, int row, int x, fl
 template <class S>
 __device__ __forceinline__ void fetch_tile(const ScArgs<S>& a, const int* s_src, int px, int py, int pz,
                                            typename S::type raw[kMom]) {
-  const int ix = (px + 8) >> 3, iy = (py + 8) >> 3;  // px, py in [-1, 16] -> 0..3
-  const int iz = pz < 0 ? 0 : (pz > 7 ? 2 : 1);
-  const int ns = s_src[ix + 4 * iy + 16 * iz];
+  // px, py, pz in [-1, 16] -> neighbourhood block 0..3 per axis
+  const int ns = s_src[((px + 8) >> 3) + 4 * ((py + 8) >> 3) + 16 * ((pz + 8) >> 3)];
   const int node = (px & 7) + 8 * (py & 7) + 64 * (pz & 7);
   const typename S::type* src = a.in + (size_t)ns * kBlockStride + node;
 #pragma unroll
@@ -532,13 +532,13 @@ __device__ __forceinline__ void fetch_tile(const ScArgs<S>& a, const int* s_src,
 template <class S>
 __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
   __shared__ __align__(16) float lds[kTC * kTRowF];
-  __shared__ int s_src[48];   // blocks (tx - 1 .. tx + 2) x (ty - 1 .. ty + 2) x (z - 1 .. z + 1)
-  __shared__ int s_mem[4];    // the tile's blocks (or -1)
+  __shared__ int s_src[64];   // blocks (qx - 1 .. qx + 2) x (qy - 1 .. qy + 2) x (qz - 1 .. qz + 2)
+  __shared__ int s_mem[8];    // the tile's blocks (or -1), x fastest
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int4 c0 = a.coord[a.tiles[xcd_remap(blockIdx.x, a.ntiles)]];
-  const int qx = c0.x & ~1, qy = c0.y & ~1, qz = c0.z;
-  if (tid < 48) {
+  const int qx = c0.x & ~1, qy = c0.y & ~1, qz = c0.z & ~1;
+  if (tid < 64) {
     const int ix = tid & 3, iy = (tid >> 2) & 3, iz = tid >> 4;
     int h[3] = {qx + ix - 1, qy + iy - 1, qz + iz - 1};
     bool inside = true;
@@ -552,9 +552,9 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
     }
     const int ns = inside ? a.dir[a.lg.off + cell_lin(a.lg, h[0], h[1], h[2])] : -1;
     s_src[tid] = ns >= 0 ? ns : a.zero_slot;
-    if (iz == 1 && ix >= 1 && ix <= 2 && iy >= 1 && iy <= 2) {
-      const bool own = qx + ix - 1 < a.lg.nb[0] && qy + iy - 1 < a.lg.nb[1];  // not wrapped
-      s_mem[(ix - 1) + 2 * (iy - 1)] = own ? ns : -1;
+    if (ix >= 1 && ix <= 2 && iy >= 1 && iy <= 2 && iz >= 1 && iz <= 2) {
+      const bool own = qx + ix - 1 < a.lg.nb[0] && qy + iy - 1 < a.lg.nb[1] && qz + iz - 1 < a.lg.nb[2];  // not wrapped
+      s_mem[(ix - 1) + 2 * (iy - 1) + 4 * (iz - 1)] = own ? ns : -1;
     }
   }
   __syncthreads();
@@ -570,15 +570,17 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
     px[r] = p % kTC - 1;
     py[r] = p / kTC - 1;
   }
-  const int slot = s_mem[wave];
+  const int slots[2] = {s_mem[wave], s_mem[wave + 4]};  // this wave's blocks, lower and upper
   const int ox = lane & 7, oy = lane >> 3;
   const int tx = (wave & 1) * 8 + ox, ty = (wave >> 1) * 8 + oy;  // tile column of this lane
   const float c216 = 1.0f / 216.0f;
-  uint64_t col_roles = 0;
-  if (slot >= 0) {
-    const uint8_t* rp = a.role + (size_t)slot * kNodes + ox + 8 * oy;
+  uint64_t col_roles[2] = {0, 0};
 #pragma unroll
-    for (int zz = 0; zz < 8; ++zz) col_roles |= (uint64_t)rp[64 * zz] << (8 * zz);
+  for (int zb = 0; zb < 2; ++zb) {
+    if (slots[zb] < 0) continue;
+    const uint8_t* rp = a.role + (size_t)slots[zb] * kNodes + ox + 8 * oy;
+#pragma unroll
+    for (int zz = 0; zz < 8; ++zz) col_roles[zb] |= (uint64_t)rp[64 * zz] << (8 * zz);
   }
 
   typedef typename S::type T;
@@ -591,14 +593,14 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) zp1[k] = zp2[k] = z0[k] = 0.0f;
 
-  for (int z = -1; z <= 8; ++z) {
+  for (int z = -1; z <= 16; ++z) {
     // ---- source: moments of plane z (+ halo) -> x-populations, into LDS
     T cur[2][kMom];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int m = 0; m < kMom; ++m) cur[r][m] = nxt[r][m];
-    if (z < 8) {
+    if (z < 16) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
         if (has[r]) fetch_tile<S>(a, s_src, px[r], py[r], z + 1, nxt[r]);
@@ -669,8 +671,9 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
     }
     __syncthreads();
 
-    // ---- z pass: output plane zo = z - 1
+    // ---- z pass: output plane zo = z - 1 (block zo / 8 of the wave's column)
     const int zo = z - 1;
+    const int slot = zo >= 8 ? slots[1] : slots[0];
     if (zo >= 0 && slot >= 0) {
       float M[10];
       float m0, m1, m2;
@@ -686,11 +689,12 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
       M[5] = m0;
       back3(zp2[5], z0[5], zpm[5], m0, m1, m2);
       M[7] = m0;
-      const int node = ox + 8 * oy + 64 * zo;
-      const uint8_t role = (uint8_t)(col_roles >> (8 * zo));
+      const int lz = zo & 7;
+      const int node = ox + 8 * oy + 64 * lz;
+      const uint8_t role = (uint8_t)((zo >= 8 ? col_roles[1] : col_roles[0]) >> (8 * lz));
       typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
       if ((role & ROLE_MASK) == ROLE_COMPUTED) {
-        if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, zo, M);
+        if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, lz, M);
         const float q0 = M[0] * c216;
         const float drho = __builtin_fmaf(__builtin_fmaf(-q0, 216.0f, M[0]), c216, q0);
         const float r216 = 216.0f + M[0];

@@ -89,7 +89,7 @@ def test_walls_two_level_channel():
 
 def test_large_level_tiled_sweep_with_partial_tiles():
     # 33 x 32 x 16 blocks on one level (above the size where the stream-collide runs on
-    # 2 x 2 tiles): an odd block count along the periodic x axis leaves a column of
+    # 2 x 2 x 2 tiles): an odd block count along the periodic x axis leaves a column of
     # half tiles whose halo wraps; no-slip walls at the z faces; 5 steps
     n = (264, 256, 128)
     bc = (P, P, P, P, W.WALL, W.WALL)

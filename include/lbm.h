@@ -201,6 +201,18 @@ lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes,
 lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes, int32_t n_steps,
                              const float* lam_next, float* lam_out, void* work, size_t work_bytes);
 
+/* The two halves of lbm_adjoint_steps, for callers that keep the whole undo log of
+ * a forward pass resident instead of recomputing it from checkpoints (one coarse
+ * step of the two-level 128^3 case logs ~45 MB; 200 steps fit easily in HBM):
+ * lbm_step_record runs n_steps coarse steps from the current state, logging into
+ * work (>= lbm_adjoint_work_bytes(ctx, n_steps)); lbm_adjoint_reverse then turns the
+ * adjoint of the final state (lam_next) into that of the state before the recorded
+ * steps (lam_out) and puts the simulation back at that state. The reverse call takes
+ * the same work buffer; LBM_ESTATE if nothing is recorded in it (lbm_step,
+ * lbm_remesh, lbm_load and lbm_set_block_moments in between drop the recording). */
+lbm_status lbm_step_record(lbm_ctx* ctx, int32_t n_steps, void* work, size_t work_bytes);
+lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_out, void* work, size_t work_bytes);
+
 /* Adjoint seed of the kinetic energy 1/2 sum rho |u|^2 over the owned nodes of
  * `level` whose fine position lies in [lo, hi): writes lam (device f32, the
  * all-level layout of lbm_adjoint_step) with d(loss)/d(moments) of the current

@@ -164,6 +164,9 @@ struct lbm_ctx {
   char* tape = nullptr;
   size_t tape_cap = 0, tape_used = 0;
   std::vector<TapeOp> ops;
+  const void* rec_work = nullptr;      // work buffer holding the recorded steps (null: none)
+  uint64_t rec_generation = 0;         // hierarchy they were recorded on
+  int rec_parity[kMaxLevels] = {0};    // time-level parities before them
 
   template <class T> T* m(size_t off) const { return reinterpret_cast<T*>(meta + off); }
   uint8_t* st(int k) const { return m<uint8_t>(lay.st[k]); }
@@ -811,6 +814,7 @@ lbm_status lbm_set_block_moments(lbm_ctx* ctx, int32_t level, const int64_t* key
   if (!level_ok(ctx, level)) return ctx ? ctx->fail(LBM_EINVAL, "bad level") : LBM_EINVAL;
   if (nb < 0 || (nb > 0 && (!keys || !in))) return ctx->fail(LBM_EINVAL, "bad block arrays");
   if (nb == 0) return LBM_OK;
+  ctx->rec_work = nullptr;
   int32_t* flag = ctx->m<int32_t>(ctx->lay.flag);
   HIPCHK(ctx, launch_fill_i32(flag, 0, 1, ctx->stream));
   HIPCHK(ctx, launch_set(io_of(ctx, level), keys, in, nb, ctx->dir(ctx->hier), flag, ctx->stream));
@@ -823,6 +827,7 @@ lbm_status lbm_set_block_moments(lbm_ctx* ctx, int32_t level, const int64_t* key
 lbm_status lbm_step(lbm_ctx* ctx, int32_t n) {
   if (!ctx) return LBM_EINVAL;
   if (n < 0) return ctx->fail(LBM_EINVAL, "negative step count");
+  ctx->rec_work = nullptr;  // a recorded undo log no longer matches the state
   for (int32_t i = 0; i < n; ++i) {
     lbm_status st = advance(ctx, ctx->G.L - 1, 1);
     if (st != LBM_OK) return st;
@@ -840,6 +845,7 @@ lbm_status lbm_advance_particles(lbm_ctx* ctx, float* particles, int64_t n, cons
 lbm_status lbm_remesh(lbm_ctx* ctx, const float* particles, int64_t n) {
   if (!ctx) return LBM_EINVAL;
   if (n < 0 || (n > 0 && !particles)) return ctx->fail(LBM_EINVAL, "bad particle array");
+  ctx->rec_work = nullptr;
   const int k = ctx->tic(LBM_PROF_REMESH);
   lbm_status st = rebuild(ctx, particles, n, false);
   ctx->toc(k);
@@ -932,6 +938,7 @@ lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes) {
     return ctx->fail(LBM_ESTATE, "not a state of this simulation");
   if (w[1] != ctx->generation || w[3] != (uint64_t)total_blocks(ctx))
     return ctx->fail(LBM_ESTATE, "state was saved under another block hierarchy");
+  ctx->rec_work = nullptr;
   const char* p = static_cast<const char*>(src) + kStateHeader;
   for (int l = 0; l < ctx->G.L; ++l) {
     HIPCHK(ctx, launch_scatter_blocks(p, ctx->cur(l), ctx->blocks(l), (int32_t)ctx->nblk[l], block_bytes(ctx),
@@ -959,6 +966,49 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes
   if (work_bytes < lbm_adjoint_work_bytes(ctx, n_steps)) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
   lbm_status st = lbm_load(ctx, state, state_bytes);
   if (st != LBM_OK) return st;
+  if ((st = lbm_step_record(ctx, n_steps, work, work_bytes)) != LBM_OK) return st;
+  return lbm_adjoint_reverse(ctx, lam_next, lam_out, work, work_bytes);
+}
+
+lbm_status lbm_step_record(lbm_ctx* ctx, int32_t n_steps, void* work, size_t work_bytes) {
+  if (!ctx) return LBM_EINVAL;
+  if (n_steps < 1) return ctx->fail(LBM_EINVAL, "step count must be positive");
+  if (!work) return ctx->fail(LBM_EINVAL, "null adjoint buffer");
+  if (work_bytes < lbm_adjoint_work_bytes(ctx, n_steps)) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
+  const int L = ctx->G.L;
+  const size_t sf = slot_floats(ctx);
+  char* aux = reinterpret_cast<char*>(static_cast<float*>(work) + 3 * sf);
+  ctx->tape = aux + aux_bytes(ctx);
+  ctx->tape_cap = work_bytes - 3 * sf * sizeof(float) - aux_bytes(ctx);
+  ctx->tape_used = 0;
+  ctx->ops.clear();
+  ctx->rec_work = work;
+  ctx->rec_generation = ctx->generation;
+  for (int l = 0; l < L; ++l) ctx->rec_parity[l] = ctx->parity[l];
+  // the coarse steps, each forward kernel keeping the old value of what it overwrites
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;
+  ctx->recording = true;
+  lbm_status st = LBM_OK;
+  for (int32_t i = 0; i < n_steps && st == LBM_OK; ++i) st = advance(ctx, L - 1, 1);
+  ctx->recording = false;
+  ctx->profiling = prof;
+  if (st != LBM_OK) {
+    ctx->ops.clear();
+    ctx->rec_work = nullptr;
+  }
+  return st;
+}
+
+lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_out, void* work, size_t work_bytes) {
+  if (!ctx) return LBM_EINVAL;
+  if (!lam_next || !lam_out || !work) return ctx->fail(LBM_EINVAL, "null adjoint buffer");
+  if (ctx->rec_work == nullptr || ctx->ops.empty() || work != ctx->rec_work)
+    return ctx->fail(LBM_ESTATE, "no recorded steps for this work buffer");
+  if (ctx->rec_generation != ctx->generation)
+    return ctx->fail(LBM_ESTATE, "the block hierarchy changed since the steps were recorded");
+  if (work_bytes < 3 * slot_floats(ctx) * sizeof(float) + aux_bytes(ctx) + ctx->tape_used)
+    return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
   hipStream_t s = ctx->stream;
   const int L = ctx->G.L;
   const size_t sf = slot_floats(ctx);
@@ -971,19 +1021,8 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes
   b.gidx = reinterpret_cast<int32_t*>(aux + part_bytes(ctx));
   b.flags = reinterpret_cast<uint8_t*>(aux + part_bytes(ctx) + round256((size_t)(ctx->cap + 1) * 4));
   ctx->tape = aux + aux_bytes(ctx);
-  ctx->tape_cap = work_bytes - 3 * sf * sizeof(float) - aux_bytes(ctx);
-  ctx->tape_used = 0;
-  ctx->ops.clear();
-  int p0[kMaxLevels];
-  for (int l = 0; l < L; ++l) p0[l] = ctx->parity[l];
-  // forward replay of the coarse steps from the loaded state, recording the undo log
-  const bool prof = ctx->profiling;
-  ctx->profiling = false;
-  ctx->recording = true;
-  for (int32_t i = 0; i < n_steps && st == LBM_OK; ++i) st = advance(ctx, L - 1, 1);
-  ctx->recording = false;
-  ctx->profiling = prof;
-  if (st == LBM_OK) {
+  lbm_status st = LBM_OK;
+  {
     // adjoint of the state after the steps: lam_next at the state nodes of the current time level
     HIPCHK(ctx, launch_fill_i32(reinterpret_cast<int32_t*>(b.mu + (size_t)ctx->cap * kBlockStride), 0, kBlockStride, s));
     HIPCHK(ctx, launch_fill_u8(b.flags, 0, ctx->cap + 1, s));
@@ -1007,15 +1046,17 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes
   // reverse sweep over every logged operation of every step (a failure leaves the
   // simulation state undefined: the undo is part of the adjoint kernels)
   for (size_t i = ctx->ops.size(); st == LBM_OK && i-- > 0;) st = adjoint_op(ctx, ctx->ops[i], b);
-  for (int l = 0; l < L; ++l) ctx->parity[l] = p0[l];
+  for (int l = 0; l < L; ++l) ctx->parity[l] = ctx->rec_parity[l];
   ctx->ops.clear();
+  ctx->rec_work = nullptr;
   ctx->tape = nullptr;
   ctx->tape_cap = 0;
   if (st != LBM_OK) return st;
   size_t off = 0;
   for (int l = 0; l < L; ++l) {
     const int32_t n = (int32_t)ctx->nblk[l];
-    HIPCHK(ctx, launch_gather_blocks(b.lam[p0[l]], lam_out + off, ctx->blocks(l), n, kBlockStride * sizeof(float), s));
+    HIPCHK(ctx, launch_gather_blocks(b.lam[ctx->parity[l]], lam_out + off, ctx->blocks(l), n,
+                                     kBlockStride * sizeof(float), s));
     off += (size_t)n * kBlockStride;
   }
   return LBM_OK;

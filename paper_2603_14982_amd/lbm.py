@@ -50,6 +50,7 @@ EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm
            "lbm_set_block_moments", "lbm_step", "lbm_advance_particles", "lbm_remesh", "lbm_get_moments",
            "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
            "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
+           "lbm_step_record", "lbm_adjoint_reverse",
            "lbm_loss_ke_grad", "lbm_last_error"]
 _SIZE_QUERIES = ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_state_bytes", "lbm_adjoint_work_bytes", "lbm_last_error")
 PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh"]
@@ -92,6 +93,8 @@ def lib():
         L.lbm_adjoint_work_bytes.argtypes = [vp, i32]
         L.lbm_adjoint_step.argtypes = [vp, vp, sz, vp, vp, vp, sz]
         L.lbm_adjoint_steps.argtypes = [vp, vp, sz, i32, vp, vp, vp, sz]
+        L.lbm_step_record.argtypes = [vp, i32, vp, sz]
+        L.lbm_adjoint_reverse.argtypes = [vp, vp, vp, vp, sz]
         L.lbm_loss_ke_grad.argtypes = [vp, i32, vp, vp, vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_last_error.argtypes = [vp]
@@ -302,6 +305,20 @@ class Sim:
                                             _dptr(lam_out), _dptr(work), work.numel()))
         return lam_out
 
+    def step_record(self, n_steps, work):
+        """`n_steps` coarse steps that keep their undo log in `work` (adjoint_work(n_steps))."""
+        self._check(lib().lbm_step_record(self.h, int(n_steps), _dptr(work), work.numel()))
+
+    def adjoint_reverse(self, lam_next, lam_out=None, work=None):
+        """Adjoint through the steps recorded by step_record; returns the simulation to
+        the state before them."""
+        if lam_out is None:
+            lam_out = torch.empty_like(lam_next)
+        assert lam_next.dtype == torch.float32 and lam_next.is_contiguous()
+        assert lam_next.shape == (self.total_blocks(), 10, 512) and lam_out.shape == lam_next.shape
+        self._check(lib().lbm_adjoint_reverse(self.h, _dptr(lam_next), _dptr(lam_out), _dptr(work), work.numel()))
+        return lam_out
+
     def loss_ke_grad(self, level, lo, hi):
         """d(1/2 sum rho |u|^2 over the level's owned nodes in [lo, hi))/d(moments), all-level layout."""
         lam = torch.empty((self.total_blocks(), 10, 512), dtype=torch.float32, device=self.device)
@@ -309,6 +326,30 @@ class Sim:
         hi_ = (ctypes.c_int32 * 3)(*hi)
         self._check(lib().lbm_loss_ke_grad(self.h, level, lo_, hi_, _dptr(lam)))
         return lam
+
+
+class _RolloutTaped(torch.autograd.Function):
+    """x0 -> moments after `steps` coarse steps, keeping the whole undo log of the
+    forward pass on the device; the backward pass is one reverse sweep."""
+
+    @staticmethod
+    def forward(ctx, x0, sim, steps):
+        sim.set_all_moments(x0.detach())
+        work = sim.adjoint_work(steps)
+        sim.step_record(steps, work)
+        out = sim.get_all_moments()
+        ctx.sim, ctx.work = sim, work
+        ctx.final = sim.save()
+        return out
+
+    @staticmethod
+    def backward(ctx, grad):
+        sim = ctx.sim
+        lam = grad.detach().to(torch.float32).contiguous().clone()
+        sim.adjoint_reverse(lam, lam, ctx.work)
+        sim.load(ctx.final)
+        ctx.work = None
+        return lam, None, None
 
 
 class _Rollout(torch.autograd.Function):
@@ -343,5 +384,10 @@ class _Rollout(torch.autograd.Function):
 
 def rollout(sim, x0, steps, checkpoint_every=20):
     """Differentiable `steps` coarse steps from the all-level moments x0 ([sum nb, 10, 512],
-    device f32); returns the all-level moments after them. The hierarchy stays fixed."""
+    device f32); returns the all-level moments after them. The hierarchy stays fixed.
+    checkpoint_every > 0: states are kept every that many steps and each segment is
+    replayed in the backward pass; 0: the forward pass keeps its whole undo log
+    (lbm_adjoint_work_bytes(steps) of device memory) and nothing is replayed."""
+    if int(checkpoint_every) == 0:
+        return _RolloutTaped.apply(x0, sim, int(steps))
     return _Rollout.apply(x0, sim, int(steps), int(checkpoint_every))

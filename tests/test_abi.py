@@ -86,6 +86,8 @@ def test_null_context_state_and_adjoint_calls_fail_cleanly():
     assert L.lbm_state_bytes(None) == 0
     assert L.lbm_adjoint_work_bytes(None, 1) == 0
     assert L.lbm_adjoint_steps(None, None, 0, 1, None, None, None, 0) == -1
+    assert L.lbm_step_record(None, 1, None, 0) == -1
+    assert L.lbm_adjoint_reverse(None, None, None, None, 0) == -1
     assert L.lbm_save(None, None, 0) == -1
     assert L.lbm_load(None, None, 0) == -1
     assert L.lbm_adjoint_step(None, None, 0, None, None, None, 0) == -1

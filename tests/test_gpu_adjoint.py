@@ -7,7 +7,8 @@ complex-step derivative of the FP64 oracle, plus the state save/load it rests on
   faces): relative error <= 1e-4 (FP32 adjoint vs FP64 complex step).
 - Entries of the gradient at nodes that carry no state (ghost, solid, inflow) are 0.
 - The checkpointed autograd rollout equals the chain of single adjoint steps and
-  leaves the simulation at its final state.
+  leaves the simulation at its final state; the rollout that keeps its whole undo
+  log (no checkpoints) gives the same gradient; a recording is dropped by a step.
 - Full size: the two-level 128^3 case, 200 coarse steps with checkpoints every 20,
   gradient with respect to the initial velocity field, against the 16 stored
   complex-step derivatives (tests/golden/, written from the oracle alone).
@@ -243,3 +244,33 @@ def test_adjoint128_gradient_against_oracle_derivatives():
           f"vector rel err {np.linalg.norm(got - want) / np.linalg.norm(want):.3e}", flush=True)
     assert np.linalg.norm(got - want) <= 1e-4 * np.linalg.norm(want)
     assert np.all(err <= 1e-4)
+
+
+def test_taped_rollout_equals_checkpointed_rollout():
+    lbm = _lbm()
+    sim = _gpu("sphere")
+    u0 = torch.as_tensor(W.smooth_random_velocity((80, 80, 80), 6, kmax=4.0, rms=0.03), dtype=torch.float32,
+                         device="cuda")
+    box = ((16, 16, 16), (64, 64, 64))
+    grads = []
+    for every in (2, 0):
+        x0 = _torch_init(sim, u0).detach().requires_grad_(True)
+        xt = lbm.rollout(sim, x0, 5, checkpoint_every=every)
+        final = sim.get_all_moments().clone()
+        loss = _torch_loss(sim, xt, 0, box)
+        (g,) = torch.autograd.grad(loss, x0)
+        assert torch.equal(sim.get_all_moments(), final)
+        grads.append(g)
+    assert torch.allclose(grads[0], grads[1], rtol=0, atol=1e-6 * grads[0].abs().max().item())
+
+
+def test_recording_dropped_by_a_step():
+    lbm = _lbm()
+    sim = _gpu("two_level")
+    work = sim.adjoint_work(2)
+    sim.step_record(2, work)
+    lam = sim.loss_ke_grad(0, (16, 16, 16), (64, 64, 64))
+    sim.step(1)
+    with pytest.raises(lbm.LBMError) as e:
+        sim.adjoint_reverse(lam, work=work)
+    assert e.value.status == -6

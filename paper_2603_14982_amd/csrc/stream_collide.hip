@@ -476,19 +476,23 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
 constexpr int kTN = 16;                 // tile columns per axis
 constexpr int kTC = kTN + 2;            // halo plane points per axis
 constexpr int kTPts = kTC * kTC;        // 324
-constexpr int kTRowF = 3 * kTN * 10;    // floats per LDS row: y-pass input [kind][16][10]
-constexpr int kTKindA = kTC * 8;        // x-pass input: [kind][col 0..17][group 0..7]
-constexpr int kTKindB = kTN * 10;
+// LDS row (plane row y = row - 1): x-pass input [kind][half][col 0..17][4] (the 8 group
+// values of a point split in two halves, so that neighbouring lanes' 128-bit accesses
+// are 16 bytes apart), later overwritten by the y-pass input [kind][col 0..15][10].
+// The row stride is 16 banks off a multiple of 32 so that the two rows read by one
+// 16-lane group of the y pass fall on different banks.
+constexpr int kTRowF = 3 * kTN * 10 + 16;  // 496 floats
+constexpr int kTHalf = kTC * 4;            // 72
+constexpr int kTKindA = 2 * kTHalf;        // 144
+constexpr int kTKindB = kTN * 10;          // 160
 
-__device__ __forceinline__ void st8_at(float* lds, int off, int row, const float v[8]) {
-  const int sw = (row & 1) << 2;
-  *reinterpret_cast<float4*>(lds + off + sw) = make_float4(v[0], v[1], v[2], v[3]);
-  *reinterpret_cast<float4*>(lds + off + (4 ^ sw)) = make_float4(v[4], v[5], v[6], v[7]);
+__device__ __forceinline__ void st8_at(float* lds, int off, const float v[8]) {
+  *reinterpret_cast<float4*>(lds + off) = make_float4(v[0], v[1], v[2], v[3]);
+  *reinterpret_cast<float4*>(lds + off + kTHalf) = make_float4(v[4], v[5], v[6], v[7]);
 }
-__device__ __forceinline__ void ld8_at(const float* lds, int off, int row, float v[8]) {
-  const int sw = (row & 1) << 2;
-  const float4 a = *reinterpret_cast<const float4*>(lds + off + sw);
-  const float4 b = *reinterpret_cast<const float4*>(lds + off + (4 ^ sw));
+__device__ __forceinline__ void ld8_at(const float* lds, int off, float v[8]) {
+  const float4 a = *reinterpret_cast<const float4*>(lds + off);
+  const float4 b = *reinterpret_cast<const float4*>(lds + off + kTHalf);
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 
@@ -496,9 +500,9 @@ __device__ __forceinline__ void ld8_at(const float* lds, int off, int row, float
 __device__ __forceinline__ void x_pass_tile(const float* lds, int row, int x, float yb[27]) {
   float pp[8], pz[8], pm[8];
   const int base = row * kTRowF;
-  ld8_at(lds, base + 0 * kTKindA + x * 8, row, pp);        // P+ of column x-1
-  ld8_at(lds, base + 1 * kTKindA + (x + 1) * 8, row, pz);  // P0 of column x
-  ld8_at(lds, base + 2 * kTKindA + (x + 2) * 8, row, pm);  // P- of column x+1
+  ld8_at(lds, base + 0 * kTKindA + x * 4, pp);        // P+ of column x-1
+  ld8_at(lds, base + 1 * kTKindA + (x + 1) * 4, pz);  // P0 of column x
+  ld8_at(lds, base + 2 * kTKindA + (x + 2) * 4, pm);  // P- of column x+1
   float B[3][3][3];  // [qx][my][mz]
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
@@ -619,7 +623,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
       for (int kind = 0; kind < 3; ++kind) {
 #pragma unroll
         for (int g = 0; g < 8; ++g) v[g] = p[3 * g + kind];
-        st8_at(lds, row * kTRowF + kind * kTKindA + col * 8, row, v);
+        st8_at(lds, row * kTRowF + kind * kTKindA + col * 4, v);
       }
     }
     __syncthreads();

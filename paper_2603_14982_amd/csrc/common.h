@@ -26,6 +26,8 @@ constexpr int32_t NBR_WALL = -2;
 // per-block summary bits
 constexpr uint8_t SUM_GHOST = 1, SUM_IU = 2, SUM_OUTFLOW = 4, SUM_TILE = 8;
 constexpr int SUM_TILE_SHIFT = 3;
+// stream-collide tiles of large levels: kTileX x 2 x 2 blocks (kTileX a power of two)
+constexpr int kTileX = 2;
 
 struct LevelGeom {
   int nb[3];       // blocks per axis

@@ -373,12 +373,13 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   const int any_i = __syncthreads_or(sum & SUM_IU);
   const int any_o = __syncthreads_or(sum & SUM_OUTFLOW);
   if (threadIdx.x == 0) {
-    // first active block (in key order) of its 2 x 2 x 2 group: the group's members
-    // are (x & ~1, y & ~1, z & ~1) + {0, 1}^3, never wrapped
-    const int c = (b[0] & 1) + 2 * (b[1] & 1) + 4 * (b[2] & 1);
+    // one representative per stream-collide tile of kTileX x 2 x 2 blocks: the
+    // active member with the lowest index (x fastest); members are never wrapped
+    const int c = (b[0] & (kTileX - 1)) + kTileX * ((b[1] & 1) + 2 * (b[2] & 1));
     bool start = true;
     for (int m = 0; m < c; ++m) {
-      const int mx = (b[0] & ~1) + (m & 1), my = (b[1] & ~1) + ((m >> 1) & 1), mz = (b[2] & ~1) + (m >> 2);
+      const int mx = (b[0] & ~(kTileX - 1)) + m % kTileX, my = (b[1] & ~1) + (m / kTileX) % 2,
+                mz = (b[2] & ~1) + m / (2 * kTileX);
       if (mx < g.nb[0] && my < g.nb[1] && mz < g.nb[2] && r.st[g.off + cell_lin(g, mx, my, mz)] == ST_ACTIVE)
         start = false;
     }

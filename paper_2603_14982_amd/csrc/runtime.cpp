@@ -181,7 +181,7 @@ struct lbm_ctx {
   int32_t* gblocks(int l) const { return m<int32_t>(lay.gblocks) + lay.level_list_off[l]; }
   int32_t* iblocks(int l) const { return m<int32_t>(lay.iblocks) + lay.level_list_off[l]; }
   int32_t* oblocks(int l) const { return m<int32_t>(lay.oblocks) + lay.level_list_off[l]; }
-  // first block (key order) of every 2 x 2 x 2 tile of the level
+  // one block of every stream-collide tile (kTileX x 2 x 2 blocks) of the level
   int32_t* tblocks(int l) const { return m<int32_t>(lay.tblocks) + lay.level_list_off[l]; }
   // time level p of the pool: cap block slots plus one all-zero slot (index cap)
   void* buf(int l, int p) const { return pool + (size_t)p * (size_t)(cap + 1) * kBlockStride * elem; }
@@ -453,9 +453,9 @@ lbm_status sc_level(lbm_ctx* c, int l) {
   a.omega = (float)(1.0 / c->tau[l]);
   a.sc = c->sc;
   a.storage = c->cfg.storage;
-  // 2 x 2 x 2 tiles once there are enough of them to fill the chip several times;
-  // single blocks below
-  const bool tiles = c->ntile[l] >= 2048;
+  // tiles once the level has enough blocks (16384) to fill the chip several times
+  // with them; single blocks below
+  const bool tiles = c->ntile[l] * 4 * kTileX >= 16384;
   a.tiles = tiles ? c->tblocks(l) : nullptr;
   a.ntiles = tiles ? (int32_t)c->ntile[l] : 0;
   a.dir = c->dir(c->hier);

@@ -473,36 +473,48 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
 // 256 lanes (source and x passes), and each wave keeps one column of blocks for the
 // y and z passes and the stores. Missing blocks of a tile read as the all-zero slot
 // and are not written.
-constexpr int kTN = 16;                 // tile columns per axis
-constexpr int kTC = kTN + 2;            // halo plane points per axis
-constexpr int kTPts = kTC * kTC;        // 324
-// LDS row (plane row y = row - 1): x-pass input [kind][half][col 0..17][4] (the 8 group
-// values of a point split in two halves, so that neighbouring lanes' 128-bit accesses
-// are 16 bytes apart), later overwritten by the y-pass input [kind][col 0..15][10].
-// The row stride is 16 banks off a multiple of 32 so that the two rows read by one
-// 16-lane group of the y pass fall on different banks.
-constexpr int kTRowF = 3 * kTN * 10 + 16;  // 496 floats
-constexpr int kTHalf = kTC * 4;            // 72
-constexpr int kTKindA = 2 * kTHalf;        // 144
-constexpr int kTKindB = kTN * 10;          // 160
+// Tile geometry for TX blocks along x (2 or 4) by 2 along y and z.
+template <int TX> struct Tile {
+  static constexpr int NX = 8 * TX;              // tile columns along x
+  static constexpr int CX = NX + 2;              // halo plane points along x
+  static constexpr int CY = 18;                  // halo plane points along y
+  static constexpr int PTS = CX * CY;
+  static constexpr int WAVES = 2 * TX;           // one per block column
+  static constexpr int THREADS = 64 * WAVES;
+  static constexpr int NXB = TX + 2;             // neighbourhood blocks along x
+  // LDS row (plane row y = row - 1): x-pass input [kind][half][col 0..CX-1][4] (the 8
+  // group values of a point split in two halves, so that neighbouring lanes' 128-bit
+  // accesses are 16 bytes apart), later overwritten by the y-pass input
+  // [kind][col 0..NX-1][10]. The row stride is 16 banks off a multiple of 32 so that
+  // the two rows read by one 16-lane group of the y pass fall on different banks.
+  static constexpr int ROW = 3 * NX * 10 + 16;
+  static constexpr int HALF = CX * 4;
+  static constexpr int KINDA = 2 * HALF;
+  static constexpr int KINDB = NX * 10;
+  static_assert(3 * KINDA <= ROW, "x-pass input must fit in a row");
+};
 
+template <int TX>
 __device__ __forceinline__ void st8_at(float* lds, int off, const float v[8]) {
   *reinterpret_cast<float4*>(lds + off) = make_float4(v[0], v[1], v[2], v[3]);
-  *reinterpret_cast<float4*>(lds + off + kTHalf) = make_float4(v[4], v[5], v[6], v[7]);
+  *reinterpret_cast<float4*>(lds + off + Tile<TX>::HALF) = make_float4(v[4], v[5], v[6], v[7]);
 }
+template <int TX>
 __device__ __forceinline__ void ld8_at(const float* lds, int off, float v[8]) {
   const float4 a = *reinterpret_cast<const float4*>(lds + off);
-  const float4 b = *reinterpret_cast<const float4*>(lds + off + kTHalf);
+  const float4 b = *reinterpret_cast<const float4*>(lds + off + Tile<TX>::HALF);
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 
 // x pass for tile row `row` (plane row row - 1), tile column x
+template <int TX>
 __device__ __forceinline__ void x_pass_tile(const float* lds, int row, int x, float yb[27]) {
+  typedef Tile<TX> G;
   float pp[8], pz[8], pm[8];
-  const int base = row * kTRowF;
-  ld8_at(lds, base + 0 * kTKindA + x * 4, pp);        // P+ of column x-1
-  ld8_at(lds, base + 1 * kTKindA + (x + 1) * 4, pz);  // P0 of column x
-  ld8_at(lds, base + 2 * kTKindA + (x + 2) * 4, pm);  // P- of column x+1
+  const int base = row * G::ROW;
+  ld8_at<TX>(lds, base + 0 * G::KINDA + x * 4, pp);        // P+ of column x-1
+  ld8_at<TX>(lds, base + 1 * G::KINDA + (x + 1) * 4, pz);  // P0 of column x
+  ld8_at<TX>(lds, base + 2 * G::KINDA + (x + 2) * 4, pm);  // P- of column x+1
   float B[3][3][3];  // [qx][my][mz]
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
@@ -522,28 +534,30 @@ __device__ __forceinline__ void x_pass_tile(const float* lds, int row, int x, fl
     }
 }
 
-template <class S>
+template <class S, int TX>
 __device__ __forceinline__ void fetch_tile(const ScArgs<S>& a, const int* s_src, int px, int py, int pz,
                                            typename S::type raw[kMom]) {
-  // px, py, pz in [-1, 16] -> neighbourhood block 0..3 per axis
-  const int ns = s_src[((px + 8) >> 3) + 4 * ((py + 8) >> 3) + 16 * ((pz + 8) >> 3)];
+  // px in [-1, 8 TX], py, pz in [-1, 16] -> neighbourhood block per axis
+  constexpr int NXB = Tile<TX>::NXB;
+  const int ns = s_src[((px + 8) >> 3) + NXB * ((py + 8) >> 3) + 4 * NXB * ((pz + 8) >> 3)];
   const int node = (px & 7) + 8 * (py & 7) + 64 * (pz & 7);
   const typename S::type* src = a.in + (size_t)ns * kBlockStride + node;
 #pragma unroll
   for (int m = 0; m < kMom; ++m) raw[m] = src[m * kNodes];
 }
 
-template <class S>
-__global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
-  __shared__ __align__(16) float lds[kTC * kTRowF];
-  __shared__ int s_src[64];   // blocks (qx - 1 .. qx + 2) x (qy - 1 .. qy + 2) x (qz - 1 .. qz + 2)
-  __shared__ int s_mem[8];    // the tile's blocks (or -1), x fastest
+template <class S, int TX>
+__global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a) {
+  typedef Tile<TX> G;
+  __shared__ __align__(16) float lds[G::CY * G::ROW];
+  __shared__ int s_src[G::NXB * 16];  // blocks (qx - 1 .. qx + TX) x (qy - 1 .. qy + 2) x (qz - 1 .. qz + 2)
+  __shared__ int s_mem[4 * TX];       // the tile's blocks (or -1), x fastest
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int4 c0 = a.coord[a.tiles[xcd_remap(blockIdx.x, a.ntiles)]];
-  const int qx = c0.x & ~1, qy = c0.y & ~1, qz = c0.z & ~1;
-  if (tid < 64) {
-    const int ix = tid & 3, iy = (tid >> 2) & 3, iz = tid >> 4;
+  const int qx = c0.x & ~(TX - 1), qy = c0.y & ~1, qz = c0.z & ~1;
+  if (tid < G::NXB * 16) {
+    const int ix = tid % G::NXB, iy = (tid / G::NXB) & 3, iz = tid / (4 * G::NXB);
     int h[3] = {qx + ix - 1, qy + iy - 1, qz + iz - 1};
     bool inside = true;
 #pragma unroll
@@ -556,27 +570,28 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
     }
     const int ns = inside ? a.dir[a.lg.off + cell_lin(a.lg, h[0], h[1], h[2])] : -1;
     s_src[tid] = ns >= 0 ? ns : a.zero_slot;
-    if (ix >= 1 && ix <= 2 && iy >= 1 && iy <= 2 && iz >= 1 && iz <= 2) {
+    if (ix >= 1 && ix <= TX && iy >= 1 && iy <= 2 && iz >= 1 && iz <= 2) {
       const bool own = qx + ix - 1 < a.lg.nb[0] && qy + iy - 1 < a.lg.nb[1] && qz + iz - 1 < a.lg.nb[2];  // not wrapped
-      s_mem[(ix - 1) + 2 * (iy - 1) + 4 * (iz - 1)] = own ? ns : -1;
+      s_mem[(ix - 1) + TX * (iy - 1) + 2 * TX * (iz - 1)] = own ? ns : -1;
     }
   }
   __syncthreads();
 
-  // source points: 256 in the first round, the other 68 on waves 2 and 3 (wave 0
+  // source points: THREADS in the first round, the rest on the last two waves (wave 0
   // takes the two extra rows of the x pass), which evens out the work per wave
+  constexpr int base1 = G::THREADS - 128;
   int px[2], py[2];
   bool has[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    const int p = r == 0 ? tid : 128 + tid;
-    has[r] = r == 0 || (tid >= 128 && p < kTPts);
-    px[r] = p % kTC - 1;
-    py[r] = p / kTC - 1;
+    const int p = r == 0 ? tid : G::THREADS + (tid - base1);
+    has[r] = r == 0 || (tid >= base1 && p < G::PTS);
+    px[r] = p % G::CX - 1;
+    py[r] = p / G::CX - 1;
   }
-  const int slots[2] = {s_mem[wave], s_mem[wave + 4]};  // this wave's blocks, lower and upper
+  const int slots[2] = {s_mem[wave], s_mem[wave + 2 * TX]};  // this wave's blocks, lower and upper
   const int ox = lane & 7, oy = lane >> 3;
-  const int tx = (wave & 1) * 8 + ox, ty = (wave >> 1) * 8 + oy;  // tile column of this lane
+  const int tx = (wave % TX) * 8 + ox, ty = (wave / TX) * 8 + oy;  // tile column of this lane
   const float c216 = 1.0f / 216.0f;
   uint64_t col_roles[2] = {0, 0};
 #pragma unroll
@@ -591,7 +606,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
   T nxt[2][kMom];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
-    if (has[r]) fetch_tile<S>(a, s_src, px[r], py[r], -1, nxt[r]);
+    if (has[r]) fetch_tile<S, TX>(a, s_src, px[r], py[r], -1, nxt[r]);
 
   float zp1[6], zp2[6], z0[6];
 #pragma unroll
@@ -607,7 +622,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
     if (z < 16) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
-        if (has[r]) fetch_tile<S>(a, s_src, px[r], py[r], z + 1, nxt[r]);
+        if (has[r]) fetch_tile<S, TX>(a, s_src, px[r], py[r], z + 1, nxt[r]);
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -623,29 +638,29 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
       for (int kind = 0; kind < 3; ++kind) {
 #pragma unroll
         for (int g = 0; g < 8; ++g) v[g] = p[3 * g + kind];
-        st8_at(lds, row * kTRowF + kind * kTKindA + col * 4, v);
+        st8_at<TX>(lds, row * G::ROW + kind * G::KINDA + col * 4, v);
       }
     }
     __syncthreads();
 
-    // ---- x pass: 18 rows x 16 columns in two rounds (rows 0..15, then 16..17); each
+    // ---- x pass: CY rows x NX columns in two rounds (rows 0..15, then 16..17); each
     // row is overwritten by its y-pass input once its reads are done
     {
       float yb[27];
-      const int row = tid >> 4, x = tid & 15;
-      x_pass_tile(lds, row, x, yb);
+      const int row = tid / G::NX, x = tid % G::NX;
+      x_pass_tile<TX>(lds, row, x, yb);
       __syncthreads();
-      st9(lds, row * kTRowF + 0 * kTKindB + x * 10, yb);
-      st9(lds, row * kTRowF + 1 * kTKindB + x * 10, yb + 9);
-      st9(lds, row * kTRowF + 2 * kTKindB + x * 10, yb + 18);
+      st9(lds, row * G::ROW + 0 * G::KINDB + x * 10, yb);
+      st9(lds, row * G::ROW + 1 * G::KINDB + x * 10, yb + 9);
+      st9(lds, row * G::ROW + 2 * G::KINDB + x * 10, yb + 18);
     }
-    if (tid < 2 * kTN) {
+    if (tid < 2 * G::NX) {
       float yb[27];
-      const int row = 16 + (tid >> 4), x = tid & 15;
-      x_pass_tile(lds, row, x, yb);
-      st9(lds, row * kTRowF + 0 * kTKindB + x * 10, yb);
-      st9(lds, row * kTRowF + 1 * kTKindB + x * 10, yb + 9);
-      st9(lds, row * kTRowF + 2 * kTKindB + x * 10, yb + 18);
+      const int row = 16 + tid / G::NX, x = tid % G::NX;
+      x_pass_tile<TX>(lds, row, x, yb);
+      st9(lds, row * G::ROW + 0 * G::KINDB + x * 10, yb);
+      st9(lds, row * G::ROW + 1 * G::KINDB + x * 10, yb + 9);
+      st9(lds, row * G::ROW + 2 * G::KINDB + x * 10, yb + 18);
     }
     __syncthreads();
 
@@ -653,9 +668,9 @@ __global__ __launch_bounds__(256) void k_stream_collide_tile(ScArgs<S> a) {
     float zpp[6], zpz[6], zpm[6];
     {
       float bp[9], bz[9], bm[9];
-      ld9(lds, ty * kTRowF + 0 * kTKindB + tx * 10, bp);        // P+ of row y-1
-      ld9(lds, (ty + 1) * kTRowF + 1 * kTKindB + tx * 10, bz);  // P0 of row y
-      ld9(lds, (ty + 2) * kTRowF + 2 * kTKindB + tx * 10, bm);  // P- of row y+1
+      ld9(lds, ty * G::ROW + 0 * G::KINDB + tx * 10, bp);        // P+ of row y-1
+      ld9(lds, (ty + 1) * G::ROW + 1 * G::KINDB + tx * 10, bz);  // P0 of row y
+      ld9(lds, (ty + 2) * G::ROW + 2 * G::KINDB + tx * 10, bm);  // P- of row y+1
       float C[3][3][3];  // [qx][qy][mz]
 #pragma unroll
       for (int qx2 = 0; qx2 < 3; ++qx2)
@@ -745,7 +760,7 @@ template <class S> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
   for (int k = 0; k < 3; ++k) a.periodic[k] = l.periodic[k];
   if (l.tiles) {
     if (l.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stream_collide_tile<S>, dim3(l.ntiles), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_stream_collide_tile<S, kTileX>), dim3(l.ntiles), dim3(Tile<kTileX>::THREADS), 0, s, a);
   } else {
     hipLaunchKernelGGL(k_stream_collide<S>, dim3(l.nblocks), dim3(64), 0, s, a);
   }

@@ -193,3 +193,50 @@ def test_half_precision_storage(storage, tol_exact, tol_emulated):
         gpu.step(20)
         ora.step(20)
         compare(gpu, ora, tol=tol, label=f"sphere128 {storage} vs {'emulating' if emulate else 'exact'} oracle")
+
+
+def test_finest_level_emptied_and_refilled_by_grid_updates():
+    # all particles leave: level 0 has no blocks and the step runs on level 1 alone;
+    # they come back: level 0 is rebuilt from level 1; parity with the oracle throughout
+    n = (96, 96, 96)
+    p = W.slab_particles(400, 8, (40.0, 40.0, 40.0), (56.0, 56.0, 56.0))
+    u0 = W.smooth_random_velocity(n, 10, kmax=4.0, rms=0.03)
+    gpu, ora = setup_pair(2, n, (P,) * 6, 0.6, lambda l, k: W.velocity_moments(l, k, u0), particles=p)
+    none = np.zeros((0, 3), dtype=np.float32)
+    gpu.step(2)
+    ora.step(2)
+    gpu.remesh(torch.zeros((0, 3), dtype=torch.float32, device="cuda"))
+    ora.remesh(none)
+    assert gpu.num_blocks(0) == 0 and ora.num_blocks(0) == 0
+    gpu.step(3)
+    ora.step(3)
+    compare(gpu, ora, label="empty level 0")
+    gpu.remesh(torch.as_tensor(p).cuda())
+    ora.remesh(p)
+    assert gpu.num_blocks(0) == ora.num_blocks(0) > 0
+    gpu.step(2)
+    ora.step(2)
+    compare(gpu, ora, label="refilled level 0")
+
+
+def test_grid_update_beyond_capacity_is_rejected_and_leaves_the_state():
+    # a pool sized for the initial hierarchy: a grid update that needs more blocks fails
+    # with LBM_ECAPACITY before anything is changed; stepping goes on as before
+    lbm = _lbm()
+    n = (96, 96, 96)
+    p = W.slab_particles(100, 9, (44.0, 44.0, 44.0), (52.0, 52.0, 52.0))
+    u0 = W.smooth_random_velocity(n, 11, kmax=4.0, rms=0.03)
+    probe = O.OracleSim(2, n, (P,) * 6, 0.6, particles=p)
+    cap = probe.num_blocks(0) + probe.num_blocks(1)
+    gpu, ora = setup_pair(2, n, (P,) * 6, 0.6, lambda l, k: W.velocity_moments(l, k, u0), particles=p,
+                          max_blocks=cap)
+    before = [gpu.block_keys(l).cpu().numpy() for l in range(2)]
+    wide = W.slab_particles(2000, 12, (8.0, 8.0, 8.0), (88.0, 88.0, 88.0))
+    with pytest.raises(lbm.LBMError) as e:
+        gpu.remesh(torch.as_tensor(wide).cuda())
+    assert e.value.status == -3
+    for l in range(2):
+        assert np.array_equal(gpu.block_keys(l).cpu().numpy(), before[l])
+    gpu.step(3)
+    ora.step(3)
+    compare(gpu, ora, label="after rejected update")

@@ -420,8 +420,8 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
 size_t block_bytes(const lbm_ctx* c) { return (size_t)kBlockStride * c->elem; }
 
 // undo-log entry of the next operation: room for the old values of the n blocks it
-// writes (and of the n2 outflow blocks of a stream-collide); the forward kernels
-// fill it while they run
+// writes (and of the n2 outflow blocks of a stream-collide); filled by a bulk copy
+// before a stream-collide, by the transfer and outflow kernels themselves otherwise
 lbm_status record(lbm_ctx* c, int kind, int l, int s, int64_t n, int64_t n2, void** tape, void** tape2) {
   const size_t bytes = (size_t)(n + n2) * block_bytes(c);
   if (c->tape_used + bytes > c->tape_cap) return c->fail(LBM_ECAPACITY, "adjoint tape too small");

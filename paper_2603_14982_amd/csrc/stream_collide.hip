@@ -6,15 +6,18 @@
 // stored before collision; collision (S <- S + omega (u u - S)) is applied when
 // a node is read.
 //
-// Design for gfx950: one 64-lane wavefront per 8^3 block sweeps the block plane by
-// plane in z. The population field is never formed. Per source node the
+// Design for gfx950: the population field is never formed. Per source node the
 // reconstruction is written in a per-axis tensor basis (p0 = 1, p1 = c and a
 // quadratic p2; 17 nonzero coefficients); the stream + moment projection factorises
 // into three 1D passes (x, y, z), each: moment->population along the axis, shift
-// by one node, population->moment. The x and y passes exchange through LDS on a
-// 10x10 halo plane; the z pass runs in registers over a sliding window of three
-// planes. Every lane owns one (x, y) column. Bounce-back at solid neighbours is a
-// per-node correction on the few flagged nodes.
+// by one node, population->moment. The sweep runs plane by plane in z: the x and
+// y passes exchange through LDS on a halo plane, the z pass runs in registers over
+// a sliding window of three planes, and every lane owns one (x, y) column.
+// Two kernels: k_stream_collide, one 64-lane wave per 8^3 block on a 10 x 10 halo
+// plane; k_stream_collide_tile, four waves per tile of 2 x 2 x 2 blocks on an
+// 18 x 18 plane (fewer halo reads and idle lanes; used on levels large enough to
+// fill the chip with tiles). Bounce-back at solid neighbours is a per-node
+// correction on the few flagged nodes.
 //
 // Only the deviation rho - 1 enters the coefficients: the rest state maps to
 // itself exactly, so rho - 1 is produced without cancellation against 1.
@@ -23,8 +26,10 @@
 // p2' = 3c^2 - 1, and every 1D pass works on six times the populations, so the
 // lattice weights become the integers (1, 4, 1) and all basis constants are small
 // integers. Only additions round (to nearest, unbiased); the factor 6^3 = 216 is
-// removed by one correctly rounded division per output. Inexact weights such as
-// fl(1/6) would bias every step the same way and the error would grow linearly.
+// removed per output without multiplying by a rounded constant reciprocal (an
+// FMA-corrected quotient for rho - 1, a reciprocal with one Newton step for the
+// others). Inexact weights such as fl(1/6) would bias every step the same way and
+// the error would grow linearly.
 #include "common.h"
 #include "kernels.h"
 

@@ -14,9 +14,11 @@
 // Bounce-back adds, at a flagged computed node, populations built from the node's
 // own coefficients; its transpose is a per-node term of the same sweep. Solid and
 // inflow nodes hold fixed values and collect no adjoint.
-// Interface transfers: the downward transfer is transposed as a gather per coarse
-// node (every ghost whose trilinear stencil contains the node), the upward
-// transfer as a one-to-one scatter; both use the forward values they depend on.
+// Interface transfers: the downward transfer is transposed per ghost block (the
+// block's contribution to each coarse node under it, summed in LDS) and then per
+// coarse node (a fixed-order sum of the at most eight ghost blocks' contributions);
+// the upward transfer is a one-to-one scatter; both use the forward values they
+// depend on.
 // Every kernel is deterministic: no atomics, each output written by one lane.
 #include "common.h"
 #include "kernels.h"

@@ -229,27 +229,25 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
 
 // LDS plane buffer, row-major so that the x pass of a row only overwrites its
 // own row: row r (plane row y = r - 1) holds
-//   x-pass input:  [kind (P+, P0, P-)][col 0..9][group 0..7]        (240 floats)
-//   y-pass input:  [kind (P+, P0, P-)][col 0..7][triple 0..8, pad 10] (240 floats)
-// Components of one point are contiguous so a lane moves them with 128-bit
-// (x-pass input) and 64-bit (y-pass input) LDS accesses.
-// The two 4-float halves of an x-pass entry swap places on odd rows, so that the
-// 128-bit accesses of two neighbouring rows fall on disjoint LDS banks.
+//   x-pass input:  [kind (P+, P0, P-)][half][col 0..9][4]                (240 floats)
+//   y-pass input:  [kind (P+, P0, P-)][col 0..7][triple 0..8, pad 10]   (240 floats)
+// The 8 group values of a point are split in two 4-float halves, so that the
+// 128-bit accesses of neighbouring lanes are 16 bytes apart (no bank conflicts);
+// the y-pass input moves with 64-bit accesses. Rows are 16 banks apart.
 constexpr int kRow = 240;
-__device__ __forceinline__ int a_off(int row, int kind, int col) { return row * kRow + kind * 80 + col * 8; }
+constexpr int kHalf = 40;
+__device__ __forceinline__ int a_off(int row, int kind, int col) { return row * kRow + kind * 80 + col * 4; }
 __device__ __forceinline__ int b_off(int row, int kind, int col) { return row * kRow + kind * 80 + col * 10; }
 
 __device__ __forceinline__ void st8(float* lds, int row, int kind, int col, const float v[8]) {
   const int off = a_off(row, kind, col);
-  const int sw = (row & 1) << 2;
-  *reinterpret_cast<float4*>(lds + off + sw) = make_float4(v[0], v[1], v[2], v[3]);
-  *reinterpret_cast<float4*>(lds + off + (4 ^ sw)) = make_float4(v[4], v[5], v[6], v[7]);
+  *reinterpret_cast<float4*>(lds + off) = make_float4(v[0], v[1], v[2], v[3]);
+  *reinterpret_cast<float4*>(lds + off + kHalf) = make_float4(v[4], v[5], v[6], v[7]);
 }
 __device__ __forceinline__ void ld8(const float* lds, int row, int kind, int col, float v[8]) {
   const int off = a_off(row, kind, col);
-  const int sw = (row & 1) << 2;
-  const float4 a = *reinterpret_cast<const float4*>(lds + off + sw);
-  const float4 b = *reinterpret_cast<const float4*>(lds + off + (4 ^ sw));
+  const float4 a = *reinterpret_cast<const float4*>(lds + off);
+  const float4 b = *reinterpret_cast<const float4*>(lds + off + kHalf);
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
 __device__ __forceinline__ void st9(float* lds, int off, const float v[9]) {

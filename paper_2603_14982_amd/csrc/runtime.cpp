@@ -3,6 +3,7 @@
 // grid-update pipeline (Sec. 6.3).
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -66,6 +67,8 @@ bool make_geom(const lbm_config* c, Geom& G, std::string& err) {
     g.off = off;
     off += g.ncell;
   }
+  // block positions are indexed with int32 (cell lists, directory entries)
+  if (off > INT32_MAX) { err = "domain too large: more than 2^31 block positions over all levels"; return false; }
   if (!(c->tau0 > 0.5) || !std::isfinite(c->tau0)) { err = "tau0 must be finite and exceed 1/2"; return false; }
   if (c->storage < LBM_F32 || c->storage > LBM_F16) { err = "unknown storage format"; return false; }
   if (c->rescale != 0 && c->rescale != 1) { err = "rescale must be 0 or 1"; return false; }

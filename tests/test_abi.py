@@ -52,6 +52,7 @@ def test_buffer_sizes():
     (dict(bc=(7, 7, 0, 0, 0, 0)), "boundary"),
     (dict(max_blocks=0), "max_blocks"),
     (dict(storage="bf16", scale=[0.0] * 10), "scales"),
+    (dict(n=(1 << 20, 1 << 20, 1 << 20)), "too large"),
 ])
 def test_invalid_configurations_are_rejected_on_host(kw, msg):
     L = lbm.lib()

@@ -41,6 +41,7 @@ struct TransferLaunch {
   const void* src_a;         // source time level (down: coarse t; up: fine current)
   const void* src_b;         // down only: coarse t+2 (same as src_a for s = 1)
   void* dst;                 // target time level
+  void* dst2;                // down only: if set, both fine substeps (s = 1 into dst, s = 2 into dst2)
   float factor;              // S^neq rescaling factor
   int midpoint;              // down only: 1 = average src_a and src_b
   Scales sc;

@@ -509,9 +509,14 @@ TransferLaunch transfer_base(lbm_ctx* c, int l) {
   return t;
 }
 
-// DownwardTransfer(l+1, s): ghosts of level l from level l+1 (old: t, current: t+2)
+// DownwardTransfer(l+1, s): ghosts of level l from level l+1 (old: t, current: t+2).
+// Both fine substeps read the same two coarse time levels, so outside the adjoint
+// replay the s = 2 ghosts are written together with the s = 1 ghosts, into the time
+// level the first fine stream-collide writes (it leaves ghost nodes alone); the
+// s = 2 call then has nothing left to do.
 lbm_status down_level(lbm_ctx* c, int l, int s) {
   if (c->ngb[l] == 0) return LBM_OK;
+  if (s == 2 && !c->recording) return LBM_OK;
   TransferLaunch t = transfer_base(c, l);
   t.blocks = c->gblocks(l);
   t.nblocks = (int32_t)c->ngb[l];
@@ -519,6 +524,7 @@ lbm_status down_level(lbm_ctx* c, int l, int s) {
   t.src_b = c->cur(l + 1);
   t.midpoint = (s == 2) ? 1 : 0;
   t.dst = c->cur(l);
+  if (!c->recording) t.dst2 = c->other(l);
   t.factor = (float)c->a_down[l];
   t.gbox = c->m<int32_t>(c->lay.gbox);
   if (c->recording) {

@@ -59,9 +59,43 @@ __device__ inline void from_neq(float q[kMom]) {
 // its 1, 2, 4 or 8 trilinear sources from LDS. Staged positions in blocks that hold
 // no coarse data (covered by the fine level) read as zero; no ghost node of a valid
 // hierarchy uses them.
+// trilinear interpolation of the staged (rho-1, u, S^neq) at local fine node lc,
+// S^neq rescaled by `factor`, back to (rho-1, u, S)
+__device__ inline void interp_ghost(const float (*cq)[125], const int lc[3], float factor, float acc[kMom]) {
+  int i0[3], i1[3];
+  float w1[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    // fine node 8b + lc sits on coarse 4b + lc/2 (even) or between the two neighbours (odd)
+    i0[ax] = lc[ax] >> 1;
+    i1[ax] = (lc[ax] + 1) >> 1;
+    w1[ax] = (lc[ax] & 1) ? 0.5f : 0.0f;
+  }
+#pragma unroll
+  for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int kx = c & 1, ky = (c >> 1) & 1, kz = c >> 2;
+    const float w = (kx ? w1[0] : 1.0f - w1[0]) * (ky ? w1[1] : 1.0f - w1[1]) * (kz ? w1[2] : 1.0f - w1[2]);
+    if (w == 0.0f) continue;
+    const int t = (kx ? i1[0] : i0[0]) + 5 * (ky ? i1[1] : i0[1]) + 25 * (kz ? i1[2] : i0[2]);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[m] += w * cq[m][t];
+    const float ws = w * factor;
+#pragma unroll
+    for (int m = 4; m < kMom; ++m) acc[m] += ws * cq[m][t];
+  }
+  from_neq(acc);
+}
+
+// a.dst2 == null: one substep (s = 1 from src_a, or s = 2 from the midpoint of
+// src_a and src_b, by a.midpoint) into a.dst. a.dst2 != null: both substeps of the
+// fine level at once, s = 1 into a.dst and s = 2 into a.dst2 (the time level the
+// first fine stream-collide writes; it never writes ghost nodes).
 template <class S>
 __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
-  __shared__ float cq[kMom][125];
+  __shared__ float cq[2][kMom][125];
+  const bool both = a.dst2 != nullptr;
   const int slot = a.blocks[blockIdx.x];
   const int4 bc = a.coord[slot];
   const int l = a.level;
@@ -83,23 +117,26 @@ __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
       else j[ax] = j[ax] >= nc ? nc - 1 : j[ax];
     }
     const int cs = a.dir[cg.off + cell_lin(cg, j[0] >> 3, j[1] >> 3, j[2] >> 3)];
-    float q[kMom];
+    float q[kMom], h[kMom];
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) q[m] = 0.0f;
+    for (int m = 0; m < kMom; ++m) q[m] = h[m] = 0.0f;
     if (cs >= 0) {
       const int cn = (j[0] & 7) + 8 * (j[1] & 7) + 64 * (j[2] & 7);
       Mom<S>::load(a.src_a, cs, cn, a.sc, q);
       to_neq(q);
-      if (a.midpoint) {
+      if (a.midpoint || both) {
         float r[kMom];
         Mom<S>::load(a.src_b, cs, cn, a.sc, r);
         to_neq(r);
 #pragma unroll
-        for (int m = 0; m < kMom; ++m) q[m] = 0.5f * (q[m] + r[m]);
+        for (int m = 0; m < kMom; ++m) h[m] = 0.5f * (q[m] + r[m]);
       }
     }
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) cq[m][t] = q[m];
+    for (int m = 0; m < kMom; ++m) {
+      cq[0][m][t] = (a.midpoint && !both) ? h[m] : q[m];
+      cq[1][m][t] = h[m];
+    }
   }
   __syncthreads();
   const int nn[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
@@ -107,33 +144,14 @@ __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
     const int lc[3] = {lo[0] + k % nn[0], lo[1] + (k / nn[0]) % nn[1], lo[2] + k / (nn[0] * nn[1])};
     const int node = lc[0] + 8 * lc[1] + 64 * lc[2];
     if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_GHOST) continue;
-    int i0[3], i1[3];
-    float w1[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      // fine node 8b + lc sits on coarse 4b + lc/2 (even) or between the two neighbours (odd)
-      i0[ax] = lc[ax] >> 1;
-      i1[ax] = (lc[ax] + 1) >> 1;
-      w1[ax] = (lc[ax] & 1) ? 0.5f : 0.0f;
-    }
     float acc[kMom];
-#pragma unroll
-    for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int kx = c & 1, ky = (c >> 1) & 1, kz = c >> 2;
-      const float w = (kx ? w1[0] : 1.0f - w1[0]) * (ky ? w1[1] : 1.0f - w1[1]) * (kz ? w1[2] : 1.0f - w1[2]);
-      if (w == 0.0f) continue;
-      const int t = (kx ? i1[0] : i0[0]) + 5 * (ky ? i1[1] : i0[1]) + 25 * (kz ? i1[2] : i0[2]);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) acc[m] += w * cq[m][t];
-      const float ws = w * a.factor;
-#pragma unroll
-      for (int m = 4; m < kMom; ++m) acc[m] += ws * cq[m][t];
-    }
-    from_neq(acc);
+    interp_ghost(cq[0], lc, a.factor, acc);
     if (a.tape) keep_old<S>(a.dst, a.tape, slot, blockIdx.x, node);
     Mom<S>::store(a.dst, slot, node, a.sc, acc);
+    if (both) {
+      interp_ghost(cq[1], lc, a.factor, acc);
+      Mom<S>::store(a.dst2, slot, node, a.sc, acc);
+    }
   }
 }
 

@@ -138,6 +138,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="run the finest level's two substeps of a parent step as two sweeps (comparison)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="print only the adjoint/forward measurement (for profiling the adjoint kernels)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -161,6 +163,8 @@ def main():
     p_host = W.slab_particles(wl["particles"], wl["seed"], wl["lo"], wl["hi"])
     particles = torch.as_tensor(p_host).cuda()
     sim = lbm.Sim(wl["levels"], wl["n"], wl["bc"], wl["tau0"], particles=particles, max_blocks=48000)
+    if args.no_fuse:
+        sim.set_option("fuse_substeps", 0)
     init_fields(sim, wl, W)
     torch.cuda.synchronize()
     sub = 1 << (wl["levels"] - 1)
@@ -199,20 +203,28 @@ def main():
     ms_per_step = elapsed / args.steps * 1e3
     mlups = updates * args.steps / elapsed / 1e6
 
-    # the dominant kernel: level 0's stream-collide, which runs on 2 x 2 x 2 block tiles
-    # (4 launches per coarse step); level 1 and 2 run the single-block kernel
-    sc_ms, sc_n = prof["sc0"]
+    # the dominant kernel: level 0's stream-collide on 2 x 2 x 2 block tiles, either both
+    # substeps of a parent step in one launch (two updates of every node, 2 launches per
+    # coarse step) or one substep per launch (4 launches per coarse step)
+    if prof["sc_pair"][1]:
+        sc_ms, sc_n = prof["sc_pair"]
+        launch_updates = 2 * per_level[0]
+        kernel = "k_stream_collide_pair<StoreF32> (level 0, two substeps per launch)"
+    else:
+        sc_ms, sc_n = prof["sc0"]
+        launch_updates = per_level[0]
+        kernel = "k_stream_collide_tile<StoreF32> (level 0)"
     sc_avg_s = sc_ms / sc_n / 1e3
-    alg_bytes = BYTES_PER_UPDATE * per_level[0]
+    alg_bytes = BYTES_PER_UPDATE * launch_updates
     achieved = alg_bytes / sc_avg_s / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("kernel_src_sha") == sc_source_hash():
+        if tr.get("kernel_src_sha") == sc_source_hash() and tr.get("kernel") == kernel:
             traffic = tr.get("hbm_bytes_per_launch")
-    all_ms = sum(prof[f"sc{l}"][0] for l in range(sim.levels))
-    all_n = sum(prof[f"sc{l}"][1] for l in range(sim.levels))
+    all_ms = sum(prof[f"sc{l}"][0] for l in range(sim.levels)) + prof["sc_pair"][0]
+    all_n = sum(prof[f"sc{l}"][1] for l in range(sim.levels)) + prof["sc_pair"][1]
     sc_updates = sum(per_level[l] * (1 << (sim.levels - 1 - l)) for l in range(sim.levels)) * args.steps
     all_bytes = BYTES_PER_UPDATE * sc_updates / all_n
     all_avg_s = all_ms / all_n / 1e3
@@ -246,7 +258,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_stream_collide_tile<StoreF32> (level 0)",
+            "kernel": kernel,
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "avg_launch_ms": round(sc_avg_s * 1e3, 5),
             "launches": sc_n,

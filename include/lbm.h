@@ -135,19 +135,34 @@ lbm_status lbm_check_finite(lbm_ctx* ctx);
 /* Phase timers. With profiling on, every launch of the listed phases is bracketed
  * by HIP events on cfg.stream; lbm_get_profile synchronises, returns the summed
  * milliseconds and launch counts per phase since the last call, and resets them.
- * Phases: stream-collide of levels 0..4, downward transfers, upward transfers,
- * outflow copies, whole grid updates (lbm_remesh, host time between its events
- * included). */
+ * Phases: stream-collide of levels 0..4 (one substep per launch), downward
+ * transfers, upward transfers, outflow copies, whole grid updates (lbm_remesh, host
+ * time between its events included), and the finest level's two substeps of a
+ * parent step in one launch (see LBM_OPT_FUSE_SUBSTEPS). */
 enum {
   LBM_PROF_SC0 = 0,            /* + level */
   LBM_PROF_DOWN = 5,
   LBM_PROF_UP = 6,
   LBM_PROF_OUTFLOW = 7,
   LBM_PROF_REMESH = 8,
-  LBM_PROFILE_PHASES = 9
+  LBM_PROF_SC_PAIR = 9,
+  LBM_PROFILE_PHASES = 10
 };
 lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t on);
 lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t count[LBM_PROFILE_PHASES]);
+
+/* Execution options (they change how a step is scheduled on the GPU, not what it
+ * computes; results agree to rounding).
+ * LBM_OPT_TILE_MIN_BLOCKS: a level with at least this many blocks (counted as
+ *   8 per 2 x 2 x 2 tile) runs its stream-collide on tiles of 2 x 2 x 2 blocks,
+ *   smaller levels one block per 64-lane workgroup. Default 16384; >= 0.
+ * LBM_OPT_FUSE_SUBSTEPS: 1 (default) runs the two substeps of every parent step of
+ *   the finest level (Alg. 1, levels >= 2) in one tiled sweep when that level is
+ *   tiled and has no outflow or bounce-back nodes, and the step is not being
+ *   recorded for the adjoint; 0 always runs them as two sweeps.
+ * LBM_EINVAL for an unknown option or a value out of range. */
+enum { LBM_OPT_TILE_MIN_BLOCKS = 0, LBM_OPT_FUSE_SUBSTEPS = 1 };
+lbm_status lbm_set_option(lbm_ctx* ctx, int32_t option, int64_t value);
 
 /* ---- states and the adjoint (gradient of a loss of the final moments with
  * respect to the initial moments; Sec. 7 differentiates the solver) ----

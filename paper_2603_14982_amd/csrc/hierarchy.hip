@@ -368,10 +368,12 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
       }
     }
     sum |= rk == ROLE_GHOST ? SUM_GHOST : (rk == ROLE_IU ? SUM_IU : (rk == ROLE_OUTFLOW ? SUM_OUTFLOW : 0));
+    if (role & ROLE_BB) sum |= SUM_BB;
   }
   const int any_g = __syncthreads_or(sum & SUM_GHOST);
   const int any_i = __syncthreads_or(sum & SUM_IU);
   const int any_o = __syncthreads_or(sum & SUM_OUTFLOW);
+  const int any_b = __syncthreads_or(sum & SUM_BB);
   if (threadIdx.x == 0) {
     // one representative per stream-collide tile of kTileX x 2 x 2 blocks: the
     // active member with the lowest index (x fastest); members are never wrapped
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
         start = false;
     }
     r.summary[slot] = (any_g ? SUM_GHOST : 0) | (any_i ? SUM_IU : 0) | (any_o ? SUM_OUTFLOW : 0) |
-                      (start ? SUM_TILE : 0);
+                      (start ? SUM_TILE : 0) | (any_b ? SUM_BB : 0);
     r.gbox[slot] = s_box[0] | s_box[3] << 3 | s_box[1] << 6 | s_box[4] << 9 | s_box[2] << 12 | s_box[5] << 15;
   }
 }

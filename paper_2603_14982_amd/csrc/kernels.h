@@ -28,6 +28,9 @@ struct ScLaunch {
   int periodic[3];
 };
 hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s);
+// both substeps of a parent step of the finest level, in -> out (tiles required; the
+// level has no outflow or bounce-back nodes, and out holds the ghosts of the second)
+hipError_t launch_stream_collide_pair(const ScLaunch& a, hipStream_t s);
 
 // ---- interface transfers and outflow ----
 struct TransferLaunch {

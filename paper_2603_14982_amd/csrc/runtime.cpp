@@ -148,6 +148,9 @@ struct lbm_ctx {
   int rcur = 0;   // which role array is current
   const uint8_t* solid = nullptr;
   int64_t nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels], ntile[kMaxLevels];
+  int64_t nbb[kMaxLevels];          // blocks holding bounce-back nodes
+  int64_t tile_min_blocks = 16384;  // LBM_OPT_TILE_MIN_BLOCKS
+  bool fuse_substeps = true;        // LBM_OPT_FUSE_SUBSTEPS
   int32_t free_top = 0;
   int32_t* host_counts = nullptr;  // pinned
   std::string err;
@@ -416,6 +419,7 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     c->nib[l] = c->host_counts[3 * l + 1];
     c->nob[l] = c->host_counts[3 * l + 2];
     c->ntile[l] = c->host_counts[32 + 3 * l];
+    c->nbb[l] = c->host_counts[33 + 3 * l];
   }
   return LBM_OK;
 }
@@ -444,7 +448,9 @@ lbm_status record(lbm_ctx* c, int kind, int l, int s, int64_t n, int64_t n2, voi
 }
 
 // ---- Alg. 1 (Sec. 5.3) ----
-lbm_status sc_level(lbm_ctx* c, int l) {
+bool tiled(const lbm_ctx* c, int l) { return c->ntile[l] > 0 && c->ntile[l] * 4 * kTileX >= c->tile_min_blocks; }
+
+ScLaunch sc_base(lbm_ctx* c, int l) {
   ScLaunch a;
   a.in = c->cur(l);
   a.out = c->other(l);
@@ -456,15 +462,20 @@ lbm_status sc_level(lbm_ctx* c, int l) {
   a.omega = (float)(1.0 / c->tau[l]);
   a.sc = c->sc;
   a.storage = c->cfg.storage;
-  // tiles once the level has enough blocks (16384) to fill the chip several times
-  // with them; single blocks below
-  const bool tiles = c->ntile[l] * 4 * kTileX >= 16384;
-  a.tiles = tiles ? c->tblocks(l) : nullptr;
-  a.ntiles = tiles ? (int32_t)c->ntile[l] : 0;
+  // tiles once the level has enough blocks (16384 by default) to fill the chip
+  // several times with them; single blocks below
+  const bool t = tiled(c, l);
+  a.tiles = t ? c->tblocks(l) : nullptr;
+  a.ntiles = t ? (int32_t)c->ntile[l] : 0;
   a.dir = c->dir(c->hier);
   a.coord = c->m<int4>(c->lay.coord);
   a.lg = c->G.lv[l];
   for (int k = 0; k < 3; ++k) a.periodic[k] = c->G.periodic[k];
+  return a;
+}
+
+lbm_status sc_level(lbm_ctx* c, int l) {
+  ScLaunch a = sc_base(c, l);
   void* otape = nullptr;
   if (c->recording) {
     // the whole blocks of the written time level go to the tape (one bulk copy)
@@ -556,13 +567,35 @@ lbm_status up_level(lbm_ctx* c, int l) {
   return LBM_OK;
 }
 
+// Both substeps of a parent step of the finest level in one sweep: its ghosts for
+// both are in place after the first downward transfer, and nothing else runs between
+// the two substeps. The result goes to the other time level, so the level's parity
+// flips once instead of twice; the intermediate time level is never stored (no finer
+// level interpolates from it).
+bool pair_ok(const lbm_ctx* c) {
+  return c->fuse_substeps && !c->recording && c->G.L >= 2 && tiled(c, 0) && c->nob[0] == 0 && c->nbb[0] == 0;
+}
+
+lbm_status sc_pair(lbm_ctx* c) {
+  ScLaunch a = sc_base(c, 0);
+  const int k = c->tic(LBM_PROF_SC_PAIR);
+  HIPCHK(c, launch_stream_collide_pair(a, c->stream));
+  c->toc(k);
+  c->parity[0] ^= 1;
+  return LBM_OK;
+}
+
 lbm_status advance(lbm_ctx* c, int l, int s) {
   const int L = c->G.L;
   lbm_status st;
   if (l < L - 1 && (st = down_level(c, l, s)) != LBM_OK) return st;
   if ((st = sc_level(c, l)) != LBM_OK) return st;
   if (l < L - 1 && s == 2 && (st = up_level(c, l)) != LBM_OK) return st;
-  if (l > 0) {
+  if (l == 1 && pair_ok(c)) {
+    if ((st = down_level(c, 0, 1)) != LBM_OK) return st;
+    if ((st = sc_pair(c)) != LBM_OK) return st;
+    if ((st = up_level(c, 0)) != LBM_OK) return st;
+  } else if (l > 0) {
     if ((st = advance(c, l - 1, 1)) != LBM_OK) return st;
     if ((st = advance(c, l - 1, 2)) != LBM_OK) return st;
   }
@@ -736,7 +769,7 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
     const double k = std::ldexp(1.0, l);
     c->tau[l] = cfg->tau0 / k + (k - 1.0) / (2.0 * k);  // tau_{l} from tau_0 (Sec. 5.2)
     c->parity[l] = 0;
-    c->nblk[l] = c->ngb[l] = c->nib[l] = c->nob[l] = c->ntile[l] = 0;
+    c->nblk[l] = c->ngb[l] = c->nib[l] = c->nob[l] = c->ntile[l] = c->nbb[l] = 0;
   }
   for (int l = 0; l < G.L; ++l) {
     c->a_up[l] = c->a_down[l] = 1.0;
@@ -866,6 +899,21 @@ lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t on) {
   ctx->collect();
   ctx->profiling = on != 0;
   return LBM_OK;
+}
+
+lbm_status lbm_set_option(lbm_ctx* ctx, int32_t option, int64_t value) {
+  if (!ctx) return LBM_EINVAL;
+  switch (option) {
+    case LBM_OPT_TILE_MIN_BLOCKS:
+      if (value < 0) return ctx->fail(LBM_EINVAL, "tile threshold must be >= 0");
+      ctx->tile_min_blocks = value;
+      return LBM_OK;
+    case LBM_OPT_FUSE_SUBSTEPS:
+      if (value != 0 && value != 1) return ctx->fail(LBM_EINVAL, "LBM_OPT_FUSE_SUBSTEPS takes 0 or 1");
+      ctx->fuse_substeps = value != 0;
+      return LBM_OK;
+  }
+  return ctx->fail(LBM_EINVAL, "unknown option");
 }
 
 lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t count[LBM_PROFILE_PHASES]) {

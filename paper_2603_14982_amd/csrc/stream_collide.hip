@@ -468,6 +468,69 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   }
 }
 
+// y pass of one column of a plane buffer whose y-pass input is [kind][col][10]
+// (kinds KINDB apart, rows ROW apart): rows r0, r0 + 1, r0 + 2 hold the rows y - 1,
+// y, y + 1 of the column's row y. Back-map after the shift along y, then forward-map
+// along z the six (qx, qy) groups the ten output moments need:
+// (0,0) (1,0) (0,1) (2,0) (0,2) (1,1).
+template <int ROW, int KINDB>
+__device__ __forceinline__ void y_pass_col(const float* lds, int r0, int col, float zpp[6], float zpz[6],
+                                           float zpm[6]) {
+  float bp[9], bz[9], bm[9];
+  ld9(lds, r0 * ROW + 0 * KINDB + col * 10, bp);        // P+ of row y-1
+  ld9(lds, (r0 + 1) * ROW + 1 * KINDB + col * 10, bz);  // P0 of row y
+  ld9(lds, (r0 + 2) * ROW + 2 * KINDB + col * 10, bm);  // P- of row y+1
+  float C[3][3][3];  // [qx][qy][mz]
+#pragma unroll
+  for (int qx = 0; qx < 3; ++qx)
+#pragma unroll
+    for (int mz = 0; mz < 3; ++mz) {
+      const int t = 3 * qx + mz;
+      float m0, m1, m2;
+      back3(bp[t], bz[t], bm[t], m0, m1, m2);
+      C[qx][0][mz] = m0; C[qx][1][mz] = m1; C[qx][2][mz] = m2;
+    }
+  fwd3(C[0][0][0], C[0][0][1], C[0][0][2], zpp[0], zpz[0], zpm[0]);
+  fwd3(C[1][0][0], C[1][0][1], C[1][0][2], zpp[1], zpz[1], zpm[1]);
+  fwd3(C[0][1][0], C[0][1][1], C[0][1][2], zpp[2], zpz[2], zpm[2]);
+  fwd3(C[2][0][0], C[2][0][1], C[2][0][2], zpp[3], zpz[3], zpm[3]);
+  fwd3(C[0][2][0], C[0][2][1], C[0][2][2], zpp[4], zpz[4], zpm[4]);
+  fwd3(C[1][1][0], C[1][1][1], C[1][1][2], zpp[5], zpz[5], zpm[5]);
+}
+
+// z pass of one node: its ten moment sums (times 216) from pop+ of the plane below,
+// pop0 of its own plane and pop- of the plane above
+__device__ __forceinline__ void z_back(const float zp[6], const float z0[6], const float zm[6], float M[10]) {
+  float m0, m1, m2;
+  back3(zp[0], z0[0], zm[0], m0, m1, m2);  // (0,0): M000, M001, M002
+  M[0] = m0; M[3] = m1; M[6] = m2;
+  back3(zp[1], z0[1], zm[1], m0, m1, m2);  // (1,0): M100, M101
+  M[1] = m0; M[8] = m1;
+  back3(zp[2], z0[2], zm[2], m0, m1, m2);  // (0,1): M010, M011
+  M[2] = m0; M[9] = m1;
+  back3(zp[3], z0[3], zm[3], m0, m1, m2);  // (2,0): M200
+  M[4] = m0;
+  back3(zp[4], z0[4], zm[4], m0, m1, m2);  // (0,2): M020
+  M[5] = m0;
+  back3(zp[5], z0[5], zm[5], m0, m1, m2);  // (1,1): M110
+  M[7] = m0;
+}
+
+// stored moments from the moment sums: remove the 6^3 scale of the three passes; no
+// constant reciprocal of 216 or 3 multiplies a result (it would bias every step the
+// same way)
+__device__ __forceinline__ void finish_moments(const float M[10], float v[kMom]) {
+  const float c216 = 1.0f / 216.0f;
+  const float q0 = M[0] * c216;
+  v[0] = __builtin_fmaf(__builtin_fmaf(-q0, 216.0f, M[0]), c216, q0);  // M0 / 216
+  const float r216 = 216.0f + M[0];          // 216 rho'
+  const float inv = recip(r216);
+  const float inv3 = recip(3.0f * r216);     // p2' = 3 p2 on the diagonal stresses
+  v[1] = M[1] * inv; v[2] = M[2] * inv; v[3] = M[3] * inv;
+  v[4] = M[4] * inv3; v[5] = M[5] * inv3; v[6] = M[6] * inv3;
+  v[7] = M[7] * inv; v[8] = M[8] * inv; v[9] = M[9] * inv;
+}
+
 // ---- 2 x 2 x 2 block tiles ------------------------------------------------------
 // One workgroup of four waves sweeps a tile of 2 x 2 x 2 blocks (16 x 16 columns,
 // 16 planes) in z. The halo plane is 18 x 18 points instead of four separate 10 x 10
@@ -497,27 +560,30 @@ template <int TX> struct Tile {
   static_assert(3 * KINDA <= ROW, "x-pass input must fit in a row");
 };
 
-template <int TX>
-__device__ __forceinline__ void st8_at(float* lds, int off, const float v[8]) {
+template <int HALF>
+__device__ __forceinline__ void st8_h(float* lds, int off, const float v[8]) {
   *reinterpret_cast<float4*>(lds + off) = make_float4(v[0], v[1], v[2], v[3]);
-  *reinterpret_cast<float4*>(lds + off + Tile<TX>::HALF) = make_float4(v[4], v[5], v[6], v[7]);
+  *reinterpret_cast<float4*>(lds + off + HALF) = make_float4(v[4], v[5], v[6], v[7]);
 }
-template <int TX>
-__device__ __forceinline__ void ld8_at(const float* lds, int off, float v[8]) {
+template <int HALF>
+__device__ __forceinline__ void ld8_h(const float* lds, int off, float v[8]) {
   const float4 a = *reinterpret_cast<const float4*>(lds + off);
-  const float4 b = *reinterpret_cast<const float4*>(lds + off + Tile<TX>::HALF);
+  const float4 b = *reinterpret_cast<const float4*>(lds + off + HALF);
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
 }
-
-// x pass for tile row `row` (plane row row - 1), tile column x
 template <int TX>
-__device__ __forceinline__ void x_pass_tile(const float* lds, int row, int x, float yb[27]) {
-  typedef Tile<TX> G;
+__device__ __forceinline__ void st8_at(float* lds, int off, const float v[8]) {
+  st8_h<Tile<TX>::HALF>(lds, off, v);
+}
+
+// x pass for one row of a plane buffer (x-pass input at `base`, kinds KINDA apart,
+// 4 floats per column, halves HALF apart), output column x (input columns x, x+1, x+2)
+template <int HALF, int KINDA>
+__device__ __forceinline__ void x_pass_row(const float* lds, int base, int x, float yb[27]) {
   float pp[8], pz[8], pm[8];
-  const int base = row * G::ROW;
-  ld8_at<TX>(lds, base + 0 * G::KINDA + x * 4, pp);        // P+ of column x-1
-  ld8_at<TX>(lds, base + 1 * G::KINDA + (x + 1) * 4, pz);  // P0 of column x
-  ld8_at<TX>(lds, base + 2 * G::KINDA + (x + 2) * 4, pm);  // P- of column x+1
+  ld8_h<HALF>(lds, base + 0 * KINDA + x * 4, pp);        // P+ of column x-1
+  ld8_h<HALF>(lds, base + 1 * KINDA + (x + 1) * 4, pz);  // P0 of column x
+  ld8_h<HALF>(lds, base + 2 * KINDA + (x + 2) * 4, pm);  // P- of column x+1
   float B[3][3][3];  // [qx][my][mz]
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
@@ -535,6 +601,13 @@ __device__ __forceinline__ void x_pass_tile(const float* lds, int row, int x, fl
       const int t = 3 * qx + mz;
       fwd3(B[qx][0][mz], B[qx][1][mz], b2, yb[t], yb[9 + t], yb[18 + t]);
     }
+}
+
+// x pass for tile row `row` (plane row row - 1), tile column x
+template <int TX>
+__device__ __forceinline__ void x_pass_tile(const float* lds, int row, int x, float yb[27]) {
+  typedef Tile<TX> G;
+  x_pass_row<G::HALF, G::KINDA>(lds, row * G::ROW, x, yb);
 }
 
 template <class S, int TX>
@@ -595,7 +668,6 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
   const int slots[2] = {s_mem[wave], s_mem[wave + 2 * TX]};  // this wave's blocks, lower and upper
   const int ox = lane & 7, oy = lane >> 3;
   const int tx = (wave % TX) * 8 + ox, ty = (wave / TX) * 8 + oy;  // tile column of this lane
-  const float c216 = 1.0f / 216.0f;
   uint64_t col_roles[2] = {0, 0};
 #pragma unroll
   for (int zb = 0; zb < 2; ++zb) {
@@ -669,28 +741,7 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
 
     // ---- y pass for the lane's column, then z-forward
     float zpp[6], zpz[6], zpm[6];
-    {
-      float bp[9], bz[9], bm[9];
-      ld9(lds, ty * G::ROW + 0 * G::KINDB + tx * 10, bp);        // P+ of row y-1
-      ld9(lds, (ty + 1) * G::ROW + 1 * G::KINDB + tx * 10, bz);  // P0 of row y
-      ld9(lds, (ty + 2) * G::ROW + 2 * G::KINDB + tx * 10, bm);  // P- of row y+1
-      float C[3][3][3];  // [qx][qy][mz]
-#pragma unroll
-      for (int qx2 = 0; qx2 < 3; ++qx2)
-#pragma unroll
-        for (int mz = 0; mz < 3; ++mz) {
-          const int t = 3 * qx2 + mz;
-          float m0, m1, m2;
-          back3(bp[t], bz[t], bm[t], m0, m1, m2);
-          C[qx2][0][mz] = m0; C[qx2][1][mz] = m1; C[qx2][2][mz] = m2;
-        }
-      fwd3(C[0][0][0], C[0][0][1], C[0][0][2], zpp[0], zpz[0], zpm[0]);
-      fwd3(C[1][0][0], C[1][0][1], C[1][0][2], zpp[1], zpz[1], zpm[1]);
-      fwd3(C[0][1][0], C[0][1][1], C[0][1][2], zpp[2], zpz[2], zpm[2]);
-      fwd3(C[2][0][0], C[2][0][1], C[2][0][2], zpp[3], zpz[3], zpm[3]);
-      fwd3(C[0][2][0], C[0][2][1], C[0][2][2], zpp[4], zpz[4], zpm[4]);
-      fwd3(C[1][1][0], C[1][1][1], C[1][1][2], zpp[5], zpz[5], zpm[5]);
-    }
+    y_pass_col<G::ROW, G::KINDB>(lds, ty, tx, zpp, zpz, zpm);
     __syncthreads();
 
     // ---- z pass: output plane zo = z - 1 (block zo / 8 of the wave's column)
@@ -698,35 +749,15 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
     const int slot = zo >= 8 ? slots[1] : slots[0];
     if (zo >= 0 && slot >= 0) {
       float M[10];
-      float m0, m1, m2;
-      back3(zp2[0], z0[0], zpm[0], m0, m1, m2);
-      M[0] = m0; M[3] = m1; M[6] = m2;
-      back3(zp2[1], z0[1], zpm[1], m0, m1, m2);
-      M[1] = m0; M[8] = m1;
-      back3(zp2[2], z0[2], zpm[2], m0, m1, m2);
-      M[2] = m0; M[9] = m1;
-      back3(zp2[3], z0[3], zpm[3], m0, m1, m2);
-      M[4] = m0;
-      back3(zp2[4], z0[4], zpm[4], m0, m1, m2);
-      M[5] = m0;
-      back3(zp2[5], z0[5], zpm[5], m0, m1, m2);
-      M[7] = m0;
+      z_back(zp2, z0, zpm, M);
       const int lz = zo & 7;
       const int node = ox + 8 * oy + 64 * lz;
       const uint8_t role = (uint8_t)((zo >= 8 ? col_roles[1] : col_roles[0]) >> (8 * lz));
       typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
       if ((role & ROLE_MASK) == ROLE_COMPUTED) {
         if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, lz, M);
-        const float q0 = M[0] * c216;
-        const float drho = __builtin_fmaf(__builtin_fmaf(-q0, 216.0f, M[0]), c216, q0);
-        const float r216 = 216.0f + M[0];
-        const float inv = recip(r216);
-        const float inv3 = recip(3.0f * r216);
         float v[kMom];
-        v[0] = drho;
-        v[1] = M[1] * inv; v[2] = M[2] * inv; v[3] = M[3] * inv;
-        v[4] = M[4] * inv3; v[5] = M[5] * inv3; v[6] = M[6] * inv3;
-        v[7] = M[7] * inv; v[8] = M[8] * inv; v[9] = M[9] * inv;
+        finish_moments(M, v);
 #pragma unroll
         for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(v[m], a.sc.s[m]);
       } else if ((role & ROLE_MASK) == ROLE_SOLID) {
@@ -739,6 +770,269 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
       zp2[k] = zp1[k];
       zp1[k] = zpp[k];
       z0[k] = zpz[k];
+    }
+  }
+}
+
+
+// ---- two substeps of the finest level in one sweep ----------------------------------
+// The finest level takes its two substeps of a parent step back to back (Alg. 1):
+// between them only its ghost nodes change, and their values for the second substep
+// are written before the first. One workgroup takes a 2 x 2 x 2 block tile through
+// both. Substep A runs on the tile plus a one-node ring (18 x 18 columns, planes -1 to
+// 16) from the input with a two-node halo (20 x 20 points, planes -2 to 17); substep B
+// runs on the tile from A's results, one plane behind. A's result never leaves the
+// chip: column p of A (the B source point p of the 18 x 18 plane) belongs to the lane
+// that feeds point p into B's source stage, so A's moments go from its z pass straight
+// into B. The input is read once (with a two-node halo) and the output written once
+// for two updates of every node.
+// Nodes of A's ring that A does not compute take what the second substep reads
+// otherwise: zero for solid nodes and missing blocks, the value already in the output
+// time level for ghost and inflow nodes (never written by either substep). Outflow
+// nodes (copied after every substep) and bounce-back nodes (whose correction needs the
+// node's own intermediate moments) are not handled: levels that have them run the two
+// substeps as two sweeps.
+struct Pair {
+  static constexpr int THREADS = 512;           // eight waves: one A point / column per lane
+  static constexpr int CXA = 20;                // A source plane: 20 x 20 points
+  static constexpr int PTSA = CXA * CXA;
+  static constexpr int CA = 18;                 // A columns: 18 x 18 (= B source points)
+  static constexpr int COLSA = CA * CA;
+  static constexpr int XA = CXA * CA;           // A x-pass outputs: 20 rows x 18 columns
+  static constexpr int HALFA = CXA * 4;         // x-pass input [kind][half][col 0..19][4]
+  static constexpr int KINDA = 2 * HALFA;
+  static constexpr int KINDB = CA * 10;         // y-pass input [kind][col 0..17][10]
+  static constexpr int ROWA = 3 * KINDB + 20;   // 560 floats, 16 banks off a multiple of 32
+  // Phases run on whole waves (a wave with no lane in a phase skips it): A source on
+  // waves 0..6, A x pass, A y/z pass and B source on 0..5, B x pass on 0..4, B y/z pass
+  // on 4..7.
+  static constexpr int BWAVE0 = 4;              // waves 4..7 run B's y and z passes
+  static_assert(3 * KINDA <= ROWA, "x-pass input must fit in a row");
+  static_assert(CXA * ROWA >= Tile<2>::CY * Tile<2>::ROW, "substep B's plane must fit");
+  static_assert(PTSA <= THREADS && XA <= THREADS && COLSA <= THREADS && Tile<2>::CY * 16 <= THREADS, "one round");
+};
+
+// role code of an A node: the role byte, or kPairZero for the all-zero slot
+constexpr uint32_t kPairZero = 0xffu;
+
+template <class S>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_stream_collide_pair(ScArgs<S> a) {
+  typedef Tile<2> G;  // substep B: the tile kernel's plane layout
+  typedef Pair P;
+  typedef typename S::type T;
+  __shared__ __align__(16) float lds[P::CXA * P::ROWA];
+  __shared__ int s_src[64];  // blocks (qx - 1 .. qx + 2) x (qy - 1 .. qy + 2) x (qz - 1 .. qz + 2)
+  __shared__ int s_mem[8];   // the tile's blocks (or -1), x fastest
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int4 c0 = a.coord[a.tiles[xcd_remap(blockIdx.x, a.ntiles)]];
+  const int qx = c0.x & ~1, qy = c0.y & ~1, qz = c0.z & ~1;
+  if (tid < 64) {
+    const int ix = tid & 3, iy = (tid >> 2) & 3, iz = tid >> 4;
+    int h[3] = {qx + ix - 1, qy + iy - 1, qz + iz - 1};
+    bool inside = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int nb = a.lg.nb[ax];
+      if (h[ax] < 0 || h[ax] >= nb) {
+        if (a.periodic[ax]) h[ax] = h[ax] < 0 ? h[ax] + nb : h[ax] - nb;
+        else inside = false;
+      }
+    }
+    const int ns = inside ? a.dir[a.lg.off + cell_lin(a.lg, h[0], h[1], h[2])] : -1;
+    s_src[tid] = ns >= 0 ? ns : a.zero_slot;
+    if (ix >= 1 && ix <= 2 && iy >= 1 && iy <= 2 && iz >= 1 && iz <= 2) {
+      const bool own = qx + ix - 1 < a.lg.nb[0] && qy + iy - 1 < a.lg.nb[1] && qz + iz - 1 < a.lg.nb[2];
+      s_mem[(ix - 1) + 2 * (iy - 1) + 4 * (iz - 1)] = own ? ns : -1;
+    }
+  }
+  __syncthreads();
+
+  // A source point (20 x 20) and A column (18 x 18, also B source point) of the lane
+  const bool shas = tid < P::PTSA;
+  const int spx = tid % P::CXA - 2, spy = tid / P::CXA - 2;
+  const bool chas = tid < P::COLSA;
+  const int cx = tid % P::CA - 1, cy = tid / P::CA - 1;
+  const int cnode = (cx & 7) + 8 * (cy & 7);
+  const int cblk = ((cx + 8) >> 3) + 4 * ((cy + 8) >> 3);
+  // B output column: waves 4..7, one block column of the tile each
+  const bool bout = wave >= P::BWAVE0;
+  const int bw = wave & 3;
+  const int ox = lane & 7, oy = lane >> 3;
+  const int tx = (bw & 1) * 8 + ox, ty = (bw >> 1) * 8 + oy;
+
+  T nxt[kMom];
+  if (shas) fetch_tile<S, 2>(a, s_src, spx, spy, -2, nxt);
+
+  float azp1[6], azp2[6], az0[6];  // A's z window (the lane's column)
+  float bzp1[6], bzp2[6], bz0[6];  // B's z window
+#pragma unroll
+  for (int k = 0; k < 6; ++k) azp1[k] = azp2[k] = az0[k] = bzp1[k] = bzp2[k] = bz0[k] = 0.0f;
+  uint32_t arole = kPairZero;  // role code of the column's node at A's output plane
+
+  for (int z = -2; z <= 17; ++z) {
+    const int zi = z - 1;  // A's output plane of this iteration (B's source plane)
+    const int zo = z - 2;  // B's output plane
+    // ---- role of B's output node (used at the end of the iteration)
+    const int bslot = bout && zo >= 0 ? s_mem[bw + (zo >= 8 ? 4 : 0)] : -1;
+    uint32_t brole = ROLE_GHOST;
+    if (bslot >= 0) brole = a.role[(size_t)bslot * kNodes + ox + 8 * oy + 64 * (zo & 7)];
+    // ---- A source: input plane z (+ two-node halo) -> x-populations
+    T cur[kMom];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) cur[m] = nxt[m];
+    if (shas && z < 17) fetch_tile<S, 2>(a, s_src, spx, spy, z + 1, nxt);
+    if (shas) {
+      float q[kMom];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(cur[m], a.sc.inv[m]);
+      float p[24];
+      source_pops(q, a.omega, p);
+      float v[8];
+      const int off = (spy + 2) * P::ROWA + (spx + 2) * 4;
+#pragma unroll
+      for (int kind = 0; kind < 3; ++kind) {
+#pragma unroll
+        for (int g = 0; g < 8; ++g) v[g] = p[3 * g + kind];
+        st8_h<P::HALFA>(lds, off + kind * P::KINDA, v);
+      }
+    }
+    // ---- value of A's output node if A does not compute it (ghost, inflow node)
+    T pv[kMom];
+    const uint32_t rk = arole & ROLE_MASK;
+    const bool pass = chas && zi >= -1 && arole != kPairZero && rk != ROLE_COMPUTED && rk != ROLE_SOLID;
+    if (pass) {
+      const int ns = s_src[cblk + 16 * ((zi + 8) >> 3)];
+      const T* src = a.out + (size_t)ns * kBlockStride + cnode + 64 * (zi & 7);
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) pv[m] = src[m * kNodes];
+    }
+    // ---- role code of the next output plane (plane z)
+    uint32_t nrole = kPairZero;
+    if (chas && z >= -1 && z <= 16) {
+      const int ns = s_src[cblk + 16 * ((z + 8) >> 3)];
+      if (ns != a.zero_slot) nrole = a.role[(size_t)ns * kNodes + cnode + 64 * (z & 7)];
+    }
+    __syncthreads();
+
+    // ---- A x pass: 20 rows x 18 columns on the first six waves, each row overwritten
+    // by its y-pass input once all its reads are done (lanes past the 360 outputs
+    // repeat output 0 and do not store)
+    {
+      const bool act = tid < P::XA;
+      const int t = act ? tid : 0;
+      const int row = t / P::CA, x = t % P::CA;
+      float yb[27];
+      if (wave < (P::XA + 63) / 64) {
+        x_pass_row<P::HALFA, P::KINDA>(lds, row * P::ROWA, x, yb);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) yb[k] = 0.0f;
+      }
+      __syncthreads();
+      if (act) {
+        st9(lds, row * P::ROWA + 0 * P::KINDB + x * 10, yb);
+        st9(lds, row * P::ROWA + 1 * P::KINDB + x * 10, yb + 9);
+        st9(lds, row * P::ROWA + 2 * P::KINDB + x * 10, yb + 18);
+      }
+    }
+    __syncthreads();
+
+    // ---- A y pass and z pass of the lane's column: output plane zi
+    float qa[kMom];
+    if (chas) {
+      float zpp[6], zpz[6], zpm[6];
+      y_pass_col<P::ROWA, P::KINDB>(lds, cy + 1, cx + 1, zpp, zpz, zpm);
+      if (zi >= -1) {
+        if (arole != kPairZero && rk == ROLE_COMPUTED) {
+          float M[10];
+          z_back(azp2, az0, zpm, M);
+          float v[kMom];
+          finish_moments(M, v);
+          // what the second substep would read back from memory
+#pragma unroll
+          for (int m = 0; m < kMom; ++m) qa[m] = Codec<S>::load(Codec<S>::store(v[m], a.sc.s[m]), a.sc.inv[m]);
+        } else if (pass) {
+#pragma unroll
+          for (int m = 0; m < kMom; ++m) qa[m] = Codec<S>::load(pv[m], a.sc.inv[m]);
+        } else {
+#pragma unroll
+          for (int m = 0; m < kMom; ++m) qa[m] = 0.0f;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        azp2[k] = azp1[k];
+        azp1[k] = zpp[k];
+        az0[k] = zpz[k];
+      }
+    }
+    arole = nrole;
+    __syncthreads();
+
+    if (zi >= -1) {
+      // ---- B source: A's plane zi -> x-populations (B layout)
+      if (chas) {
+        float p[24];
+        source_pops(qa, a.omega, p);
+        float v[8];
+        const int off = (cy + 1) * G::ROW + (cx + 1) * 4;
+#pragma unroll
+        for (int kind = 0; kind < 3; ++kind) {
+#pragma unroll
+          for (int g = 0; g < 8; ++g) v[g] = p[3 * g + kind];
+          st8_at<2>(lds, off + kind * G::KINDA, v);
+        }
+      }
+      __syncthreads();
+
+      // ---- B x pass: 18 rows x 16 columns on the first five waves
+      {
+        const bool act = tid < G::CY * G::NX;
+        const int t = act ? tid : 0;
+        const int row = t / G::NX, x = t % G::NX;
+        float yb[27];
+        if (wave < (G::CY * G::NX + 63) / 64) {
+          x_pass_tile<2>(lds, row, x, yb);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 27; ++k) yb[k] = 0.0f;
+        }
+        __syncthreads();
+        if (act) {
+          st9(lds, row * G::ROW + 0 * G::KINDB + x * 10, yb);
+          st9(lds, row * G::ROW + 1 * G::KINDB + x * 10, yb + 9);
+          st9(lds, row * G::ROW + 2 * G::KINDB + x * 10, yb + 18);
+        }
+      }
+      __syncthreads();
+
+      // ---- B y pass, z pass: output plane zo = zi - 1
+      if (bout) {
+        float zpp[6], zpz[6], zpm[6];
+        y_pass_col<G::ROW, G::KINDB>(lds, ty, tx, zpp, zpz, zpm);
+        if (bslot >= 0) {
+          float M[10];
+          z_back(bzp2, bz0, zpm, M);
+          T* dst = a.out + (size_t)bslot * kBlockStride + ox + 8 * oy + 64 * (zo & 7);
+          if ((brole & ROLE_MASK) == ROLE_COMPUTED) {
+            float v[kMom];
+            finish_moments(M, v);
+#pragma unroll
+            for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(v[m], a.sc.s[m]);
+          } else if ((brole & ROLE_MASK) == ROLE_SOLID) {
+#pragma unroll
+            for (int m = 0; m < kMom; ++m) dst[m * kNodes] = Codec<S>::store(0.0f, a.sc.s[m]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          bzp2[k] = bzp1[k];
+          bzp1[k] = zpp[k];
+          bz0[k] = zpz[k];
+        }
+      }
+      __syncthreads();
     }
   }
 }
@@ -770,7 +1064,38 @@ template <class S> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class S> hipError_t launch_pair_t(const ScLaunch& l, hipStream_t s) {
+  if (!l.tiles || l.ntiles <= 0) return l.tiles ? hipSuccess : hipErrorInvalidValue;
+  ScArgs<S> a;
+  a.in = static_cast<const typename S::type*>(l.in);
+  a.out = static_cast<typename S::type*>(l.out);
+  a.blocks = l.blocks;
+  a.nbr = l.nbr;
+  a.role = l.role;
+  a.nblocks = l.nblocks;
+  a.zero_slot = l.zero_slot;
+  a.omega = l.omega;
+  a.sc = l.sc;
+  a.tiles = l.tiles;
+  a.ntiles = l.ntiles;
+  a.dir = l.dir;
+  a.coord = l.coord;
+  a.lg = l.lg;
+  for (int k = 0; k < 3; ++k) a.periodic[k] = l.periodic[k];
+  hipLaunchKernelGGL(k_stream_collide_pair<S>, dim3(l.ntiles), dim3(Pair::THREADS), 0, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_stream_collide_pair(const ScLaunch& a, hipStream_t s) {
+  switch (a.storage) {
+    case 0: return launch_pair_t<StoreF32>(a, s);
+    case 1: return launch_pair_t<StoreBF16>(a, s);
+    case 2: return launch_pair_t<StoreF16>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s) {
   switch (a.storage) {

@@ -51,9 +51,10 @@ EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm
            "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
            "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
            "lbm_step_record", "lbm_adjoint_reverse",
-           "lbm_loss_ke_grad", "lbm_last_error"]
+           "lbm_loss_ke_grad", "lbm_set_option", "lbm_last_error"]
 _SIZE_QUERIES = ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_state_bytes", "lbm_adjoint_work_bytes", "lbm_last_error")
-PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh"]
+PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh", "sc_pair"]
+OPTIONS = {"tile_min_blocks": 0, "fuse_substeps": 1}
 
 _lib = None
 
@@ -96,6 +97,7 @@ def lib():
         L.lbm_step_record.argtypes = [vp, i32, vp, sz]
         L.lbm_adjoint_reverse.argtypes = [vp, vp, vp, vp, sz]
         L.lbm_loss_ke_grad.argtypes = [vp, i32, vp, vp, vp]
+        L.lbm_set_option.argtypes = [vp, i32, i64]
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_last_error.argtypes = [vp]
         for name in EXPORTS:
@@ -238,6 +240,12 @@ class Sim:
         out = (ctypes.c_double * 5)()
         self._check(lib().lbm_reduce_f64(self.h, level, lo_, hi_, out))
         return np.array(list(out))
+
+    def set_option(self, name, value):
+        """Execution options: "tile_min_blocks" (blocks a level needs for the tiled
+        stream-collide, default 16384) and "fuse_substeps" (1: the finest level's two
+        substeps per parent step in one sweep where allowed, 0: always two)."""
+        self._check(lib().lbm_set_option(self.h, OPTIONS[name], int(value)))
 
     def set_profiling(self, on=True):
         self._check(lib().lbm_set_profiling(self.h, 1 if on else 0))

@@ -80,6 +80,7 @@ def test_null_context_calls_fail_cleanly():
     assert L.lbm_destroy(None) == -1
     out = ctypes.c_int64()
     assert L.lbm_num_blocks(None, 0, ctypes.byref(out)) == -1
+    assert L.lbm_set_option(None, 0, 16384) == -1
 
 
 def test_null_context_state_and_adjoint_calls_fail_cleanly():

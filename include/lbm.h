@@ -48,10 +48,21 @@ typedef enum {
 typedef enum { LBM_F32 = 0, LBM_BF16 = 1, LBM_F16 = 2 } lbm_storage;
 
 /* Per-face boundary kind. INFLOW holds nodes on the face at the equilibrium
- * moments (1, inflow_u, inflow_u inflow_u); OUTFLOW copies the inward
- * neighbour after each step (zero gradient); WALL is halfway bounce-back half a
- * node outside the face. Faces of one axis are either both PERIODIC or neither. */
-typedef enum { LBM_PERIODIC = 0, LBM_INFLOW = 1, LBM_OUTFLOW = 2, LBM_WALL = 3 } lbm_bc;
+ * moments (1, u, u u) of the inflow velocity u (inflow_u, times the log profile
+ * below if selected); OUTFLOW copies the inward neighbour after each step (zero
+ * gradient); OUTFLOW_CONV is the convective outflow condition of Sec. 7 (dune
+ * migration): after each step every moment M of a face node takes one implicit
+ * upwind step of dM/dt + u_n dM/dn = 0, M <- (M + lam M_in) / (1 + lam), with M_in
+ * the new moments of the inward neighbour and lam = max(u_n, 0) its outward
+ * velocity; WALL is halfway bounce-back half a node outside the face. Faces of one
+ * axis are either both PERIODIC or neither. */
+typedef enum { LBM_PERIODIC = 0, LBM_INFLOW = 1, LBM_OUTFLOW = 2, LBM_WALL = 3, LBM_OUTFLOW_CONV = 4 } lbm_bc;
+
+/* Inflow velocity profile (Sec. 7, sand ripples): UNIFORM holds inflow_u on every
+ * inflow node; LOG holds inflow_u * ln(1 + inflow_beta (h - inflow_h0)) at height h
+ * (the node's coordinate along inflow_axis, in fine-level node units), zero where
+ * h <= inflow_h0. */
+typedef enum { LBM_INFLOW_UNIFORM = 0, LBM_INFLOW_LOG = 1 } lbm_inflow_profile;
 
 typedef struct {
   int32_t levels;          /* L in 1..5; level 0 is the finest */
@@ -66,6 +77,10 @@ typedef struct {
   void* pool;              /* device, >= lbm_pool_bytes(cfg): moment storage, two time levels */
   void* meta;              /* device, >= lbm_meta_bytes(cfg): hierarchy tables and scratch */
   void* stream;            /* hipStream_t the context launches on (NULL = default stream) */
+  int32_t inflow_profile;  /* lbm_inflow_profile */
+  int32_t inflow_axis;     /* LOG: axis of the height (0, 1, 2) */
+  float inflow_beta;       /* LOG: shear coefficient, >= 0, per fine node */
+  float inflow_h0;         /* LOG: height of the profile's zero, fine nodes */
 } lbm_config;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -25,8 +25,14 @@
 //   * Sec. 6.3: the block set after a grid update, written as the canonical
 //     hierarchy H(Phi); new nodes initialised by downward interpolation from
 //     coarser or upward transfer from finer nodes of the old hierarchy.
-// Bounce-back, periodic wrap, inflow and zero-gradient outflow are not in the
-// paper; they are the halfway bounce-back and equilibrium/copy conditions of
+//   * Sec. 7 (dune migration, sand ripples): the convective outflow condition
+//     (the moments of a boundary node obey dM/dt + u_n dM/dn = 0, u_n from the
+//     nearest inner node along the face normal), taken as the implicit upwind
+//     step M_b(t+1) = (M_b(t) + lam M_h(t+1)) / (1 + lam), lam = max(u_n, 0); and
+//     the logarithmic inflow profile u(h) = u0 ln(1 + beta (h - h0)) over the
+//     height h above h0 (zero at or below h0).
+// Bounce-back, periodic wrap, uniform inflow and zero-gradient outflow are not in
+// the paper; they are the halfway bounce-back and equilibrium/copy conditions of
 // the standard LBM literature.
 //
 // Everything is templated on the scalar type so that std::complex<double> can
@@ -56,7 +62,7 @@ constexpr int kMom = 10;             // rho, u(3), S(6)
 // node roles
 enum : uint8_t { R_INTERIOR = 0, R_GHOST = 1, R_IU = 2, R_SOLID = 3, R_INFLOW = 4, R_OUTFLOW = 5 };
 // boundary kinds per domain face
-enum : int { BC_PERIODIC = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_WALL = 3 };
+enum : int { BC_PERIODIC = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_WALL = 3, BC_OUTFLOW_CONV = 4 };
 // block state per level
 enum : uint8_t { ST_ABSENT = 0, ST_ACTIVE = 1, ST_DELETED = 2 };
 
@@ -206,10 +212,18 @@ struct oc_config {
   int32_t rescale;     // 0: Chapman-Enskog S^neq factors; 1: factors as printed
   int32_t storage;     // 0: exact; 1: bf16, 2: f16 storage emulation (rho-1 shift, scales)
   double scale[10];    // per-moment power-of-two storage scales
+  int32_t inflow_profile;  // 0: uniform uin; 1: uin * ln(1 + beta (h - h0)) over the height h
+  int32_t inflow_axis;     // axis of the height h (fine units)
+  double inflow_beta;
+  double inflow_h0;
 };
 }
 
 namespace {
+
+// real part (branch decisions of the complex-step instance follow the real run)
+inline double re(double v) { return v; }
+inline double re(const std::complex<double>& v) { return v.real(); }
 
 template <class T> Mom<T> quantize(const Mom<T>& q, const oc_config&) { return q; }
 template <> Mom<double> quantize(const Mom<double>& q, const oc_config& c) {
@@ -319,11 +333,18 @@ template <class T> struct Sim {
 
   // --- roles (inflow/outflow on domain faces; ghost = outer shell of a level's
   //     region; IU = nodes next to blocks covered by the finer level) ---
+  static bool is_outflow(int kind) { return kind == BC_OUTFLOW || kind == BC_OUTFLOW_CONV; }
+  // outward normal of the first outflow face (in axis order) the node lies on;
+  // returns that face's kind, or 0 if none
   int face_normal_outflow(int l, const int g[3], int normal[3]) const {
     for (int a = 0; a < 3; ++a) {
       if (periodic(a)) continue;
-      if (g[a] == 0 && cfg.bc[2 * a] == BC_OUTFLOW) { normal[0] = normal[1] = normal[2] = 0; normal[a] = -1; return 1; }
-      if (g[a] == nl(l, a) - 1 && cfg.bc[2 * a + 1] == BC_OUTFLOW) { normal[0] = normal[1] = normal[2] = 0; normal[a] = 1; return 1; }
+      if (g[a] == 0 && is_outflow(cfg.bc[2 * a])) {
+        normal[0] = normal[1] = normal[2] = 0; normal[a] = -1; return cfg.bc[2 * a];
+      }
+      if (g[a] == nl(l, a) - 1 && is_outflow(cfg.bc[2 * a + 1])) {
+        normal[0] = normal[1] = normal[2] = 0; normal[a] = 1; return cfg.bc[2 * a + 1];
+      }
     }
     return 0;
   }
@@ -334,7 +355,7 @@ template <class T> struct Sim {
       if (g[a] == 0) kind = cfg.bc[2 * a];
       else if (g[a] == nl(l, a) - 1) kind = cfg.bc[2 * a + 1];
       if (kind == BC_INFLOW) return R_INFLOW;
-      if (kind == BC_OUTFLOW) return R_OUTFLOW;
+      if (is_outflow(kind)) return R_OUTFLOW;
     }
     return 255;
   }
@@ -458,12 +479,26 @@ template <class T> struct Sim {
     q.v[0] = T(1);
     return q;
   }
-  Mom<T> inflow_state() const {
+  // inflow node g of level l: rho = 1, u = uin (times the log profile at the node's
+  // height), S = u u
+  Mom<T> inflow_state(int l, const int g[3]) const {
+    double f = 1.0;
+    if (cfg.inflow_profile == 1) {
+      const double h = double(g[cfg.inflow_axis]) * double(1 << l);  // fine units
+      f = h > cfg.inflow_h0 ? std::log(1.0 + cfg.inflow_beta * (h - cfg.inflow_h0)) : 0.0;
+    }
+    double u[3];
+    for (int a = 0; a < 3; ++a) u[a] = cfg.uin[a] * f;
     Mom<T> q = rest_state();
-    for (int a = 0; a < 3; ++a) q.v[1 + a] = T(cfg.uin[a]);
+    for (int a = 0; a < 3; ++a) q.v[1 + a] = T(u[a]);
     for (int a = 0; a < 3; ++a)
-      for (int b = a; b < 3; ++b) q.S(a, b) = T(cfg.uin[a] * cfg.uin[b]);
+      for (int b = a; b < 3; ++b) q.S(a, b) = T(u[a] * u[b]);
     return q;
+  }
+  static void node_coords(const int b[3], int n, int g[3]) {
+    g[0] = b[0] * kBlock + n % kBlock;
+    g[1] = b[1] * kBlock + (n / kBlock) % kBlock;
+    g[2] = b[2] * kBlock + n / (kBlock * kBlock);
   }
 
   void build(const std::vector<std::map<uint64_t, uint8_t>>& states) {
@@ -673,19 +708,35 @@ template <class T> struct Sim {
       }
     }
     if (!local_err.empty()) throw std::runtime_error(local_err);
-    // zero-gradient outflow: copy the new value of the inward neighbour when
-    // that neighbour is a computed node; otherwise keep the node's value.
+    // outflow nodes, from the new value of the inward neighbour when that
+    // neighbour is a computed node (otherwise the node keeps its value):
+    // zero gradient copies it; the convective condition takes one implicit upwind
+    // step of dM/dt + u_n dM/dn = 0 with u_n the neighbour's new outward velocity
+    // (clamped at zero: no transport into the domain through an outlet).
     for (size_t k = 0; k < blocks.size(); ++k) {
       Blk<T>* B = blocks[k];
       for (int n = 0; n < kNodes; ++n) {
         if (B->role[n] != R_OUTFLOW) continue;
-        int g[3] = {B->b[0] * kBlock + n % kBlock, B->b[1] * kBlock + (n / kBlock) % kBlock, B->b[2] * kBlock + n / (kBlock * kBlock)};
+        int g[3];
+        node_coords(B->b, n, g);
         int nrm[3];
-        face_normal_outflow(l, g, nrm);
+        const int kind = face_normal_outflow(l, g, nrm);
         int h[3] = {g[0] - nrm[0], g[1] - nrm[1], g[2] - nrm[2]};
         int node;
         Blk<T>* S = locate(l, h, node);
-        if (S && S->role[node] == R_INTERIOR) next[k][n] = next[S->idx][node];
+        if (!(S && S->role[node] == R_INTERIOR)) continue;
+        const Mom<T>& qh = next[S->idx][node];
+        if (kind == BC_OUTFLOW) {
+          next[k][n] = qh;
+          continue;
+        }
+        T un = T(0.0);
+        for (int a = 0; a < 3; ++a) un = un + double(nrm[a]) * qh.v[1 + a];
+        const T lam = re(un) > 0.0 ? un : T(0.0);
+        const Mom<T>& qb = B->cur[n];
+        Mom<T> q;
+        for (int m = 0; m < kMom; ++m) q.v[m] = (qb.v[m] + lam * qh.v[m]) / (1.0 + lam);
+        next[k][n] = stored(q);
       }
     }
     for (size_t k = 0; k < blocks.size(); ++k) {
@@ -784,8 +835,9 @@ template <class T> struct Sim {
           bool fresh = (O == nullptr) || (!owned(O->role[n]) && owned(r));
           if (!fresh) { B->cur[n] = O->cur[n]; continue; }
           if (r == R_SOLID) { B->cur[n] = rest_state(); continue; }
-          if (r == R_INFLOW) { B->cur[n] = stored(inflow_state()); continue; }
-          int g[3] = {B->b[0] * kBlock + n % kBlock, B->b[1] * kBlock + (n / kBlock) % kBlock, B->b[2] * kBlock + n / (kBlock * kBlock)};
+          int g[3];
+          node_coords(B->b, n, g);
+          if (r == R_INFLOW) { B->cur[n] = stored(inflow_state(l, g)); continue; }
           try {
             B->cur[n] = stored(mom_of(sample_old(l, g)));
           } catch (const std::exception& e) {
@@ -813,7 +865,10 @@ void validate(const oc_config& c) {
     if (p0 != p1) throw std::runtime_error("periodic faces must come in pairs");
   }
   for (int f = 0; f < 6; ++f)
-    if (c.bc[f] < 0 || c.bc[f] > 3) throw std::runtime_error("bad boundary kind");
+    if (c.bc[f] < 0 || c.bc[f] > 4) throw std::runtime_error("bad boundary kind");
+  if (c.inflow_profile < 0 || c.inflow_profile > 1) throw std::runtime_error("bad inflow profile");
+  if (c.inflow_profile == 1 && (c.inflow_axis < 0 || c.inflow_axis > 2 || !(c.inflow_beta >= 0.0)))
+    throw std::runtime_error("bad log inflow profile");
   if (!(c.tau0 > 0.5)) throw std::runtime_error("tau0 must exceed 1/2");
   if (c.storage < 0 || c.storage > 2) throw std::runtime_error("bad storage emulation");
   if (c.storage != 0)
@@ -835,7 +890,11 @@ template <class T> Sim<T>* create(const oc_config* cfg, const uint8_t* solid, co
   for (int l = 0; l < s->L; ++l)
     for (auto& kv : s->lv[l])
       for (int n = 0; n < kNodes; ++n) {
-        if (kv.second.role[n] == R_INFLOW) kv.second.cur[n] = s->stored(s->inflow_state());
+        if (kv.second.role[n] == R_INFLOW) {
+          int g[3];
+          s->node_coords(kv.second.b, n, g);
+          kv.second.cur[n] = s->stored(s->inflow_state(l, g));
+        }
         kv.second.prev[n] = kv.second.cur[n];
       }
   return s;
@@ -883,7 +942,11 @@ int oc_set_block_moments(void* h, int level, const int64_t* keys, const double* 
       for (int m = 0; m < kMom; ++m) q.v[m] = in[(k * kMom + m) * kNodes + n];
       q.v[0] += 1.0;
       if (B.role[n] == R_SOLID) q = s->rest_state();
-      if (B.role[n] == R_INFLOW) q = s->inflow_state();
+      if (B.role[n] == R_INFLOW) {
+        int g[3];
+        s->node_coords(B.b, n, g);
+        q = s->inflow_state(level, g);
+      }
       q = s->stored(q);
       B.cur[n] = q;
       B.prev[n] = q;
@@ -952,7 +1015,11 @@ int occ_set_block_moments(void* h, int level, const int64_t* keys, const double*
       }
       q.v[0] += 1.0;
       if (B.role[n] == R_SOLID) q = s->rest_state();
-      if (B.role[n] == R_INFLOW) q = s->inflow_state();
+      if (B.role[n] == R_INFLOW) {
+        int g[3];
+        s->node_coords(B.b, n, g);
+        q = s->inflow_state(level, g);
+      }
       B.cur[n] = q;
       B.prev[n] = q;
     }

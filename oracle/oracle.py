@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_oracle.so")
 
-PERIODIC, INFLOW, OUTFLOW, WALL = 0, 1, 2, 3
+PERIODIC, INFLOW, OUTFLOW, WALL, OUTFLOW_CONV = 0, 1, 2, 3, 4
 R_INTERIOR, R_GHOST, R_IU, R_SOLID, R_INFLOW, R_OUTFLOW = range(6)
 
 
@@ -30,7 +30,24 @@ class _Cfg(ctypes.Structure):
         ("rescale", ctypes.c_int32),
         ("storage", ctypes.c_int32),
         ("scale", ctypes.c_double * 10),
+        ("inflow_profile", ctypes.c_int32),
+        ("inflow_axis", ctypes.c_int32),
+        ("inflow_beta", ctypes.c_double),
+        ("inflow_h0", ctypes.c_double),
     ]
+
+
+def _set_log_inflow(c, log_inflow):
+    """log_inflow = (axis, beta, h0): inflow velocity uin * ln(1 + beta (h - h0)) at
+    height h (fine units) along axis, zero at or below h0; None: uniform uin."""
+    if log_inflow is None:
+        c.inflow_profile = 0
+        return
+    axis, beta, h0 = log_inflow
+    c.inflow_profile = 1
+    c.inflow_axis = int(axis)
+    c.inflow_beta = float(beta)
+    c.inflow_h0 = float(h0)
 
 
 _lib = None
@@ -90,8 +107,9 @@ class OracleSim:
     """One simulation held by the oracle."""
 
     def __init__(self, levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), force=(0.0, 0.0, 0.0),
-                 solid=None, particles=None, rescale="ce", storage="exact", scale=None):
+                 solid=None, particles=None, rescale="ce", storage="exact", scale=None, log_inflow=None):
         c = _Cfg()
+        _set_log_inflow(c, log_inflow)
         c.levels = levels
         for a in range(3):
             c.n[a] = int(n[a])
@@ -184,9 +202,12 @@ class OracleSimComplex:
     """The same oracle on std::complex<double>, for complex-step derivatives: set
     moments with an imaginary part h*d, step, read the imaginary part of the loss."""
 
-    def __init__(self, levels, n, bc, tau0, particles=None, solid=None, uin=(0.0, 0.0, 0.0), rescale="ce"):
-        self._real = OracleSim(levels, n, bc, tau0, uin=uin, solid=solid, particles=particles, rescale=rescale)
+    def __init__(self, levels, n, bc, tau0, particles=None, solid=None, uin=(0.0, 0.0, 0.0), rescale="ce",
+                 log_inflow=None):
+        self._real = OracleSim(levels, n, bc, tau0, uin=uin, solid=solid, particles=particles, rescale=rescale,
+                               log_inflow=log_inflow)
         c = _Cfg()
+        _set_log_inflow(c, log_inflow)
         c.levels = levels
         for a in range(3):
             c.n[a] = int(n[a])

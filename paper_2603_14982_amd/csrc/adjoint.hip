@@ -650,18 +650,30 @@ __global__ __launch_bounds__(256) void k_up_adj(AdjTransferLaunch a) {
   }
 }
 
-// ---- zero-gradient outflow copy, transposed -----------------------------------
-// Phase 1: every outflow node hands its adjoint either to its inward computed
-// neighbour (through LDS) or to its own old value. Phase 2: every computed node
-// collects from the outflow nodes that copied it (at most one per face).
-__device__ inline int outflow_src(const Geom& G, const LevelGeom& lg, const int4 bc, const uint8_t* role, int node) {
+// ---- outflow conditions, transposed ----------------------------------------------
+// Phase 1: every outflow node hands its adjoint to its inward computed neighbour
+// (through LDS) and to its own old value: all of it to one of them for the zero-
+// gradient copy; for the convective step y = (x + lam h) / (1 + lam), lam =
+// max(s h_n, 0) (x the node's old value, h the neighbour's new value, s the outward
+// sign), 1 / (1 + lam) of it to x and lam / (1 + lam) to h, plus the derivative
+// through lam, sum_m ybar_m (h_m - x_m) / (1 + lam)^2 times s, to h_n where lam > 0.
+// Phase 2: every computed node collects from the outflow nodes that read it (at most
+// one per face).
+__device__ inline int outflow_src(const Geom& G, const LevelGeom& lg, const int4 bc, const uint8_t* role, int node,
+                                  int& kind, int& sgn, int& axn) {
   const int g[3] = {bc.x * kEdge + (node & 7), bc.y * kEdge + ((node >> 3) & 7), bc.z * kEdge + (node >> 6)};
   int step = 0;
+  kind = BC_OUTFLOW;
+  sgn = 0;
+  axn = 0;
   for (int ax = 0; ax < 3 && step == 0; ++ax) {
     if (G.periodic[ax]) continue;
     const int stride = ax == 0 ? 1 : (ax == 1 ? 8 : 64);
-    if (g[ax] == 0 && G.bc[2 * ax] == BC_OUTFLOW) step = stride;
-    else if (g[ax] == lg.nn[ax] - 1 && G.bc[2 * ax + 1] == BC_OUTFLOW) step = -stride;
+    if (g[ax] == 0 && is_outflow_bc(G.bc[2 * ax])) {
+      step = stride; kind = G.bc[2 * ax]; sgn = -1; axn = ax;
+    } else if (g[ax] == lg.nn[ax] - 1 && is_outflow_bc(G.bc[2 * ax + 1])) {
+      step = -stride; kind = G.bc[2 * ax + 1]; sgn = 1; axn = ax;
+    }
   }
   if (step == 0) return -1;
   const int src = node + step;
@@ -678,16 +690,44 @@ __global__ __launch_bounds__(256) void k_outflow_adj(AdjTransferLaunch a) {
   const uint8_t* role = a.role + (size_t)slot * kNodes;
   float* ly = a.lam_coarse_a + (size_t)slot * kBlockStride;  // adjoint of the new time level
   float* lx = a.lam_fine + (size_t)slot * kBlockStride;      // adjoint of the old time level
+  typedef typename S::type T;
+  const T* newb = static_cast<const T*>(a.undo_dst) + (size_t)slot * kBlockStride;  // state after the step
+  const T* oldb = static_cast<const T*>(a.src_a) + (size_t)slot * kBlockStride;
   for (int node = threadIdx.x; node < kNodes; node += 256) {
     int dst = -1;
     if ((role[node] & ROLE_MASK) == ROLE_OUTFLOW) {
-      dst = outflow_src(a.G, lg, bc, role, node);
+      int kind, sgn, axn;
+      dst = outflow_src(a.G, lg, bc, role, node, kind, sgn, axn);
+      float v[kMom];
 #pragma unroll
       for (int m = 0; m < kMom; ++m) {
-        const float v = ly[m * kNodes + node];
+        v[m] = ly[m * kNodes + node];
         ly[m * kNodes + node] = 0.0f;
-        sv[m][node] = v;
-        if (dst < 0) lx[m * kNodes + node] += v;
+      }
+      if (dst < 0) {
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) lx[m * kNodes + node] += v[m];
+      } else if (kind == BC_OUTFLOW) {
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) sv[m][node] = v[m];
+      } else {
+        float qh[kMom], qb[kMom];
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) {
+          qh[m] = Codec<S>::load(newb[m * kNodes + dst], a.sc.inv[m]);
+          qb[m] = Codec<S>::load(oldb[m * kNodes + node], a.sc.inv[m]);
+        }
+        const float un = sgn * qh[1 + axn];
+        const float lam = un > 0.0f ? un : 0.0f;
+        const float w = 1.0f / (1.0f + lam);
+        float dl = 0.0f;
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) {
+          lx[m * kNodes + node] += w * v[m];
+          sv[m][node] = lam * w * v[m];
+          dl += v[m] * (qh[m] - qb[m]);
+        }
+        if (un > 0.0f) sv[1 + axn][node] += sgn * dl * w * w;
       }
       undo_node<S>(a.undo_dst, a.undo_tape, slot, blockIdx.x, node);
     }

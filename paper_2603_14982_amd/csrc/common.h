@@ -19,7 +19,8 @@ constexpr uint8_t ROLE_BB = 0x80;
 // block state per level
 enum : uint8_t { ST_ABSENT = 0, ST_ACTIVE = 1, ST_DELETED = 2 };
 // boundary kinds
-enum : int { BC_PERIODIC = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_WALL = 3 };
+enum : int { BC_PERIODIC = 0, BC_INFLOW = 1, BC_OUTFLOW = 2, BC_WALL = 3, BC_OUTFLOW_CONV = 4 };
+__host__ __device__ inline bool is_outflow_bc(int kind) { return kind == BC_OUTFLOW || kind == BC_OUTFLOW_CONV; }
 // neighbour-table sentinels
 constexpr int32_t NBR_NONE = -1;
 constexpr int32_t NBR_WALL = -2;
@@ -44,7 +45,23 @@ struct Geom {
   int periodic[3];
   int N[3];
   LevelGeom lv[kMaxLevels];
+  float inflow[3];       // inflow velocity (times the profile factor)
+  int inflow_profile;    // 0 uniform, 1 logarithmic in the height along inflow_axis
+  int inflow_axis;
+  float inflow_beta, inflow_h0;
 };
+
+// inflow velocity of level-l node g: inflow (times ln(1 + beta (h - h0)) for the
+// logarithmic profile, h the node's height in fine-level nodes; zero at or below h0)
+__device__ inline void inflow_velocity(const Geom& G, int l, const int g[3], float u[3]) {
+  float f = 1.0f;
+  if (G.inflow_profile == 1) {
+    const float h = (float)(g[G.inflow_axis] << l);
+    f = h > G.inflow_h0 ? logf(1.0f + G.inflow_beta * (h - G.inflow_h0)) : 0.0f;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) u[a] = G.inflow[a] * f;
+}
 
 __host__ __device__ inline int64_t cell_lin(const LevelGeom& g, int bx, int by, int bz) {
   return bx + (int64_t)g.nb[0] * (by + (int64_t)g.nb[1] * bz);

@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
         if (gc[a] == 0) kind = G.bc[2 * a];
         else if (gc[a] == g.nn[a] - 1) kind = G.bc[2 * a + 1];
         if (kind == BC_INFLOW) role = ROLE_INFLOW;
-        else if (kind == BC_OUTFLOW) role = ROLE_OUTFLOW;
+        else if (is_outflow_bc(kind)) role = ROLE_OUTFLOW;
       }
     }
     if (role == 255) {
@@ -492,7 +492,8 @@ __global__ __launch_bounds__(256) void k_init(InitLaunch a) {
 #pragma unroll
     for (int m = 0; m < kMom; ++m) q[m] = 0.0f;
     if (rn == ROLE_INFLOW) {
-      q[1] = a.inflow[0]; q[2] = a.inflow[1]; q[3] = a.inflow[2];
+      const int gn[3] = {b[0] * kEdge + (node & 7), b[1] * kEdge + ((node >> 3) & 7), b[2] * kEdge + (node >> 6)};
+      inflow_velocity(a.G, a.level, gn, q + 1);
       q[4] = q[1] * q[1]; q[5] = q[2] * q[2]; q[6] = q[3] * q[3];
       q[7] = q[1] * q[2]; q[8] = q[1] * q[3]; q[9] = q[2] * q[3];
     } else if (rn != ROLE_SOLID && !a.create) {

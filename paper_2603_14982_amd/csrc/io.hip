@@ -56,8 +56,9 @@ __global__ __launch_bounds__(256) void k_set(IoLaunch a, const int64_t* keys, co
 #pragma unroll
       for (int m = 0; m < kMom; ++m) q[m] = 0.0f;
     } else if (r == ROLE_INFLOW) {
+      const int gn[3] = {bx * kEdge + (node & 7), by * kEdge + ((node >> 3) & 7), bz * kEdge + (node >> 6)};
       q[0] = 0.0f;
-      q[1] = a.inflow[0]; q[2] = a.inflow[1]; q[3] = a.inflow[2];
+      inflow_velocity(a.G, a.level, gn, q + 1);
       q[4] = q[1] * q[1]; q[5] = q[2] * q[2]; q[6] = q[3] * q[3];
       q[7] = q[1] * q[2]; q[8] = q[1] * q[3]; q[9] = q[2] * q[3];
     }

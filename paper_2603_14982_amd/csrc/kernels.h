@@ -65,6 +65,7 @@ struct OutflowLaunch {
   const int4* coord;
   const void* old_buf;
   void* new_buf;
+  Scales sc;
   int storage;
   void* tape = nullptr;      // adjoint replay: old values of the written nodes, [list index][10][512]
 };
@@ -146,7 +147,6 @@ struct InitLaunch {
   void* dst_other;           // other time level of this level
   float a_up[kMaxLevels];
   float a_down[kMaxLevels];
-  float inflow[3];
   int create;                // 1: no old hierarchy, start at rest
   Scales sc;
   int storage;
@@ -165,7 +165,6 @@ struct IoLaunch {
   void* other;               // other time level (set only)
   Scales sc;
   int storage;
-  float inflow[3];
 };
 hipError_t launch_get(const IoLaunch& a, int64_t* keys, float* out, hipStream_t s);
 hipError_t launch_get_roles(const IoLaunch& a, uint8_t* out, hipStream_t s);

@@ -44,7 +44,7 @@ bool make_geom(const lbm_config* c, Geom& G, std::string& err) {
     G.N[a] = c->fine_extent[a];
   }
   for (int f = 0; f < 6; ++f) {
-    if (c->bc[f] < 0 || c->bc[f] > 3) { err = "unknown boundary kind"; return false; }
+    if (c->bc[f] < 0 || c->bc[f] > LBM_OUTFLOW_CONV) { err = "unknown boundary kind"; return false; }
     G.bc[f] = c->bc[f];
   }
   for (int a = 0; a < 3; ++a) {
@@ -78,6 +78,21 @@ bool make_geom(const lbm_config* c, Geom& G, std::string& err) {
       if (!(c->scale[m] > 0.0f) || !std::isfinite(c->scale[m])) { err = "storage scales must be positive"; return false; }
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(c->inflow_u[a])) { err = "inflow_u must be finite"; return false; }
+  if (c->inflow_profile != LBM_INFLOW_UNIFORM && c->inflow_profile != LBM_INFLOW_LOG) {
+    err = "unknown inflow profile";
+    return false;
+  }
+  if (c->inflow_profile == LBM_INFLOW_LOG &&
+      (c->inflow_axis < 0 || c->inflow_axis > 2 || !(c->inflow_beta >= 0.0f) || !std::isfinite(c->inflow_beta) ||
+       !std::isfinite(c->inflow_h0))) {
+    err = "log inflow profile: axis 0..2, finite beta >= 0 and h0";
+    return false;
+  }
+  for (int a = 0; a < 3; ++a) G.inflow[a] = c->inflow_u[a];
+  G.inflow_profile = c->inflow_profile;
+  G.inflow_axis = c->inflow_profile == LBM_INFLOW_LOG ? c->inflow_axis : 0;
+  G.inflow_beta = c->inflow_beta;
+  G.inflow_h0 = c->inflow_h0;
   return true;
 }
 
@@ -258,7 +273,6 @@ IoLaunch io_of(const lbm_ctx* c, int level) {
   a.other = c->other(level);
   a.sc = c->sc;
   a.storage = c->cfg.storage;
-  for (int k = 0; k < 3; ++k) a.inflow[k] = c->cfg.inflow_u[k];
   return a;
 }
 
@@ -387,7 +401,6 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
       a.a_up[k] = (float)c->a_up[k];
       a.a_down[k] = (float)c->a_down[k];
     }
-    for (int k = 0; k < 3; ++k) a.inflow[k] = c->cfg.inflow_u[k];
     a.create = create ? 1 : 0;
     a.sc = c->sc;
     a.storage = c->cfg.storage;
@@ -497,6 +510,7 @@ lbm_status sc_level(lbm_ctx* c, int l) {
     o.coord = c->m<int4>(c->lay.coord);
     o.old_buf = c->cur(l);
     o.new_buf = c->other(l);
+    o.sc = c->sc;
     o.storage = c->cfg.storage;
     o.tape = otape;
     const int ko = c->tic(LBM_PROF_OUTFLOW);
@@ -672,6 +686,7 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
       t.lam_coarse_a = b.lam[1 - p];
       t.lam_fine = b.lam[p];
       t.undo_dst = c->buf(l, 1 - p);
+      t.src_a = c->buf(l, p);  // the old time level (convective outflow)
       t.undo_tape = c->tape + op.off2;
       HIPCHK(c, launch_outflow_adj(t, s));
     }

@@ -190,18 +190,38 @@ __global__ __launch_bounds__(256) void k_outflow(OutflowLaunch a) {
     if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_OUTFLOW) continue;
     const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
     const int g[3] = {bc.x * kEdge + lc[0], bc.y * kEdge + lc[1], bc.z * kEdge + lc[2]};
-    int step = 0;
+    // the first outflow face of the node (axis order): inward step, kind, outward sign
+    int step = 0, kind = BC_OUTFLOW, sgn = 0, axn = 0;
     for (int ax = 0; ax < 3 && step == 0; ++ax) {
       if (a.G.periodic[ax]) continue;
       const int stride = ax == 0 ? 1 : (ax == 1 ? 8 : 64);
-      if (g[ax] == 0 && a.G.bc[2 * ax] == BC_OUTFLOW) step = stride;              // inward is +axis
-      else if (g[ax] == lg.nn[ax] - 1 && a.G.bc[2 * ax + 1] == BC_OUTFLOW) step = -stride;
+      if (g[ax] == 0 && is_outflow_bc(a.G.bc[2 * ax])) {
+        step = stride; kind = a.G.bc[2 * ax]; sgn = -1; axn = ax;  // inward is +axis
+      } else if (g[ax] == lg.nn[ax] - 1 && is_outflow_bc(a.G.bc[2 * ax + 1])) {
+        step = -stride; kind = a.G.bc[2 * ax + 1]; sgn = 1; axn = ax;
+      }
     }
     const int src = node + step;
     const bool computed = step != 0 && (a.role[(size_t)slot * kNodes + src] & ROLE_MASK) == ROLE_COMPUTED;
     if (a.tape) keep_old<S>(a.new_buf, a.tape, slot, blockIdx.x, node);
+    if (!computed || kind == BC_OUTFLOW) {
+      // zero gradient: the inward neighbour's new value (or the node's own)
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) newb[m * kNodes + node] = computed ? newb[m * kNodes + src] : oldb[m * kNodes + node];
+      for (int m = 0; m < kMom; ++m) newb[m * kNodes + node] = computed ? newb[m * kNodes + src] : oldb[m * kNodes + node];
+    } else {
+      // convective (Sec. 7): one implicit upwind step of dM/dt + u_n dM/dn = 0
+      float qh[kMom], qb[kMom];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) {
+        qh[m] = Codec<S>::load(newb[m * kNodes + src], a.sc.inv[m]);
+        qb[m] = Codec<S>::load(oldb[m * kNodes + node], a.sc.inv[m]);
+      }
+      const float un = sgn * qh[1 + axn];
+      const float lam = un > 0.0f ? un : 0.0f;
+#pragma unroll
+      for (int m = 0; m < kMom; ++m)
+        newb[m * kNodes + node] = Codec<S>::store((qb[m] + lam * qh[m]) / (1.0f + lam), a.sc.s[m]);
+    }
   }
 }
 

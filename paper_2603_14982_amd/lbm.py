@@ -43,6 +43,10 @@ class LBMConfig(ctypes.Structure):
         ("pool", ctypes.c_void_p),
         ("meta", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+        ("inflow_profile", ctypes.c_int32),
+        ("inflow_axis", ctypes.c_int32),
+        ("inflow_beta", ctypes.c_float),
+        ("inflow_h0", ctypes.c_float),
     ]
 
 
@@ -108,8 +112,15 @@ def lib():
 
 
 def make_config(levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), storage="f32", scale=None, rescale="ce",
-                max_blocks=1):
+                max_blocks=1, log_inflow=None):
+    """log_inflow = (axis, beta, h0): inflow velocity uin * ln(1 + beta (h - h0)) at
+    height h (fine nodes) along axis, zero at or below h0; None: uniform uin."""
     c = LBMConfig()
+    if log_inflow is not None:
+        c.inflow_profile = 1
+        c.inflow_axis = int(log_inflow[0])
+        c.inflow_beta = float(log_inflow[1])
+        c.inflow_h0 = float(log_inflow[2])
     c.levels = int(levels)
     for a in range(3):
         c.fine_extent[a] = int(n[a])
@@ -134,7 +145,7 @@ class Sim:
     """One block-adaptive simulation on a GPU; buffers are torch tensors."""
 
     def __init__(self, levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), storage="f32", scale=None, rescale="ce",
-                 max_blocks=None, solid=None, particles=None, device="cuda"):
+                 max_blocks=None, solid=None, particles=None, device="cuda", log_inflow=None):
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -143,7 +154,7 @@ class Sim:
         if max_blocks is None:
             max_blocks = sum((n[0] >> l) // 8 * ((n[1] >> l) // 8) * ((n[2] >> l) // 8) for l in range(levels))
             max_blocks = min(max_blocks, 1 << 16)
-        self.cfg = make_config(levels, n, bc, tau0, uin, storage, scale, rescale, max_blocks)
+        self.cfg = make_config(levels, n, bc, tau0, uin, storage, scale, rescale, max_blocks, log_inflow)
         L = lib()
         pool_bytes = L.lbm_pool_bytes(ctypes.byref(self.cfg))
         meta_bytes = L.lbm_meta_bytes(ctypes.byref(self.cfg))

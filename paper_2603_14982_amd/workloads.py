@@ -13,7 +13,7 @@ Addressing conventions (shared by specification, not by code):
 """
 import numpy as np
 
-PERIODIC, INFLOW, OUTFLOW, WALL = 0, 1, 2, 3
+PERIODIC, INFLOW, OUTFLOW, WALL, OUTFLOW_CONV = 0, 1, 2, 3, 4
 
 
 def morton_encode(bx, by, bz):

@@ -79,3 +79,26 @@ def from_moments(q):
 def to_moments(f):
     rho, u, S = moments(f)
     return np.stack([rho - 1.0, u[0], u[1], u[2], S[0, 0], S[1, 1], S[2, 2], S[0, 1], S[0, 2], S[1, 2]])
+
+
+def step_channel(f, omega, outflow="zero_gradient"):
+    """One step with a held inflow plane at x = 0 and an outflow plane at x = X - 1
+    (y, z periodic); f is [27, X, Y, Z]. Interior planes pull from their neighbours;
+    the inflow plane keeps its populations; the outflow plane takes, per node, the
+    new moments of its inner neighbour (zero gradient) or one implicit upwind step of
+    dM/dt + u_n dM/dn = 0 with u_n = max(u_x of that neighbour, 0) (convective)."""
+    rho, u, S = moments(f)
+    fp = hermite(*collide(rho, u, S, omega))
+    out = np.empty_like(fp)
+    for i in range(27):
+        out[i] = np.roll(fp[i], shift=tuple(int(v) for v in C[i]), axis=(0, 1, 2))
+    out[:, 0] = f[:, 0]
+    q_old = to_moments(f[:, -1:])[:, 0]
+    q_in = to_moments(out[:, -2:-1])[:, 0]
+    if outflow == "zero_gradient":
+        q_new = q_in
+    else:
+        lam = np.maximum(q_in[1], 0.0)
+        q_new = (q_old + lam[None] * q_in) / (1.0 + lam[None])
+    out[:, -1] = from_moments(q_new[:, None])[:, 0]
+    return out

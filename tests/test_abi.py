@@ -53,6 +53,9 @@ def test_buffer_sizes():
     (dict(max_blocks=0), "max_blocks"),
     (dict(storage="bf16", scale=[0.0] * 10), "scales"),
     (dict(n=(1 << 20, 1 << 20, 1 << 20)), "too large"),
+    (dict(bc=(1, 4, 0, 0, 0, 0), log_inflow=(3, 0.1, 0.0)), "log inflow"),
+    (dict(bc=(1, 4, 0, 0, 0, 0), log_inflow=(2, -0.1, 0.0)), "log inflow"),
+    (dict(bc=(1, 4, 0, 0, 0, 0), log_inflow=(2, float("nan"), 0.0)), "log inflow"),
 ])
 def test_invalid_configurations_are_rejected_on_host(kw, msg):
     L = lbm.lib()
@@ -63,6 +66,17 @@ def test_invalid_configurations_are_rejected_on_host(kw, msg):
     assert st == -1
     assert msg in L.lbm_last_error(None).decode()
     assert not h.value
+
+
+def test_open_boundary_configuration_accepted_and_unknown_profile_rejected():
+    L = lbm.lib()
+    c = _cfg(bc=(1, 4, 0, 0, 3, 3), log_inflow=(2, 0.05, 4.0))
+    assert L.lbm_pool_bytes(ctypes.byref(c)) > 0
+    c.inflow_profile = 2
+    assert L.lbm_pool_bytes(ctypes.byref(c)) == 0
+    h = ctypes.c_void_p()
+    assert L.lbm_create(ctypes.byref(c), None, None, 0, ctypes.byref(h)) == -1
+    assert "inflow profile" in L.lbm_last_error(None).decode()
 
 
 def test_missing_buffers_rejected():

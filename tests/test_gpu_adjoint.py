@@ -4,7 +4,8 @@ complex-step derivative of the FP64 oracle, plus the state save/load it rests on
 - Directional derivatives of a kinetic-energy loss after a few coarse steps with
   respect to every initial moment, along random directions, on one level (periodic;
   walls for bounce-back), two levels (periodic; sphere with inflow and outflow
-  faces) and three levels: relative error <= 1e-4 (FP32 adjoint vs FP64 complex
+  faces; the same with a logarithmic inflow profile, convective outflow and walls)
+  and three levels: relative error <= 1e-4 (FP32 adjoint vs FP64 complex
   step). With BF16 storage the gradient stays within 3% of the FP32 one.
 - Entries of the gradient at nodes that carry no state (ghost, solid, inflow) are 0.
 - The checkpointed autograd rollout equals the chain of single adjoint steps and
@@ -26,7 +27,7 @@ from paper_2603_14982_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-P, INF, OUT, WALL = W.PERIODIC, W.INFLOW, W.OUTFLOW, W.WALL
+P, INF, OUT, WALL, CONV = W.PERIODIC, W.INFLOW, W.OUTFLOW, W.WALL, W.OUTFLOW_CONV
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 CASES = {
@@ -39,6 +40,10 @@ CASES = {
     "sphere": (2, (80, 80, 80), (INF, OUT, P, P, P, P), (0.03, 0.0, 0.0),
                W.sphere_solid((80, 80, 80), (40.0, 40.0, 40.0), 3.0), None,
                {0: ((16, 16, 16), (64, 64, 64)), 1: ((0, 0, 0), (80, 80, 80))}),
+    # log inflow along z (zero at the lower wall), convective outflow, no-slip z faces
+    "open": (2, (80, 80, 80), (INF, CONV, P, P, WALL, WALL), (0.03, 0.0, 0.0),
+             W.sphere_solid((80, 80, 80), (40.0, 40.0, 40.0), 3.0), None,
+             {0: ((16, 16, 16), (64, 64, 64)), 1: ((0, 0, 0), (80, 80, 80))}),
     # three levels: 512 + 504 + 56 blocks, two interfaces
     "three_level": (3, (128, 128, 128), (P,) * 6, (0.0, 0.0, 0.0), None, W.block_centre_markers((7, 8)),
                     {0: ((32, 32, 32), (96, 96, 96)), 1: ((0, 0, 0), (128, 128, 128)),
@@ -51,15 +56,18 @@ def _lbm():
     return lbm
 
 
+LOG_INFLOW = {"open": (2, 0.08, 0.0)}  # axis, beta, h0
+
+
 def _gpu(case):
     L, n, bc, uin, solid, parts, _ = CASES[case]
-    return _lbm().Sim(L, n, bc, 0.6, uin=uin, solid=solid, particles=parts)
+    return _lbm().Sim(L, n, bc, 0.6, uin=uin, solid=solid, particles=parts, log_inflow=LOG_INFLOW.get(case))
 
 
 def _oracle(case, complex_=False):
     L, n, bc, uin, solid, parts, _ = CASES[case]
     cls = O.OracleSimComplex if complex_ else O.OracleSim
-    return cls(L, n, bc, 0.6, uin=uin, solid=solid, particles=parts)
+    return cls(L, n, bc, 0.6, uin=uin, solid=solid, particles=parts, log_inflow=LOG_INFLOW.get(case))
 
 
 def _fields(case, keys, seed):

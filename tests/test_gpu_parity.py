@@ -126,6 +126,35 @@ def test_sphere_two_level_inflow_outflow_bounce_back():
     compare(gpu, ora, label="sphere128")
 
 
+def test_open_channel_log_inflow_convective_outflow():
+    # the two-level sphere geometry with the open boundaries of Sec. 7: inflow with a
+    # logarithmic profile over the height z (zero at the lower wall), convective
+    # outflow on x+, no-slip walls on z, periodic y; 30 coarse steps from a smooth
+    # random field, so that the outward velocity changes sign over the outlet
+    wl = W.workload("sphere128")
+    c, r = wl["sphere"]
+    n = wl["n"]
+    bc = (W.INFLOW, W.OUTFLOW_CONV, P, P, W.WALL, W.WALL)
+    solid = W.sphere_solid(n, c, r)
+    u0 = W.smooth_random_velocity(n, 17, kmax=4.0, rms=0.03)
+    lbm = _lbm()
+    ora = O.OracleSim(2, n, bc, wl["tau0"], uin=(0.05, 0.0, 0.0), solid=solid, log_inflow=(2, 0.04, 0.0))
+    gpu = lbm.Sim(2, n, bc, wl["tau0"], uin=(0.05, 0.0, 0.0), solid=solid, log_inflow=(2, 0.04, 0.0))
+    for l in range(2):
+        keys = ora.block_keys(l)
+        assert np.array_equal(gpu.block_keys(l).cpu().numpy(), keys)
+        vals = W.velocity_moments(l, keys, u0)
+        ora.set_block_moments(l, keys, vals)
+        gpu.set_block_moments(l, keys, vals.astype(np.float32))
+    inflow = ora.roles(1) == O.R_INFLOW
+    _, v1 = gpu.get_moments(1)
+    ux = v1.cpu().numpy()[:, 1][inflow]
+    assert ux.min() == 0.0 and ux.max() > 0.05  # the profile, from the wall upwards
+    gpu.step(30)
+    ora.step(30)
+    compare(gpu, ora, label="open channel")
+
+
 @pytest.mark.parametrize("levels", [2, 3])
 def test_moving_slab_with_grid_updates(levels):
     # particles falling through a periodic box; grid update after every coarse step

@@ -7,7 +7,9 @@ Configurations (two coarse steps each):
 - two levels, 80^3 periodic, level 0 over [16, 64)^3 fixed by marker particles
   (stream-collide on both levels, downward and upward transfers);
 - the same block set from a solid sphere (r = 3 at the centre) with an inflow
-  face at x- and an outflow face at x+ (bounce-back, inflow, outflow copy).
+  face at x- and an outflow face at x+ (bounce-back, inflow, outflow copy);
+- the sphere with a logarithmic inflow profile along z, a convective outflow face
+  and no-slip z faces (the outflow step and its velocity-dependent rate).
 """
 import numpy as np
 import pytest
@@ -15,7 +17,7 @@ import pytest
 from oracle import oracle as O
 from paper_2603_14982_amd import workloads as W
 
-P, INF, OUT = W.PERIODIC, W.INFLOW, W.OUTFLOW
+P, INF, OUT, CONV, WALL = W.PERIODIC, W.INFLOW, W.OUTFLOW, W.OUTFLOW_CONV, W.WALL
 N = (80, 80, 80)
 BOX = ((16, 16, 16), (64, 64, 64))
 
@@ -24,6 +26,9 @@ def _config(kind):
     if kind == "periodic":
         return dict(bc=(P,) * 6, particles=W.block_centre_markers((4, 5)), solid=None, uin=(0.0, 0.0, 0.0))
     solid = W.sphere_solid(N, (40.0, 40.0, 40.0), 3.0)
+    if kind == "open":
+        return dict(bc=(INF, CONV, P, P, WALL, WALL), particles=None, solid=solid, uin=(0.03, 0.0, 0.0),
+                    log_inflow=(2, 0.08, 0.0))
     return dict(bc=(INF, OUT, P, P, P, P), particles=None, solid=solid, uin=(0.03, 0.0, 0.0))
 
 
@@ -45,7 +50,8 @@ def _fields(sim, seed):
 
 def _real_loss(kind, x, steps):
     c = _config(kind)
-    sim = O.OracleSim(2, N, c["bc"], 0.6, uin=c["uin"], solid=c["solid"], particles=c["particles"])
+    sim = O.OracleSim(2, N, c["bc"], 0.6, uin=c["uin"], solid=c["solid"], particles=c["particles"],
+                      log_inflow=c.get("log_inflow"))
     for l in range(2):
         sim.set_block_moments(l, sim.block_keys(l), x[l])
     sim.step(steps)
@@ -54,21 +60,23 @@ def _real_loss(kind, x, steps):
 
 def _complex_loss(kind, x, v, h, steps):
     c = _config(kind)
-    sim = O.OracleSimComplex(2, N, c["bc"], 0.6, uin=c["uin"], solid=c["solid"], particles=c["particles"])
+    sim = O.OracleSimComplex(2, N, c["bc"], 0.6, uin=c["uin"], solid=c["solid"], particles=c["particles"],
+                             log_inflow=c.get("log_inflow"))
     for l in range(2):
         sim.set_block_moments(l, sim.block_keys(l), x[l], h * v[l])
     sim.step(steps)
     return sim.kinetic_energy(0, *BOX) + sim.kinetic_energy(1, *BOX)
 
 
-@pytest.mark.parametrize("kind", ["periodic", "sphere"])
+@pytest.mark.parametrize("kind", ["periodic", "sphere", "open"])
 def test_complex_step_matches_central_difference(kind):
     c = _config(kind)
-    probe = O.OracleSim(2, N, c["bc"], 0.6, uin=c["uin"], solid=c["solid"], particles=c["particles"])
+    probe = O.OracleSim(2, N, c["bc"], 0.6, uin=c["uin"], solid=c["solid"], particles=c["particles"],
+                        log_inflow=c.get("log_inflow"))
     assert probe.num_blocks(0) == 216 and probe.num_blocks(1) == 124
     roles0 = probe.roles(0)
     assert (roles0 == O.R_GHOST).any()
-    if kind == "sphere":
+    if kind != "periodic":
         assert (roles0 == O.R_SOLID).any()
         assert (probe.roles(1) == O.R_OUTFLOW).any() and (probe.roles(1) == O.R_INFLOW).any()
     x, v = _fields(probe, 11)

@@ -81,6 +81,7 @@ typedef struct {
   int32_t inflow_axis;     /* LOG: axis of the height (0, 1, 2) */
   float inflow_beta;       /* LOG: shear coefficient, >= 0, per fine node */
   float inflow_h0;         /* LOG: height of the profile's zero, fine nodes */
+  int32_t coupling;        /* 1: the finest level carries coupling fields (lbm_set_coupling); 0: none */
 } lbm_config;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -118,6 +119,25 @@ lbm_status lbm_set_block_moments(lbm_ctx* ctx, int32_t level, const int64_t* key
  * downward transfer (Eq. downward_rescale, with temporal interpolation) before
  * each fine stream-collide, upward transfer (Eq. upload_S) after the second. */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
+
+/* Coupling fields of the finest level, the hook for an external granular solver
+ * (Sec. 4): per node the fluid fraction eps, which scales the relaxation time to
+ * eps tau0, and a force density F (lattice units, the external part of the paper's
+ * force, e.g. drag and gravity over the conversion factor). The collision of a node
+ * then uses rate 1 / (eps tau0) and Guo's force terms in moment form (S gains
+ * (1 - om/2)(u F + F u)/rho, the carried velocity is u + F/(2 rho)), and its stored
+ * velocity after streaming is (sum c f + F/2) / rho (Eq. rho_u_stress). The stored
+ * moments between steps are the state before collision, where the external solver
+ * reads the velocity and supplies the next F.
+ * keys: device int64 [nb], keys of active finest-level blocks (lbm_block_keys);
+ * fields: device f32 [nb][4][512] = (eps, Fx, Fy, Fz) per node. Blocks keep their
+ * fields until set again; blocks created by a grid update start at eps = 1, F = 0;
+ * solid nodes keep eps = 1, F = 0. Requires cfg.coupling = 1 (LBM_EINVAL otherwise).
+ * LBM_EINVAL, with no field changed, if a key is not an active finest-level block or
+ * a value is not finite or has eps tau0 <= 1/2. Synchronises. With coupling fields
+ * the finest level always runs one stream-collide per substep, and the adjoint entry
+ * points return LBM_EINVAL. */
+lbm_status lbm_set_coupling(lbm_ctx* ctx, const int64_t* keys, const float* fields, int64_t nb);
 
 /* Moves particles by d (fine units) in f32: p[i] = p[i] + d, as a prescribed
  * stand-in for the granular solver. particles: device float [n][3]. */

@@ -242,6 +242,9 @@ template <class T> struct Blk {
   uint8_t role[kNodes];
   Blk* nb[27];                        // same-level neighbour blocks (periodic wrap), or null
   long idx = 0;                       // position in the per-step block list
+  // finest level only: coupling fields [4][512] (fluid fraction eps, force density
+  // F), empty for eps = 1, F = 0
+  std::vector<double> cpl;
 };
 
 template <class T> struct Sim {
@@ -279,6 +282,16 @@ template <class T> struct Sim {
   }
   void force_at(int l, double F[3]) const {
     for (int a = 0; a < 3; ++a) F[a] = cfg.force[a] * std::ldexp(1.0, l);
+  }
+  // relaxation rate and force of node n of a block on level l: the level's, with the
+  // finest level's coupling fields (Sec. 4: tau scaled by the fluid fraction eps,
+  // the external force density F added to the body force)
+  void node_params(int l, const Blk<T>& B, int n, double& om, double F[3]) const {
+    force_at(l, F);
+    om = omega[l];
+    if (l != 0 || B.cpl.empty()) return;
+    om = 1.0 / (B.cpl[n] * tau[0]);
+    for (int a = 0; a < 3; ++a) F[a] += B.cpl[(1 + a) * kNodes + n];
   }
 
   // --- domain helpers ---
@@ -641,16 +654,17 @@ template <class T> struct Sim {
   void stream_collide(int l) {
     std::vector<Blk<T>*> blocks;
     for (auto& kv : lv[l]) blocks.push_back(&kv.second);
-    double F[3];
-    force_at(l, F);
-    const double om = omega[l];
     // collision applied at every node (moments stored before collision)
     std::vector<std::vector<Mom<T>>> post(blocks.size());
     for (size_t k = 0; k < blocks.size(); ++k) blocks[k]->idx = long(k);
 #pragma omp parallel for schedule(static)
     for (long k = 0; k < long(blocks.size()); ++k) {
       post[k].resize(kNodes);
-      for (int n = 0; n < kNodes; ++n) post[k][n] = collide(blocks[k]->cur[n], om, F);
+      for (int n = 0; n < kNodes; ++n) {
+        double om, F[3];
+        node_params(l, *blocks[k], n, om, F);
+        post[k][n] = collide(blocks[k]->cur[n], om, F);
+      }
     }
     std::vector<std::vector<Mom<T>>> next(blocks.size());
     std::string local_err;
@@ -699,6 +713,8 @@ template <class T> struct Sim {
           for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) pi[a][b] = pi[a][b] + double(LAT.c[i][a] * LAT.c[i][b]) * f;
         }
+        double om_n, F[3];
+        node_params(l, *B, n, om_n, F);
         Mom<T> q;
         q.v[0] = rho;
         for (int a = 0; a < 3; ++a) q.v[1 + a] = (j[a] + 0.5 * F[a]) / rho;
@@ -830,6 +846,8 @@ template <class T> struct Sim {
         Blk<T>* B = work[l][k];
         Blk<T>* O = find_block(l, B->b);
         B->cur.assign(kNodes, rest_state());
+        // coupling fields stay with blocks that remain; new blocks start at eps = 1, F = 0
+        if (O) B->cpl = O->cpl;
         for (int n = 0; n < kNodes; ++n) {
           uint8_t r = B->role[n];
           bool fresh = (O == nullptr) || (!owned(O->role[n]) && owned(r));
@@ -951,6 +969,19 @@ int oc_set_block_moments(void* h, int level, const int64_t* keys, const double* 
       B.cur[n] = q;
       B.prev[n] = q;
     }
+  }
+  return 0;
+}
+// finest-level coupling fields of the given blocks: in [nb][4][512] (eps, Fx, Fy, Fz)
+int oc_set_coupling(void* h, const int64_t* keys, const double* in, int64_t nb) {
+  auto* s = static_cast<OSim*>(h);
+  for (int64_t k = 0; k < nb; ++k) {
+    auto it = s->lv[0].find(uint64_t(keys[k]));
+    if (it == s->lv[0].end()) { g_err = "set_coupling: unknown finest-level block"; return -1; }
+    const double* src = in + size_t(k) * 4 * kNodes;
+    for (int n = 0; n < kNodes; ++n)
+      if (!(src[n] * s->tau[0] > 0.5) || !std::isfinite(src[n])) { g_err = "set_coupling: eps tau0 must exceed 1/2"; return -1; }
+    it->second.cpl.assign(src, src + 4 * kNodes);
   }
   return 0;
 }

@@ -71,6 +71,8 @@ def lib():
         L.oc_set_block_moments.restype = i32
         L.oc_set_block_moments.argtypes = [vp, i32, vp, vp, i64]
         L.oc_get_block_moments.argtypes = [vp, i32, vp, vp]
+        L.oc_set_coupling.restype = i32
+        L.oc_set_coupling.argtypes = [vp, vp, vp, i64]
         L.oc_get_roles.argtypes = [vp, i32, vp]
         L.oc_step.restype = i32
         L.oc_step.argtypes = [vp, i32]
@@ -140,6 +142,15 @@ class OracleSim:
                 self.h = None
         except Exception:
             pass
+
+    def set_coupling(self, keys, fields):
+        """Finest-level coupling fields of blocks `keys`: fields [nb, 4, 512] = (eps, Fx, Fy, Fz),
+        eps the fluid fraction (tau scaled to eps tau), F the force density."""
+        keys = np.ascontiguousarray(keys, dtype=np.int64)
+        f = np.ascontiguousarray(fields, dtype=np.float64)
+        assert f.shape == (len(keys), 4, 512)
+        if lib().oc_set_coupling(self.h, _ptr(keys), _ptr(f), len(keys)) != 0:
+            raise ValueError(lib().oc_last_error().decode())
 
     def num_blocks(self, level):
         return int(lib().oc_num_blocks(self.h, level))

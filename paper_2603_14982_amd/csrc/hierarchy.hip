@@ -478,6 +478,11 @@ __global__ __launch_bounds__(256) void k_init(InitLaunch a) {
   T* cur = static_cast<T*>(a.dst_cur) + (size_t)slot * kBlockStride;
   T* oth = static_cast<T*>(a.dst_other) + (size_t)slot * kBlockStride;
   Sampler<S> smp(a);
+  if (a.cpl && new_block) {
+    // a new finest-level block starts with eps = 1, F = 0
+    float* c = a.cpl + (size_t)slot * 4 * kNodes;
+    for (int i = threadIdx.x; i < 4 * kNodes; i += 256) c[i] = i < kNodes ? 1.0f : 0.0f;
+  }
   for (int node = threadIdx.x; node < kNodes; node += 256) {
     const uint8_t rn = a.role_new[(size_t)slot * kNodes + node] & ROLE_MASK;
     bool fresh = new_block;

@@ -142,6 +142,50 @@ __global__ void k_advance(float* p, int64_t n, float dx, float dy, float dz) {
   p[3 * i + 2] = __fadd_rn(p[3 * i + 2], dz);
 }
 
+// ---- finest-level coupling fields [slot][4][512]: eps, Fx, Fy, Fz ----
+// every slot (the all-zero one included) starts at eps = 1, F = 0
+__global__ void k_cpl_default(float* cpl, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cpl[i] = ((i / kNodes) & 3) == 0 ? 1.0f : 0.0f;
+}
+// check of the caller's fields of finest-level blocks: err 1 for a key that is no
+// active block, 2 for a value that is not finite or an eps with eps tau0 <= 1/2
+__global__ __launch_bounds__(256) void k_cpl_check(LevelGeom g, const int64_t* keys, const float* in,
+                                                   const int32_t* dir, float tau0, int32_t* err) {
+  int bx, by, bz;
+  morton_decode3((uint64_t)keys[blockIdx.x], bx, by, bz);
+  int32_t slot = -1;
+  if (bx < g.nb[0] && by < g.nb[1] && bz < g.nb[2]) slot = dir[g.off + cell_lin(g, bx, by, bz)];
+  if (slot < 0) {
+    if (threadIdx.x == 0) atomicMax(err, 1);
+    return;
+  }
+  const float* src = in + (size_t)blockIdx.x * 4 * kNodes;
+  int bad = 0;
+  for (int i = threadIdx.x; i < 4 * kNodes; i += 256) {
+    const float v = src[i];
+    if (!__builtin_isfinite(v) || (i < kNodes && !(v * tau0 > 0.5f))) bad = 1;
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicMax(err, 2);
+}
+// scatter into the slots; solid nodes keep eps = 1, F = 0 (they carry no moments, and
+// a force there would give them nonzero populations)
+__global__ __launch_bounds__(256) void k_cpl_set(LevelGeom g, const int64_t* keys, const float* in, const int32_t* dir,
+                                                 const uint8_t* role, float* cpl) {
+  int bx, by, bz;
+  morton_decode3((uint64_t)keys[blockIdx.x], bx, by, bz);
+  if (!(bx < g.nb[0] && by < g.nb[1] && bz < g.nb[2])) return;
+  const int32_t slot = dir[g.off + cell_lin(g, bx, by, bz)];
+  if (slot < 0) return;
+  const float* src = in + (size_t)blockIdx.x * 4 * kNodes;
+  float* dst = cpl + (size_t)slot * 4 * kNodes;
+  for (int i = threadIdx.x; i < 4 * kNodes; i += 256) {
+    const bool solid = (role[(size_t)slot * kNodes + (i % kNodes)] & ROLE_MASK) == ROLE_SOLID;
+    dst[i] = solid ? (i < kNodes ? 1.0f : 0.0f) : src[i];
+  }
+}
+
 template <template <class> class K, class... Args>
 hipError_t dispatch(int storage, dim3 g, dim3 b, hipStream_t s, Args... args) {
   switch (storage) {
@@ -191,6 +235,24 @@ hipError_t launch_reduce(const IoLaunch& a, const int32_t lo[3], const int32_t h
 hipError_t launch_finite(const IoLaunch& a, int32_t* flag, hipStream_t s) {
   if (a.nblocks <= 0) return hipSuccess;
   return dispatch<FinK>(a.storage, dim3(a.nblocks), dim3(256), s, a, flag);
+}
+hipError_t launch_cpl_default(float* cpl, int64_t nslots, hipStream_t s) {
+  const int64_t n = nslots * 4 * kNodes;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpl_default, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cpl, n);
+  return hipGetLastError();
+}
+hipError_t launch_cpl_check(const LevelGeom& g, const int64_t* keys, const float* in, int64_t nb, const int32_t* dir,
+                            float tau0, int32_t* err, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpl_check, dim3((unsigned)nb), dim3(256), 0, s, g, keys, in, dir, tau0, err);
+  return hipGetLastError();
+}
+hipError_t launch_cpl_set(const LevelGeom& g, const int64_t* keys, const float* in, int64_t nb, const int32_t* dir,
+                          const uint8_t* role, float* cpl, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cpl_set, dim3((unsigned)nb), dim3(256), 0, s, g, keys, in, dir, role, cpl);
+  return hipGetLastError();
 }
 hipError_t launch_advance_particles(float* p, int64_t n, float dx, float dy, float dz, hipStream_t s) {
   if (n <= 0) return hipSuccess;

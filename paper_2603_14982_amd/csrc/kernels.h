@@ -26,6 +26,7 @@ struct ScLaunch {
   const int4* coord;
   LevelGeom lg;
   int periodic[3];
+  const float* cpl;          // finest level with coupling fields: [slot][4][512] (eps, F); else null
 };
 hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s);
 // both substeps of a parent step of the finest level, in -> out (tiles required; the
@@ -150,6 +151,7 @@ struct InitLaunch {
   int create;                // 1: no old hierarchy, start at rest
   Scales sc;
   int storage;
+  float* cpl;                // finest level with coupling fields: reset for new blocks; else null
 };
 hipError_t launch_init(const InitLaunch& a, hipStream_t s);
 
@@ -168,6 +170,12 @@ struct IoLaunch {
 };
 hipError_t launch_get(const IoLaunch& a, int64_t* keys, float* out, hipStream_t s);
 hipError_t launch_get_roles(const IoLaunch& a, uint8_t* out, hipStream_t s);
+// finest-level coupling fields [slot][4][512] (eps, F)
+hipError_t launch_cpl_default(float* cpl, int64_t nslots, hipStream_t s);
+hipError_t launch_cpl_check(const LevelGeom& g, const int64_t* keys, const float* in, int64_t nb, const int32_t* dir,
+                            float tau0, int32_t* err, hipStream_t s);
+hipError_t launch_cpl_set(const LevelGeom& g, const int64_t* keys, const float* in, int64_t nb, const int32_t* dir,
+                          const uint8_t* role, float* cpl, hipStream_t s);
 hipError_t launch_set(const IoLaunch& a, const int64_t* keys, const float* in, int64_t nb,
                       const int32_t* dir, int32_t* err_flag, hipStream_t s);
 hipError_t launch_keys(const IoLaunch& a, int64_t* keys, hipStream_t s);

@@ -22,7 +22,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   size_t t0, t0s, t0p, flags, st[2], dir[2], lists, wave, counts, coord, nbr, role[2], summary, gbox, free_stack, blocks,
-      gblocks, iblocks, oblocks, tblocks, red_partial, red_out, flag;
+      gblocks, iblocks, oblocks, tblocks, red_partial, red_out, flag, cpl;
   size_t total;
   int64_t level_list_off[kMaxLevels];  // offset (elements) of each level's segment in blocks / g/i/o lists
   int64_t level_list_cap[kMaxLevels];
@@ -72,6 +72,7 @@ bool make_geom(const lbm_config* c, Geom& G, std::string& err) {
   if (!(c->tau0 > 0.5) || !std::isfinite(c->tau0)) { err = "tau0 must be finite and exceed 1/2"; return false; }
   if (c->storage < LBM_F32 || c->storage > LBM_F16) { err = "unknown storage format"; return false; }
   if (c->rescale != 0 && c->rescale != 1) { err = "rescale must be 0 or 1"; return false; }
+  if (c->coupling != 0 && c->coupling != 1) { err = "coupling must be 0 or 1"; return false; }
   if (c->max_blocks < 1 || c->max_blocks > (int64_t(1) << 26)) { err = "max_blocks must be in 1..2^26"; return false; }
   if (c->storage != LBM_F32)
     for (int m = 0; m < kMom; ++m)
@@ -139,6 +140,8 @@ Layout make_layout(const lbm_config* c, const Geom& G) {
   L.red_partial = take(cap * 5 * 8);
   L.red_out = take(8 * 8);
   L.flag = take(64);
+  // finest-level coupling fields (eps, F) per slot and for the all-zero slot
+  L.cpl = c->coupling ? take((size_t)(cap + 1) * 4 * kNodes * sizeof(float)) : 0;
   L.total = o;
   return L;
 }
@@ -204,6 +207,8 @@ struct lbm_ctx {
   int32_t* oblocks(int l) const { return m<int32_t>(lay.oblocks) + lay.level_list_off[l]; }
   // one block of every stream-collide tile (kTileX x 2 x 2 blocks) of the level
   int32_t* tblocks(int l) const { return m<int32_t>(lay.tblocks) + lay.level_list_off[l]; }
+  // finest-level coupling fields [slot][4][512] (eps, F), null without coupling
+  float* cpl() const { return cfg.coupling ? m<float>(lay.cpl) : nullptr; }
   // time level p of the pool: cap block slots plus one all-zero slot (index cap)
   void* buf(int l, int p) const { return pool + (size_t)p * (size_t)(cap + 1) * kBlockStride * elem; }
   void* cur(int l) const { return buf(l, parity[l]); }
@@ -404,6 +409,7 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     a.create = create ? 1 : 0;
     a.sc = c->sc;
     a.storage = c->cfg.storage;
+    a.cpl = l == 0 ? c->cpl() : nullptr;
     HIPCHK(c, launch_init(a, s));
   }
   c->hier = nh;
@@ -484,6 +490,7 @@ ScLaunch sc_base(lbm_ctx* c, int l) {
   a.coord = c->m<int4>(c->lay.coord);
   a.lg = c->G.lv[l];
   for (int k = 0; k < 3; ++k) a.periodic[k] = c->G.periodic[k];
+  a.cpl = l == 0 ? c->cpl() : nullptr;
   return a;
 }
 
@@ -587,7 +594,8 @@ lbm_status up_level(lbm_ctx* c, int l) {
 // flips once instead of twice; the intermediate time level is never stored (no finer
 // level interpolates from it).
 bool pair_ok(const lbm_ctx* c) {
-  return c->fuse_substeps && !c->recording && c->G.L >= 2 && tiled(c, 0) && c->nob[0] == 0 && c->nbb[0] == 0;
+  return c->fuse_substeps && !c->recording && c->G.L >= 2 && tiled(c, 0) && c->nob[0] == 0 && c->nbb[0] == 0 &&
+         !c->cfg.coupling;
 }
 
 lbm_status sc_pair(lbm_ctx* c) {
@@ -824,6 +832,7 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
                        (int64_t)kBlockStride * (int64_t)c->elem, c->stream),
         "zero slot");
   chk(launch_fill_i32(c->dir(0), NBR_NONE, ncell, c->stream), "clear directory");
+  if (c->cpl()) chk(launch_cpl_default(c->cpl(), c->cap + 1, c->stream), "coupling fields");
   std::vector<int32_t> fs((size_t)c->cap);
   for (int64_t i = 0; i < c->cap; ++i) fs[(size_t)i] = (int32_t)(c->cap - 1 - i);
   chk(hipMemcpyAsync(c->m<int32_t>(c->lay.free_stack), fs.data(), fs.size() * 4, hipMemcpyHostToDevice, c->stream),
@@ -878,6 +887,24 @@ lbm_status lbm_set_block_moments(lbm_ctx* ctx, int32_t level, const int64_t* key
   HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, flag, 4, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
   if (ctx->host_counts[0]) return ctx->fail(LBM_EINVAL, "a key is not an active block of this level");
+  return LBM_OK;
+}
+
+lbm_status lbm_set_coupling(lbm_ctx* ctx, const int64_t* keys, const float* fields, int64_t nb) {
+  if (!ctx) return LBM_EINVAL;
+  if (!ctx->cfg.coupling) return ctx->fail(LBM_EINVAL, "coupling fields not enabled in the configuration");
+  if (nb < 0 || (nb > 0 && (!keys || !fields))) return ctx->fail(LBM_EINVAL, "bad block arrays");
+  if (nb == 0) return LBM_OK;
+  int32_t* flag = ctx->m<int32_t>(ctx->lay.flag);
+  HIPCHK(ctx, launch_fill_i32(flag, 0, 1, ctx->stream));
+  HIPCHK(ctx, launch_cpl_check(ctx->G.lv[0], keys, fields, nb, ctx->dir(ctx->hier), (float)ctx->tau[0], flag,
+                               ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, flag, 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->host_counts[0] == 1) return ctx->fail(LBM_EINVAL, "a key is not an active finest-level block");
+  if (ctx->host_counts[0] == 2) return ctx->fail(LBM_EINVAL, "coupling fields must be finite with eps tau0 > 1/2");
+  HIPCHK(ctx, launch_cpl_set(ctx->G.lv[0], keys, fields, nb, ctx->dir(ctx->hier), ctx->role(ctx->rcur), ctx->cpl(),
+                             ctx->stream));
   return LBM_OK;
 }
 
@@ -1033,6 +1060,7 @@ lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes,
 lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes, int32_t n_steps,
                              const float* lam_next, float* lam_out, void* work, size_t work_bytes) {
   if (!ctx) return LBM_EINVAL;
+  if (ctx->cfg.coupling) return ctx->fail(LBM_EINVAL, "the adjoint does not cover coupling fields");
   if (n_steps < 1) return ctx->fail(LBM_EINVAL, "step count must be positive");
   if (!lam_next || !lam_out || !work) return ctx->fail(LBM_EINVAL, "null adjoint buffer");
   if (work_bytes < lbm_adjoint_work_bytes(ctx, n_steps)) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
@@ -1044,6 +1072,7 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes
 
 lbm_status lbm_step_record(lbm_ctx* ctx, int32_t n_steps, void* work, size_t work_bytes) {
   if (!ctx) return LBM_EINVAL;
+  if (ctx->cfg.coupling) return ctx->fail(LBM_EINVAL, "the adjoint does not cover coupling fields");
   if (n_steps < 1) return ctx->fail(LBM_EINVAL, "step count must be positive");
   if (!work) return ctx->fail(LBM_EINVAL, "null adjoint buffer");
   if (work_bytes < lbm_adjoint_work_bytes(ctx, n_steps)) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");

@@ -37,6 +37,7 @@ namespace lbmx {
 namespace {
 
 template <class S> struct ScArgs {
+  const float* cpl;  // coupling fields of the finest level, [slot][4][512] (eps, F), or null
   const typename S::type* in;
   typename S::type* out;
   const int32_t* blocks;
@@ -58,17 +59,36 @@ template <class S> struct ScArgs {
 // source node, three per group (P(+1), P(0), P(-1)):
 //   P(+-1) = a0 +- a1 + 2 a2,  P(0) = 4 (a0 - a2)
 // for the group's coefficients (a0, a1, a2) of p0, p1, p2' along x.
-__device__ __forceinline__ void source_pops(const float q[kMom], float omega, float p[24]) {
+// With coupling fields c4 = (eps, F) (CPL) the node relaxes at omega / eps (tau
+// scaled by the fluid fraction) and the force enters in Guo's moment form: S gains
+// (1 - om/2)(u F + F u)/rho, and the carried velocity is u + F/(2 rho).
+template <bool CPL>
+__device__ __forceinline__ void source_pops(const float q[kMom], float omega, const float c4[4], float p[24]) {
   const float drho = q[0];
   const float rho = 1.0f + drho;
-  const float ux = q[1], uy = q[2], uz = q[3];
+  float ux = q[1], uy = q[2], uz = q[3];
+  const float om = CPL ? omega / c4[0] : omega;
   // collision: S relaxes to u u
-  const float sxx = q[4] + omega * (ux * ux - q[4]);
-  const float syy = q[5] + omega * (uy * uy - q[5]);
-  const float szz = q[6] + omega * (uz * uz - q[6]);
-  const float sxy = q[7] + omega * (ux * uy - q[7]);
-  const float sxz = q[8] + omega * (ux * uz - q[8]);
-  const float syz = q[9] + omega * (uy * uz - q[9]);
+  float sxx = q[4] + om * (ux * ux - q[4]);
+  float syy = q[5] + om * (uy * uy - q[5]);
+  float szz = q[6] + om * (uz * uz - q[6]);
+  float sxy = q[7] + om * (ux * uy - q[7]);
+  float sxz = q[8] + om * (ux * uz - q[8]);
+  float syz = q[9] + om * (uy * uz - q[9]);
+  if (CPL) {
+    const float g = (1.0f - 0.5f * om) / rho;
+    const float fx = c4[1], fy = c4[2], fz = c4[3];
+    sxx += g * (ux * fx + fx * ux);
+    syy += g * (uy * fy + fy * uy);
+    szz += g * (uz * fz + fz * uz);
+    sxy += g * (ux * fy + fx * uy);
+    sxz += g * (ux * fz + fx * uz);
+    syz += g * (uy * fz + fy * uz);
+    const float h = 0.5f / rho;
+    ux += h * fx;
+    uy += h * fy;
+    uz += h * fz;
+  }
   // third-order terms Gamma_aab = S_aa u_b + 2 S_ab u_a - 2 u_a^2 u_b
   //                             = u_b (S_aa - 2 u_a^2) + 2 S_ab u_a
   const float tx = sxx - 2.0f * (ux * ux), ty = syy - 2.0f * (uy * uy), tz = szz - 2.0f * (uz * uz);
@@ -106,18 +126,37 @@ __device__ __forceinline__ void source_pops(const float q[kMom], float omega, fl
   // (1,2): (a012, 0, 0)
   p[21] = a012;  p[22] = 4.0f * a012;  p[23] = a012;
 }
+__device__ __forceinline__ void source_pops(const float q[kMom], float omega, float p[24]) {
+  source_pops<false>(q, omega, nullptr, p);
+}
 
 // The 17 tensor-basis coefficients of a node (bounce-back path only), p2' basis.
-__device__ void node_coeffs(const float q[kMom], float omega, float a[17]) {
+template <bool CPL>
+__device__ void node_coeffs(const float q[kMom], float omega, const float c4[4], float a[17]) {
   const float drho = q[0];
   const float rho = 1.0f + drho;
-  const float ux = q[1], uy = q[2], uz = q[3];
-  const float sxx = q[4] + omega * (ux * ux - q[4]);
-  const float syy = q[5] + omega * (uy * uy - q[5]);
-  const float szz = q[6] + omega * (uz * uz - q[6]);
-  const float sxy = q[7] + omega * (ux * uy - q[7]);
-  const float sxz = q[8] + omega * (ux * uz - q[8]);
-  const float syz = q[9] + omega * (uy * uz - q[9]);
+  float ux = q[1], uy = q[2], uz = q[3];
+  const float om = CPL ? omega / c4[0] : omega;
+  float sxx = q[4] + om * (ux * ux - q[4]);
+  float syy = q[5] + om * (uy * uy - q[5]);
+  float szz = q[6] + om * (uz * uz - q[6]);
+  float sxy = q[7] + om * (ux * uy - q[7]);
+  float sxz = q[8] + om * (ux * uz - q[8]);
+  float syz = q[9] + om * (uy * uz - q[9]);
+  if (CPL) {
+    const float g = (1.0f - 0.5f * om) / rho;
+    const float fx = c4[1], fy = c4[2], fz = c4[3];
+    sxx += g * (ux * fx + fx * ux);
+    syy += g * (uy * fy + fy * uy);
+    szz += g * (uz * fz + fz * uz);
+    sxy += g * (ux * fy + fx * uy);
+    sxz += g * (ux * fz + fx * uz);
+    syz += g * (uy * fz + fy * uz);
+    const float h = 0.5f / rho;
+    ux += h * fx;
+    uy += h * fy;
+    uz += h * fz;
+  }
   a[0] = drho;                      // 000
   a[1] = 3.0f * (rho * ux);         // 100
   a[2] = 3.0f * (rho * uy);         // 010
@@ -178,17 +217,31 @@ __device__ __forceinline__ void fetch_point(const ScArgs<S>& a, const int* s_src
   for (int m = 0; m < kMom; ++m) raw[m] = src[m * kNodes];
 }
 
+// coupling fields (eps, F) of a plane point of the single-block kernel / of a node
+__device__ __forceinline__ void load_cpl(const float* cpl, int slot, int node, float c4[4]) {
+  const float* src = cpl + (size_t)slot * 4 * kNodes + node;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) c4[m] = src[m * kNodes];
+}
+__device__ __forceinline__ void fetch_cpl_point(const float* cpl, const int* s_src, int px, int py, int pz,
+                                                float c4[4]) {
+  const int ox = px < 0 ? -1 : (px > 7 ? 1 : 0);
+  const int oy = py < 0 ? -1 : (py > 7 ? 1 : 0);
+  const int oz = pz < 0 ? -1 : (pz > 7 ? 1 : 0);
+  load_cpl(cpl, s_src[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)], (px & 7) + 8 * (py & 7) + 64 * (pz & 7), c4);
+}
+
 // bounce-back correction of one computed node: every direction c_i whose source
 // x - c_i is solid (or behind a wall) receives f_{-c_i}(x) instead.
-template <class S>
-__device__ void bounce_back(const ScArgs<S>& a, int slot, int lx, int ly, int lz, float M[10]) {
+template <class S, bool CPL>
+__device__ void bounce_back(const ScArgs<S>& a, int slot, int lx, int ly, int lz, const float c4[4], float M[10]) {
   const int32_t* nbr = a.nbr + (size_t)slot * 27;
   float q[kMom];
   const int node = lx + 8 * ly + 64 * lz;
   const typename S::type* src = a.in + (size_t)slot * kBlockStride + node;
   for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(src[m * kNodes], a.sc.inv[m]);
   float c[17];
-  node_coeffs(q, a.omega, c);
+  node_coeffs<CPL>(q, a.omega, c4, c);
 #pragma unroll 1
   for (int i = 0; i < 27; ++i) {
     if (i == 13) continue;
@@ -298,7 +351,7 @@ __device__ __forceinline__ void x_pass(const float* lds, int row, int x, float y
     }
 }
 
-template <class S>
+template <class S, bool CPL>
 __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   __shared__ __align__(16) float lds[10 * kRow];
   __shared__ int s_src[27];
@@ -328,9 +381,13 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
 
   typedef typename S::type T;
   T nxt[2][kMom];
+  float ncp[2][4];  // coupling fields of the prefetched points
 #pragma unroll
   for (int r = 0; r < 2; ++r)
-    if (has[r]) fetch_point<S>(a, s_src, px[r], py[r], -1, nxt[r]);
+    if (has[r]) {
+      fetch_point<S>(a, s_src, px[r], py[r], -1, nxt[r]);
+      if (CPL) fetch_cpl_point(a.cpl, s_src, px[r], py[r], -1, ncp[r]);
+    }
 
   float zp1[6], zp2[6], z0[6];  // z-window: pop+ of planes z-1, z-2; pop0 of plane z-1
 #pragma unroll
@@ -339,14 +396,21 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
   for (int z = -1; z <= 8; ++z) {
     // ---- pass 0: moments of plane z (+ halo) -> x-populations, into LDS
     T cur[2][kMom];
+    float ccp[2][4];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < 2; ++r) {
 #pragma unroll
       for (int m = 0; m < kMom; ++m) cur[r][m] = nxt[r][m];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) ccp[r][m] = CPL ? ncp[r][m] : 0.0f;
+    }
     if (z < 8) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
-        if (has[r]) fetch_point<S>(a, s_src, px[r], py[r], z + 1, nxt[r]);
+        if (has[r]) {
+          fetch_point<S>(a, s_src, px[r], py[r], z + 1, nxt[r]);
+          if (CPL) fetch_cpl_point(a.cpl, s_src, px[r], py[r], z + 1, ncp[r]);
+        }
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -355,7 +419,7 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
 #pragma unroll
       for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(cur[r][m], a.sc.inv[m]);
       float p[24];
-      source_pops(q, a.omega, p);
+      source_pops<CPL>(q, a.omega, ccp[r], p);
       float v[8];
       const int row = py[r] + 1, col = px[r] + 1;
 #pragma unroll
@@ -439,7 +503,15 @@ __global__ __launch_bounds__(64) void k_stream_collide(ScArgs<S> a) {
       const uint8_t role = (uint8_t)(col_roles >> (8 * zo));
       typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
       if ((role & ROLE_MASK) == ROLE_COMPUTED) {
-        if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, zo, M);
+        float c4[4] = {1.0f, 0.0f, 0.0f, 0.0f};
+        if (CPL) load_cpl(a.cpl, slot, node, c4);
+        if (role & ROLE_BB) bounce_back<S, CPL>(a, slot, ox, oy, zo, c4, M);
+        // half the node's force in its velocity (Eq. rho_u_stress); 108 = 216 / 2
+        if (CPL) {
+          M[1] += 108.0f * c4[1];
+          M[2] += 108.0f * c4[2];
+          M[3] += 108.0f * c4[3];
+        }
         // remove the 6^3 scale of the three passes; no constant reciprocal of
         // 216 or 3 multiplies a result (it would bias every step the same way)
         const float q0 = M[0] * c216;
@@ -622,7 +694,15 @@ __device__ __forceinline__ void fetch_tile(const ScArgs<S>& a, const int* s_src,
   for (int m = 0; m < kMom; ++m) raw[m] = src[m * kNodes];
 }
 
-template <class S, int TX>
+template <int TX>
+__device__ __forceinline__ void fetch_cpl_tile(const float* cpl, const int* s_src, int px, int py, int pz,
+                                               float c4[4]) {
+  constexpr int NXB = Tile<TX>::NXB;
+  const int ns = s_src[((px + 8) >> 3) + NXB * ((py + 8) >> 3) + 4 * NXB * ((pz + 8) >> 3)];
+  load_cpl(cpl, ns, (px & 7) + 8 * (py & 7) + 64 * (pz & 7), c4);
+}
+
+template <class S, int TX, bool CPL>
 __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a) {
   typedef Tile<TX> G;
   __shared__ __align__(16) float lds[G::CY * G::ROW];
@@ -679,9 +759,13 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
 
   typedef typename S::type T;
   T nxt[2][kMom];
+  float ncp[2][4];  // coupling fields of the prefetched points
 #pragma unroll
   for (int r = 0; r < 2; ++r)
-    if (has[r]) fetch_tile<S, TX>(a, s_src, px[r], py[r], -1, nxt[r]);
+    if (has[r]) {
+      fetch_tile<S, TX>(a, s_src, px[r], py[r], -1, nxt[r]);
+      if (CPL) fetch_cpl_tile<TX>(a.cpl, s_src, px[r], py[r], -1, ncp[r]);
+    }
 
   float zp1[6], zp2[6], z0[6];
 #pragma unroll
@@ -690,14 +774,21 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
   for (int z = -1; z <= 16; ++z) {
     // ---- source: moments of plane z (+ halo) -> x-populations, into LDS
     T cur[2][kMom];
+    float ccp[2][4];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < 2; ++r) {
 #pragma unroll
       for (int m = 0; m < kMom; ++m) cur[r][m] = nxt[r][m];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) ccp[r][m] = CPL ? ncp[r][m] : 0.0f;
+    }
     if (z < 16) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
-        if (has[r]) fetch_tile<S, TX>(a, s_src, px[r], py[r], z + 1, nxt[r]);
+        if (has[r]) {
+          fetch_tile<S, TX>(a, s_src, px[r], py[r], z + 1, nxt[r]);
+          if (CPL) fetch_cpl_tile<TX>(a.cpl, s_src, px[r], py[r], z + 1, ncp[r]);
+        }
     }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -706,7 +797,7 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
 #pragma unroll
       for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(cur[r][m], a.sc.inv[m]);
       float p[24];
-      source_pops(q, a.omega, p);
+      source_pops<CPL>(q, a.omega, ccp[r], p);
       float v[8];
       const int row = py[r] + 1, col = px[r] + 1;
 #pragma unroll
@@ -755,7 +846,15 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
       const uint8_t role = (uint8_t)((zo >= 8 ? col_roles[1] : col_roles[0]) >> (8 * lz));
       typename S::type* dst = a.out + (size_t)slot * kBlockStride + node;
       if ((role & ROLE_MASK) == ROLE_COMPUTED) {
-        if (role & ROLE_BB) bounce_back<S>(a, slot, ox, oy, lz, M);
+        float c4[4] = {1.0f, 0.0f, 0.0f, 0.0f};
+        if (CPL) load_cpl(a.cpl, slot, node, c4);
+        if (role & ROLE_BB) bounce_back<S, CPL>(a, slot, ox, oy, lz, c4, M);
+        // half the node's force in its velocity (Eq. rho_u_stress); 108 = 216 / 2
+        if (CPL) {
+          M[1] += 108.0f * c4[1];
+          M[2] += 108.0f * c4[2];
+          M[3] += 108.0f * c4[3];
+        }
         float v[kMom];
         finish_moments(M, v);
 #pragma unroll
@@ -1055,11 +1154,15 @@ template <class S> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
   a.coord = l.coord;
   a.lg = l.lg;
   for (int k = 0; k < 3; ++k) a.periodic[k] = l.periodic[k];
+  a.cpl = l.cpl;
+  const dim3 tg(Tile<kTileX>::THREADS);
   if (l.tiles) {
     if (l.ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_stream_collide_tile<S, kTileX>), dim3(l.ntiles), dim3(Tile<kTileX>::THREADS), 0, s, a);
+    if (l.cpl) hipLaunchKernelGGL((k_stream_collide_tile<S, kTileX, true>), dim3(l.ntiles), tg, 0, s, a);
+    else hipLaunchKernelGGL((k_stream_collide_tile<S, kTileX, false>), dim3(l.ntiles), tg, 0, s, a);
   } else {
-    hipLaunchKernelGGL(k_stream_collide<S>, dim3(l.nblocks), dim3(64), 0, s, a);
+    if (l.cpl) hipLaunchKernelGGL((k_stream_collide<S, true>), dim3(l.nblocks), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((k_stream_collide<S, false>), dim3(l.nblocks), dim3(64), 0, s, a);
   }
   return hipGetLastError();
 }
@@ -1082,6 +1185,8 @@ template <class S> hipError_t launch_pair_t(const ScLaunch& l, hipStream_t s) {
   a.coord = l.coord;
   a.lg = l.lg;
   for (int k = 0; k < 3; ++k) a.periodic[k] = l.periodic[k];
+  a.cpl = nullptr;  // levels with coupling fields run two sweeps
+  if (l.cpl) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_stream_collide_pair<S>, dim3(l.ntiles), dim3(Pair::THREADS), 0, s, a);
   return hipGetLastError();
 }

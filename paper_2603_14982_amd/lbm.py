@@ -47,6 +47,7 @@ class LBMConfig(ctypes.Structure):
         ("inflow_axis", ctypes.c_int32),
         ("inflow_beta", ctypes.c_float),
         ("inflow_h0", ctypes.c_float),
+        ("coupling", ctypes.c_int32),
     ]
 
 
@@ -55,7 +56,7 @@ EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm
            "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
            "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
            "lbm_step_record", "lbm_adjoint_reverse",
-           "lbm_loss_ke_grad", "lbm_set_option", "lbm_last_error"]
+           "lbm_loss_ke_grad", "lbm_set_option", "lbm_set_coupling", "lbm_last_error"]
 _SIZE_QUERIES = ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_state_bytes", "lbm_adjoint_work_bytes", "lbm_last_error")
 PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh", "sc_pair"]
 OPTIONS = {"tile_min_blocks": 0, "fuse_substeps": 1}
@@ -102,6 +103,7 @@ def lib():
         L.lbm_adjoint_reverse.argtypes = [vp, vp, vp, vp, sz]
         L.lbm_loss_ke_grad.argtypes = [vp, i32, vp, vp, vp]
         L.lbm_set_option.argtypes = [vp, i32, i64]
+        L.lbm_set_coupling.argtypes = [vp, vp, vp, i64]
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_last_error.argtypes = [vp]
         for name in EXPORTS:
@@ -112,10 +114,11 @@ def lib():
 
 
 def make_config(levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), storage="f32", scale=None, rescale="ce",
-                max_blocks=1, log_inflow=None):
+                max_blocks=1, log_inflow=None, coupling=False):
     """log_inflow = (axis, beta, h0): inflow velocity uin * ln(1 + beta (h - h0)) at
     height h (fine nodes) along axis, zero at or below h0; None: uniform uin."""
     c = LBMConfig()
+    c.coupling = 1 if coupling else 0
     if log_inflow is not None:
         c.inflow_profile = 1
         c.inflow_axis = int(log_inflow[0])
@@ -145,7 +148,7 @@ class Sim:
     """One block-adaptive simulation on a GPU; buffers are torch tensors."""
 
     def __init__(self, levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), storage="f32", scale=None, rescale="ce",
-                 max_blocks=None, solid=None, particles=None, device="cuda", log_inflow=None):
+                 max_blocks=None, solid=None, particles=None, device="cuda", log_inflow=None, coupling=False):
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -154,7 +157,7 @@ class Sim:
         if max_blocks is None:
             max_blocks = sum((n[0] >> l) // 8 * ((n[1] >> l) // 8) * ((n[2] >> l) // 8) for l in range(levels))
             max_blocks = min(max_blocks, 1 << 16)
-        self.cfg = make_config(levels, n, bc, tau0, uin, storage, scale, rescale, max_blocks, log_inflow)
+        self.cfg = make_config(levels, n, bc, tau0, uin, storage, scale, rescale, max_blocks, log_inflow, coupling)
         L = lib()
         pool_bytes = L.lbm_pool_bytes(ctypes.byref(self.cfg))
         meta_bytes = L.lbm_meta_bytes(ctypes.byref(self.cfg))
@@ -251,6 +254,16 @@ class Sim:
         out = (ctypes.c_double * 5)()
         self._check(lib().lbm_reduce_f64(self.h, level, lo_, hi_, out))
         return np.array(list(out))
+
+    def set_coupling(self, keys, fields):
+        """Finest-level coupling fields (needs coupling=True): keys of level-0 blocks and
+        fields [nb, 4, 512] = (eps, Fx, Fy, Fz) per node (fluid fraction, force density)."""
+        k = torch.as_tensor(np.asarray(keys, dtype=np.int64) if not torch.is_tensor(keys) else keys,
+                            dtype=torch.int64, device=self.device).contiguous()
+        f = torch.as_tensor(fields, dtype=torch.float32, device=self.device).contiguous()
+        if tuple(f.shape) != (k.numel(), 4, 512):
+            raise ValueError("fields must be [nb, 4, 512]")
+        self._check(lib().lbm_set_coupling(self.h, _dptr(k), _dptr(f), k.numel()))
 
     def set_option(self, name, value):
         """Execution options: "tile_min_blocks" (blocks a level needs for the tiled

@@ -79,6 +79,18 @@ def test_open_boundary_configuration_accepted_and_unknown_profile_rejected():
     assert "inflow profile" in L.lbm_last_error(None).decode()
 
 
+def test_coupling_configuration():
+    L = lbm.lib()
+    plain = L.lbm_meta_bytes(ctypes.byref(_cfg()))
+    c = _cfg(coupling=True)
+    assert L.lbm_meta_bytes(ctypes.byref(c)) >= plain + 601 * 4 * 512 * 4  # fields of every slot
+    c.coupling = 2
+    assert L.lbm_meta_bytes(ctypes.byref(c)) == 0
+    h = ctypes.c_void_p()
+    assert L.lbm_create(ctypes.byref(c), None, None, 0, ctypes.byref(h)) == -1
+    assert "coupling" in L.lbm_last_error(None).decode()
+
+
 def test_missing_buffers_rejected():
     L = lbm.lib()
     c = _cfg()
@@ -95,6 +107,7 @@ def test_null_context_calls_fail_cleanly():
     out = ctypes.c_int64()
     assert L.lbm_num_blocks(None, 0, ctypes.byref(out)) == -1
     assert L.lbm_set_option(None, 0, 16384) == -1
+    assert L.lbm_set_coupling(None, None, None, 0) == -1
 
 
 def test_null_context_state_and_adjoint_calls_fail_cleanly():

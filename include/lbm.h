@@ -82,6 +82,7 @@ typedef struct {
   float inflow_beta;       /* LOG: shear coefficient, >= 0, per fine node */
   float inflow_h0;         /* LOG: height of the profile's zero, fine nodes */
   int32_t coupling;        /* 1: the finest level carries coupling fields (lbm_set_coupling); 0: none */
+  int32_t scalar;          /* 1: the finest level carries the powder-snow volume fraction (lbm_scalar_*) */
 } lbm_config;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -138,6 +139,29 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
  * the finest level always runs one stream-collide per substep, and the adjoint entry
  * points return LBM_EINVAL. */
 lbm_status lbm_set_coupling(lbm_ctx* ctx, const int64_t* keys, const float* fields, int64_t nb);
+
+/* Powder-snow volume fraction phi on the finest level (Sec. 7, powder snow), with
+ * cfg.scalar = 1 (LBM_EINVAL otherwise): dphi/dt + u . grad phi = q + D lap phi.
+ * lbm_scalar_advance takes one step of dt finest-level time steps: semi-Lagrangian
+ * advection through the finest level's current velocity (departure point by Ralston's
+ * third-order Runge-Kutta, trilinear interpolation of u and phi), then one forward-
+ * Euler step of the 7-point Laplacian, then dt q. phi lives on the finest level's
+ * owned nodes: nodes outside its blocks, its ghost nodes, nodes beyond walls and
+ * solid nodes count as phi = 0, u = 0 (and stay at phi = 0); a departure point
+ * is kept within 7 nodes of its node per axis (|u| dt below 7 is the accurate range).
+ * source: device f32 [nb][512] in the key order of the finest level's blocks (as
+ * lbm_scalar_get returns them), or NULL. LBM_EINVAL unless dt > 0, D >= 0 and
+ * D dt <= 1/6. Async.
+ * lbm_scalar_set: phi of the listed finest-level blocks (device keys [nb], values
+ * [nb][512]); solid and ghost nodes are set to 0. LBM_EINVAL for a key that is not an active
+ * finest-level block (blocks listed before it may have been written). Synchronises.
+ * lbm_scalar_get: keys and phi of every finest-level block, key order (keys_out
+ * [nb], phi_out [nb][512], nb = lbm_num_blocks(ctx, 0)). Async.
+ * Blocks keep phi through grid updates; blocks created by one start at 0; phi of a
+ * block that leaves the finest level is dropped. */
+lbm_status lbm_scalar_set(lbm_ctx* ctx, const int64_t* keys, const float* phi, int64_t nb);
+lbm_status lbm_scalar_get(lbm_ctx* ctx, int64_t* keys_out, float* phi_out);
+lbm_status lbm_scalar_advance(lbm_ctx* ctx, float dt, float D, const float* source);
 
 /* Moves particles by d (fine units) in f32: p[i] = p[i] + d, as a prescribed
  * stand-in for the granular solver. particles: device float [n][3]. */

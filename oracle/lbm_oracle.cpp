@@ -31,6 +31,11 @@
 //     step M_b(t+1) = (M_b(t) + lam M_h(t+1)) / (1 + lam), lam = max(u_n, 0); and
 //     the logarithmic inflow profile u(h) = u0 ln(1 + beta (h - h0)) over the
 //     height h above h0 (zero at or below h0).
+//   * Sec. 7 (powder snow): the volume fraction phi carried by the fluid velocity,
+//     diffused and fed by a source (semi-Lagrangian RK3 advection, forward-Euler
+//     diffusion), on the finest level.
+//   * Sec. 4: the fluid fraction eps scaling tau and an external force density on
+//     the finest level (Guo's forcing in moment form), the coupling hook.
 // Bounce-back, periodic wrap, uniform inflow and zero-gradient outflow are not in
 // the paper; they are the halfway bounce-back and equilibrium/copy conditions of
 // the standard LBM literature.
@@ -245,6 +250,8 @@ template <class T> struct Blk {
   // finest level only: coupling fields [4][512] (fluid fraction eps, force density
   // F), empty for eps = 1, F = 0
   std::vector<double> cpl;
+  // finest level only: the powder-snow volume fraction phi [512], empty for 0
+  std::vector<double> phi;
 };
 
 template <class T> struct Sim {
@@ -761,6 +768,99 @@ template <class T> struct Sim {
     }
   }
 
+  // --- powder-snow volume fraction phi on the finest level (Sec. 7, powder snow):
+  //     dphi/dt + u . grad phi = q + D lap phi, advected semi-Lagrangian with an RK3
+  //     backtrace, then diffused with one forward-Euler step, then the source added.
+  //     phi lives on the finest level's owned nodes: values outside its blocks, at its
+  //     ghost nodes (the coarser level's region), beyond walls and at solid nodes are
+  //     0, velocities there 0; periodic axes wrap.
+  static bool off_scalar(uint8_t r) { return r == R_SOLID || r == R_GHOST; }
+  double phi_node(const int g0[3]) {
+    int g[3] = {g0[0], g0[1], g0[2]};
+    if (!wrap_node(0, g)) return 0.0;
+    int node;
+    Blk<T>* B = locate(0, g, node);
+    if (!B || B->phi.empty() || off_scalar(B->role[node])) return 0.0;
+    return B->phi[node];
+  }
+  void u_node(const int g0[3], double u[3]) {
+    int g[3] = {g0[0], g0[1], g0[2]};
+    u[0] = u[1] = u[2] = 0.0;
+    if (!wrap_node(0, g)) return;
+    int node;
+    Blk<T>* B = locate(0, g, node);
+    if (!B || off_scalar(B->role[node])) return;
+    for (int a = 0; a < 3; ++a) u[a] = re(B->cur[node].v[1 + a]);
+  }
+  // trilinear interpolation at a point x (finest-level node units)
+  template <class F> void trilinear(const double x[3], int ncomp, F value, double* out) {
+    int i0[3];
+    double w[3];
+    for (int a = 0; a < 3; ++a) {
+      const double f = std::floor(x[a]);
+      i0[a] = int(f);
+      w[a] = x[a] - f;
+    }
+    for (int c = 0; c < ncomp; ++c) out[c] = 0.0;
+    for (int dz = 0; dz < 2; ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const double wt = (dx ? w[0] : 1.0 - w[0]) * (dy ? w[1] : 1.0 - w[1]) * (dz ? w[2] : 1.0 - w[2]);
+          const int g[3] = {i0[0] + dx, i0[1] + dy, i0[2] + dz};
+          double v[3];
+          value(g, v);
+          for (int c = 0; c < ncomp; ++c) out[c] += wt * v[c];
+        }
+  }
+  void scalar_advance(double dt, double D, const double* source /* [nb][512] key order or null */) {
+    std::vector<Blk<T>*> blocks;
+    for (auto& kv : lv[0]) blocks.push_back(&kv.second);
+    auto uval = [&](const int g[3], double* v) { u_node(g, v); };
+    auto pval = [&](const int g[3], double* v) { v[0] = phi_node(g); };
+    // semi-Lagrangian advection: departure point by Ralston's RK3 backwards in time
+    std::vector<std::vector<double>> adv(blocks.size(), std::vector<double>(kNodes, 0.0));
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < long(blocks.size()); ++k) {
+      Blk<T>* B = blocks[k];
+      for (int n = 0; n < kNodes; ++n) {
+        if (off_scalar(B->role[n])) continue;
+        int g[3];
+        node_coords(B->b, n, g);
+        const double x[3] = {double(g[0]), double(g[1]), double(g[2])};
+        double k1[3], k2[3], k3[3], y[3];
+        trilinear(x, 3, uval, k1);
+        for (int a = 0; a < 3; ++a) y[a] = x[a] - 0.5 * dt * k1[a];
+        trilinear(y, 3, uval, k2);
+        for (int a = 0; a < 3; ++a) y[a] = x[a] - 0.75 * dt * k2[a];
+        trilinear(y, 3, uval, k3);
+        for (int a = 0; a < 3; ++a) y[a] = x[a] - dt * (2.0 * k1[a] + 3.0 * k2[a] + 4.0 * k3[a]) / 9.0;
+        trilinear(y, 1, pval, &adv[k][n]);
+      }
+    }
+    for (size_t k = 0; k < blocks.size(); ++k) blocks[k]->phi = adv[k];
+    // forward-Euler diffusion (7-point Laplacian) and the source
+    std::vector<std::vector<double>> out(blocks.size(), std::vector<double>(kNodes, 0.0));
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < long(blocks.size()); ++k) {
+      Blk<T>* B = blocks[k];
+      for (int n = 0; n < kNodes; ++n) {
+        if (off_scalar(B->role[n])) continue;
+        int g[3];
+        node_coords(B->b, n, g);
+        const double c = B->phi[n];
+        double lap = 0.0;
+        for (int a = 0; a < 3; ++a)
+          for (int sgn = -1; sgn <= 1; sgn += 2) {
+            int h[3] = {g[0], g[1], g[2]};
+            h[a] += sgn;
+            lap += phi_node(h) - c;
+          }
+        out[k][n] = c + D * dt * lap + (source ? dt * source[k * kNodes + n] : 0.0);
+      }
+    }
+    for (size_t k = 0; k < blocks.size(); ++k) blocks[k]->phi = out[k];
+  }
+
   // Alg. 1
   void advance(int l, int s) {
     if (l < L - 1) downward(l, s);
@@ -846,8 +946,12 @@ template <class T> struct Sim {
         Blk<T>* B = work[l][k];
         Blk<T>* O = find_block(l, B->b);
         B->cur.assign(kNodes, rest_state());
-        // coupling fields stay with blocks that remain; new blocks start at eps = 1, F = 0
-        if (O) B->cpl = O->cpl;
+        // coupling fields and phi stay with blocks that remain; new blocks start at
+        // eps = 1, F = 0, phi = 0
+        if (O) {
+          B->cpl = O->cpl;
+          B->phi = O->phi;
+        }
         for (int n = 0; n < kNodes; ++n) {
           uint8_t r = B->role[n];
           bool fresh = (O == nullptr) || (!owned(O->role[n]) && owned(r));
@@ -971,6 +1075,30 @@ int oc_set_block_moments(void* h, int level, const int64_t* keys, const double* 
     }
   }
   return 0;
+}
+// powder-snow volume fraction of the finest level: set per block, get all (key order),
+// advance by dt finest-level steps with diffusivity D and a source [nb][512] (or null)
+int oc_scalar_set(void* h, const int64_t* keys, const double* in, int64_t nb) {
+  auto* s = static_cast<OSim*>(h);
+  for (int64_t k = 0; k < nb; ++k) {
+    auto it = s->lv[0].find(uint64_t(keys[k]));
+    if (it == s->lv[0].end()) { g_err = "scalar_set: unknown finest-level block"; return -1; }
+    it->second.phi.assign(in + size_t(k) * kNodes, in + size_t(k + 1) * kNodes);
+    for (int n = 0; n < kNodes; ++n)
+      if (it->second.role[n] == R_SOLID || it->second.role[n] == R_GHOST) it->second.phi[n] = 0.0;
+  }
+  return 0;
+}
+void oc_scalar_get(void* h, double* out) {
+  auto* s = static_cast<OSim*>(h);
+  size_t k = 0;
+  for (auto& kv : s->lv[0]) {
+    for (int n = 0; n < kNodes; ++n) out[k * kNodes + n] = kv.second.phi.empty() ? 0.0 : kv.second.phi[n];
+    ++k;
+  }
+}
+void oc_scalar_advance(void* h, double dt, double D, const double* source) {
+  static_cast<OSim*>(h)->scalar_advance(dt, D, source);
 }
 // finest-level coupling fields of the given blocks: in [nb][4][512] (eps, Fx, Fy, Fz)
 int oc_set_coupling(void* h, const int64_t* keys, const double* in, int64_t nb) {

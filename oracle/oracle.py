@@ -73,6 +73,10 @@ def lib():
         L.oc_get_block_moments.argtypes = [vp, i32, vp, vp]
         L.oc_set_coupling.restype = i32
         L.oc_set_coupling.argtypes = [vp, vp, vp, i64]
+        L.oc_scalar_set.restype = i32
+        L.oc_scalar_set.argtypes = [vp, vp, vp, i64]
+        L.oc_scalar_get.argtypes = [vp, vp]
+        L.oc_scalar_advance.argtypes = [vp, ctypes.c_double, ctypes.c_double, vp]
         L.oc_get_roles.argtypes = [vp, i32, vp]
         L.oc_step.restype = i32
         L.oc_step.argtypes = [vp, i32]
@@ -142,6 +146,24 @@ class OracleSim:
                 self.h = None
         except Exception:
             pass
+
+    def scalar_set(self, keys, phi):
+        """Powder-snow volume fraction of finest-level blocks `keys`: phi [nb, 512]."""
+        keys = np.ascontiguousarray(keys, dtype=np.int64)
+        f = np.ascontiguousarray(phi, dtype=np.float64)
+        assert f.shape == (len(keys), 512)
+        if lib().oc_scalar_set(self.h, _ptr(keys), _ptr(f), len(keys)) != 0:
+            raise ValueError(lib().oc_last_error().decode())
+
+    def scalar_get(self):
+        """phi of every finest-level block, [nb, 512] in key order."""
+        out = np.empty((self.num_blocks(0), 512))
+        lib().oc_scalar_get(self.h, _ptr(out))
+        return out
+
+    def scalar_advance(self, dt, D, source=None):
+        src = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
+        lib().oc_scalar_advance(self.h, float(dt), float(D), _ptr(src))
 
     def set_coupling(self, keys, fields):
         """Finest-level coupling fields of blocks `keys`: fields [nb, 4, 512] = (eps, Fx, Fy, Fz),

@@ -10,7 +10,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "liblbmx.so")
 
-SOURCES = ["stream_collide.hip", "adjoint.hip", "transfer.hip", "hierarchy.hip", "io.hip", "runtime.cpp"]
+SOURCES = ["stream_collide.hip", "adjoint.hip", "transfer.hip", "hierarchy.hip", "io.hip", "scalar.hip",
+           "runtime.cpp"]
 ARCH = os.environ.get("LBMX_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions stay off: some of their forms are unreliable on this part

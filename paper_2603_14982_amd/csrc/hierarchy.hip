@@ -483,6 +483,10 @@ __global__ __launch_bounds__(256) void k_init(InitLaunch a) {
     float* c = a.cpl + (size_t)slot * 4 * kNodes;
     for (int i = threadIdx.x; i < 4 * kNodes; i += 256) c[i] = i < kNodes ? 1.0f : 0.0f;
   }
+  if (a.phi && new_block) {
+    // and with no powder snow
+    for (int i = threadIdx.x; i < kNodes; i += 256) a.phi[(size_t)slot * kNodes + i] = 0.0f;
+  }
   for (int node = threadIdx.x; node < kNodes; node += 256) {
     const uint8_t rn = a.role_new[(size_t)slot * kNodes + node] & ROLE_MASK;
     bool fresh = new_block;

@@ -152,8 +152,29 @@ struct InitLaunch {
   Scales sc;
   int storage;
   float* cpl;                // finest level with coupling fields: reset for new blocks; else null
+  float* phi;                // finest level with a powder-snow field: zero for new blocks; else null
 };
 hipError_t launch_init(const InitLaunch& a, hipStream_t s);
+
+// ---- powder-snow volume fraction on the finest level ----
+struct ScalarLaunch {
+  const int32_t* blocks;     // the finest level's blocks (key order)
+  int32_t nblocks;
+  const int32_t* nbr;        // [slot][27] neighbour slots (< 0: none / wall)
+  const uint8_t* role;       // [slot][512]
+  const void* moments;       // the finest level's current time level (velocity)
+  Scales sc;
+  int storage;
+  const float* phi_in;       // [slot][512]
+  float* phi_out;            // [slot][512]
+  const float* source;       // [list index][512] or null (diffusion step only)
+  float dt, D;
+};
+hipError_t launch_scalar_advect(const ScalarLaunch& a, hipStream_t s);
+hipError_t launch_scalar_diffuse(const ScalarLaunch& a, hipStream_t s);
+hipError_t launch_scalar_set(const LevelGeom& g, const int64_t* keys, const float* in, int64_t nb, const int32_t* dir,
+                             const uint8_t* role, float* phi, int32_t* err, hipStream_t s);
+hipError_t launch_scalar_get(const int32_t* blocks, int32_t nblocks, const float* phi, float* out, hipStream_t s);
 
 // ---- data movement and reductions ----
 struct IoLaunch {

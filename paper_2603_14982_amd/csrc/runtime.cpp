@@ -22,7 +22,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   size_t t0, t0s, t0p, flags, st[2], dir[2], lists, wave, counts, coord, nbr, role[2], summary, gbox, free_stack, blocks,
-      gblocks, iblocks, oblocks, tblocks, red_partial, red_out, flag, cpl;
+      gblocks, iblocks, oblocks, tblocks, red_partial, red_out, flag, cpl, phi;
   size_t total;
   int64_t level_list_off[kMaxLevels];  // offset (elements) of each level's segment in blocks / g/i/o lists
   int64_t level_list_cap[kMaxLevels];
@@ -73,6 +73,7 @@ bool make_geom(const lbm_config* c, Geom& G, std::string& err) {
   if (c->storage < LBM_F32 || c->storage > LBM_F16) { err = "unknown storage format"; return false; }
   if (c->rescale != 0 && c->rescale != 1) { err = "rescale must be 0 or 1"; return false; }
   if (c->coupling != 0 && c->coupling != 1) { err = "coupling must be 0 or 1"; return false; }
+  if (c->scalar != 0 && c->scalar != 1) { err = "scalar must be 0 or 1"; return false; }
   if (c->max_blocks < 1 || c->max_blocks > (int64_t(1) << 26)) { err = "max_blocks must be in 1..2^26"; return false; }
   if (c->storage != LBM_F32)
     for (int m = 0; m < kMom; ++m)
@@ -142,6 +143,8 @@ Layout make_layout(const lbm_config* c, const Geom& G) {
   L.flag = take(64);
   // finest-level coupling fields (eps, F) per slot and for the all-zero slot
   L.cpl = c->coupling ? take((size_t)(cap + 1) * 4 * kNodes * sizeof(float)) : 0;
+  // finest-level powder-snow volume fraction, current and intermediate field per slot
+  L.phi = c->scalar ? take((size_t)2 * cap * kNodes * sizeof(float)) : 0;
   L.total = o;
   return L;
 }
@@ -209,6 +212,8 @@ struct lbm_ctx {
   int32_t* tblocks(int l) const { return m<int32_t>(lay.tblocks) + lay.level_list_off[l]; }
   // finest-level coupling fields [slot][4][512] (eps, F), null without coupling
   float* cpl() const { return cfg.coupling ? m<float>(lay.cpl) : nullptr; }
+  // finest-level powder-snow volume fraction [k][slot][512], k = 0 current, 1 intermediate
+  float* phi(int k) const { return cfg.scalar ? m<float>(lay.phi) + (size_t)k * cap * kNodes : nullptr; }
   // time level p of the pool: cap block slots plus one all-zero slot (index cap)
   void* buf(int l, int p) const { return pool + (size_t)p * (size_t)(cap + 1) * kBlockStride * elem; }
   void* cur(int l) const { return buf(l, parity[l]); }
@@ -410,6 +415,7 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     a.sc = c->sc;
     a.storage = c->cfg.storage;
     a.cpl = l == 0 ? c->cpl() : nullptr;
+    a.phi = l == 0 ? c->phi(0) : nullptr;
     HIPCHK(c, launch_init(a, s));
   }
   c->hier = nh;
@@ -833,6 +839,7 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
         "zero slot");
   chk(launch_fill_i32(c->dir(0), NBR_NONE, ncell, c->stream), "clear directory");
   if (c->cpl()) chk(launch_cpl_default(c->cpl(), c->cap + 1, c->stream), "coupling fields");
+  if (c->phi(0)) chk(launch_fill_i32(reinterpret_cast<int32_t*>(c->phi(0)), 0, 2 * c->cap * kNodes, c->stream), "phi");
   std::vector<int32_t> fs((size_t)c->cap);
   for (int64_t i = 0; i < c->cap; ++i) fs[(size_t)i] = (int32_t)(c->cap - 1 - i);
   chk(hipMemcpyAsync(c->m<int32_t>(c->lay.free_stack), fs.data(), fs.size() * 4, hipMemcpyHostToDevice, c->stream),
@@ -905,6 +912,57 @@ lbm_status lbm_set_coupling(lbm_ctx* ctx, const int64_t* keys, const float* fiel
   if (ctx->host_counts[0] == 2) return ctx->fail(LBM_EINVAL, "coupling fields must be finite with eps tau0 > 1/2");
   HIPCHK(ctx, launch_cpl_set(ctx->G.lv[0], keys, fields, nb, ctx->dir(ctx->hier), ctx->role(ctx->rcur), ctx->cpl(),
                              ctx->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_scalar_set(lbm_ctx* ctx, const int64_t* keys, const float* phi, int64_t nb) {
+  if (!ctx) return LBM_EINVAL;
+  if (!ctx->cfg.scalar) return ctx->fail(LBM_EINVAL, "the powder-snow field is not enabled in the configuration");
+  if (nb < 0 || (nb > 0 && (!keys || !phi))) return ctx->fail(LBM_EINVAL, "bad block arrays");
+  if (nb == 0) return LBM_OK;
+  int32_t* flag = ctx->m<int32_t>(ctx->lay.flag);
+  HIPCHK(ctx, launch_fill_i32(flag, 0, 1, ctx->stream));
+  HIPCHK(ctx, launch_scalar_set(ctx->G.lv[0], keys, phi, nb, ctx->dir(ctx->hier), ctx->role(ctx->rcur), ctx->phi(0), flag,
+                                ctx->stream));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, flag, 4, hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->host_counts[0]) return ctx->fail(LBM_EINVAL, "a key is not an active finest-level block");
+  return LBM_OK;
+}
+
+lbm_status lbm_scalar_get(lbm_ctx* ctx, int64_t* keys_out, float* phi_out) {
+  if (!ctx) return LBM_EINVAL;
+  if (!ctx->cfg.scalar) return ctx->fail(LBM_EINVAL, "the powder-snow field is not enabled in the configuration");
+  if (ctx->nblk[0] > 0 && (!keys_out || !phi_out)) return ctx->fail(LBM_EINVAL, "null output");
+  HIPCHK(ctx, launch_keys(io_of(ctx, 0), keys_out, ctx->stream));
+  HIPCHK(ctx, launch_scalar_get(ctx->blocks(0), (int32_t)ctx->nblk[0], ctx->phi(0), phi_out, ctx->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_scalar_advance(lbm_ctx* ctx, float dt, float D, const float* source) {
+  if (!ctx) return LBM_EINVAL;
+  if (!ctx->cfg.scalar) return ctx->fail(LBM_EINVAL, "the powder-snow field is not enabled in the configuration");
+  if (!(dt > 0.0f) || !std::isfinite(dt) || !(D >= 0.0f) || !std::isfinite(D))
+    return ctx->fail(LBM_EINVAL, "dt must be positive and D non-negative");
+  if (D * dt > 1.0f / 6.0f) return ctx->fail(LBM_EINVAL, "forward-Euler diffusion needs D dt <= 1/6");
+  ScalarLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  a.blocks = ctx->blocks(0);
+  a.nblocks = (int32_t)ctx->nblk[0];
+  a.nbr = ctx->m<int32_t>(ctx->lay.nbr);
+  a.role = ctx->role(ctx->rcur);
+  a.moments = ctx->cur(0);
+  a.sc = ctx->sc;
+  a.storage = ctx->cfg.storage;
+  a.dt = dt;
+  a.D = D;
+  a.phi_in = ctx->phi(0);
+  a.phi_out = ctx->phi(1);
+  HIPCHK(ctx, launch_scalar_advect(a, ctx->stream));
+  a.phi_in = ctx->phi(1);
+  a.phi_out = ctx->phi(0);
+  a.source = source;
+  HIPCHK(ctx, launch_scalar_diffuse(a, ctx->stream));
   return LBM_OK;
 }
 

@@ -48,6 +48,7 @@ class LBMConfig(ctypes.Structure):
         ("inflow_beta", ctypes.c_float),
         ("inflow_h0", ctypes.c_float),
         ("coupling", ctypes.c_int32),
+        ("scalar", ctypes.c_int32),
     ]
 
 
@@ -56,7 +57,8 @@ EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm
            "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
            "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
            "lbm_step_record", "lbm_adjoint_reverse",
-           "lbm_loss_ke_grad", "lbm_set_option", "lbm_set_coupling", "lbm_last_error"]
+           "lbm_loss_ke_grad", "lbm_set_option", "lbm_set_coupling",
+           "lbm_scalar_set", "lbm_scalar_get", "lbm_scalar_advance", "lbm_last_error"]
 _SIZE_QUERIES = ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_state_bytes", "lbm_adjoint_work_bytes", "lbm_last_error")
 PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh", "sc_pair"]
 OPTIONS = {"tile_min_blocks": 0, "fuse_substeps": 1}
@@ -104,6 +106,9 @@ def lib():
         L.lbm_loss_ke_grad.argtypes = [vp, i32, vp, vp, vp]
         L.lbm_set_option.argtypes = [vp, i32, i64]
         L.lbm_set_coupling.argtypes = [vp, vp, vp, i64]
+        L.lbm_scalar_set.argtypes = [vp, vp, vp, i64]
+        L.lbm_scalar_get.argtypes = [vp, vp, vp]
+        L.lbm_scalar_advance.argtypes = [vp, ctypes.c_float, ctypes.c_float, vp]
         L.lbm_last_error.restype = ctypes.c_char_p
         L.lbm_last_error.argtypes = [vp]
         for name in EXPORTS:
@@ -114,11 +119,12 @@ def lib():
 
 
 def make_config(levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), storage="f32", scale=None, rescale="ce",
-                max_blocks=1, log_inflow=None, coupling=False):
+                max_blocks=1, log_inflow=None, coupling=False, scalar=False):
     """log_inflow = (axis, beta, h0): inflow velocity uin * ln(1 + beta (h - h0)) at
     height h (fine nodes) along axis, zero at or below h0; None: uniform uin."""
     c = LBMConfig()
     c.coupling = 1 if coupling else 0
+    c.scalar = 1 if scalar else 0
     if log_inflow is not None:
         c.inflow_profile = 1
         c.inflow_axis = int(log_inflow[0])
@@ -148,7 +154,8 @@ class Sim:
     """One block-adaptive simulation on a GPU; buffers are torch tensors."""
 
     def __init__(self, levels, n, bc, tau0, uin=(0.0, 0.0, 0.0), storage="f32", scale=None, rescale="ce",
-                 max_blocks=None, solid=None, particles=None, device="cuda", log_inflow=None, coupling=False):
+                 max_blocks=None, solid=None, particles=None, device="cuda", log_inflow=None, coupling=False,
+                 scalar=False):
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -157,7 +164,8 @@ class Sim:
         if max_blocks is None:
             max_blocks = sum((n[0] >> l) // 8 * ((n[1] >> l) // 8) * ((n[2] >> l) // 8) for l in range(levels))
             max_blocks = min(max_blocks, 1 << 16)
-        self.cfg = make_config(levels, n, bc, tau0, uin, storage, scale, rescale, max_blocks, log_inflow, coupling)
+        self.cfg = make_config(levels, n, bc, tau0, uin, storage, scale, rescale, max_blocks, log_inflow, coupling,
+                               scalar)
         L = lib()
         pool_bytes = L.lbm_pool_bytes(ctypes.byref(self.cfg))
         meta_bytes = L.lbm_meta_bytes(ctypes.byref(self.cfg))
@@ -264,6 +272,27 @@ class Sim:
         if tuple(f.shape) != (k.numel(), 4, 512):
             raise ValueError("fields must be [nb, 4, 512]")
         self._check(lib().lbm_set_coupling(self.h, _dptr(k), _dptr(f), k.numel()))
+
+    def scalar_set(self, keys, phi):
+        """Powder-snow volume fraction of finest-level blocks (needs scalar=True): phi [nb, 512]."""
+        k = torch.as_tensor(np.asarray(keys, dtype=np.int64) if not torch.is_tensor(keys) else keys,
+                            dtype=torch.int64, device=self.device).contiguous()
+        f = torch.as_tensor(phi, dtype=torch.float32, device=self.device).contiguous()
+        if tuple(f.shape) != (k.numel(), 512):
+            raise ValueError("phi must be [nb, 512]")
+        self._check(lib().lbm_scalar_set(self.h, _dptr(k), _dptr(f), k.numel()))
+
+    def scalar_get(self):
+        """(keys [nb], phi [nb, 512]) of every finest-level block, key order."""
+        nb = self.num_blocks(0)
+        keys = torch.empty(nb, dtype=torch.int64, device=self.device)
+        phi = torch.empty((nb, 512), dtype=torch.float32, device=self.device)
+        self._check(lib().lbm_scalar_get(self.h, _dptr(keys), _dptr(phi)))
+        return keys, phi
+
+    def scalar_advance(self, dt, D, source=None):
+        src = None if source is None else torch.as_tensor(source, dtype=torch.float32, device=self.device).contiguous()
+        self._check(lib().lbm_scalar_advance(self.h, float(dt), float(D), _dptr(src)))
 
     def set_option(self, name, value):
         """Execution options: "tile_min_blocks" (blocks a level needs for the tiled

@@ -108,6 +108,9 @@ def test_null_context_calls_fail_cleanly():
     assert L.lbm_num_blocks(None, 0, ctypes.byref(out)) == -1
     assert L.lbm_set_option(None, 0, 16384) == -1
     assert L.lbm_set_coupling(None, None, None, 0) == -1
+    assert L.lbm_scalar_advance(None, 1.0, 0.0, None) == -1
+    assert L.lbm_scalar_set(None, None, None, 0) == -1
+    assert L.lbm_scalar_get(None, None, None) == -1
 
 
 def test_null_context_state_and_adjoint_calls_fail_cleanly():

@@ -30,6 +30,7 @@ METRIC = "MLUPS + achieved HBM GB/s per LBM step; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 80.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_slab512_traffic.json")
+VALU_CUS, VALU_CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 
 
 def sc_source_hash():
@@ -218,11 +219,18 @@ def main():
     alg_bytes = BYTES_PER_UPDATE * launch_updates
     achieved = alg_bytes / sc_avg_s / 1e9
     traffic = None
+    valu = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if tr.get("kernel_src_sha") == sc_source_hash() and tr.get("kernel") == kernel:
             traffic = tr.get("hbm_bytes_per_launch")
+            insts = tr.get("valu_wave_instructions_per_launch")
+            if insts:
+                # issue rate: one wave64 FP32 instruction per cycle per CU (4 SIMDs of 16 lanes)
+                valu = {"wave_instructions_per_launch": insts,
+                        "lane_instructions_per_update": round(insts * 64 / launch_updates, 1),
+                        "issue_frac": round(insts / (VALU_CUS * VALU_CLOCK_HZ * sc_avg_s), 4)}
     all_ms = sum(prof[f"sc{l}"][0] for l in range(sim.levels)) + prof["sc_pair"][0]
     all_n = sum(prof[f"sc{l}"][1] for l in range(sim.levels)) + prof["sc_pair"][1]
     sc_updates = sum(per_level[l] * (1 << (sim.levels - 1 - l)) for l in range(sim.levels)) * args.steps
@@ -258,6 +266,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "valu": valu,
             "kernel": kernel,
             "algorithmic_bytes_per_launch": int(alg_bytes),
             "avg_launch_ms": round(sc_avg_s * 1e3, 5),

@@ -188,6 +188,37 @@ def test_moving_slab_with_grid_updates(levels):
     compare(gpu, ora, label=f"slab L={levels} final")
 
 
+@pytest.mark.parametrize("n,tile_min", [((512, 512, 512), None), ((512, 512, 512), 0), ((128, 128, 128), None)])
+def test_five_levels(n, tile_min):
+    # the deepest hierarchy (16 finest-level substeps per coarse step): at 512^3 every
+    # level holds blocks; at 128^3 the two coarsest levels are empty while the finer
+    # ones step; tiles forced on every level in one case (the finest level's two
+    # substeps then run as one sweep); a grid update after the first coarse step
+    lbm = _lbm()
+    c = n[0] / 2
+    p = W.slab_particles(300, 11, (c - 8.0, c - 8.0, c - 8.0), (c + 8.0, c + 8.0, c + 8.0))
+    u0 = W.smooth_random_velocity(n, 14, kmax=3.0, rms=0.03)
+    gpu, ora = setup_pair(5, n, (P,) * 6, 0.6, lambda l, k: W.velocity_moments(l, k, u0), particles=p)
+    counts = [ora.num_blocks(l) for l in range(5)]
+    assert all(counts) if n[0] == 512 else (counts[3] == 0 and counts[4] == 0 and counts[2] > 0), counts
+    if tile_min is not None:
+        gpu.set_option("tile_min_blocks", tile_min)
+    gpu.set_profiling(True)
+    gpu.step(1)
+    ora.step(1)
+    d = np.array([8.0, -8.0, 4.0], dtype=np.float32)
+    pg = torch.as_tensor(p).cuda()
+    gpu.advance_particles(pg, d)
+    O.advance_particles(p, d)
+    gpu.remesh(pg)
+    ora.remesh(p)
+    gpu.step(1)
+    ora.step(1)
+    prof = gpu.profile()
+    assert prof["sc_pair"][1] == (16 if tile_min == 0 else 0), prof
+    compare(gpu, ora, label=f"five levels {n[0]}^3 tile_min={tile_min}")
+
+
 def test_uniform_state_through_remesh():
     n = (64, 64, 64)
     u = (0.05, 0.02, -0.01)

@@ -228,7 +228,8 @@ lbm_status lbm_set_option(lbm_ctx* ctx, int32_t option, int64_t value);
  *
  * A state is the current time level of every block of every level, in level
  * order and key order, behind a 256-byte header that names the block hierarchy
- * it belongs to. The hierarchy must not change between saving and loading.
+ * it belongs to (the coupling fields and the powder-snow field are not part of
+ * it). The hierarchy must not change between saving and loading.
  *
  * lbm_state_bytes: size of a state under the current hierarchy (0 for NULL).
  * lbm_save: writes the state to dst (device, >= lbm_state_bytes bytes); async.

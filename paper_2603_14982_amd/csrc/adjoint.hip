@@ -246,19 +246,55 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
   const int pmx[8] = {0, 1, 2, 0, 1, 2, 0, 1};
   const int pmy[8] = {0, 0, 0, 1, 1, 1, 2, 2};
 
+  // mu of a plane point, one plane ahead of its use
+  auto load_mu = [&](int r, int z, float m[kMom]) {
+    const int ox_ = px[r] < 0 ? -1 : (px[r] > 7 ? 1 : 0);
+    const int oy_ = py[r] < 0 ? -1 : (py[r] > 7 ? 1 : 0);
+    const int oz_ = z < 0 ? -1 : (z > 7 ? 1 : 0);
+    const int ns = s_src[(ox_ + 1) + 3 * (oy_ + 1) + 9 * (oz_ + 1)];
+    const float* src = a.mu + (size_t)ns * kBlockStride + (px[r] & 7) + 8 * (py[r] & 7) + 64 * (z & 7);
+#pragma unroll
+    for (int k = 0; k < kMom; ++k) m[k] = src[k * kNodes];
+  };
+  float mnxt[2][kMom];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+    if (has[r]) load_mu(r, -1, mnxt[r]);
+
   for (int z = -1; z <= 8; ++z) {
+    // ---- the output node of this plane (zo = z - 1): role, state and adjoint, loaded
+    // before the passes so that the loads overlap them
+    const int zo = z - 1;
+    const int onode = ox + 8 * oy + 64 * (zo < 0 ? 0 : zo);
+    const uint8_t orole = zo >= 0 ? a.role[(size_t)slot * kNodes + onode] : (uint8_t)ROLE_SOLID;
+    const uint8_t orm = orole & ROLE_MASK;
+    const bool oact = zo >= 0 && orm != ROLE_SOLID && orm != ROLE_INFLOW;
+    typename S::type xq[kMom];
+    float L[kMom];
+    if (oact) {
+      const typename S::type* xs = a.x + (size_t)slot * kBlockStride + onode;
+      const float* lam = a.lam_x + (size_t)slot * kBlockStride + onode;
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) {
+        xq[m] = xs[m * kNodes];
+        L[m] = lam[m * kNodes];
+      }
+    }
     // ---- mu of plane z (+ halo) -> transposed x back-map per (qy, qz) group
+    float mcur[2][kMom];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < kMom; ++k) mcur[r][k] = mnxt[r][k];
+    if (z < 8) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        if (has[r]) load_mu(r, z + 1, mnxt[r]);
+    }
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       if (!has[r]) continue;
-      const int ox_ = px[r] < 0 ? -1 : (px[r] > 7 ? 1 : 0);
-      const int oy_ = py[r] < 0 ? -1 : (py[r] > 7 ? 1 : 0);
-      const int oz_ = z < 0 ? -1 : (z > 7 ? 1 : 0);
-      const int ns = s_src[(ox_ + 1) + 3 * (oy_ + 1) + 9 * (oz_ + 1)];
-      const float* src = a.mu + (size_t)ns * kBlockStride + (px[r] & 7) + 8 * (py[r] & 7) + 64 * (z & 7);
-      float m[kMom];
-#pragma unroll
-      for (int k = 0; k < kMom; ++k) m[k] = src[k * kNodes];
+      const float* m = mcur[r];
       float P[3][6];
       back3_t(m[0], m[1], m[4], P[0][0], P[1][0], P[2][0]);  // (qy,qz) = (0,0): mu000, mu100, mu200
       back3_t(m[2], m[7], 0.0f, P[0][1], P[1][1], P[2][1]);  // (1,0): mu010, mu110
@@ -315,29 +351,19 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
     }
     __syncthreads();
     // ---- z pass: source plane zo = z - 1 takes P+ of plane z, P0 of z-1, P- of z-2
-    const int zo = z - 1;
-    if (zo >= 0) {
-      const int node = ox + 8 * oy + 64 * zo;
-      const uint8_t role = a.role[(size_t)slot * kNodes + node];
-      const uint8_t rm = role & ROLE_MASK;
-      if (rm != ROLE_SOLID && rm != ROLE_INFLOW) {
-        float nu[3][3][3];
+    if (oact) {
+      float nu[3][3][3];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) fwd3_t(cp[k], w0[k], wm2[k], nu[pmx[k]][pmy[k]][0], nu[pmx[k]][pmy[k]][1], nu[pmx[k]][pmy[k]][2]);
-        nu[2][2][0] = nu[2][2][1] = nu[2][2][2] = 0.0f;
-        if (rm == ROLE_COMPUTED && (role & ROLE_BB)) bounce_back_t<S>(a, slot, ox, oy, zo, nu);
-        const typename S::type* xs = a.x + (size_t)slot * kBlockStride + node;
-        float q[kMom];
+      for (int k = 0; k < 8; ++k) fwd3_t(cp[k], w0[k], wm2[k], nu[pmx[k]][pmy[k]][0], nu[pmx[k]][pmy[k]][1], nu[pmx[k]][pmy[k]][2]);
+      nu[2][2][0] = nu[2][2][1] = nu[2][2][2] = 0.0f;
+      if (orm == ROLE_COMPUTED && (orole & ROLE_BB)) bounce_back_t<S>(a, slot, ox, oy, zo, nu);
+      float q[kMom];
 #pragma unroll
-        for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(xs[m * kNodes], a.sc.inv[m]);
-        float* lam = a.lam_x + (size_t)slot * kBlockStride + node;
-        float L[kMom];
+      for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(xq[m], a.sc.inv[m]);
+      coeff_jacobian_t(q, a.omega, nu, L);
+      float* lam = a.lam_x + (size_t)slot * kBlockStride + onode;
 #pragma unroll
-        for (int m = 0; m < kMom; ++m) L[m] = lam[m * kNodes];
-        coeff_jacobian_t(q, a.omega, nu, L);
-#pragma unroll
-        for (int m = 0; m < kMom; ++m) lam[m * kNodes] = L[m];
-      }
+      for (int m = 0; m < kMom; ++m) lam[m * kNodes] = L[m];
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {

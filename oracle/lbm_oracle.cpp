@@ -1244,6 +1244,13 @@ int oc_num_threads() {
   return 1;
 #endif
 }
+void oc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 
 // Single-node pieces, exposed for the pinning tests.
 void oc_lattice(int32_t* c, double* w) {

@@ -89,6 +89,7 @@ def lib():
         L.oc_reconstruct.argtypes = [vp, vp]
         L.oc_collide.argtypes = [vp, ctypes.c_double, vp, vp]
         L.oc_num_threads.restype = ctypes.c_int
+        L.oc_set_num_threads.argtypes = [ctypes.c_int]
         L.oc_loss_ke.restype = ctypes.c_double
         L.oc_loss_ke.argtypes = [vp, i32, vp, vp]
         L.occ_create.restype = vp
@@ -302,6 +303,11 @@ def store_round(v, storage, scale):
 def num_threads():
     """OpenMP threads the oracle runs with."""
     return int(lib().oc_num_threads())
+
+
+def set_num_threads(n):
+    """OpenMP threads of the oracle's parallel loops."""
+    lib().oc_set_num_threads(int(n))
 
 
 def lattice():

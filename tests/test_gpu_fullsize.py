@@ -101,14 +101,14 @@ def _sphere_run(storage):
     return sim
 
 
-@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "sphere128_oracle_sample.npz")),
-                    reason="stored oracle sample not generated")
 HALF_BOUNDS = {  # relative L2 per group after 500 coarse steps (measured 2.1/4.2/9.0% and 0.13/0.29/0.85%)
     "bf16": {"rho-1": 0.03, "u": 0.06, "S": 0.12},
     "f16": {"rho-1": 0.002, "u": 0.004, "S": 0.012},
 }
 
 
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "sphere128_oracle_sample.npz")),
+                    reason="stored oracle sample not generated")
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
 def test_sphere128_half_precision_full_run(storage):
     tol_oracle = tol_f32 = HALF_BOUNDS[storage]

@@ -429,16 +429,20 @@ __device__ inline void undo_node(void* buf, const void* tape, int slot, int idx,
 }
 
 // ---- downward transfer, transposed --------------------------------------------
+// One forward launch wrote the ghosts of both fine substeps: s = 1 from coarse t
+// (src_a) into undo_dst, s = 2 from the midpoint of t and t + 2 into undo_dst2.
 // (a) one workgroup per ghost block of level l: adjoint of every ghost's moments ->
 //     adjoint of its interpolated (rho-1, u, S^neq) (the u u term needs the
-//     interpolated u), kept in LDS; ghost adjoint cleared and ghost values restored;
+//     interpolated u of its substep); ghost adjoints cleared and ghost values
+//     restored; the s = 2 part splits evenly over the two coarse time levels, so
+//     per ghost node ga = g1 + g2 / 2 goes to t and gb = g2 / 2 to t + 2 (in LDS);
 //     then the block's contribution to each of the 5^3 coarse nodes under it (the
 //     transposed trilinear weights, a fixed-order sum over <= 27 ghosts), written
-//     to the block's partial [list index][10][125].
+//     to the partials [list index][10][125] of t (scratch) and of t + 2 (scratch2).
 template <class S>
 __global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
-  __shared__ float cu[3][125];
-  __shared__ float gl[kMom][kNodes];
+  __shared__ float cu[2][3][125];
+  __shared__ float gl[2][kMom][kNodes];
   const int slot = a.blocks[blockIdx.x];
   const int4 bc = a.coord[slot];
   const int l = a.level;
@@ -454,7 +458,7 @@ __global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
       else j[ax] = j[ax] >= nc ? nc - 1 : j[ax];
     }
     const int cs = a.dir[cg.off + cell_lin(cg, j[0] >> 3, j[1] >> 3, j[2] >> 3)];
-    float u[3] = {0.0f, 0.0f, 0.0f};
+    float u[3] = {0.0f, 0.0f, 0.0f}, h[3] = {0.0f, 0.0f, 0.0f};
     if (cs >= 0) {
       const int cn = (j[0] & 7) + 8 * (j[1] & 7) + 64 * (j[2] & 7);
       const T* pa = static_cast<const T*>(a.src_a) + (size_t)cs * kBlockStride + cn;
@@ -462,92 +466,117 @@ __global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         u[k] = Codec<S>::load(pa[(1 + k) * kNodes], a.sc.inv[1 + k]);
-        if (a.midpoint) u[k] = 0.5f * (u[k] + Codec<S>::load(pb[(1 + k) * kNodes], a.sc.inv[1 + k]));
+        h[k] = 0.5f * (u[k] + Codec<S>::load(pb[(1 + k) * kNodes], a.sc.inv[1 + k]));
       }
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) cu[k][t] = u[k];
+    for (int k = 0; k < 3; ++k) {
+      cu[0][k][t] = u[k];
+      cu[1][k][t] = h[k];
+    }
   }
   __syncthreads();
-  float* lamb = a.lam_fine + (size_t)slot * kBlockStride;
-  T* dstb = static_cast<T*>(a.undo_dst) + (size_t)slot * kBlockStride;
-  const T* tapeb = static_cast<const T*>(a.undo_tape) + (size_t)blockIdx.x * kBlockStride;
+  const size_t boff = (size_t)slot * kBlockStride;
+  const size_t toff = (size_t)blockIdx.x * kBlockStride;
   for (int node = threadIdx.x; node < kNodes; node += 256) {
-    float g[kMom];
+    float ga[kMom], gb[kMom];
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) g[m] = 0.0f;
+    for (int m = 0; m < kMom; ++m) ga[m] = gb[m] = 0.0f;
     if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) == ROLE_GHOST) {
-      float L[kMom];
-      T old[kMom];
-#pragma unroll
-      for (int m = 0; m < kMom; ++m) {
-        L[m] = lamb[m * kNodes + node];
-        old[m] = tapeb[m * kNodes + node];
-      }
       const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
-      float ug[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int kx = c & 1, ky = (c >> 1) & 1, kz = c >> 2;
-        const float wx = (lc[0] & 1) ? 0.5f : (kx ? 0.0f : 1.0f);
-        const float wy = (lc[1] & 1) ? 0.5f : (ky ? 0.0f : 1.0f);
-        const float wz = (lc[2] & 1) ? 0.5f : (kz ? 0.0f : 1.0f);
-        const float w = wx * wy * wz;
-        if (w == 0.0f) continue;
-        const int t = ((lc[0] + kx) >> 1) + 5 * ((lc[1] + ky) >> 1) + 25 * ((lc[2] + kz) >> 1);
+      for (int sub = 0; sub < 2; ++sub) {
+        float* lamb = (sub ? a.lam_fine2 : a.lam_fine) + boff;
+        T* dstb = static_cast<T*>(sub ? a.undo_dst2 : a.undo_dst) + boff;
+        const T* tapeb = static_cast<const T*>(sub ? a.undo_tape2 : a.undo_tape) + toff;
+        float L[kMom];
+        T old[kMom];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) ug[k] += w * cu[k][t];
-      }
-      g[0] = L[0];
-      g[1] = L[1] + 2.0f * L[4] * ug[0] + L[7] * ug[1] + L[8] * ug[2];
-      g[2] = L[2] + 2.0f * L[5] * ug[1] + L[7] * ug[0] + L[9] * ug[2];
-      g[3] = L[3] + 2.0f * L[6] * ug[2] + L[8] * ug[0] + L[9] * ug[1];
+        for (int m = 0; m < kMom; ++m) {
+          L[m] = lamb[m * kNodes + node];
+          old[m] = tapeb[m * kNodes + node];
+        }
+        float ug[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int m = 4; m < kMom; ++m) g[m] = a.factor * L[m];
+        for (int c = 0; c < 8; ++c) {
+          const int kx = c & 1, ky = (c >> 1) & 1, kz = c >> 2;
+          const float wx = (lc[0] & 1) ? 0.5f : (kx ? 0.0f : 1.0f);
+          const float wy = (lc[1] & 1) ? 0.5f : (ky ? 0.0f : 1.0f);
+          const float wz = (lc[2] & 1) ? 0.5f : (kz ? 0.0f : 1.0f);
+          const float w = wx * wy * wz;
+          if (w == 0.0f) continue;
+          const int t = ((lc[0] + kx) >> 1) + 5 * ((lc[1] + ky) >> 1) + 25 * ((lc[2] + kz) >> 1);
 #pragma unroll
-      for (int m = 0; m < kMom; ++m) {
-        lamb[m * kNodes + node] = 0.0f;
-        dstb[m * kNodes + node] = old[m];
-      }
-    }
+          for (int k = 0; k < 3; ++k) ug[k] += w * cu[sub][k][t];
+        }
+        float g[kMom];
+        g[0] = L[0];
+        g[1] = L[1] + 2.0f * L[4] * ug[0] + L[7] * ug[1] + L[8] * ug[2];
+        g[2] = L[2] + 2.0f * L[5] * ug[1] + L[7] * ug[0] + L[9] * ug[2];
+        g[3] = L[3] + 2.0f * L[6] * ug[2] + L[8] * ug[0] + L[9] * ug[1];
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) gl[m][node] = g[m];
-  }
-  __syncthreads();
-  // footprint node t (coarse 4b + t per axis) collects fine local 2t-1, 2t, 2t+1
-  // (weights 1/2, 1, 1/2) that lie inside the block
-  float* part = a.scratch + (size_t)blockIdx.x * (kMom * 125);
-  for (int t = threadIdx.x; t < 125; t += 256) {
-    const int tt[3] = {t % 5, (t / 5) % 5, t / 25};
-    float acc[kMom];
+        for (int m = 4; m < kMom; ++m) g[m] = a.factor * L[m];
+        if (sub == 0) {
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
-    for (int dz = -1; dz <= 1; ++dz) {
-      const int z = 2 * tt[2] + dz;
-      if (z < 0 || z > 7) continue;
-      const float wz = dz ? 0.5f : 1.0f;
-      for (int dy = -1; dy <= 1; ++dy) {
-        const int y = 2 * tt[1] + dy;
-        if (y < 0 || y > 7) continue;
-        const float wy = dy ? 0.5f : 1.0f;
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int x = 2 * tt[0] + dx;
-          if (x < 0 || x > 7) continue;
-          const float w = wz * wy * (dx ? 0.5f : 1.0f);
-          const int n = x + 8 * y + 64 * z;
+          for (int m = 0; m < kMom; ++m) ga[m] = g[m];
+        } else {
 #pragma unroll
-          for (int m = 0; m < kMom; ++m) acc[m] += w * gl[m][n];
+          for (int m = 0; m < kMom; ++m) {
+            ga[m] += 0.5f * g[m];
+            gb[m] = 0.5f * g[m];
+          }
+        }
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) {
+          lamb[m * kNodes + node] = 0.0f;
+          dstb[m * kNodes + node] = old[m];
         }
       }
     }
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) part[m * 125 + t] = acc[m];
+    for (int m = 0; m < kMom; ++m) {
+      gl[0][m][node] = ga[m];
+      gl[1][m][node] = gb[m];
+    }
   }
+  __syncthreads();
+  // footprint node t (coarse 4b + t per axis) collects fine local 2t-1, 2t, 2t+1
+  // (weights 1/2, 1, 1/2) that lie inside the block; threads 0..124 take the
+  // partial of t, threads 128..252 that of t + 2
+  const int tl = threadIdx.x >> 7;
+  const int t = threadIdx.x & 127;
+  if (t >= 125) return;
+  const int tt[3] = {t % 5, (t / 5) % 5, t / 25};
+  float acc[kMom];
+#pragma unroll
+  for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
+  for (int dz = -1; dz <= 1; ++dz) {
+    const int z = 2 * tt[2] + dz;
+    if (z < 0 || z > 7) continue;
+    const float wz = dz ? 0.5f : 1.0f;
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int y = 2 * tt[1] + dy;
+      if (y < 0 || y > 7) continue;
+      const float wy = dy ? 0.5f : 1.0f;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int x = 2 * tt[0] + dx;
+        if (x < 0 || x > 7) continue;
+        const float w = wz * wy * (dx ? 0.5f : 1.0f);
+        const int n = x + 8 * y + 64 * z;
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) acc[m] += w * gl[tl][m][n];
+      }
+    }
+  }
+  float* part = (tl ? a.scratch2 : a.scratch) + (size_t)blockIdx.x * (kMom * 125);
+#pragma unroll
+  for (int m = 0; m < kMom; ++m) part[m * 125 + t] = acc[m];
 }
 
-// (b) per coarse node of a flagged level-(l+1) block: sum of the partials of the
-//     <= 2 x 2 x 2 ghost blocks whose footprint holds it (fixed order), then the
-//     split over the two coarse time levels through lin = (rho-1, u, S - u u)
+// (b) per coarse node of a flagged level-(l+1) block: for each coarse time level,
+//     the sum of its partials from the <= 2 x 2 x 2 ghost blocks whose footprint
+//     holds the node (fixed order), then the Jacobian of lin = (rho-1, u, S - u u)
+//     at that time level
 template <class S>
 __global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
   const int cslot = a.blocks[blockIdx.x];
@@ -574,9 +603,9 @@ __global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
       if (!a.G.periodic[ax] && j[ax] == nc - 1) { fb[ax][k] = nbf - 1; ft[ax][k] = 4; ++k; }
       nb[ax] = k;
     }
-    float acc[kMom];
+    float acc[2][kMom];
 #pragma unroll
-    for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
+    for (int m = 0; m < kMom; ++m) acc[0][m] = acc[1][m] = 0.0f;
     bool any = false;
     for (int iz = 0; iz < nb[2]; ++iz)
       for (int iy = 0; iy < nb[1]; ++iy)
@@ -585,24 +614,23 @@ __global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
           if (fs < 0) continue;
           const int gi = a.gidx[fs];
           if (gi < 0) continue;
-          const int t = ft[0][ix] + 5 * ft[1][iy] + 25 * ft[2][iz];
-          const float* src = a.scratch + (size_t)gi * (kMom * 125) + t;
+          const size_t po = (size_t)gi * (kMom * 125) + ft[0][ix] + 5 * ft[1][iy] + 25 * ft[2][iz];
 #pragma unroll
-          for (int m = 0; m < kMom; ++m) acc[m] += src[m * 125];
+          for (int m = 0; m < kMom; ++m) {
+            acc[0][m] += a.scratch[po + m * 125];
+            acc[1][m] += a.scratch2[po + m * 125];
+          }
           any = true;
         }
     if (!any) continue;
-    // time levels: s = 1 uses coarse t only; s = 2 averages t and t + 2
-    for (int tl = 0; tl < (a.midpoint ? 2 : 1); ++tl) {
-      const float c = a.midpoint ? 0.5f : 1.0f;
+#pragma unroll
+    for (int tl = 0; tl < 2; ++tl) {
       const T* qs = static_cast<const T*>(tl == 0 ? a.src_a : a.src_b) + (size_t)cslot * kBlockStride + node;
       float* lam = (tl == 0 ? a.lam_coarse_a : a.lam_coarse_b) + (size_t)cslot * kBlockStride + node;
+      const float* g = acc[tl];
       float u[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) u[k] = Codec<S>::load(qs[(1 + k) * kNodes], a.sc.inv[1 + k]);
-      float g[kMom];
-#pragma unroll
-      for (int m = 0; m < kMom; ++m) g[m] = c * acc[m];
       const float gu0 = g[1] - (2.0f * g[4] * u[0] + g[7] * u[1] + g[8] * u[2]);
       const float gu1 = g[2] - (2.0f * g[5] * u[1] + g[7] * u[0] + g[9] * u[2]);
       const float gu2 = g[3] - (2.0f * g[6] * u[2] + g[8] * u[0] + g[9] * u[1]);

@@ -43,14 +43,14 @@ struct TransferLaunch {
   const uint8_t* role;       // [slot][512]
   const int4* coord;         // [slot] block coordinates and level
   const void* src_a;         // source time level (down: coarse t; up: fine current)
-  const void* src_b;         // down only: coarse t+2 (same as src_a for s = 1)
-  void* dst;                 // target time level
-  void* dst2;                // down only: if set, both fine substeps (s = 1 into dst, s = 2 into dst2)
+  const void* src_b;         // down only: coarse t+2
+  void* dst;                 // target time level (down: the first fine substep's ghosts)
+  void* dst2;                // down only: the second fine substep's ghosts (midpoint of src_a and src_b)
   float factor;              // S^neq rescaling factor
-  int midpoint;              // down only: 1 = average src_a and src_b
   Scales sc;
   int storage;
-  void* tape;                // adjoint replay: old values of the written nodes, [list index][10][512]
+  void* tape;                // adjoint replay: old values of the nodes written in dst, [list index][10][512]
+  void* tape2;               // down, adjoint replay: the same for dst2
   const int32_t* gbox;       // down: per slot bounding box of the ghost nodes (from the grid update)
 };
 hipError_t launch_downward(const TransferLaunch& a, hipStream_t s);
@@ -240,16 +240,19 @@ struct AdjTransferLaunch {
   const void* src_a;         // forward sources (down: coarse t and t + 2; up: fine current)
   const void* src_b;
   float factor;
-  int midpoint;
   Scales sc;
   int storage;
-  float* lam_fine;           // adjoint of the level-l time level involved
+  float* lam_fine;           // adjoint of the level-l time level involved (down: the s = 1 ghosts')
+  float* lam_fine2;          // down: adjoint of the time level holding the s = 2 ghosts
   float* lam_coarse_a;       // adjoint of the level-(l+1) time level src_a (up: the target)
   float* lam_coarse_b;       // adjoint of the level-(l+1) time level src_b
-  float* scratch;            // down: per ghost block [list index][10][125] coarse-footprint partials
+  float* scratch;            // down: per ghost block [list index][10][125] coarse-footprint partials for src_a
+  float* scratch2;           // down: the same for src_b
   const int32_t* gidx;       // down: ghost-list index per slot (-1 if not a ghost block of level l)
   void* undo_dst;            // time level the forward operation wrote (restored from undo_tape)
   const void* undo_tape;     // its old values, [list index][10][512]
+  void* undo_dst2;           // down: the time level of the s = 2 ghosts
+  const void* undo_tape2;    // down: its old values
   uint8_t* flags;            // per slot: level-(l+1) block read by a level-l ghost
 };
 // downward transfer: (a) over the ghost blocks of level l, (b) over the blocks of level l+1

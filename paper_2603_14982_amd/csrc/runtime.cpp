@@ -336,13 +336,12 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
   HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 3 * L * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   int64_t nact[kMaxLevels], nnew[kMaxLevels], nrem[kMaxLevels];
-  int64_t tot_new = 0, tot_rem = 0, tot_act = 0;
+  int64_t tot_new = 0, tot_act = 0;
   for (int l = 0; l < L; ++l) {
     nact[l] = c->host_counts[3 * l];
     nnew[l] = c->host_counts[3 * l + 1];
     nrem[l] = c->host_counts[3 * l + 2];
     tot_new += nnew[l];
-    tot_rem += nrem[l];
     tot_act += nact[l];
     if (nact[l] > c->lay.level_list_cap[l]) return c->fail(LBM_ECAPACITY, "level block count exceeds the pool capacity");
   }
@@ -548,25 +547,23 @@ TransferLaunch transfer_base(lbm_ctx* c, int l) {
 }
 
 // DownwardTransfer(l+1, s): ghosts of level l from level l+1 (old: t, current: t+2).
-// Both fine substeps read the same two coarse time levels, so outside the adjoint
-// replay the s = 2 ghosts are written together with the s = 1 ghosts, into the time
-// level the first fine stream-collide writes (it leaves ghost nodes alone); the
-// s = 2 call then has nothing left to do.
+// Both fine substeps read the same two coarse time levels, so the s = 2 ghosts are
+// written together with the s = 1 ghosts, into the time level the first fine
+// stream-collide writes (it leaves ghost nodes alone); the s = 2 call then has
+// nothing left to do. The adjoint replay keeps the old values of both ghost sets.
 lbm_status down_level(lbm_ctx* c, int l, int s) {
-  if (c->ngb[l] == 0) return LBM_OK;
-  if (s == 2 && !c->recording) return LBM_OK;
+  if (c->ngb[l] == 0 || s == 2) return LBM_OK;
   TransferLaunch t = transfer_base(c, l);
   t.blocks = c->gblocks(l);
   t.nblocks = (int32_t)c->ngb[l];
   t.src_a = c->other(l + 1);
   t.src_b = c->cur(l + 1);
-  t.midpoint = (s == 2) ? 1 : 0;
   t.dst = c->cur(l);
-  if (!c->recording) t.dst2 = c->other(l);
+  t.dst2 = c->other(l);
   t.factor = (float)c->a_down[l];
   t.gbox = c->m<int32_t>(c->lay.gbox);
   if (c->recording) {
-    lbm_status st = record(c, lbm_ctx::OP_DOWN, l, s, c->ngb[l], 0, &t.tape, nullptr);
+    lbm_status st = record(c, lbm_ctx::OP_DOWN, l, s, c->ngb[l], c->ngb[l], &t.tape, &t.tape2);
     if (st != LBM_OK) return st;
   }
   const int k = c->tic(LBM_PROF_DOWN);
@@ -648,7 +645,7 @@ size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 size_t part_bytes(const lbm_ctx* c) {
   int64_t n = 0;
   for (int l = 0; l < c->G.L; ++l) n += c->ngb[l];
-  return round256((size_t)n * kMom * 125 * sizeof(float));
+  return round256((size_t)n * 2 * kMom * 125 * sizeof(float));  // two per ghost block
 }
 size_t aux_bytes(const lbm_ctx* c) {
   return part_bytes(c) + round256((size_t)(c->cap + 1) * 4) + round256((size_t)(c->cap + 1));
@@ -722,23 +719,27 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
     HIPCHK(c, launch_sc_mu(a, s));
     HIPCHK(c, launch_sc_transpose(a, s));
   } else if (op.kind == lbm_ctx::OP_DOWN) {
+    // both substeps' ghosts: s = 1 in time level pf, s = 2 in 1 - pf
     AdjTransferLaunch t = adj_base(c, l);
     t.blocks = c->gblocks(l);
     t.nblocks = (int32_t)c->ngb[l];
     t.src_a = c->buf(l + 1, 1 - op.pc);
     t.src_b = c->buf(l + 1, op.pc);
-    t.midpoint = op.s == 2 ? 1 : 0;
     t.factor = (float)c->a_down[l];
     t.lam_fine = b.lam[op.pf];
+    t.lam_fine2 = b.lam[1 - op.pf];
     t.lam_coarse_a = b.lam[1 - op.pc];
     t.lam_coarse_b = b.lam[op.pc];
     size_t poff = 0;
-    for (int k = 0; k < l; ++k) poff += (size_t)c->ngb[k] * kMom * 125;
+    for (int k = 0; k < l; ++k) poff += (size_t)c->ngb[k] * 2 * kMom * 125;
     t.scratch = b.part + poff;
+    t.scratch2 = t.scratch + (size_t)c->ngb[l] * kMom * 125;
     t.gidx = b.gidx;
     t.flags = b.flags;
     t.undo_dst = c->buf(l, op.pf);
+    t.undo_dst2 = c->buf(l, 1 - op.pf);
     t.undo_tape = c->tape + op.off;
+    t.undo_tape2 = c->tape + op.off2;
     HIPCHK(c, launch_down_adj_lin(t, s));
     t.blocks = c->blocks(l + 1);
     t.nblocks = (int32_t)c->nblk[l + 1];

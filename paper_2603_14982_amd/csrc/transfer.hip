@@ -88,14 +88,12 @@ __device__ inline void interp_ghost(const float (*cq)[125], const int lc[3], flo
   from_neq(acc);
 }
 
-// a.dst2 == null: one substep (s = 1 from src_a, or s = 2 from the midpoint of
-// src_a and src_b, by a.midpoint) into a.dst. a.dst2 != null: both substeps of the
-// fine level at once, s = 1 into a.dst and s = 2 into a.dst2 (the time level the
-// first fine stream-collide writes; it never writes ghost nodes).
+// both substeps of the fine level at once: s = 1 (coarse t, src_a) into a.dst and
+// s = 2 (the midpoint of src_a and src_b) into a.dst2, the time level the first
+// fine stream-collide writes (it never writes ghost nodes)
 template <class S>
 __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
   __shared__ float cq[2][kMom][125];
-  const bool both = a.dst2 != nullptr;
   const int slot = a.blocks[blockIdx.x];
   const int4 bc = a.coord[slot];
   const int l = a.level;
@@ -122,19 +120,17 @@ __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
     for (int m = 0; m < kMom; ++m) q[m] = h[m] = 0.0f;
     if (cs >= 0) {
       const int cn = (j[0] & 7) + 8 * (j[1] & 7) + 64 * (j[2] & 7);
+      float r[kMom];
       Mom<S>::load(a.src_a, cs, cn, a.sc, q);
+      Mom<S>::load(a.src_b, cs, cn, a.sc, r);
       to_neq(q);
-      if (a.midpoint || both) {
-        float r[kMom];
-        Mom<S>::load(a.src_b, cs, cn, a.sc, r);
-        to_neq(r);
+      to_neq(r);
 #pragma unroll
-        for (int m = 0; m < kMom; ++m) h[m] = 0.5f * (q[m] + r[m]);
-      }
+      for (int m = 0; m < kMom; ++m) h[m] = 0.5f * (q[m] + r[m]);
     }
 #pragma unroll
     for (int m = 0; m < kMom; ++m) {
-      cq[0][m][t] = (a.midpoint && !both) ? h[m] : q[m];
+      cq[0][m][t] = q[m];
       cq[1][m][t] = h[m];
     }
   }
@@ -148,10 +144,9 @@ __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
     interp_ghost(cq[0], lc, a.factor, acc);
     if (a.tape) keep_old<S>(a.dst, a.tape, slot, blockIdx.x, node);
     Mom<S>::store(a.dst, slot, node, a.sc, acc);
-    if (both) {
-      interp_ghost(cq[1], lc, a.factor, acc);
-      Mom<S>::store(a.dst2, slot, node, a.sc, acc);
-    }
+    interp_ghost(cq[1], lc, a.factor, acc);
+    if (a.tape2) keep_old<S>(a.dst2, a.tape2, slot, blockIdx.x, node);
+    Mom<S>::store(a.dst2, slot, node, a.sc, acc);
   }
 }
 

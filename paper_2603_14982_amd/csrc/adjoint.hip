@@ -49,6 +49,7 @@ template <class S> struct TrArgs {
   const uint8_t* role;
   int32_t nblocks;
   int32_t zero_slot;
+  int32_t zsplit;             // workgroups per block, each over 8 / zsplit output planes
   float omega;
   Scales sc;
 };
@@ -222,12 +223,19 @@ __device__ __forceinline__ int xcd_remap_t(int bid, int n) {
   return x * per + (x < rem ? x : rem) + k;
 }
 
+// One workgroup per block and z range: output planes zlo .. zlo + zn - 1 take the
+// planes zlo - 1 .. zlo + zn (the window of the z pass); every output node has one
+// writer. The parts of a block go to neighbouring workgroup indices after the remap,
+// which places them on one XCD (one L2) except at the ends of an XCD's range.
 template <class S>
 __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
   __shared__ __align__(16) float lds[10 * kRowT];
   __shared__ int s_src[27];
   const int lane = threadIdx.x;
-  const int slot = a.blocks[xcd_remap_t(blockIdx.x, a.nblocks)];
+  const int item = xcd_remap_t(blockIdx.x, a.nblocks * a.zsplit);
+  const int slot = a.blocks[item / a.zsplit];
+  const int zn = 8 / a.zsplit;
+  const int zlo = (item % a.zsplit) * zn;
   if (lane < 27) {
     const int ns = a.nbr[(size_t)slot * 27 + lane];
     s_src[lane] = ns >= 0 ? ns : a.zero_slot;
@@ -259,16 +267,16 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
   float mnxt[2][kMom];
 #pragma unroll
   for (int r = 0; r < 2; ++r)
-    if (has[r]) load_mu(r, -1, mnxt[r]);
+    if (has[r]) load_mu(r, zlo - 1, mnxt[r]);
 
-  for (int z = -1; z <= 8; ++z) {
+  for (int z = zlo - 1; z <= zlo + zn; ++z) {
     // ---- the output node of this plane (zo = z - 1): role, state and adjoint, loaded
     // before the passes so that the loads overlap them
     const int zo = z - 1;
-    const int onode = ox + 8 * oy + 64 * (zo < 0 ? 0 : zo);
-    const uint8_t orole = zo >= 0 ? a.role[(size_t)slot * kNodes + onode] : (uint8_t)ROLE_SOLID;
+    const int onode = ox + 8 * oy + 64 * (zo < zlo ? zlo : zo);
+    const uint8_t orole = zo >= zlo ? a.role[(size_t)slot * kNodes + onode] : (uint8_t)ROLE_SOLID;
     const uint8_t orm = orole & ROLE_MASK;
-    const bool oact = zo >= 0 && orm != ROLE_SOLID && orm != ROLE_INFLOW;
+    const bool oact = zo >= zlo && orm != ROLE_SOLID && orm != ROLE_INFLOW;
     typename S::type xq[kMom];
     float L[kMom];
     if (oact) {
@@ -286,7 +294,7 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int k = 0; k < kMom; ++k) mcur[r][k] = mnxt[r][k];
-    if (z < 8) {
+    if (z < zlo + zn) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
         if (has[r]) load_mu(r, z + 1, mnxt[r]);
@@ -379,14 +387,14 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
 // the diagonal S): mu_m = lambda_m dY_m/dM_m, mu_0 = lambda_0 / 216 - sum_m
 // lambda_m Y_m / (216 + M0). The outputs are then restored from the tape.
 template <class S>
-__global__ __launch_bounds__(256) void k_sc_mu(AdjScLaunch a) {
+__global__ __launch_bounds__(kNodes) void k_sc_mu(AdjScLaunch a) {
   typedef typename S::type T;
   const int slot = a.blocks[blockIdx.x];
   T* y = static_cast<T*>(a.y) + (size_t)slot * kBlockStride;
   const T* tp = static_cast<const T*>(a.tape) + (size_t)blockIdx.x * kBlockStride;
   float* lam = a.lam_y + (size_t)slot * kBlockStride;
   float* mu = a.mu + (size_t)slot * kBlockStride;
-  for (int node = threadIdx.x; node < kNodes; node += 256) {
+  for (int node = threadIdx.x; node < kNodes; node += kNodes) {
     const uint8_t r = a.role[(size_t)slot * kNodes + node] & ROLE_MASK;
     float g[kMom];
 #pragma unroll
@@ -440,7 +448,7 @@ __device__ inline void undo_node(void* buf, const void* tape, int slot, int idx,
 //     transposed trilinear weights, a fixed-order sum over <= 27 ghosts), written
 //     to the partials [list index][10][125] of t (scratch) and of t + 2 (scratch2).
 template <class S>
-__global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
+__global__ __launch_bounds__(kNodes) void k_down_adj_lin(AdjTransferLaunch a) {
   __shared__ float cu[2][3][125];
   __shared__ float gl[2][kMom][kNodes];
   const int slot = a.blocks[blockIdx.x];
@@ -449,7 +457,7 @@ __global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
   const LevelGeom& cg = a.G.lv[l + 1];
   const int base[3] = {4 * bc.x, 4 * bc.y, 4 * bc.z};
   typedef typename S::type T;
-  for (int t = threadIdx.x; t < 125; t += 256) {
+  for (int t = threadIdx.x; t < 125; t += kNodes) {
     int j[3] = {base[0] + t % 5, base[1] + (t / 5) % 5, base[2] + t / 25};
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
@@ -478,7 +486,7 @@ __global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
   __syncthreads();
   const size_t boff = (size_t)slot * kBlockStride;
   const size_t toff = (size_t)blockIdx.x * kBlockStride;
-  for (int node = threadIdx.x; node < kNodes; node += 256) {
+  for (int node = threadIdx.x; node < kNodes; node += kNodes) {
     float ga[kMom], gb[kMom];
 #pragma unroll
     for (int m = 0; m < kMom; ++m) ga[m] = gb[m] = 0.0f;
@@ -543,6 +551,7 @@ __global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
   // footprint node t (coarse 4b + t per axis) collects fine local 2t-1, 2t, 2t+1
   // (weights 1/2, 1, 1/2) that lie inside the block; threads 0..124 take the
   // partial of t, threads 128..252 that of t + 2
+  if (threadIdx.x >= 256) return;
   const int tl = threadIdx.x >> 7;
   const int t = threadIdx.x & 127;
   if (t >= 125) return;
@@ -578,7 +587,7 @@ __global__ __launch_bounds__(256) void k_down_adj_lin(AdjTransferLaunch a) {
 //     holds the node (fixed order), then the Jacobian of lin = (rho-1, u, S - u u)
 //     at that time level
 template <class S>
-__global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
+__global__ __launch_bounds__(kNodes) void k_down_adj_gather(AdjTransferLaunch a) {
   const int cslot = a.blocks[blockIdx.x];
   if (!a.flags[cslot]) return;  // no ghost of level l interpolates from this block
   const int4 bc = a.coord[cslot];
@@ -586,7 +595,7 @@ __global__ __launch_bounds__(256) void k_down_adj_gather(AdjTransferLaunch a) {
   const LevelGeom& fg = a.G.lv[l];
   const LevelGeom& cg = a.G.lv[l + 1];
   typedef typename S::type T;
-  for (int node = threadIdx.x; node < kNodes; node += 256) {
+  for (int node = threadIdx.x; node < kNodes; node += kNodes) {
     const int j[3] = {bc.x * kEdge + (node & 7), bc.y * kEdge + ((node >> 3) & 7), bc.z * kEdge + (node >> 6)};
     // per axis: (fine block, footprint index) pairs whose staged coarse index is j
     int nb[3], fb[3][2], ft[3][2];
@@ -671,13 +680,13 @@ __global__ void k_mark_gather(AdjTransferLaunch a) {
 
 // ---- upward transfer, transposed ------------------------------------------------
 template <class S>
-__global__ __launch_bounds__(256) void k_up_adj(AdjTransferLaunch a) {
+__global__ __launch_bounds__(kNodes) void k_up_adj(AdjTransferLaunch a) {
   const int slot = a.blocks[blockIdx.x];
   const int4 bc = a.coord[slot];
   const LevelGeom& fg = a.G.lv[a.level];
   typedef typename S::type T;
   const float f = a.factor;
-  for (int node = threadIdx.x; node < kNodes; node += 256) {
+  for (int node = threadIdx.x; node < kNodes; node += kNodes) {
     if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_IU) continue;
     const int p[3] = {2 * (bc.x * kEdge + (node & 7)), 2 * (bc.y * kEdge + ((node >> 3) & 7)), 2 * (bc.z * kEdge + (node >> 6))};
     const int fs = a.dir[fg.off + cell_lin(fg, p[0] >> 3, p[1] >> 3, p[2] >> 3)];
@@ -866,22 +875,27 @@ __global__ void k_zero_blocks(float* buf, const int32_t* blocks, int32_t n) {
   for (int i = threadIdx.x; i < kBlockStride; i += blockDim.x) p[i] = 0.0f;
 }
 
-__global__ __launch_bounds__(256) void k_gather_blocks(const uint4* src, uint4* dst, const int32_t* blocks,
-                                                       int32_t per_block) {
+// block copies between the pool and a packed list (source and target never overlap,
+// so the loads of several iterations can be in flight together)
+__global__ __launch_bounds__(256) void k_gather_blocks(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                       const int32_t* blocks, int32_t per_block) {
   const uint4* s = src + (size_t)blocks[blockIdx.x] * per_block;
   uint4* d = dst + (size_t)blockIdx.x * per_block;
+#pragma unroll 5
   for (int i = threadIdx.x; i < per_block; i += 256) d[i] = s[i];
 }
-__global__ __launch_bounds__(256) void k_scatter_blocks(const uint4* src, uint4* dst, const int32_t* blocks,
-                                                        int32_t per_block) {
+__global__ __launch_bounds__(256) void k_scatter_blocks(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                        const int32_t* blocks, int32_t per_block) {
   const uint4* s = src + (size_t)blockIdx.x * per_block;
   uint4* d = dst + (size_t)blocks[blockIdx.x] * per_block;
+#pragma unroll 5
   for (int i = threadIdx.x; i < per_block; i += 256) d[i] = s[i];
 }
 __global__ void k_write_words(uint64_t* dst, Words8 w) {
   if (threadIdx.x < 8) dst[threadIdx.x] = w.v[threadIdx.x];
 }
 
+constexpr int64_t kTransposeWaves = 2048;
 template <class S> hipError_t tr_t(const AdjScLaunch& l, hipStream_t s) {
   if (l.nblocks <= 0) return hipSuccess;
   TrArgs<S> a;
@@ -895,17 +909,21 @@ template <class S> hipError_t tr_t(const AdjScLaunch& l, hipStream_t s) {
   a.zero_slot = l.zero_slot;
   a.omega = l.omega;
   a.sc = l.sc;
-  hipLaunchKernelGGL(k_sc_transpose<S>, dim3(l.nblocks), dim3(64), 0, s, a);
+  // split the blocks' z ranges over 2 or 4 workgroups while the level has too few
+  // blocks to give every SIMD of the chip a wave (4 per CU, 256 CUs)
+  a.zsplit = 1;
+  while (a.zsplit < 4 && (int64_t)l.nblocks * a.zsplit < kTransposeWaves) a.zsplit *= 2;
+  hipLaunchKernelGGL(k_sc_transpose<S>, dim3(l.nblocks * a.zsplit), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
-template <template <class> class K>
+template <template <class> class K, int NT>
 hipError_t dispatch_adj(const AdjTransferLaunch& a, hipStream_t s) {
   if (a.nblocks <= 0) return hipSuccess;
   switch (a.storage) {
-    case 0: hipLaunchKernelGGL(K<StoreF32>::fn, dim3(a.nblocks), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(K<StoreBF16>::fn, dim3(a.nblocks), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(K<StoreF16>::fn, dim3(a.nblocks), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL(K<StoreF32>::fn, dim3(a.nblocks), dim3(NT), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(K<StoreBF16>::fn, dim3(a.nblocks), dim3(NT), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(K<StoreF16>::fn, dim3(a.nblocks), dim3(NT), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -925,10 +943,11 @@ hipError_t launch_sc_transpose(const AdjScLaunch& l, hipStream_t s) {
   }
   return hipErrorInvalidValue;
 }
-hipError_t launch_down_adj_lin(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<DownLinK>(a, s); }
-hipError_t launch_down_adj_gather(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<DownGatherK>(a, s); }
-hipError_t launch_up_adj(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<UpAdjK>(a, s); }
-hipError_t launch_outflow_adj(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<OutflowAdjK>(a, s); }
+// one lane per node where the kernel allows it (more loads in flight on small levels)
+hipError_t launch_down_adj_lin(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<DownLinK, kNodes>(a, s); }
+hipError_t launch_down_adj_gather(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<DownGatherK, kNodes>(a, s); }
+hipError_t launch_up_adj(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<UpAdjK, kNodes>(a, s); }
+hipError_t launch_outflow_adj(const AdjTransferLaunch& a, hipStream_t s) { return dispatch_adj<OutflowAdjK, 256>(a, s); }
 hipError_t launch_ghost_index(const int32_t* blocks, int32_t n, int32_t* gidx, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_ghost_index, dim3((n + 255) / 256), dim3(256), 0, s, blocks, n, gidx);
@@ -942,9 +961,9 @@ hipError_t launch_mark_gather(const AdjTransferLaunch& a, hipStream_t s) {
 hipError_t launch_sc_mu(const AdjScLaunch& l, hipStream_t s) {
   if (l.nblocks <= 0) return hipSuccess;
   switch (l.storage) {
-    case 0: hipLaunchKernelGGL(k_sc_mu<StoreF32>, dim3(l.nblocks), dim3(256), 0, s, l); break;
-    case 1: hipLaunchKernelGGL(k_sc_mu<StoreBF16>, dim3(l.nblocks), dim3(256), 0, s, l); break;
-    case 2: hipLaunchKernelGGL(k_sc_mu<StoreF16>, dim3(l.nblocks), dim3(256), 0, s, l); break;
+    case 0: hipLaunchKernelGGL(k_sc_mu<StoreF32>, dim3(l.nblocks), dim3(kNodes), 0, s, l); break;
+    case 1: hipLaunchKernelGGL(k_sc_mu<StoreBF16>, dim3(l.nblocks), dim3(kNodes), 0, s, l); break;
+    case 2: hipLaunchKernelGGL(k_sc_mu<StoreF16>, dim3(l.nblocks), dim3(kNodes), 0, s, l); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

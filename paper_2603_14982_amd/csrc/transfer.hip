@@ -88,11 +88,13 @@ __device__ inline void interp_ghost(const float (*cq)[125], const int lc[3], flo
   from_neq(acc);
 }
 
+constexpr int kDownThreads = 256;
+
 // both substeps of the fine level at once: s = 1 (coarse t, src_a) into a.dst and
 // s = 2 (the midpoint of src_a and src_b) into a.dst2, the time level the first
 // fine stream-collide writes (it never writes ghost nodes)
 template <class S>
-__global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
+__global__ __launch_bounds__(kDownThreads) void k_downward(TransferLaunch a) {
   __shared__ float cq[2][kMom][125];
   const int slot = a.blocks[blockIdx.x];
   const int4 bc = a.coord[slot];
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
   const int hi[3] = {(box >> 3) & 7, (box >> 9) & 7, (box >> 15) & 7};
   const int clo[3] = {lo[0] >> 1, lo[1] >> 1, lo[2] >> 1};
   const int cn[3] = {((hi[0] + 1) >> 1) - clo[0] + 1, ((hi[1] + 1) >> 1) - clo[1] + 1, ((hi[2] + 1) >> 1) - clo[2] + 1};
-  for (int k = threadIdx.x; k < cn[0] * cn[1] * cn[2]; k += 256) {
+  for (int k = threadIdx.x; k < cn[0] * cn[1] * cn[2]; k += kDownThreads) {
     const int t = (clo[0] + k % cn[0]) + 5 * (clo[1] + (k / cn[0]) % cn[1]) + 25 * (clo[2] + k / (cn[0] * cn[1]));
     int j[3] = {base[0] + t % 5, base[1] + (t / 5) % 5, base[2] + t / 25};
 #pragma unroll
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(256) void k_downward(TransferLaunch a) {
   }
   __syncthreads();
   const int nn[3] = {hi[0] - lo[0] + 1, hi[1] - lo[1] + 1, hi[2] - lo[2] + 1};
-  for (int k = threadIdx.x; k < nn[0] * nn[1] * nn[2]; k += 256) {
+  for (int k = threadIdx.x; k < nn[0] * nn[1] * nn[2]; k += kDownThreads) {
     const int lc[3] = {lo[0] + k % nn[0], lo[1] + (k / nn[0]) % nn[1], lo[2] + k / (nn[0] * nn[1])};
     const int node = lc[0] + 8 * lc[1] + 64 * lc[2];
     if ((a.role[(size_t)slot * kNodes + node] & ROLE_MASK) != ROLE_GHOST) continue;
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(256) void k_outflow(OutflowLaunch a) {
 
 template <class S> hipError_t down_t(const TransferLaunch& a, hipStream_t s) {
   if (a.nblocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_downward<S>, dim3(a.nblocks), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_downward<S>, dim3(a.nblocks), dim3(kDownThreads), 0, s, a);
   return hipGetLastError();
 }
 template <class S> hipError_t up_t(const TransferLaunch& a, hipStream_t s) {

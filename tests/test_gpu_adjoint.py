@@ -2,8 +2,8 @@
 complex-step derivative of the FP64 oracle, plus the state save/load it rests on.
 
 - Directional derivatives of a kinetic-energy loss after a few coarse steps with
-  respect to every initial moment, along random directions, on one level (periodic;
-  walls for bounce-back), two levels (periodic; sphere with inflow and outflow
+  respect to every initial moment, along random directions, on one level (periodic at
+  three sizes; walls for bounce-back), two levels (periodic; sphere with inflow and outflow
   faces; the same with a logarithmic inflow profile, convective outflow and walls)
   and three levels: relative error <= 1e-4 (FP32 adjoint vs FP64 complex
   step). With BF16 storage the gradient stays within 3% of the FP32 one.
@@ -35,6 +35,10 @@ CASES = {
     "single": (1, (32, 32, 32), (P,) * 6, (0.0, 0.0, 0.0), None, None, {0: ((8, 8, 8), (24, 24, 24))}),
     "walls": (1, (32, 32, 32), (P, P, P, P, WALL, WALL), (0.0, 0.0, 0.0), None, None,
               {0: ((0, 0, 0), (32, 32, 32))}),
+    # levels of 1728 and 4096 blocks: the transpose takes a block's output planes in
+    # 2 workgroups and in 1 (levels under 1024 blocks, as in every other case, in 4)
+    "single96": (1, (96, 96, 96), (P,) * 6, (0.0, 0.0, 0.0), None, None, {0: ((24, 24, 24), (72, 72, 72))}),
+    "single128": (1, (128, 128, 128), (P,) * 6, (0.0, 0.0, 0.0), None, None, {0: ((32, 32, 32), (96, 96, 96))}),
     "two_level": (2, (80, 80, 80), (P,) * 6, (0.0, 0.0, 0.0), None, W.block_centre_markers((4, 5)),
                   {0: ((16, 16, 16), (64, 64, 64)), 1: ((0, 0, 0), (80, 80, 80))}),
     "sphere": (2, (80, 80, 80), (INF, OUT, P, P, P, P), (0.03, 0.0, 0.0),

@@ -28,7 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + achieved HBM GB/s per LBM step; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE = 80.0
+BYTES_PER_UPDATE = {"f32": 80.0, "bf16": 40.0, "f16": 40.0}  # 10 moments read + 10 written
+# per-moment power-of-two scales of the 16-bit formats: rho - 1, u (3), S (6)
+HALF_SCALES = [64.0, 8.0, 8.0, 8.0, 64.0, 64.0, 64.0, 64.0, 64.0, 64.0]
+STORE_NAME = {"f32": "StoreF32", "bf16": "StoreBF16", "f16": "StoreF16"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_slab512_traffic.json")
 VALU_CUS, VALU_CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 
@@ -154,6 +157,8 @@ def main():
                     help="run the finest level's two substeps of a parent step as two sweeps (comparison)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="print only the adjoint/forward measurement (for profiling the adjoint kernels)")
+    ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32",
+                    help="moment storage format (FP32 arithmetic in every case)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -174,7 +179,9 @@ def main():
           file=sys.stderr, flush=True)
     p_host = W.slab_particles(wl["particles"], wl["seed"], wl["lo"], wl["hi"])
     particles = torch.as_tensor(p_host).cuda()
-    sim = lbm.Sim(wl["levels"], wl["n"], wl["bc"], wl["tau0"], particles=particles, max_blocks=48000)
+    half = args.storage != "f32"
+    sim = lbm.Sim(wl["levels"], wl["n"], wl["bc"], wl["tau0"], particles=particles, max_blocks=48000,
+                  storage=args.storage, scale=HALF_SCALES if half else None)
     if args.no_fuse:
         sim.set_option("fuse_substeps", 0)
     init_fields(sim, wl, W)
@@ -221,13 +228,13 @@ def main():
     if prof["sc_pair"][1]:
         sc_ms, sc_n = prof["sc_pair"]
         launch_updates = 2 * per_level[0]
-        kernel = "k_stream_collide_pair<StoreF32> (level 0, two substeps per launch)"
+        kernel = f"k_stream_collide_pair<{STORE_NAME[args.storage]}> (level 0, two substeps per launch)"
     else:
         sc_ms, sc_n = prof["sc0"]
         launch_updates = per_level[0]
-        kernel = "k_stream_collide_tile<StoreF32> (level 0)"
+        kernel = f"k_stream_collide_tile<{STORE_NAME[args.storage]}> (level 0)"
     sc_avg_s = sc_ms / sc_n / 1e3
-    alg_bytes = BYTES_PER_UPDATE * launch_updates
+    alg_bytes = BYTES_PER_UPDATE[args.storage] * launch_updates
     achieved = alg_bytes / sc_avg_s / 1e9
     traffic = None
     valu = None
@@ -245,7 +252,7 @@ def main():
     all_ms = sum(prof[f"sc{l}"][0] for l in range(sim.levels)) + prof["sc_pair"][0]
     all_n = sum(prof[f"sc{l}"][1] for l in range(sim.levels)) + prof["sc_pair"][1]
     sc_updates = sum(per_level[l] * (1 << (sim.levels - 1 - l)) for l in range(sim.levels)) * args.steps
-    all_bytes = BYTES_PER_UPDATE * sc_updates / all_n
+    all_bytes = BYTES_PER_UPDATE[args.storage] * sc_updates / all_n
     all_avg_s = all_ms / all_n / 1e3
     out = {
         "metric": METRIC,
@@ -263,7 +270,8 @@ def main():
         "config": {
             "workload": "slab512: 512^3 fine-equivalent periodic, 3 levels of 8^3 blocks, 2M seeded particles "
                         "falling at 0.02/finest step drive the grid update every coarse step, 3D Taylor-Green "
-                        "U=0.05, tau0=0.6, f32 moments",
+                        f"U=0.05, tau0=0.6, {args.storage} moments",
+            "storage": args.storage,
             "levels": sim.levels,
             "fine_extent": list(wl["n"]),
             "blocks_per_level": blocks_after,

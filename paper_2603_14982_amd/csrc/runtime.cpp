@@ -171,7 +171,7 @@ struct lbm_ctx {
   int64_t nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels], ntile[kMaxLevels];
   int64_t nbb[kMaxLevels];          // blocks holding bounce-back nodes
   int64_t tile_min_blocks = 16384;  // LBM_OPT_TILE_MIN_BLOCKS
-  bool fuse_substeps = true;        // LBM_OPT_FUSE_SUBSTEPS
+  int fuse_substeps = 1;            // LBM_OPT_FUSE_SUBSTEPS: 0 never, 1 with FP32 storage, 2 always
   int32_t free_top = 0;
   int32_t* host_counts = nullptr;  // pinned
   std::string err;
@@ -597,7 +597,10 @@ lbm_status up_level(lbm_ctx* c, int l) {
 // flips once instead of twice; the intermediate time level is never stored (no finer
 // level interpolates from it).
 bool pair_ok(const lbm_ctx* c) {
-  return c->fuse_substeps && !c->recording && c->G.L >= 2 && tiled(c, 0) && c->nob[0] == 0 && c->nbb[0] == 0 &&
+  // with 16-bit storage the two sweeps are faster: they move half the bytes, while
+  // the one-sweep kernel is bound by its arithmetic, to which the codec adds
+  const bool want = c->fuse_substeps == 2 || (c->fuse_substeps == 1 && c->cfg.storage == LBM_F32);
+  return want && !c->recording && c->G.L >= 2 && tiled(c, 0) && c->nob[0] == 0 && c->nbb[0] == 0 &&
          !c->cfg.coupling;
 }
 
@@ -1010,8 +1013,8 @@ lbm_status lbm_set_option(lbm_ctx* ctx, int32_t option, int64_t value) {
       ctx->tile_min_blocks = value;
       return LBM_OK;
     case LBM_OPT_FUSE_SUBSTEPS:
-      if (value != 0 && value != 1) return ctx->fail(LBM_EINVAL, "LBM_OPT_FUSE_SUBSTEPS takes 0 or 1");
-      ctx->fuse_substeps = value != 0;
+      if (value < 0 || value > 2) return ctx->fail(LBM_EINVAL, "LBM_OPT_FUSE_SUBSTEPS takes 0, 1 or 2");
+      ctx->fuse_substeps = (int)value;
       return LBM_OK;
   }
   return ctx->fail(LBM_EINVAL, "unknown option");

@@ -55,7 +55,8 @@ def _slab_run(levels, storage="f32", fuse=True, steps=6, oracle=False):
             gpu.set_block_moments(l, keys, init(l, keys).astype(np.float32))
         ora = None
     gpu.set_option("tile_min_blocks", 0)
-    gpu.set_option("fuse_substeps", 1 if fuse else 0)
+    if fuse is not None:  # None: the default (one sweep with FP32 storage only)
+        gpu.set_option("fuse_substeps", 2 if fuse else 0)
     gpu.set_profiling(True)
     pg = torch.as_tensor(p).cuda()
     po = p.copy()
@@ -92,6 +93,15 @@ def test_pair_half_precision_matches_two_sweeps(storage):
     _agree(_moments(a), _moments(b), 1e-3 if storage == "bf16" else 1e-4, f"pair {storage}")
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_default_fuses_substeps_with_f32_storage_only(storage):
+    _, _, prof = _slab_run(2, storage=storage, fuse=None, steps=2)
+    if storage == "f32":
+        assert prof["sc_pair"][1] == 2 and prof["sc0"][1] == 0, prof
+    else:
+        assert prof["sc_pair"][1] == 0 and prof["sc0"][1] == 4, prof
+
+
 def test_pair_not_used_with_bounce_back_or_outflow():
     # no-slip walls at the z faces, with the finest level next to the lower one: its
     # bounce-back nodes keep it on two sweeps per parent step (on the oracle)
@@ -119,5 +129,5 @@ def test_options_rejected_values():
     with pytest.raises(lbm.LBMError):
         sim.set_option("tile_min_blocks", -1)
     with pytest.raises(lbm.LBMError):
-        sim.set_option("fuse_substeps", 2)
+        sim.set_option("fuse_substeps", 3)
     assert lbm.lib().lbm_set_option(sim.h, 7, 0) == -1  # unknown option

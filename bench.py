@@ -121,7 +121,11 @@ def adjoint_ratio(lbm, W, torch):
     torch.cuda.synchronize()
     fwd = time.perf_counter() - t0
     x = x0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     xt = lbm.rollout(sim, x, steps, checkpoint_every=wl["checkpoint_every"])
+    torch.cuda.synchronize()
+    fwd_ckpt = time.perf_counter() - t0
     seed = sim.loss_ke_grad(0, *wl["box"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -140,6 +144,9 @@ def adjoint_ratio(lbm, W, torch):
     torch.cuda.synchronize()
     bwd_tape = time.perf_counter() - t0
     return {"value": round(bwd / fwd, 3), "forward_s": round(fwd, 4), "backward_s": round(bwd, 4),
+            "rollout_forward_s": round(fwd_ckpt, 4),
+            "note": "checkpoints every 20 steps; the rollout's forward pass records the last segment's undo log, "
+                    "so the backward pass replays the other segments only",
             "workload": "adjoint128: 128^3, 2 levels (512 + 504 blocks), 200 coarse steps, checkpoints every 20",
             "full_tape": {"value": round(bwd_tape / fwd, 3), "forward_recording_s": round(fwd_rec, 4),
                           "backward_s": round(bwd_tape, 4),

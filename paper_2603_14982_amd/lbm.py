@@ -417,18 +417,25 @@ class _RolloutTaped(torch.autograd.Function):
 class _Rollout(torch.autograd.Function):
     """x0 (all-level moments) -> moments after `steps` coarse steps. Checkpoints
     every `every` steps; the backward pass hands each segment, last first, to the
-    library's multi-step adjoint (one replay with the undo log, one reverse sweep)."""
+    library's multi-step adjoint (one replay with the undo log, one reverse sweep).
+    The forward pass records the last segment's undo log itself (in the work buffer
+    the backward pass needs anyway), so that segment is not replayed unless the
+    simulation changed in between (the library then refuses the recording and the
+    segment is replayed from its checkpoint)."""
 
     @staticmethod
     def forward(ctx, x0, sim, steps, every):
         sim.set_all_moments(x0.detach())
         ckpts = []
-        for k in range(steps):
-            if k % every == 0:
-                ckpts.append((k, sim.save()))
-            sim.step(1)
+        last = (steps - 1) // every * every
+        work = sim.adjoint_work(min(every, steps))
+        for k in range(0, last, every):
+            ckpts.append((k, sim.save()))
+            sim.step(min(every, last - k))
+        ckpts.append((last, sim.save()))
+        sim.step_record(steps - last, work)
         out = sim.get_all_moments()
-        ctx.sim, ctx.steps, ctx.every, ctx.ckpts = sim, steps, every, ckpts
+        ctx.sim, ctx.steps, ctx.every, ctx.ckpts, ctx.work = sim, steps, every, ckpts, work
         ctx.final = sim.save()
         return out
 
@@ -436,11 +443,20 @@ class _Rollout(torch.autograd.Function):
     def backward(ctx, grad):
         sim = ctx.sim
         lam = grad.detach().to(torch.float32).contiguous().clone()
-        work = sim.adjoint_work(min(ctx.every, ctx.steps))
-        for k0, ck in reversed(ctx.ckpts):
+        work = ctx.work
+        ckpts = list(ctx.ckpts)
+        k0, ck = ckpts.pop()
+        try:
+            sim.adjoint_reverse(lam, lam, work)
+        except LBMError as e:
+            if e.status != -6:  # LBM_ESTATE: the recording no longer matches the simulation
+                raise
+            sim.adjoint_step(ck, lam, lam, work, n_steps=ctx.steps - k0)
+        for k0, ck in reversed(ckpts):
             k1 = min(k0 + ctx.every, ctx.steps)
             sim.adjoint_step(ck, lam, lam, work, n_steps=k1 - k0)
         sim.load(ctx.final)
+        ctx.work = None
         return lam, None, None, None
 
 

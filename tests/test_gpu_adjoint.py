@@ -9,8 +9,9 @@ complex-step derivative of the FP64 oracle, plus the state save/load it rests on
   step). With BF16 storage the gradient stays within 3% of the FP32 one.
 - Entries of the gradient at nodes that carry no state (ghost, solid, inflow) are 0.
 - The checkpointed autograd rollout equals the chain of single adjoint steps and
-  leaves the simulation at its final state; the rollout that keeps its whole undo
-  log (no checkpoints) gives the same gradient; a recording is dropped by a step.
+  leaves the simulation at its final state, also when the simulation stepped on
+  before the backward pass; the rollout that keeps its whole undo log (no
+  checkpoints) gives the same gradient; a recording is dropped by a step.
 - Full size: the two-level 128^3 case, 200 coarse steps with checkpoints every 20,
   gradient with respect to the initial velocity field, against the 16 stored
   complex-step derivatives (tests/golden/, written from the oracle alone).
@@ -275,6 +276,28 @@ def test_taped_rollout_equals_checkpointed_rollout():
         xt = lbm.rollout(sim, x0, 5, checkpoint_every=every)
         final = sim.get_all_moments().clone()
         loss = _torch_loss(sim, xt, 0, box)
+        (g,) = torch.autograd.grad(loss, x0)
+        assert torch.equal(sim.get_all_moments(), final)
+        grads.append(g)
+    assert torch.allclose(grads[0], grads[1], rtol=0, atol=1e-6 * grads[0].abs().max().item())
+
+
+def test_checkpointed_rollout_when_the_simulation_moved_on():
+    # the forward pass records its last segment; if the simulation steps before the
+    # backward pass, that recording is refused and the segment is replayed instead
+    lbm = _lbm()
+    sim = _gpu("two_level")
+    u0 = torch.as_tensor(W.smooth_random_velocity((80, 80, 80), 8, kmax=4.0, rms=0.03), dtype=torch.float32,
+                         device="cuda")
+    box = ((16, 16, 16), (64, 64, 64))
+    grads = []
+    for moved in (False, True):
+        x0 = _torch_init(sim, u0).detach().requires_grad_(True)
+        xt = lbm.rollout(sim, x0, 5, checkpoint_every=2)
+        final = sim.get_all_moments().clone()
+        loss = _torch_loss(sim, xt, 0, box)
+        if moved:
+            sim.step(2)
         (g,) = torch.autograd.grad(loss, x0)
         assert torch.equal(sim.get_all_moments(), final)
         grads.append(g)

@@ -254,9 +254,9 @@ lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes);
  *              ghost, solid and inflow nodes, which do not influence the step).
  *              May alias lam_next.
  *   work       device scratch of >= lbm_adjoint_work_bytes(ctx, 1) bytes (caller-owned):
- *              the adjoint of both time levels, the adjoint of the per-node
- *              moment sums, one flag byte per block slot, and the undo log of
- *              the replayed step.
+ *              the adjoint of both time levels, two buffers of the adjoint of
+ *              the per-node moment sums, one flag byte per block slot, and the
+ *              undo log of the replayed step.
  * The call loads `state` (synchronises once), replays the coarse step while the
  * forward kernels keep the old value of every node they overwrite (the undo log),
  * then walks the log backwards: adjoint of each operation, whose kernels also put

@@ -40,6 +40,20 @@ __device__ __forceinline__ void fwd3_t(float pp, float p0, float pm, float& a0, 
   a2 = 2.0f * (pp + pm) - 4.0f * p0;
 }
 
+// adjoint of the division by 216 rho' at one computed node: Y0 = M0 / 216, Y_m =
+// M_m / (216 + M0) (u and off-diagonal S; a further / 3 on the diagonal S), so
+// mu_m = lambda_m dY_m/dM_m and mu_0 = lambda_0 / 216 - sum_m lambda_m Y_m / (216 + M0)
+__device__ __forceinline__ void mu_of(const float Y[kMom], const float L[kMom], float g[kMom]) {
+  const float inv = 1.0f / (216.0f * (1.0f + Y[0]));
+  float dot = 0.0f;
+#pragma unroll
+  for (int m = 1; m < kMom; ++m) {
+    g[m] = L[m] * ((m >= 4 && m <= 6) ? inv * (1.0f / 3.0f) : inv);
+    dot += L[m] * Y[m];
+  }
+  g[0] = L[0] * (1.0f / 216.0f) - dot * inv;
+}
+
 template <class S> struct TrArgs {
   const typename S::type* x;  // forward input time level
   const float* mu;            // adjoint of M (one f32 time level, all-zero slot at zero_slot)
@@ -52,6 +66,11 @@ template <class S> struct TrArgs {
   int32_t zsplit;             // workgroups per block, each over 8 / zsplit output planes
   float omega;
   Scales sc;
+  // FUSE: the next operation of the reverse sweep is the stream-collide of the same
+  // level that wrote x; its first pass (k_sc_mu) is done here per output node
+  typename S::type* x_next;    // = x, written: restored from tape_next
+  const typename S::type* tape_next;
+  float* mu_next;              // its mu (the other mu buffer)
 };
 
 // lambda_X += (da/dX)^T nu for one source node; nu[m] indexed [mx][my][mz]
@@ -227,7 +246,11 @@ __device__ __forceinline__ int xcd_remap_t(int bid, int n) {
 // planes zlo - 1 .. zlo + zn (the window of the z pass); every output node has one
 // writer. The parts of a block go to neighbouring workgroup indices after the remap,
 // which places them on one XCD (one L2) except at the ends of an XCD's range.
-template <class S>
+// FUSE: each output node, once its adjoint is final, also gets the next operation's
+// first pass (the same node's mu, adjoint cleared, value restored), as k_sc_mu would
+// do right after this kernel; mu itself is read from the other buffer, so no
+// workgroup's halo reads see the new values.
+template <class S, bool FUSE>
 __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
   __shared__ __align__(16) float lds[10 * kRowT];
   __shared__ int s_src[27];
@@ -370,8 +393,42 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
       for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(xq[m], a.sc.inv[m]);
       coeff_jacobian_t(q, a.omega, nu, L);
       float* lam = a.lam_x + (size_t)slot * kBlockStride + onode;
+      if (FUSE && orm == ROLE_COMPUTED) {
+        float g[kMom];
+        mu_of(q, L, g);
+        typename S::type* xw = a.x_next + (size_t)slot * kBlockStride + onode;
+        const typename S::type* tp = a.tape_next + (size_t)(item / a.zsplit) * kBlockStride + onode;
+        float* mn = a.mu_next + (size_t)slot * kBlockStride + onode;
 #pragma unroll
-      for (int m = 0; m < kMom; ++m) lam[m * kNodes] = L[m];
+        for (int m = 0; m < kMom; ++m) {
+          lam[m * kNodes] = 0.0f;
+          xw[m * kNodes] = tp[m * kNodes];
+          mn[m * kNodes] = g[m];
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) lam[m * kNodes] = L[m];
+        if (FUSE) {
+          float* mn = a.mu_next + (size_t)slot * kBlockStride + onode;
+#pragma unroll
+          for (int m = 0; m < kMom; ++m) mn[m * kNodes] = 0.0f;
+        }
+      }
+    } else if (FUSE && zo >= zlo) {
+      // solid or inflow node: no adjoint of its own; a solid node is restored
+      float* mn = a.mu_next + (size_t)slot * kBlockStride + onode;
+      if (orm == ROLE_SOLID) {
+        float* lam = a.lam_x + (size_t)slot * kBlockStride + onode;
+        typename S::type* xw = a.x_next + (size_t)slot * kBlockStride + onode;
+        const typename S::type* tp = a.tape_next + (size_t)(item / a.zsplit) * kBlockStride + onode;
+#pragma unroll
+        for (int m = 0; m < kMom; ++m) {
+          lam[m * kNodes] = 0.0f;
+          xw[m * kNodes] = tp[m * kNodes];
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) mn[m * kNodes] = 0.0f;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -382,10 +439,8 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
   }
 }
 
-// ---- adjoint of the division by 216 rho' (per computed node) -------------------
-// Y0 = M0 / 216, Y_m = M_m / (216 + M0) (u and off-diagonal S; a further / 3 on
-// the diagonal S): mu_m = lambda_m dY_m/dM_m, mu_0 = lambda_0 / 216 - sum_m
-// lambda_m Y_m / (216 + M0). The outputs are then restored from the tape.
+// ---- adjoint of the division by 216 rho' (per computed node, mu_of); the outputs
+// are then restored from the tape and their adjoint cleared
 template <class S>
 __global__ __launch_bounds__(kNodes) void k_sc_mu(AdjScLaunch a) {
   typedef typename S::type T;
@@ -406,14 +461,7 @@ __global__ __launch_bounds__(kNodes) void k_sc_mu(AdjScLaunch a) {
         Y[m] = Codec<S>::load(y[m * kNodes + node], a.sc.inv[m]);
         L[m] = lam[m * kNodes + node];
       }
-      const float inv = 1.0f / (216.0f * (1.0f + Y[0]));
-      float dot = 0.0f;
-#pragma unroll
-      for (int m = 1; m < kMom; ++m) {
-        g[m] = L[m] * ((m >= 4 && m <= 6) ? inv * (1.0f / 3.0f) : inv);
-        dot += L[m] * Y[m];
-      }
-      g[0] = L[0] * (1.0f / 216.0f) - dot * inv;
+      mu_of(Y, L, g);
     }
     if (r == ROLE_COMPUTED || r == ROLE_SOLID) {
 #pragma unroll
@@ -909,11 +957,17 @@ template <class S> hipError_t tr_t(const AdjScLaunch& l, hipStream_t s) {
   a.zero_slot = l.zero_slot;
   a.omega = l.omega;
   a.sc = l.sc;
+  a.x_next = static_cast<typename S::type*>(l.next_x);
+  a.tape_next = static_cast<const typename S::type*>(l.next_tape);
+  a.mu_next = l.next_mu;
   // split the blocks' z ranges over 2 or 4 workgroups while the level has too few
   // blocks to give every SIMD of the chip a wave (4 per CU, 256 CUs)
   a.zsplit = 1;
   while (a.zsplit < 4 && (int64_t)l.nblocks * a.zsplit < kTransposeWaves) a.zsplit *= 2;
-  hipLaunchKernelGGL(k_sc_transpose<S>, dim3(l.nblocks * a.zsplit), dim3(64), 0, s, a);
+  if (l.next_mu)
+    hipLaunchKernelGGL((k_sc_transpose<S, true>), dim3(l.nblocks * a.zsplit), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_sc_transpose<S, false>), dim3(l.nblocks * a.zsplit), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

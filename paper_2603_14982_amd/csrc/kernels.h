@@ -225,6 +225,13 @@ struct AdjScLaunch {
   float omega;
   Scales sc;
   int storage;
+  // transpose only: if next_mu is set, the next operation of the reverse sweep is the
+  // stream-collide of this level that wrote x; the transpose then also does that
+  // operation's k_sc_mu pass (its mu into next_mu, x restored from next_tape, the
+  // adjoint of x cleared at computed and solid nodes)
+  void* next_x;
+  const void* next_tape;
+  float* next_mu;
 };
 hipError_t launch_sc_mu(const AdjScLaunch& a, hipStream_t s);
 hipError_t launch_sc_transpose(const AdjScLaunch& a, hipStream_t s);

@@ -638,7 +638,7 @@ constexpr size_t kStateHeader = 256;
 
 struct AdjBufs {
   float* lam[2];   // adjoint of the pool's two time levels (f32, slot layout)
-  float* mu;       // adjoint of the scaled moments M (f32, slot layout)
+  float* mu[2];    // adjoint of the scaled moments M (f32, slot layout; two, see adjoint_op)
   float* part;     // downward transfer: coarse-footprint partials per ghost block, all levels
   int32_t* gidx;   // per slot: index in its level's ghost-block list, or -1
   uint8_t* flags;  // per slot: coarse block read by ghosts of the next finer level
@@ -655,6 +655,7 @@ size_t aux_bytes(const lbm_ctx* c) {
 }
 
 size_t slot_floats(const lbm_ctx* c) { return (size_t)(c->cap + 1) * kBlockStride; }
+constexpr size_t kAdjSlotBufs = 4;  // lam[2], mu[2]
 
 size_t tape_bytes(const lbm_ctx* c) {
   const int L = c->G.L;
@@ -686,9 +687,17 @@ AdjTransferLaunch adj_base(lbm_ctx* c, int l) {
   return t;
 }
 
+// state carried from one operation of the reverse sweep to the next
+struct AdjSweep {
+  int mu_cur = 0;         // mu buffer of the next stream-collide
+  bool mu_ready = false;  // its first pass (k_sc_mu) already done by the previous transpose
+};
+
 // adjoint of one recorded operation in the state right after it, then its undo
-// (folded into the adjoint kernels: each restores the nodes the operation wrote)
-lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
+// (folded into the adjoint kernels: each restores the nodes the operation wrote).
+// next: the operation the sweep takes after this one (recorded just before it).
+lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const lbm_ctx::TapeOp* next, const AdjBufs& b,
+                      AdjSweep& sw) {
   const int l = op.level;
   hipStream_t s = c->stream;
   if (op.kind == lbm_ctx::OP_SC) {
@@ -705,10 +714,11 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
       HIPCHK(c, launch_outflow_adj(t, s));
     }
     AdjScLaunch a;
+    std::memset(&a, 0, sizeof(a));
     a.x = c->buf(l, p);
     a.y = c->buf(l, 1 - p);
     a.tape = c->tape + op.off;
-    a.mu = b.mu;
+    a.mu = b.mu[sw.mu_cur];
     a.lam_x = b.lam[p];
     a.lam_y = b.lam[1 - p];
     a.blocks = c->blocks(l);
@@ -719,8 +729,21 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
     a.omega = (float)(1.0 / c->tau[l]);
     a.sc = c->sc;
     a.storage = c->cfg.storage;
-    HIPCHK(c, launch_sc_mu(a, s));
+    if (!sw.mu_ready) HIPCHK(c, launch_sc_mu(a, s));
+    // the next operation is the stream-collide of this level that wrote this one's
+    // input (consecutive substeps of the finest level, or consecutive steps of a
+    // single level), with no outflow adjoint before its first pass: the transpose
+    // does that pass per node, into the other mu buffer
+    const bool fuse = next && next->kind == lbm_ctx::OP_SC && next->level == l && next->pf == 1 - p &&
+                      c->nob[l] == 0;
+    if (fuse) {
+      a.next_x = c->buf(l, p);
+      a.next_tape = c->tape + next->off;
+      a.next_mu = b.mu[1 - sw.mu_cur];
+    }
     HIPCHK(c, launch_sc_transpose(a, s));
+    sw.mu_ready = fuse;
+    if (fuse) sw.mu_cur = 1 - sw.mu_cur;
   } else if (op.kind == lbm_ctx::OP_DOWN) {
     // both substeps' ghosts: s = 1 in time level pf, s = 2 in 1 - pf
     AdjTransferLaunch t = adj_base(c, l);
@@ -1111,7 +1134,7 @@ lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes) {
 
 size_t lbm_adjoint_work_bytes(const lbm_ctx* ctx, int32_t n_steps) {
   if (!ctx || n_steps < 1) return 0;
-  return 3 * slot_floats(ctx) * sizeof(float) + aux_bytes(ctx) + (size_t)n_steps * tape_bytes(ctx);
+  return kAdjSlotBufs * slot_floats(ctx) * sizeof(float) + aux_bytes(ctx) + (size_t)n_steps * tape_bytes(ctx);
 }
 
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* state, size_t state_bytes, const float* lam_next, float* lam_out,
@@ -1140,9 +1163,9 @@ lbm_status lbm_step_record(lbm_ctx* ctx, int32_t n_steps, void* work, size_t wor
   if (work_bytes < lbm_adjoint_work_bytes(ctx, n_steps)) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
   const int L = ctx->G.L;
   const size_t sf = slot_floats(ctx);
-  char* aux = reinterpret_cast<char*>(static_cast<float*>(work) + 3 * sf);
+  char* aux = reinterpret_cast<char*>(static_cast<float*>(work) + kAdjSlotBufs * sf);
   ctx->tape = aux + aux_bytes(ctx);
-  ctx->tape_cap = work_bytes - 3 * sf * sizeof(float) - aux_bytes(ctx);
+  ctx->tape_cap = work_bytes - kAdjSlotBufs * sf * sizeof(float) - aux_bytes(ctx);
   ctx->tape_used = 0;
   ctx->ops.clear();
   ctx->rec_work = work;
@@ -1170,7 +1193,7 @@ lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_o
     return ctx->fail(LBM_ESTATE, "no recorded steps for this work buffer");
   if (ctx->rec_generation != ctx->generation)
     return ctx->fail(LBM_ESTATE, "the block hierarchy changed since the steps were recorded");
-  if (work_bytes < 3 * slot_floats(ctx) * sizeof(float) + aux_bytes(ctx) + ctx->tape_used)
+  if (work_bytes < kAdjSlotBufs * slot_floats(ctx) * sizeof(float) + aux_bytes(ctx) + ctx->tape_used)
     return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
   hipStream_t s = ctx->stream;
   const int L = ctx->G.L;
@@ -1178,8 +1201,9 @@ lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_o
   AdjBufs b;
   b.lam[0] = static_cast<float*>(work);
   b.lam[1] = b.lam[0] + sf;
-  b.mu = b.lam[1] + sf;
-  char* aux = reinterpret_cast<char*>(b.mu + sf);
+  b.mu[0] = b.lam[1] + sf;
+  b.mu[1] = b.mu[0] + sf;
+  char* aux = reinterpret_cast<char*>(b.mu[1] + sf);
   b.part = reinterpret_cast<float*>(aux);
   b.gidx = reinterpret_cast<int32_t*>(aux + part_bytes(ctx));
   b.flags = reinterpret_cast<uint8_t*>(aux + part_bytes(ctx) + round256((size_t)(ctx->cap + 1) * 4));
@@ -1187,7 +1211,8 @@ lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_o
   lbm_status st = LBM_OK;
   {
     // adjoint of the state after the steps: lam_next at the state nodes of the current time level
-    HIPCHK(ctx, launch_fill_i32(reinterpret_cast<int32_t*>(b.mu + (size_t)ctx->cap * kBlockStride), 0, kBlockStride, s));
+    for (int k = 0; k < 2; ++k)
+      HIPCHK(ctx, launch_fill_i32(reinterpret_cast<int32_t*>(b.mu[k] + (size_t)ctx->cap * kBlockStride), 0, kBlockStride, s));
     HIPCHK(ctx, launch_fill_u8(b.flags, 0, ctx->cap + 1, s));
     HIPCHK(ctx, launch_fill_i32(b.gidx, -1, ctx->cap + 1, s));
     for (int l = 0; l + 1 < L; ++l) {
@@ -1208,7 +1233,9 @@ lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_o
   }
   // reverse sweep over every logged operation of every step (a failure leaves the
   // simulation state undefined: the undo is part of the adjoint kernels)
-  for (size_t i = ctx->ops.size(); st == LBM_OK && i-- > 0;) st = adjoint_op(ctx, ctx->ops[i], b);
+  AdjSweep sw;
+  for (size_t i = ctx->ops.size(); st == LBM_OK && i-- > 0;)
+    st = adjoint_op(ctx, ctx->ops[i], i > 0 ? &ctx->ops[i - 1] : nullptr, b, sw);
   for (int l = 0; l < L; ++l) ctx->parity[l] = ctx->rec_parity[l];
   ctx->ops.clear();
   ctx->rec_work = nullptr;

@@ -932,6 +932,15 @@ __global__ __launch_bounds__(256) void k_gather_blocks(const uint4* __restrict__
 #pragma unroll 5
   for (int i = threadIdx.x; i < per_block; i += 256) d[i] = s[i];
 }
+__global__ __launch_bounds__(256) void k_gather_blocks2(const uint4* __restrict__ src_a,
+                                                        const uint4* __restrict__ src_b, uint4* __restrict__ dst,
+                                                        const int32_t* blocks, int32_t n, int32_t per_block) {
+  const int i = blockIdx.x < n ? blockIdx.x : blockIdx.x - n;
+  const uint4* s = (blockIdx.x < n ? src_a : src_b) + (size_t)blocks[i] * per_block;
+  uint4* d = dst + (size_t)blockIdx.x * per_block;
+#pragma unroll 5
+  for (int k = threadIdx.x; k < per_block; k += 256) d[k] = s[k];
+}
 __global__ __launch_bounds__(256) void k_scatter_blocks(const uint4* __restrict__ src, uint4* __restrict__ dst,
                                                         const int32_t* blocks, int32_t per_block) {
   const uint4* s = src + (size_t)blockIdx.x * per_block;
@@ -1050,6 +1059,15 @@ hipError_t launch_gather_blocks(const void* src, void* dst, const int32_t* block
   if (block_bytes % 16) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gather_blocks, dim3(n), dim3(256), 0, s, static_cast<const uint4*>(src),
                      static_cast<uint4*>(dst), blocks, (int32_t)(block_bytes / 16));
+  return hipGetLastError();
+}
+hipError_t launch_gather_blocks2(const void* src_a, const void* src_b, void* dst, const int32_t* blocks, int32_t n,
+                                 size_t block_bytes, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (block_bytes % 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather_blocks2, dim3(2 * n), dim3(256), 0, s, static_cast<const uint4*>(src_a),
+                     static_cast<const uint4*>(src_b), static_cast<uint4*>(dst), blocks, n,
+                     (int32_t)(block_bytes / 16));
   return hipGetLastError();
 }
 hipError_t launch_scatter_blocks(const void* src, void* dst, const int32_t* blocks, int32_t n, size_t block_bytes,

@@ -288,6 +288,9 @@ hipError_t launch_gather_blocks(const void* src, void* dst, const int32_t* block
                                 hipStream_t s);
 hipError_t launch_scatter_blocks(const void* src, void* dst, const int32_t* blocks, int32_t n, size_t block_bytes,
                                  hipStream_t s);
+// dst[i] = src_a[blocks[i]] and dst[n + i] = src_b[blocks[i]] in one launch
+hipError_t launch_gather_blocks2(const void* src_a, const void* src_b, void* dst, const int32_t* blocks, int32_t n,
+                                 size_t block_bytes, hipStream_t s);
 // eight 64-bit words written by a kernel (kernel arguments: no host buffer to keep alive)
 struct Words8 { uint64_t v[8]; };
 hipError_t launch_write_words(uint64_t* dst, Words8 w, hipStream_t s);

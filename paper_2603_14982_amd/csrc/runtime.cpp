@@ -191,6 +191,7 @@ struct lbm_ctx {
   char* tape = nullptr;
   size_t tape_cap = 0, tape_used = 0;
   std::vector<TapeOp> ops;
+  size_t pending_sc_tape = SIZE_MAX;   // tape of the finest level's second substep, taken with the first's
   const void* rec_work = nullptr;      // work buffer holding the recorded steps (null: none)
   uint64_t rec_generation = 0;         // hierarchy they were recorded on
   int rec_parity[kMaxLevels] = {0};    // time-level parities before them
@@ -499,15 +500,36 @@ ScLaunch sc_base(lbm_ctx* c, int l) {
   return a;
 }
 
-lbm_status sc_level(lbm_ctx* c, int l) {
+lbm_status sc_level(lbm_ctx* c, int l, int s) {
   ScLaunch a = sc_base(c, l);
   void* otape = nullptr;
   if (c->recording) {
-    // the whole blocks of the written time level go to the tape (one bulk copy)
+    // the whole blocks of the written time level go to the tape (one bulk copy). On
+    // the finest level (below a coarser one) nothing else runs between the two
+    // substeps of a parent step, and the first does not write the time level the
+    // second writes, whose computed and solid nodes (all its undo restores; the
+    // downward transfer restores ghosts itself) are already final: both copies are
+    // taken in one launch before the first substep.
+    const int64_t nb = c->nblk[l];
+    const bool pair = l == 0 && c->G.L >= 2;
     void* tape = nullptr;
-    lbm_status st = record(c, lbm_ctx::OP_SC, l, 0, c->nblk[l], c->nob[l], &tape, &otape);
-    if (st != LBM_OK) return st;
-    HIPCHK(c, launch_gather_blocks(c->other(l), tape, c->blocks(l), (int32_t)c->nblk[l], block_bytes(c), c->stream));
+    lbm_status st;
+    if (pair && s == 2 && c->pending_sc_tape != SIZE_MAX) {
+      st = record(c, lbm_ctx::OP_SC, l, 0, 0, c->nob[l], &tape, &otape);
+      if (st != LBM_OK) return st;
+      c->ops.back().off = c->pending_sc_tape;
+      c->pending_sc_tape = SIZE_MAX;
+    } else {
+      st = record(c, lbm_ctx::OP_SC, l, 0, pair && s == 1 ? 2 * nb : nb, c->nob[l], &tape, &otape);
+      if (st != LBM_OK) return st;
+      if (pair && s == 1) {
+        HIPCHK(c, launch_gather_blocks2(c->other(l), c->cur(l), tape, c->blocks(l), (int32_t)nb, block_bytes(c),
+                                        c->stream));
+        c->pending_sc_tape = c->ops.back().off + (size_t)nb * block_bytes(c);
+      } else {
+        HIPCHK(c, launch_gather_blocks(c->other(l), tape, c->blocks(l), (int32_t)nb, block_bytes(c), c->stream));
+      }
+    }
   }
   const int k = c->tic(LBM_PROF_SC0 + l);
   HIPCHK(c, launch_stream_collide(a, c->stream));
@@ -617,7 +639,7 @@ lbm_status advance(lbm_ctx* c, int l, int s) {
   const int L = c->G.L;
   lbm_status st;
   if (l < L - 1 && (st = down_level(c, l, s)) != LBM_OK) return st;
-  if ((st = sc_level(c, l)) != LBM_OK) return st;
+  if ((st = sc_level(c, l, s)) != LBM_OK) return st;
   if (l < L - 1 && s == 2 && (st = up_level(c, l)) != LBM_OK) return st;
   if (l == 1 && pair_ok(c)) {
     if ((st = down_level(c, 0, 1)) != LBM_OK) return st;
@@ -1168,6 +1190,7 @@ lbm_status lbm_step_record(lbm_ctx* ctx, int32_t n_steps, void* work, size_t wor
   ctx->tape_cap = work_bytes - kAdjSlotBufs * sf * sizeof(float) - aux_bytes(ctx);
   ctx->tape_used = 0;
   ctx->ops.clear();
+  ctx->pending_sc_tape = SIZE_MAX;
   ctx->rec_work = work;
   ctx->rec_generation = ctx->generation;
   for (int l = 0; l < L; ++l) ctx->rec_parity[l] = ctx->parity[l];

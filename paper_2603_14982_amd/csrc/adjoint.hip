@@ -311,6 +311,13 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
         L[m] = lam[m * kNodes];
       }
     }
+    // FUSE: the next operation's old values of this node (its undo), loaded with the rest
+    typename S::type tn[kMom];
+    if (FUSE && zo >= zlo && (orm == ROLE_COMPUTED || orm == ROLE_SOLID)) {
+      const typename S::type* tp = a.tape_next + (size_t)(item / a.zsplit) * kBlockStride + onode;
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) tn[m] = tp[m * kNodes];
+    }
     // ---- mu of plane z (+ halo) -> transposed x back-map per (qy, qz) group
     float mcur[2][kMom];
 #pragma unroll
@@ -397,12 +404,11 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
         float g[kMom];
         mu_of(q, L, g);
         typename S::type* xw = a.x_next + (size_t)slot * kBlockStride + onode;
-        const typename S::type* tp = a.tape_next + (size_t)(item / a.zsplit) * kBlockStride + onode;
         float* mn = a.mu_next + (size_t)slot * kBlockStride + onode;
 #pragma unroll
         for (int m = 0; m < kMom; ++m) {
           lam[m * kNodes] = 0.0f;
-          xw[m * kNodes] = tp[m * kNodes];
+          xw[m * kNodes] = tn[m];
           mn[m * kNodes] = g[m];
         }
       } else {
@@ -420,11 +426,10 @@ __global__ __launch_bounds__(64) void k_sc_transpose(TrArgs<S> a) {
       if (orm == ROLE_SOLID) {
         float* lam = a.lam_x + (size_t)slot * kBlockStride + onode;
         typename S::type* xw = a.x_next + (size_t)slot * kBlockStride + onode;
-        const typename S::type* tp = a.tape_next + (size_t)(item / a.zsplit) * kBlockStride + onode;
 #pragma unroll
         for (int m = 0; m < kMom; ++m) {
           lam[m * kNodes] = 0.0f;
-          xw[m * kNodes] = tp[m * kNodes];
+          xw[m * kNodes] = tn[m];
         }
       }
 #pragma unroll

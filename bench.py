@@ -162,6 +162,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward time ratio")
     ap.add_argument("--no-fuse", action="store_true",
                     help="run the finest level's two substeps of a parent step as two sweeps (comparison)")
+    ap.add_argument("--fuse", type=int, choices=[0, 1, 2], default=None,
+                    help="the library's substep-fusion option (0 never, 1 with FP32 storage, 2 always)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="print only the adjoint/forward measurement (for profiling the adjoint kernels)")
     ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32",
@@ -191,6 +193,8 @@ def main():
                   storage=args.storage, scale=HALF_SCALES if half else None)
     if args.no_fuse:
         sim.set_option("fuse_substeps", 0)
+    elif args.fuse is not None:
+        sim.set_option("fuse_substeps", args.fuse)
     init_fields(sim, wl, W)
     torch.cuda.synchronize()
     sub = 1 << (wl["levels"] - 1)

@@ -147,10 +147,12 @@ lbm_status lbm_set_coupling(lbm_ctx* ctx, const int64_t* keys, const float* fiel
  * third-order Runge-Kutta, trilinear interpolation of u and phi), then one forward-
  * Euler step of the 7-point Laplacian, then dt q. phi lives on the finest level's
  * owned nodes: nodes outside its blocks, its ghost nodes, nodes beyond walls and
- * solid nodes count as phi = 0, u = 0 (and stay at phi = 0); a departure point
- * is kept within 7 nodes of its node per axis (|u| dt below 7 is the accurate range).
+ * solid nodes count as phi = 0, u = 0 (and stay at phi = 0). Every sample point of
+ * the backtrace is kept within 7 nodes of its node per axis: with dt <= 7 this only
+ * acts where a velocity component exceeds one node per step, beyond the lattice's
+ * range (a run with |u| that large has lost accuracy anyway).
  * source: device f32 [nb][512] in the key order of the finest level's blocks (as
- * lbm_scalar_get returns them), or NULL. LBM_EINVAL unless dt > 0, D >= 0 and
+ * lbm_scalar_get returns them), or NULL. LBM_EINVAL unless 0 < dt <= 7, D >= 0 and
  * D dt <= 1/6. Async.
  * lbm_scalar_set: phi of the listed finest-level blocks (device keys [nb], values
  * [nb][512]); solid and ghost nodes are set to 0. LBM_EINVAL for a key that is not an active

@@ -775,6 +775,7 @@ template <class T> struct Sim {
   //     ghost nodes (the coarser level's region), beyond walls and at solid nodes are
   //     0, velocities there 0; periodic axes wrap.
   static bool off_scalar(uint8_t r) { return r == R_SOLID || r == R_GHOST; }
+  static constexpr double kReach = 7.0;  // departure search range, nodes per axis
   double phi_node(const int g0[3]) {
     int g[3] = {g0[0], g0[1], g0[2]};
     if (!wrap_node(0, g)) return 0.0;
@@ -827,13 +828,21 @@ template <class T> struct Sim {
         int g[3];
         node_coords(B->b, n, g);
         const double x[3] = {double(g[0]), double(g[1]), double(g[2])};
+        // every sample point is kept within kReach nodes of x per axis (the reading
+        // of the search range: the paper bounds no departure distance)
+        auto reach = [&](double* y) {
+          for (int a = 0; a < 3; ++a) y[a] = std::min(std::max(y[a], x[a] - kReach), x[a] + kReach);
+        };
         double k1[3], k2[3], k3[3], y[3];
         trilinear(x, 3, uval, k1);
         for (int a = 0; a < 3; ++a) y[a] = x[a] - 0.5 * dt * k1[a];
+        reach(y);
         trilinear(y, 3, uval, k2);
         for (int a = 0; a < 3; ++a) y[a] = x[a] - 0.75 * dt * k2[a];
+        reach(y);
         trilinear(y, 3, uval, k3);
         for (int a = 0; a < 3; ++a) y[a] = x[a] - dt * (2.0 * k1[a] + 3.0 * k2[a] + 4.0 * k3[a]) / 9.0;
+        reach(y);
         trilinear(y, 1, pval, &adv[k][n]);
       }
     }

@@ -994,6 +994,9 @@ lbm_status lbm_scalar_advance(lbm_ctx* ctx, float dt, float D, const float* sour
   if (!(dt > 0.0f) || !std::isfinite(dt) || !(D >= 0.0f) || !std::isfinite(D))
     return ctx->fail(LBM_EINVAL, "dt must be positive and D non-negative");
   if (D * dt > 1.0f / 6.0f) return ctx->fail(LBM_EINVAL, "forward-Euler diffusion needs D dt <= 1/6");
+  if (dt > 7.0f)
+    return ctx->fail(LBM_EINVAL, "dt must not exceed 7 finest-level steps (departure points are searched within "
+                                 "7 nodes)");
   ScalarLaunch a;
   std::memset(&a, 0, sizeof(a));
   a.blocks = ctx->blocks(0);

@@ -2,10 +2,12 @@
 
 Calls only the FP64 oracle (oracle/) and the seeded input generators; no value
 here comes from the GPU path. Each output holds a seeded sample of owned nodes
-(level, block key, node index, 10 moments) of the oracle's state.
+(level, block key, node index, 10 moments) of the oracle's state; the slab file
+holds samples by node class after 20 and 200 coarse steps and the composite
+conservation sums every 10 steps.
 
   python tests/golden/make_golden.py sphere128   # 500 coarse steps
-  python tests/golden/make_golden.py slab512     # 20 coarse steps with grid updates
+  python tests/golden/make_golden.py slab512     # 200 coarse steps with grid updates
   python tests/golden/make_golden.py adjoint128  # loss and 16 directional derivatives
 
 The adjoint file holds the kinetic-energy loss after 200 coarse steps of the
@@ -66,8 +68,57 @@ def sphere128(steps=500):
     np.savez_compressed(os.path.join(HERE, "sphere128_oracle_sample.npz"), **res)
 
 
-def slab512(coarse_steps=20):
+SAMPLE_CLASSES = ("bulk", "iu", "edge")
+
+
+def sample_classes(sim, seed, per_class=(8192, 4096, 4096)):
+    """Seeded samples of one state in three classes per level: "bulk" (computed nodes),
+    "iu" (upward-interface nodes, written by the upward transfer) and "edge" (computed
+    nodes of blocks that hold ghost nodes: the ones whose neighbours the downward
+    transfer writes)."""
+    rng = np.random.default_rng(seed)
+    out = {"level": [], "cls": [], "key": [], "node": [], "values": []}
+    counts = []
+    for l in range(sim.levels):
+        keys, vals = sim.get_block_moments(l)
+        roles = sim.roles(l)
+        counts.append(len(keys))
+        has_ghost = (roles == O.R_GHOST).any(axis=1)
+        masks = (roles == O.R_INTERIOR, roles == O.R_IU, (roles == O.R_INTERIOR) & has_ghost[:, None])
+        for c, (m, k) in enumerate(zip(masks, per_class)):
+            cand = np.argwhere(m)
+            if len(cand) == 0:
+                continue
+            pick = cand[np.sort(rng.choice(len(cand), size=min(k, len(cand)), replace=False))]
+            out["level"].append(np.full(len(pick), l, dtype=np.int32))
+            out["cls"].append(np.full(len(pick), c, dtype=np.int32))
+            out["key"].append(keys[pick[:, 0]])
+            out["node"].append(pick[:, 1].astype(np.int32))
+            out["values"].append(vals[pick[:, 0], :, pick[:, 1]])
+    res = {k: np.concatenate(v) for k, v in out.items()}
+    res["blocks_per_level"] = np.array(counts, dtype=np.int64)
+    return res
+
+
+def conservation(sim):
+    """Composite sums of one oracle state: volume, mass excess, momentum (tests/util.py)."""
+    from tests.util import composite_sums
+    keys, vals, roles = [], [], []
+    for l in range(sim.levels):
+        k, v = sim.get_block_moments(l)
+        keys.append(k)
+        vals.append(v)
+        roles.append(sim.roles(l))
+    c = composite_sums(sim.levels, keys, vals, roles)
+    return np.array([c["volume"], c["mass_excess"], *c["momentum"]])
+
+
+def slab512(coarse_steps=None, sample_at=(20,), sums_every=10):
+    """The three-level slab case over its coarse steps with grid updates: samples of
+    every class after `sample_at` steps and at the end, composite conservation sums
+    every `sums_every` steps (and at step 0)."""
     wl = W.workload("slab512")
+    coarse_steps = wl["steps"] if coarse_steps is None else coarse_steps
     p = W.slab_particles(wl["particles"], wl["seed"], wl["lo"], wl["hi"])
     t = time.time()
     sim = O.OracleSim(3, wl["n"], wl["bc"], wl["tau0"], particles=p)
@@ -79,14 +130,25 @@ def slab512(coarse_steps=20):
             sim.set_block_moments(l, k, W.tgv3d_field(l, k, wl["n"], wl["amp"]))
     sub = 1 << (wl["levels"] - 1)
     d = np.array([v * sub for v in wl["v_fine"]], dtype=np.float32)
+    res = {"steps": np.array(coarse_steps), "sums_steps": [0], "sums": [conservation(sim)]}
     for i in range(coarse_steps):
         sim.step(1)
         O.advance_particles(p, d)
         sim.remesh(p)
-        print(f"slab512 coarse step {i + 1} ({time.time() - t:.0f} s)", flush=True)
-    res = sample_state(sim, 8192, seed=512)
-    res["steps"] = np.array(coarse_steps)
-    np.savez_compressed(os.path.join(HERE, "slab512_oracle_sample.npz"), **res)
+        done = i + 1
+        if done in sample_at or done == coarse_steps:
+            s = sample_classes(sim, seed=512 + done)
+            for k, v in s.items():
+                res[f"s{done}_{k}"] = v
+        if done % sums_every == 0 or done == coarse_steps:
+            res["sums_steps"].append(done)
+            res["sums"].append(conservation(sim))
+            print(f"slab512 step {done}: sums {res['sums'][-1]}", flush=True)
+        print(f"slab512 coarse step {done} ({time.time() - t:.0f} s)", flush=True)
+    res["sums_steps"] = np.array(res["sums_steps"])
+    res["sums"] = np.array(res["sums"])
+    res["sample_steps"] = np.array(sorted(set(sample_at) | {coarse_steps}))
+    np.savez_compressed(os.path.join(HERE, "slab512_oracle_run.npz"), **res)
 
 
 def adjoint_setup(wl):

@@ -102,6 +102,33 @@ def test_scalar_around_a_sphere_against_oracle():
     _compare_phi(gpu, ora, "sphere")
 
 
+def test_scalar_departure_range_against_oracle():
+    """Velocities above one node per step with dt up to 7: sample points of the backtrace
+    that would leave the 7-node range are held at it, on both sides (two levels, so
+    the range also meets ghost nodes and missing blocks)."""
+    lbm = _lbm()
+    n = (64, 64, 64)
+    particles = W.slab_particles(40, 9, (20.0, 20.0, 20.0), (44.0, 44.0, 44.0))
+    ora = O.OracleSim(2, n, (P,) * 6, 0.6, particles=particles)
+    gpu = lbm.Sim(2, n, (P,) * 6, 0.6, particles=particles, scalar=True)
+    u0 = W.smooth_random_velocity(n, 21, kmax=3.0, rms=1.2)
+    for l in range(2):
+        keys = ora.block_keys(l)
+        vals = W.velocity_moments(l, keys, u0)
+        ora.set_block_moments(l, keys, vals)
+        gpu.set_block_moments(l, keys, vals.astype(np.float32))
+    k0 = ora.block_keys(0)
+    ua = np.abs(ora.get_block_moments(0)[1][:, 1:4])
+    assert (ua * 6.5 > 7).any(), "the field must reach beyond the range"
+    phi = _phi(k0, 5)
+    for dt in (6.5, 7.0, 3.0):
+        ora.scalar_set(k0, phi)
+        gpu.scalar_set(k0, phi.astype(np.float32))
+        ora.scalar_advance(dt, 0.02)
+        gpu.scalar_advance(dt, 0.02)
+        _compare_phi(gpu, ora, f"fast field dt={dt}")
+
+
 def test_scalar_arguments_rejected():
     lbm = _lbm()
     sim = lbm.Sim(1, (32, 32, 32), (P,) * 6, 0.6, scalar=True)
@@ -109,6 +136,8 @@ def test_scalar_arguments_rejected():
         sim.scalar_advance(2.0, 0.1)  # D dt > 1/6
     with pytest.raises(lbm.LBMError):
         sim.scalar_advance(0.0, 0.01)
+    with pytest.raises(lbm.LBMError):
+        sim.scalar_advance(7.5, 0.0)  # beyond the 7-node departure range
     bad = np.array([W.morton_encode(np.array([9]), np.array([0]), np.array([0]))[0]], dtype=np.int64)
     with pytest.raises(lbm.LBMError):
         sim.scalar_set(bad, np.zeros((1, 512), dtype=np.float32))

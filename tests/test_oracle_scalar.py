@@ -110,3 +110,26 @@ def test_solid_body_rotation_third_order_backtrace():
     print("RK3 error", err, "first-order backtrace error", first_order)
     assert err < 1e-6 * np.abs(a).sum() * 16
     assert first_order > 100 * err
+
+
+def test_departure_points_stay_within_seven_nodes():
+    """A uniform velocity of more than one node per step carries the departure point
+    beyond the 7-node search range per axis: every sample point is held at 7 nodes, so
+    the field moves by exactly 7 nodes (not u dt) along the axes where u dt exceeds 7,
+    and by u dt where it does not."""
+    n = (32, 32, 32)
+    for U, dt, shift in [((1.5, 0.0, 0.0), 6.0, (7, 0, 0)),      # 9 nodes asked, 7 taken
+                         ((-2.0, 0.5, 0.0), 5.0, (-7, 2.5, 0)),  # -10 -> -7; y within range
+                         ((0.0, 0.0, 1.0), 7.0, (0, 0, 7))]:     # exactly at the limit
+        sim = O.OracleSim(1, n, (P,) * 6, 0.6)
+        _set_velocity(sim, lambda p: np.broadcast_to(np.array(U), p.shape).copy())
+        phi = _random_phi(sim, 3)
+        before = _dense(sim, phi, n)
+        sim.scalar_advance(dt, 0.0)
+        after = _dense(sim, sim.scalar_get(), n)
+        exp = before
+        for a, s in enumerate(shift):
+            whole = int(np.floor(s))
+            frac = s - whole
+            exp = (1.0 - frac) * np.roll(exp, whole, axis=a) + frac * np.roll(exp, whole + 1, axis=a)
+        assert np.abs(after - exp).max() < 1e-14, (U, dt)

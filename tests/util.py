@@ -86,3 +86,43 @@ def canonical_sets(levels, nblk0, periodic, t0):
                   for i in (0, 1) for j in (0, 1) for k in (0, 1)}
             active.append(ch - D[l])
     return active, D
+
+
+# ---- composite conservation sums over a multi-level state --------------------
+def composite_sums(levels, keys, vals, roles):
+    """FP64 sums over the composite grid: every owned node (not ghost, not solid)
+    of level l weighs 8^l fine-node volumes, and a node of level l+1 counts only if
+    level l does not own the node at the same position (coarse node q sits on fine
+    node 2q), so the overlap of two levels is counted once, on the finer one.
+    keys[l]: sorted block keys; vals[l]: [nb, 10, 512] moments with rho - 1 in slot 0;
+    roles[l]: [nb, 512]. Returns {"volume", "mass_excess" (sum w (rho - 1)),
+    "momentum" (sum w rho u, 3)}."""
+    out = {"volume": 0.0, "mass_excess": 0.0, "momentum": np.zeros(3)}
+    node = np.arange(512)
+    nx, ny, nz = node & 7, (node >> 3) & 7, node >> 6
+    for l in range(levels):
+        own = (roles[l] != 1) & (roles[l] != 3)
+        if l > 0 and len(keys[l]):
+            # the coincident node 2q of level l-1: block 2b + n // 4, node 2n % 8
+            bx, by, bz = W.morton_decode(np.asarray(keys[l]))
+            fb = [2 * bx[:, None] + (nx >> 2)[None], 2 * by[:, None] + (ny >> 2)[None],
+                  2 * bz[:, None] + (nz >> 2)[None]]
+            fk = W.morton_encode(fb[0].ravel(), fb[1].ravel(), fb[2].ravel()).reshape(fb[0].shape)
+            fn = ((2 * nx) & 7) + 8 * ((2 * ny) & 7) + 64 * ((2 * nz) & 7)
+            fine_keys = np.asarray(keys[l - 1])
+            covered = np.zeros_like(own)
+            if len(fine_keys):
+                idx = np.clip(np.searchsorted(fine_keys, fk), 0, len(fine_keys) - 1)
+                hit = fine_keys[idx] == fk
+                fr = roles[l - 1][idx, np.broadcast_to(fn[None], fk.shape)]
+                covered = hit & (fr != 1) & (fr != 3)
+            own = own & ~covered
+        w = float(8 ** l)
+        v = np.asarray(vals[l], dtype=np.float64)
+        r = v[:, 0][own]
+        rho = 1.0 + r
+        out["volume"] += w * own.sum()
+        out["mass_excess"] += w * r.sum()
+        for a in range(3):
+            out["momentum"][a] += w * (rho * v[:, 1 + a][own]).sum()
+    return out

@@ -190,6 +190,18 @@ lbm_status lbm_get_roles(lbm_ctx* ctx, int32_t level, uint8_t* out);
 lbm_status lbm_reduce_f64(lbm_ctx* ctx, int32_t level, const int32_t lo[3], const int32_t hi[3],
                           double out[5]);
 
+/* The sums of lbm_reduce_f64 for callers that cannot allocate device memory or
+ * wait on the stream (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): out is device double[5], written on cfg.stream without
+ * synchronising. The per-block partials live in a static device array of the
+ * library instead of the meta buffer: one per GPU, 2^18 blocks x 5 doubles
+ * (10 MiB), held until the process ends. LBM_EINVAL if the level has more than
+ * 2^18 blocks. Every call on a GPU shares that array: calls that overlap in time on
+ * one GPU (other streams, other contexts) race; calls on one stream are ordered.
+ * Allocates nothing. */
+lbm_status lbm_reduce_f64_noalloc(lbm_ctx* ctx, int32_t level, const int32_t lo[3], const int32_t hi[3],
+                                  double* out);
+
 /* LBM_ENAN if any stored moment of an active block is not finite. Synchronises. */
 lbm_status lbm_check_finite(lbm_ctx* ctx);
 

@@ -1,5 +1,7 @@
 // Moment upload / download, node roles, FP64 reductions, finiteness check and the
 // prescribed particle motion.
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -232,6 +234,30 @@ hipError_t launch_reduce(const IoLaunch& a, const int32_t lo[3], const int32_t h
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, (const double*)partial, a.nblocks, out);
   return hipGetLastError();
 }
+// One array per GPU, held until the process ends. In host code its name is a host-side
+// stand-in, not a device address: kernels get the address hipGetSymbolAddress returns
+// for the current device.
+static __device__ __align__(256) double scratch[kNoAllocReduceBlocks * 5];
+
+hipError_t noalloc_reduce_scratch(double** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
 hipError_t launch_finite(const IoLaunch& a, int32_t* flag, hipStream_t s) {
   if (a.nblocks <= 0) return hipSuccess;
   return dispatch<FinK>(a.storage, dim3(a.nblocks), dim3(256), s, a, flag);

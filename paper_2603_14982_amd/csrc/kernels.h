@@ -203,6 +203,11 @@ hipError_t launch_keys(const IoLaunch& a, int64_t* keys, hipStream_t s);
 hipError_t launch_reduce(const IoLaunch& a, const int32_t lo[3], const int32_t hi[3], double* partial,
                          double* out, hipStream_t s);
 hipError_t launch_finite(const IoLaunch& a, int32_t* flag, hipStream_t s);
+// partials of the reductions of callers that cannot allocate: a static device array of
+// kNoAllocReduceBlocks x 5 doubles per GPU; noalloc_reduce_scratch returns its device
+// address on the current device (looked up once per device)
+constexpr int64_t kNoAllocReduceBlocks = int64_t(1) << 18;
+hipError_t noalloc_reduce_scratch(double** out);
 hipError_t launch_advance_particles(float* p, int64_t n, float dx, float dy, float dz, hipStream_t s);
 
 // ---- adjoint (reverse mode) ----

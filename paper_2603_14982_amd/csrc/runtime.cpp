@@ -174,6 +174,7 @@ struct lbm_ctx {
   int fuse_substeps = 1;            // LBM_OPT_FUSE_SUBSTEPS: 0 never, 1 with FP32 storage, 2 always
   int32_t free_top = 0;
   int32_t* host_counts = nullptr;  // pinned
+  double* noalloc_partial = nullptr;  // this GPU's static reduction partials (lbm_reduce_f64_noalloc)
   std::string err;
   // phase timers (HIP events around launches, enabled on request)
   bool profiling = false;
@@ -895,6 +896,7 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
       "free list");
   c->free_top = (int32_t)c->cap;
   chk(launch_mark_static(G, solid_fine, c->m<uint8_t>(c->lay.t0s), c->stream), "static targets");
+  chk(noalloc_reduce_scratch(&c->noalloc_partial), "address of the static reduction partials");
   chk(hipStreamSynchronize(c->stream), "synchronise");
   if (st == LBM_OK) {
     st = rebuild(c, particles, n, true);
@@ -1098,6 +1100,17 @@ lbm_status lbm_reduce_f64(lbm_ctx* ctx, int32_t level, const int32_t lo[3], cons
   HIPCHK(ctx, launch_reduce(io_of(ctx, level), lo, hi, ctx->m<double>(ctx->lay.red_partial), dev, ctx->stream));
   HIPCHK(ctx, hipMemcpyAsync(out, dev, 5 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_reduce_f64_noalloc(lbm_ctx* ctx, int32_t level, const int32_t lo[3], const int32_t hi[3],
+                                  double* out) {
+  if (!level_ok(ctx, level) || !lo || !hi || !out) return ctx ? ctx->fail(LBM_EINVAL, "bad arguments") : LBM_EINVAL;
+  if (ctx->nblk[level] > kNoAllocReduceBlocks)
+    return ctx->fail(LBM_EINVAL, "level has more blocks than the static reduction partials hold (2^18)");
+  if (!ctx->noalloc_partial) return ctx->fail(LBM_EDEVICE, "static reduction partials not available");
+  // every partial the final pass reads is written by this call's first pass
+  HIPCHK(ctx, launch_reduce(io_of(ctx, level), lo, hi, ctx->noalloc_partial, out, ctx->stream));
   return LBM_OK;
 }
 

@@ -54,7 +54,7 @@ class LBMConfig(ctypes.Structure):
 
 EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm_num_blocks", "lbm_block_keys",
            "lbm_set_block_moments", "lbm_step", "lbm_advance_particles", "lbm_remesh", "lbm_get_moments",
-           "lbm_get_roles", "lbm_reduce_f64", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
+           "lbm_get_roles", "lbm_reduce_f64", "lbm_reduce_f64_noalloc", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
            "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
            "lbm_step_record", "lbm_adjoint_reverse",
            "lbm_loss_ke_grad", "lbm_set_option", "lbm_set_coupling",
@@ -90,6 +90,7 @@ def lib():
         L.lbm_get_moments.argtypes = [vp, i32, vp, vp]
         L.lbm_get_roles.argtypes = [vp, i32, vp]
         L.lbm_reduce_f64.argtypes = [vp, i32, vp, vp, vp]
+        L.lbm_reduce_f64_noalloc.argtypes = [vp, i32, vp, vp, vp]
         L.lbm_check_finite.argtypes = [vp]
         L.lbm_set_profiling.argtypes = [vp, i32]
         L.lbm_get_profile.argtypes = [vp, vp, vp]
@@ -262,6 +263,16 @@ class Sim:
         out = (ctypes.c_double * 5)()
         self._check(lib().lbm_reduce_f64(self.h, level, lo_, hi_, out))
         return np.array(list(out))
+
+    def reduce_noalloc(self, level, out, lo=(0, 0, 0), hi=None):
+        """The sums of reduce() into out (device float64 tensor of 5), asynchronously,
+        with the partials in the library's static device array."""
+        hi = self.n if hi is None else hi
+        assert out.dtype == torch.float64 and out.is_cuda and out.numel() >= 5 and out.is_contiguous()
+        lo_ = (ctypes.c_int32 * 3)(*lo)
+        hi_ = (ctypes.c_int32 * 3)(*hi)
+        self._check(lib().lbm_reduce_f64_noalloc(self.h, level, lo_, hi_, ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def set_coupling(self, keys, fields):
         """Finest-level coupling fields (needs coupling=True): keys of level-0 blocks and

@@ -11,10 +11,15 @@ the particle advance and one grid update.
 
 Prints one JSON line. `value` is MLUPS (computed-node updates per second over
 the whole step, grid update included). The roofline object is the dominant
-kernel, level 0's stream-collide on 2 x 2 x 2 block tiles (4 launches per coarse
-step): algorithmic bytes (80 B per computed-node update: 10 f32 moments read and
-written) per launch over its HIP-event-timed average launch duration; the same
-figures over every stream-collide launch of all levels are given beside it.
+kernel, level 0's stream-collide on 2 x 2 x 2 block tiles: with FP32 storage both
+substeps of a level-1 step in one launch (2 launches per coarse step), otherwise
+one substep per launch (4 per coarse step). `achieved` is its algorithmic bytes
+(80 B per computed-node update: 10 f32 moments read and written, counted per
+update, so a launch of two updates counts 160 B per node) over its HIP-event-timed
+average launch duration; `hbm_achieved` is the HBM traffic the counters measured
+for that launch (`traffic`, when the stored counter run matches the kernel source)
+over the same duration. The same figures over every stream-collide launch of all
+levels are given beside it.
 """
 import argparse
 import hashlib
@@ -55,47 +60,91 @@ def computed_nodes(sim):
     return [int((sim.roles(l) == 0).sum().item()) for l in range(sim.levels)]
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(W):
-    """The oracle on a bounded sample of the same workload: the three-level slab
-    case scaled to 128^3 (particles 2M/64 in the scaled slab), 2 coarse steps with
-    particle advance and grid update, after one warm-up step."""
+    """The oracle on the benchmark's own inputs: the 512^3 three-level slab hierarchy of
+    2M particles with the Taylor-Green field, one coarse step (4 finest substeps, every
+    transfer) plus the particle advance and the grid update, timed once after the
+    hierarchy is built (building it is not timed); its node updates per second. The
+    same single step on one core would take minutes, so the one-core figure is taken on
+    the workload scaled to 128^3 (31,250 particles in the scaled slab)."""
     import numpy as np
     from oracle import oracle as O
-    n = (128, 128, 128)
-    p = W.slab_particles(2_000_000 // 64, 3, (16.0, 16.0, 88.0), (112.0, 112.0, 96.0))
-    sim = O.OracleSim(3, n, (W.PERIODIC,) * 6, 0.6, particles=p)
+    wl = W.workload("slab512")
+    p = W.slab_particles(wl["particles"], wl["seed"], wl["lo"], wl["hi"])
+    sim = O.OracleSim(3, wl["n"], wl["bc"], wl["tau0"], particles=p)
     for l in range(3):
         keys = sim.block_keys(l)
-        sim.set_block_moments(l, keys, W.tgv3d_field(l, keys, n, 0.05))
+        for s in range(0, len(keys), 2048):
+            k = keys[s:s + 2048]
+            sim.set_block_moments(l, k, W.tgv3d_field(l, k, wl["n"], wl["amp"]))
     roles = [sim.roles(l) for l in range(3)]
     updates = sum((roles[l] == 0).sum() * (1 << (2 - l)) for l in range(3))
-    d = np.array([0.0, 0.0, -0.08], dtype=np.float32)
-
-    def one():
-        sim.step(1)
-        O.advance_particles(p, d)
-        sim.remesh(p)
-
-    one()
-    reps = 2
+    d = np.array([v * 4 for v in wl["v_fine"]], dtype=np.float32)
     cores = O.num_threads()
     t0 = time.perf_counter()
-    for _ in range(reps):
-        one()
-    dt = (time.perf_counter() - t0) / reps
-    # the same coarse step on one core
+    sim.step(1)
+    O.advance_particles(p, d)
+    sim.remesh(p)
+    dt = time.perf_counter() - t0
+    del sim
+    # one core, on the slab scaled to 128^3
+    n = (128, 128, 128)
+    ps = W.slab_particles(2_000_000 // 64, 3, (16.0, 16.0, 88.0), (112.0, 112.0, 96.0))
+    small = O.OracleSim(3, n, (W.PERIODIC,) * 6, 0.6, particles=ps)
+    for l in range(3):
+        keys = small.block_keys(l)
+        small.set_block_moments(l, keys, W.tgv3d_field(l, keys, n, 0.05))
+    r = [small.roles(l) for l in range(3)]
+    small_updates = sum((r[l] == 0).sum() * (1 << (2 - l)) for l in range(3))
     O.set_num_threads(1)
     try:
         t0 = time.perf_counter()
-        one()
+        small.step(1)
+        O.advance_particles(ps, d)
+        small.remesh(ps)
         dt1 = time.perf_counter() - t0
     finally:
         O.set_num_threads(cores)
     return {"value": round(float(updates) / dt / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "single_core": round(float(updates) / dt1 / 1e6, 3),
-            "sample": "FP64 oracle, same three-level slab workload scaled to 128^3 (31,250 particles), "
-                      f"{reps} coarse steps with grid update after 1 warm-up, then 1 more on one core; "
-                      f"{int(updates)} node updates per step"}
+            "cpu": cpu_model(),
+            "single_core": round(float(small_updates) / dt1 / 1e6, 3),
+            "sample": "FP64 oracle on the benchmark's inputs (512^3, 3 levels, 2M particles, Taylor-Green): one "
+                      f"coarse step with particle advance and grid update, {int(updates)} node updates, "
+                      f"{dt:.1f} s on {cores} threads; single_core: the same step on the slab scaled to 128^3 "
+                      f"({int(small_updates)} node updates) on one thread"}
+
+
+def remesh_change(sim, particles, torch, ms_per_step, reps=4):
+    """Grid updates that change the block set: the particles move by one level-0 block
+    (8 fine nodes) along x and back, so every update creates and deletes blocks on every
+    level and initialises the new ones; each update timed alone (host wall clock around
+    lbm_remesh, with the device synchronised before and after)."""
+    times = []
+    before = sim.block_keys(0).cpu()
+    for k in range(reps):
+        sim.advance_particles(particles, (8.0 if k % 2 == 0 else -8.0, 0.0, 0.0))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.remesh(particles)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        keys = sim.block_keys(0).cpu()
+        assert keys.shape != before.shape or not torch.equal(keys, before), "the block set did not change"
+        before = keys
+    ms = sum(times) / len(times) * 1e3
+    return {"ms": round(ms, 4), "frac_of_step": round(ms / ms_per_step, 4), "updates": reps,
+            "note": "particles moved by one level-0 block (8 fine nodes) along x and back; every update "
+                    "changes the block set of every level"}
 
 
 def adjoint_ratio(lbm, W, torch):
@@ -153,6 +202,63 @@ def adjoint_ratio(lbm, W, torch):
                           "note": "no checkpoints: the forward pass keeps its undo log in HBM"}}
 
 
+def adjoint_slab(lbm, W, torch, steps=10, every=5):
+    """Adjoint/forward time ratio on the benchmark's hierarchy held fixed (512^3, 3 levels,
+    39,060 blocks, states far beyond the caches): `steps` coarse steps, checkpoints every
+    `every`; and the transposed stream-collide's achieved bandwidth against its
+    algorithmic bytes (160 B per node: state and mu read, the adjoint read and written;
+    280 B when the launch also takes the next stream-collide's first pass: its tape read,
+    the state restored, its mu written)."""
+    wl = W.workload("slab512")
+    p = torch.as_tensor(W.slab_particles(wl["particles"], wl["seed"], wl["lo"], wl["hi"])).cuda()
+    sim = lbm.Sim(wl["levels"], wl["n"], wl["bc"], wl["tau0"], particles=p, max_blocks=48000)
+    init_fields(sim, wl, W)
+    nodes = computed_nodes(sim)
+    box = ((0, 0, 0), (512, 512, 512))
+    x0 = sim.get_all_moments().clone()
+    x = x0.clone().requires_grad_(True)
+    lbm.rollout(sim, x, every, checkpoint_every=every).backward(sim.loss_ke_grad(0, *box))  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    x = x0.clone().requires_grad_(True)
+    xt = lbm.rollout(sim, x, steps, checkpoint_every=every)
+    seed = sim.loss_ke_grad(0, *box)
+    torch.cuda.synchronize()
+    sim.profile()
+    sim.set_profiling(True)
+    t0 = time.perf_counter()
+    xt.backward(seed)
+    torch.cuda.synchronize()
+    bwd = time.perf_counter() - t0
+    sim.set_profiling(False)
+    prof = sim.profile()
+    # per coarse step the reverse sweep transposes 4 level-0, 2 level-1 and 1 level-2
+    # stream-collides; two level-0 launches also take the next one's first pass
+    ms_u, n_u = prof["adj_sc"]
+    ms_f, n_f = prof["adj_sc_fused"]
+    bytes_u = 160.0 * steps * (2 * nodes[0] + 2 * nodes[1] + nodes[2])
+    bytes_f = 280.0 * steps * 2 * nodes[0]
+    out = {"value": round(bwd / fwd, 3), "forward_ms_per_step": round(fwd / steps * 1e3, 4),
+           "backward_ms_per_step": round(bwd / steps * 1e3, 4),
+           "workload": f"slab512 hierarchy held fixed (no grid updates), {steps} coarse steps, checkpoints every "
+                       f"{every}, loss = kinetic energy of level 0",
+           "transpose": None}
+    if n_u == steps * 5 and n_f == steps * 2:
+        achieved = (bytes_u + bytes_f) / ((ms_u + ms_f) / 1e3) / 1e9
+        out["transpose"] = {"kernel": "k_sc_transpose<StoreF32> (all levels)", "achieved": round(achieved, 1),
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                            "launches": n_u + n_f,
+                            "avg_launch_ms": round((ms_u + ms_f) / (n_u + n_f), 5),
+                            "ms_per_step": round((ms_u + ms_f) / steps, 4),
+                            "other_adjoint_ms_per_step": round(prof["adj"][0] / steps, 4)}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +274,8 @@ def main():
                     help="print only the adjoint/forward measurement (for profiling the adjoint kernels)")
     ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32",
                     help="moment storage format (FP32 arithmetic in every case)")
+    ap.add_argument("--no-adjoint-slab", action="store_true",
+                    help="skip the adjoint/forward ratio on the benchmark's (fixed) hierarchy")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -296,6 +404,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "hbm_achieved": round(traffic / sc_avg_s / 1e9, 1) if traffic else None,
+            "hbm_frac": round(traffic / sc_avg_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
             "valu": valu,
             "kernel": kernel,
             "algorithmic_bytes_per_launch": int(alg_bytes),
@@ -309,6 +419,7 @@ def main():
         "adjoint_forward_ratio": None,  # filled below
         "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]},
     }
+    out["remesh_block_change"] = remesh_change(sim, particles, torch, ms_per_step)
     if args.calibrate_copy_mib > 0:
         # one elementwise kernel that reads and writes the buffer once (torch's neg)
         src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
@@ -320,6 +431,11 @@ def main():
     if not args.no_adjoint:
         print("[bench] adjoint/forward ratio (adjoint128)", file=sys.stderr, flush=True)
         out["adjoint_forward_ratio"] = adjoint_ratio(lbm, W, torch)
+    if not args.no_adjoint and not args.no_adjoint_slab:
+        del sim
+        torch.cuda.empty_cache()
+        print("[bench] adjoint/forward ratio (slab512 hierarchy, fixed)", file=sys.stderr, flush=True)
+        out["adjoint_forward_ratio"]["slab512"] = adjoint_slab(lbm, W, torch)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W)

@@ -121,6 +121,23 @@ lbm_status lbm_set_block_moments(lbm_ctx* ctx, int32_t level, const int64_t* key
  * each fine stream-collide, upward transfer (Eq. upload_S) after the second. */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
 
+/* Advances n finest-level steps: Alg. 1 with a stop after every finest-level
+ * stream-collide, the exchange point of the coupling loop (Sec. 5.4 and Fig. pipeline:
+ * fluid step, granular step, exchange; Sec. 7 runs one granular step per finest LBM
+ * step). A coarse step is 2^(L-1) finest steps. After each one the finest level's
+ * stored moments (the state before collision, where an external solver reads u and
+ * supplies the next F through lbm_set_coupling) are one finest step on; coarser levels
+ * are where Alg. 1 has taken them (ahead of the finest level inside a coarse step).
+ * The finest level runs one stream-collide per substep (never the two-substep sweep),
+ * so a whole coarse step taken this way computes what lbm_step computes. While a
+ * coarse step is under way (lbm_finest_phase != 0), lbm_step, lbm_remesh,
+ * lbm_set_block_moments, lbm_save, lbm_load and the adjoint calls return LBM_ESTATE.
+ * Async.
+ * lbm_finest_phase: finest steps taken since the last coarse-step boundary (0 at a
+ * boundary). Host-side. */
+lbm_status lbm_step_finest(lbm_ctx* ctx, int32_t n);
+lbm_status lbm_finest_phase(lbm_ctx* ctx, int32_t* out);
+
 /* Coupling fields of the finest level, the hook for an external granular solver
  * (Sec. 4): per node the fluid fraction eps, which scales the relaxation time to
  * eps tau0, and a force density F (lattice units, the external part of the paper's
@@ -131,7 +148,8 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
  * moments between steps are the state before collision, where the external solver
  * reads the velocity and supplies the next F.
  * keys: device int64 [nb], keys of active finest-level blocks (lbm_block_keys);
- * fields: device f32 [nb][4][512] = (eps, Fx, Fy, Fz) per node. Blocks keep their
+ * fields: device f32 [nb][4][512] = (eps, Fx, Fy, Fz) per node (may be called between
+ * the finest steps of lbm_step_finest). Blocks keep their
  * fields until set again; blocks created by a grid update start at eps = 1, F = 0;
  * solid nodes keep eps = 1, F = 0. Requires cfg.coupling = 1 (LBM_EINVAL otherwise).
  * LBM_EINVAL, with no field changed, if a key is not an active finest-level block or
@@ -210,8 +228,11 @@ lbm_status lbm_check_finite(lbm_ctx* ctx);
  * milliseconds and launch counts per phase since the last call, and resets them.
  * Phases: stream-collide of levels 0..4 (one substep per launch), downward
  * transfers, upward transfers, outflow copies, whole grid updates (lbm_remesh, host
- * time between its events included), and the finest level's two substeps of a
- * parent step in one launch (see LBM_OPT_FUSE_SUBSTEPS). */
+ * time between its events included), the finest level's two substeps of a
+ * parent step in one launch (see LBM_OPT_FUSE_SUBSTEPS), and in the adjoint's reverse
+ * sweep: the transposed stream-collide (k_sc_transpose), the same launch when it also
+ * takes the first pass of the next stream-collide in the sweep, and every other
+ * adjoint launch (first passes, transfers, outflow). */
 enum {
   LBM_PROF_SC0 = 0,            /* + level */
   LBM_PROF_DOWN = 5,
@@ -219,7 +240,10 @@ enum {
   LBM_PROF_OUTFLOW = 7,
   LBM_PROF_REMESH = 8,
   LBM_PROF_SC_PAIR = 9,
-  LBM_PROFILE_PHASES = 10
+  LBM_PROF_ADJ_SC = 10,
+  LBM_PROF_ADJ_SC_FUSED = 11,
+  LBM_PROF_ADJ = 12,
+  LBM_PROFILE_PHASES = 13
 };
 lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t on);
 lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t count[LBM_PROFILE_PHASES]);
@@ -299,9 +323,34 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes
  * adjoint of the final state (lam_next) into that of the state before the recorded
  * steps (lam_out) and puts the simulation back at that state. The reverse call takes
  * the same work buffer; LBM_ESTATE if nothing is recorded in it (lbm_step,
- * lbm_remesh, lbm_load and lbm_set_block_moments in between drop the recording). */
+ * lbm_remesh, lbm_load and lbm_set_block_moments in between drop the recording).
+ * lbm_adjoint_reverse also takes the recordings of lbm_record_begin / lbm_record_end
+ * (below), grid updates included. */
 lbm_status lbm_step_record(lbm_ctx* ctx, int32_t n_steps, void* work, size_t work_bytes);
 lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_out, void* work, size_t work_bytes);
+
+/* A recording that may include grid updates (Sec. 6.3), for the adjoint of adaptive
+ * runs: between lbm_record_begin and lbm_record_end, lbm_step runs its coarse steps
+ * with the undo log (one stream-collide per finest substep) and lbm_remesh logs every
+ * grid update that changes the block set: the meta buffer and both time levels of
+ * every block before it. lbm_adjoint_reverse then walks the whole log back: the
+ * adjoint of a grid update sends the adjoint of every node the update wrote through
+ * the transposed new-node sampler (own value, upward from the nearest finer level
+ * with S^neq times a_up, trilinear downward with a_down) into the nodes of the old
+ * hierarchy it was sampled from, and restores the old hierarchy. lam_next is then in
+ * the layout of the hierarchy at lbm_record_end, lam_out in that of the hierarchy at
+ * lbm_record_begin (its block count), and the simulation returns to the state and
+ * hierarchy at lbm_record_begin.
+ * While a recording is open, lbm_set_block_moments, lbm_load, lbm_step_finest,
+ * lbm_step_record and lbm_adjoint_reverse return LBM_ESTATE; LBM_ECAPACITY when the log
+ * is full (the step or update that did not fit is not applied, the recording stays
+ * open; close it and start again with a larger buffer).
+ * lbm_record_work_bytes: a work size for n_steps coarse steps and n_updates grid
+ * updates on hierarchies the size of the current one (the adjoint buffers sized for
+ * the pool capacity, so that any hierarchy fits them). Synchronises: no. */
+size_t lbm_record_work_bytes(const lbm_ctx* ctx, int32_t n_steps, int32_t n_updates);
+lbm_status lbm_record_begin(lbm_ctx* ctx, void* work, size_t work_bytes);
+lbm_status lbm_record_end(lbm_ctx* ctx);
 
 /* Adjoint seed of the kinetic energy 1/2 sum rho |u|^2 over the owned nodes of
  * `level` whose fine position lies in [lo, hi): writes lam (device f32, the

@@ -47,6 +47,7 @@
 #include <array>
 #include <cmath>
 #include <complex>
+#include <functional>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -872,10 +873,60 @@ template <class T> struct Sim {
 
   // Alg. 1
   void advance(int l, int s) {
+    if (ops_taken != 0) throw std::runtime_error("a coarse step is under way (finest steps)");
     if (l < L - 1) downward(l, s);
     stream_collide(l);
     if (l < L - 1 && s == 2) upward(l);
     if (l > 0) { advance(l - 1, 1); advance(l - 1, 2); }
+  }
+
+  // --- finest-level steps: the coupling loop exchanges with the granular solver
+  //     after every finest-level step (Sec. 5.4, Fig. pipeline; Sec. 7). The walk is
+  //     the recursion of Alg. 1 for the current coarse step; an operation runs only if
+  //     it is the next one not yet taken and finest steps remain to be taken. A finest
+  //     step ends with the finest level's stream-collide (and, on its second substep,
+  //     the upward transfer that follows it).
+  long ops_taken = 0;  // operations of the current coarse step taken so far
+  long ops_seen = 0;   // operations met by the current walk
+  int fine_left = 0;   // finest steps this call still has to take
+  bool due() {
+    const bool run = fine_left > 0 && ops_seen == ops_taken;
+    ++ops_seen;
+    if (run) ++ops_taken;
+    return run;
+  }
+  void walk(int l, int s) {
+    if (l < L - 1 && due()) downward(l, s);
+    const bool sc = due();
+    if (sc) stream_collide(l);
+    if (l < L - 1 && s == 2 && due()) upward(l);
+    if (l == 0 && sc) --fine_left;
+    if (l > 0) { walk(l - 1, 1); walk(l - 1, 2); }
+  }
+  void step_finest(int n) {
+    fine_left = n;
+    while (fine_left > 0) {
+      ops_seen = 0;
+      walk(L - 1, 1);
+      if (ops_taken == ops_seen) ops_taken = 0;  // the coarse step is complete
+    }
+  }
+  int finest_phase() const {
+    // finest steps whose stream-collide is among the operations taken: count them by
+    // walking the operation numbers of Alg. 1's recursion
+    long seen = 0;
+    int k = 0;
+    std::function<void(int, int)> count = [&](int l, int s) {
+      if (l < L - 1) ++seen;
+      if (seen++ < ops_taken && l == 0) ++k;
+      if (l < L - 1 && s == 2) ++seen;
+      if (l > 0) { count(l - 1, 1); count(l - 1, 2); }
+    };
+    count(L - 1, 1);
+    return k;
+  }
+  void need_boundary(const char* what) const {
+    if (ops_taken != 0) throw std::runtime_error(std::string(what) + ": a coarse step is under way (finest steps)");
   }
 
   // --- grid update (Sec. 6.3) ---
@@ -1151,9 +1202,19 @@ int oc_step(void* h, int n) {
   } catch (const std::exception& e) { g_err = e.what(); return -1; }
   return 0;
 }
+int oc_step_finest(void* h, int n) {
+  auto* s = static_cast<OSim*>(h);
+  try { s->step_finest(n); }
+  catch (const std::exception& e) { g_err = e.what(); return -1; }
+  return 0;
+}
+int oc_finest_phase(void* h) { return static_cast<OSim*>(h)->finest_phase(); }
 int oc_remesh(void* h, const float* particles, int64_t np) {
   auto* s = static_cast<OSim*>(h);
-  try { return s->remesh(particles, np); }
+  try {
+    s->need_boundary("remesh");
+    return s->remesh(particles, np);
+  }
   catch (const std::exception& e) { g_err = e.what(); return -1; }
 }
 double oc_loss_ke(void* h, int level, const int32_t lo[3], const int32_t hi[3]) {
@@ -1200,6 +1261,11 @@ int occ_step(void* h, int n) {
     for (int i = 0; i < n; ++i) s->advance(s->L - 1, 1);
   } catch (const std::exception& e) { g_err = e.what(); return -1; }
   return 0;
+}
+int occ_remesh(void* h, const float* particles, int64_t np) {
+  auto* s = static_cast<CSim*>(h);
+  try { return s->remesh(particles, np); }
+  catch (const std::exception& e) { g_err = e.what(); return -1; }
 }
 void occ_loss_ke(void* h, int level, const int32_t lo[3], const int32_t hi[3], double out[2]) {
   const std::complex<double> v = static_cast<CSim*>(h)->kinetic_energy(level, lo, hi);

@@ -80,6 +80,10 @@ def lib():
         L.oc_get_roles.argtypes = [vp, i32, vp]
         L.oc_step.restype = i32
         L.oc_step.argtypes = [vp, i32]
+        L.oc_step_finest.restype = i32
+        L.oc_step_finest.argtypes = [vp, i32]
+        L.oc_finest_phase.restype = i32
+        L.oc_finest_phase.argtypes = [vp]
         L.oc_remesh.restype = i32
         L.oc_remesh.argtypes = [vp, vp, i64]
         L.oc_advance_particles.argtypes = [vp, i64, vp]
@@ -100,6 +104,8 @@ def lib():
         L.occ_step.restype = i32
         L.occ_step.argtypes = [vp, i32]
         L.occ_loss_ke.argtypes = [vp, i32, vp, vp, vp]
+        L.occ_remesh.restype = i32
+        L.occ_remesh.argtypes = [vp, vp, i64]
         L.oc_store_round.restype = ctypes.c_double
         L.oc_store_round.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_double]
         _lib = L
@@ -206,6 +212,14 @@ class OracleSim:
         if lib().oc_step(self.h, n) != 0:
             raise RuntimeError(lib().oc_last_error().decode())
 
+    def step_finest(self, n=1):
+        """n finest-level steps (Alg. 1 walked up to the end of each finest step)."""
+        if lib().oc_step_finest(self.h, int(n)) != 0:
+            raise RuntimeError(lib().oc_last_error().decode())
+
+    def finest_phase(self):
+        return int(lib().oc_finest_phase(self.h))
+
     def remesh(self, particles):
         p = np.ascontiguousarray(particles, dtype=np.float32)
         if lib().oc_remesh(self.h, _ptr(p), p.shape[0]) != 0:
@@ -279,6 +293,13 @@ class OracleSimComplex:
     def step(self, n=1):
         if lib().occ_step(self.h, n) != 0:
             raise RuntimeError(lib().oc_last_error().decode())
+
+    def remesh(self, particles):
+        """Grid update of both the complex instance and the real one that names its blocks."""
+        p = np.ascontiguousarray(particles, dtype=np.float32)
+        if lib().occ_remesh(self.h, _ptr(p), p.shape[0]) < 0:
+            raise RuntimeError(lib().oc_last_error().decode())
+        self._real.remesh(p)
 
     def kinetic_energy(self, level, lo, hi):
         lo_ = np.array(lo, dtype=np.int32)

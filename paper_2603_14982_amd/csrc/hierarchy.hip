@@ -392,40 +392,40 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
 }
 
 // ---------------------------------------------------------------- new-node initialisation
-// Value of level-l node g in the old hierarchy, accumulated linearly in
-// (rho-1, u, S^neq) with weight w and S^neq factor sf: the node's own value if
-// owned; else the nearest finer level owning the coincident node (upward, S^neq
-// times a_up per level); else trilinear from level l+1 (downward, times a_down).
+// Value of level-l node g in the old hierarchy, as a linear combination in
+// (rho-1, u, S^neq) of old owned nodes with weight w and S^neq factor sf: the node's
+// own value if owned; else the nearest finer level owning the coincident node
+// (upward, S^neq times a_up per level); else trilinear from level l+1 (downward,
+// times a_down). visit() hands every source node with its weight and factor to fn.
 template <class S> struct Sampler {
   const InitLaunch& a;
   __device__ explicit Sampler(const InitLaunch& x) : a(x) {}
 
-  __device__ bool owned(int l, int gx, int gy, int gz, float q[kMom]) const {
-    const LevelGeom& g = a.G.lv[l];
+  // slot and node of level-k node (gx, gy, gz) if the old hierarchy owns it
+  __device__ bool source(int k, int gx, int gy, int gz, int32_t& slot, int& node) const {
+    const LevelGeom& g = a.G.lv[k];
     const int64_t c = g.off + cell_lin(g, gx >> 3, gy >> 3, gz >> 3);
     if (a.st_old[c] != ST_ACTIVE) return false;
-    const int32_t slot = a.dir_old[c];
+    slot = a.dir_old[c];
     if (slot < 0) return false;
-    const int node = (gx & 7) + 8 * (gy & 7) + 64 * (gz & 7);
+    node = (gx & 7) + 8 * (gy & 7) + 64 * (gz & 7);
     const uint8_t r = a.role_old[(size_t)slot * kNodes + node] & ROLE_MASK;
-    if (!(r == ROLE_COMPUTED || r == ROLE_IU || r == ROLE_INFLOW || r == ROLE_OUTFLOW)) return false;
-    const typename S::type* p = static_cast<const typename S::type*>(a.cur[l]) + (size_t)slot * kBlockStride + node;
+    return r == ROLE_COMPUTED || r == ROLE_IU || r == ROLE_INFLOW || r == ROLE_OUTFLOW;
+  }
+  __device__ void load(int k, int32_t slot, int node, float q[kMom]) const {
+    const typename S::type* p = static_cast<const typename S::type*>(a.cur[k]) + (size_t)slot * kBlockStride + node;
 #pragma unroll
     for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(p[m * kNodes], a.sc.inv[m]);
-    return true;
   }
 
-  __device__ bool upchain(int l, const int g[3], float w, float sf, float acc[kMom]) const {
+  template <class F> __device__ bool upchain(int l, const int g[3], float w, float sf, F& fn) const {
     float f = sf;
     for (int k = l; k >= 0; --k) {
       const int sh = l - k;
-      float q[kMom];
-      if (owned(k, g[0] << sh, g[1] << sh, g[2] << sh, q)) {
-        acc[0] += w * q[0];
-        acc[1] += w * q[1]; acc[2] += w * q[2]; acc[3] += w * q[3];
-        const float ws = w * f;
-        acc[4] += ws * (q[4] - q[1] * q[1]); acc[5] += ws * (q[5] - q[2] * q[2]); acc[6] += ws * (q[6] - q[3] * q[3]);
-        acc[7] += ws * (q[7] - q[1] * q[2]); acc[8] += ws * (q[8] - q[1] * q[3]); acc[9] += ws * (q[9] - q[2] * q[3]);
+      int32_t slot;
+      int node;
+      if (source(k, g[0] << sh, g[1] << sh, g[2] << sh, slot, node)) {
+        fn(k, slot, node, w, f);
         return true;
       }
       if (k > 0) f *= a.a_up[k - 1];
@@ -433,9 +433,9 @@ template <class S> struct Sampler {
     return false;
   }
 
-  template <int D>
-  __device__ bool sample(int l, const int g[3], float w, float sf, float acc[kMom]) const {
-    if (upchain(l, g, w, sf, acc)) return true;
+  template <int D, class F>
+  __device__ bool visit(int l, const int g[3], float w, float sf, F& fn) const {
+    if (upchain(l, g, w, sf, fn)) return true;
     if constexpr (D == 0) {
       return false;
     } else {
@@ -459,12 +459,38 @@ template <class S> struct Sampler {
         for (int ky = 0; ky < cnt[1]; ++ky)
           for (int kx = 0; kx < cnt[0]; ++kx) {
             const int j[3] = {cand[0][kx], cand[1][ky], cand[2][kz]};
-            ok = sample<D - 1>(l + 1, j, w * wv[0][kx] * wv[1][ky] * wv[2][kz], sf * a.a_down[l], acc) && ok;
+            ok = visit<D - 1>(l + 1, j, w * wv[0][kx] * wv[1][ky] * wv[2][kz], sf * a.a_down[l], fn) && ok;
           }
       return ok;
     }
   }
+
+  // accumulated (rho-1, u, S^neq) of V_old(l, g)
+  __device__ void sample(int l, const int g[3], float acc[kMom]) const {
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
+    auto add = [&](int k, int32_t slot, int node, float w, float f) {
+      float q[kMom];
+      load(k, slot, node, q);
+      acc[0] += w * q[0];
+      acc[1] += w * q[1]; acc[2] += w * q[2]; acc[3] += w * q[3];
+      const float ws = w * f;
+      acc[4] += ws * (q[4] - q[1] * q[1]); acc[5] += ws * (q[5] - q[2] * q[2]); acc[6] += ws * (q[6] - q[3] * q[3]);
+      acc[7] += ws * (q[7] - q[1] * q[2]); acc[8] += ws * (q[8] - q[1] * q[3]); acc[9] += ws * (q[9] - q[2] * q[3]);
+    };
+    visit<kMaxLevels - 1>(l, g, 1.0f, 1.0f, add);
+  }
 };
+
+// the nodes a grid update writes in a block of the new hierarchy: every node of a new
+// block, and the nodes of a surviving block that become owned
+__device__ inline bool fresh_node(const InitLaunch& a, bool new_block, int32_t slot, int node, uint8_t rn) {
+  if (new_block) return true;
+  const uint8_t ro = a.role_old[(size_t)slot * kNodes + node] & ROLE_MASK;
+  const bool own_old = ro == ROLE_COMPUTED || ro == ROLE_IU || ro == ROLE_INFLOW || ro == ROLE_OUTFLOW;
+  const bool own_new = rn == ROLE_COMPUTED || rn == ROLE_IU || rn == ROLE_INFLOW || rn == ROLE_OUTFLOW;
+  return !own_old && own_new;
+}
 
 template <class S>
 __global__ __launch_bounds__(256) void k_init(InitLaunch a) {
@@ -489,14 +515,7 @@ __global__ __launch_bounds__(256) void k_init(InitLaunch a) {
   }
   for (int node = threadIdx.x; node < kNodes; node += 256) {
     const uint8_t rn = a.role_new[(size_t)slot * kNodes + node] & ROLE_MASK;
-    bool fresh = new_block;
-    if (!fresh) {
-      const uint8_t ro = a.role_old[(size_t)slot * kNodes + node] & ROLE_MASK;
-      const bool own_old = ro == ROLE_COMPUTED || ro == ROLE_IU || ro == ROLE_INFLOW || ro == ROLE_OUTFLOW;
-      const bool own_new = rn == ROLE_COMPUTED || rn == ROLE_IU || rn == ROLE_INFLOW || rn == ROLE_OUTFLOW;
-      fresh = !own_old && own_new;
-    }
-    if (!fresh) continue;
+    if (!fresh_node(a, new_block, slot, node, rn)) continue;
     float q[kMom];
 #pragma unroll
     for (int m = 0; m < kMom; ++m) q[m] = 0.0f;
@@ -508,9 +527,7 @@ __global__ __launch_bounds__(256) void k_init(InitLaunch a) {
     } else if (rn != ROLE_SOLID && !a.create) {
       const int gn[3] = {b[0] * kEdge + (node & 7), b[1] * kEdge + ((node >> 3) & 7), b[2] * kEdge + (node >> 6)};
       float acc[kMom];
-#pragma unroll
-      for (int m = 0; m < kMom; ++m) acc[m] = 0.0f;
-      smp.template sample<kMaxLevels - 1>(a.level, gn, 1.0f, 1.0f, acc);
+      smp.sample(a.level, gn, acc);
       q[0] = acc[0];
       q[1] = acc[1]; q[2] = acc[2]; q[3] = acc[3];
       q[4] = acc[4] + acc[1] * acc[1]; q[5] = acc[5] + acc[2] * acc[2]; q[6] = acc[6] + acc[3] * acc[3];
@@ -521,6 +538,66 @@ __global__ __launch_bounds__(256) void k_init(InitLaunch a) {
       const T v = Codec<S>::store(q[m], a.sc.s[m]);
       cur[m * kNodes + node] = v;
       oth[m * kNodes + node] = v;
+    }
+  }
+}
+
+// Adjoint of k_init (reverse sweep of a recorded grid update): the pool holds the old
+// state again and the tables of both hierarchies are in place. For every node the
+// update wrote, its adjoint (both time levels: the update wrote the same value into
+// each) goes through the transposed sampler into the adjoint of the old nodes it was
+// sampled from, and is then cleared. Sources are nodes the old hierarchy owns, written
+// nodes are not, so the atomic adds never touch a node read in the same launch.
+template <class S>
+__global__ __launch_bounds__(256) void k_init_adj(InitAdjLaunch x) {
+  const InitLaunch& a = x.f;
+  const LevelGeom& g = a.G.lv[a.level];
+  const int32_t cell = a.cells[blockIdx.x];
+  const int32_t slot = a.dir_new[g.off + cell];
+  if (slot < 0) return;
+  const bool new_block = a.st_old[g.off + cell] != ST_ACTIVE;
+  const int b[3] = {cell % g.nb[0], (cell / g.nb[0]) % g.nb[1], cell / (g.nb[0] * g.nb[1])};
+  Sampler<S> smp(a);
+  float* lc = x.lam[x.parity[a.level]] + (size_t)slot * kBlockStride;
+  float* lo = x.lam[1 - x.parity[a.level]] + (size_t)slot * kBlockStride;
+  for (int node = threadIdx.x; node < kNodes; node += 256) {
+    const uint8_t rn = a.role_new[(size_t)slot * kNodes + node] & ROLE_MASK;
+    if (!fresh_node(a, new_block, slot, node, rn)) continue;
+    if (rn != ROLE_INFLOW && rn != ROLE_SOLID) {
+      const int gn[3] = {b[0] * kEdge + (node & 7), b[1] * kEdge + ((node >> 3) & 7), b[2] * kEdge + (node >> 6)};
+      float acc[kMom], lq[kMom], la[kMom];
+      smp.sample(a.level, gn, acc);
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) lq[m] = lc[m * kNodes + node] + lo[m * kNodes + node];
+      // q = (acc0, acc_u, acc_N + acc_u acc_u)
+      la[0] = lq[0];
+#pragma unroll
+      for (int m = 4; m < kMom; ++m) la[m] = lq[m];
+      la[1] = lq[1] + 2.0f * acc[1] * lq[4] + acc[2] * lq[7] + acc[3] * lq[8];
+      la[2] = lq[2] + 2.0f * acc[2] * lq[5] + acc[1] * lq[7] + acc[3] * lq[9];
+      la[3] = lq[3] + 2.0f * acc[3] * lq[6] + acc[1] * lq[8] + acc[2] * lq[9];
+      // each source: (rho-1, u, f (S - u u)) with weight w
+      auto scatter = [&](int k, int32_t s, int nd, float w, float f) {
+        float q[kMom];
+        smp.load(k, s, nd, q);
+        float* t = x.lam[x.parity[k]] + (size_t)s * kBlockStride + nd;
+        const float ws = w * f;
+        float ln[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) ln[j] = ws * la[4 + j];
+        atomicAdd(t, w * la[0]);
+        atomicAdd(t + 1 * kNodes, w * la[1] - (2.0f * q[1] * ln[0] + q[2] * ln[3] + q[3] * ln[4]));
+        atomicAdd(t + 2 * kNodes, w * la[2] - (2.0f * q[2] * ln[1] + q[1] * ln[3] + q[3] * ln[5]));
+        atomicAdd(t + 3 * kNodes, w * la[3] - (2.0f * q[3] * ln[2] + q[1] * ln[4] + q[2] * ln[5]));
+#pragma unroll
+        for (int j = 0; j < 6; ++j) atomicAdd(t + (4 + j) * kNodes, ln[j]);
+      };
+      smp.template visit<kMaxLevels - 1>(a.level, gn, 1.0f, 1.0f, scatter);
+    }
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) {
+      lc[m * kNodes + node] = 0.0f;
+      lo[m * kNodes + node] = 0.0f;
     }
   }
 }
@@ -630,6 +707,17 @@ hipError_t launch_init(const InitLaunch& a, hipStream_t s) {
     case 0: hipLaunchKernelGGL(k_init<StoreF32>, dim3(a.n), dim3(256), 0, s, a); break;
     case 1: hipLaunchKernelGGL(k_init<StoreBF16>, dim3(a.n), dim3(256), 0, s, a); break;
     case 2: hipLaunchKernelGGL(k_init<StoreF16>, dim3(a.n), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_adj(const InitAdjLaunch& x, hipStream_t s) {
+  if (x.f.n <= 0) return hipSuccess;
+  switch (x.f.storage) {
+    case 0: hipLaunchKernelGGL(k_init_adj<StoreF32>, dim3(x.f.n), dim3(256), 0, s, x); break;
+    case 1: hipLaunchKernelGGL(k_init_adj<StoreBF16>, dim3(x.f.n), dim3(256), 0, s, x); break;
+    case 2: hipLaunchKernelGGL(k_init_adj<StoreF16>, dim3(x.f.n), dim3(256), 0, s, x); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

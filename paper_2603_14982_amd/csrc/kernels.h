@@ -155,6 +155,14 @@ struct InitLaunch {
   float* phi;                // finest level with a powder-snow field: zero for new blocks; else null
 };
 hipError_t launch_init(const InitLaunch& a, hipStream_t s);
+// adjoint of launch_init over the same cells: lam[p] is the adjoint of time level p
+// (f32 slot layout), parity[k] the current time level of level k
+struct InitAdjLaunch {
+  InitLaunch f;
+  float* lam[2];
+  int parity[kMaxLevels];
+};
+hipError_t launch_init_adj(const InitAdjLaunch& x, hipStream_t s);
 
 // ---- powder-snow volume fraction on the finest level ----
 struct ScalarLaunch {

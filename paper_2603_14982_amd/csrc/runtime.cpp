@@ -175,6 +175,11 @@ struct lbm_ctx {
   int32_t free_top = 0;
   int32_t* host_counts = nullptr;  // pinned
   double* noalloc_partial = nullptr;  // this GPU's static reduction partials (lbm_reduce_f64_noalloc)
+  // Alg. 1 of one coarse step as a flat list (lbm_step_finest stops after a finest-level
+  // stream-collide); fine_cursor = operations of the current coarse step already run
+  struct SchedOp { int kind, level, s; };
+  std::vector<SchedOp> sched;
+  size_t fine_cursor = 0;
   std::string err;
   // phase timers (HIP events around launches, enabled on request)
   bool profiling = false;
@@ -186,8 +191,21 @@ struct lbm_ctx {
   uint64_t generation = 0;  // bumped by every grid update that changes the hierarchy
   // undo log of one coarse step replayed for the adjoint: before every operation
   // the blocks it is about to overwrite are copied to the tape
-  enum { OP_SC = 0, OP_DOWN = 1, OP_UP = 2 };
-  struct TapeOp { int kind, level, s, pf, pc; size_t off, off2; };
+  enum { OP_SC = 0, OP_DOWN = 1, OP_UP = 2, OP_REMESH = 3 };
+  // OP_REMESH: off = the meta buffer before the update, off2 = both time levels of every
+  // block before it (level order, key order), aux = index of the host-side counts in hier_saves
+  struct TapeOp { int kind, level, s, pf, pc; size_t off, off2; int aux = -1; };
+  struct HierSave {
+    int64_t nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels], ntile[kMaxLevels],
+        nbb[kMaxLevels];
+    int hier, rcur;
+    int32_t free_top;
+    uint64_t generation;
+    int parity[kMaxLevels];  // time-level parity of every level (a grid update leaves it)
+  };
+  std::vector<HierSave> hier_saves;
+  bool rec_open = false;     // a recording opened by lbm_record_begin (steps and grid updates)
+  size_t rec_aux = 0;        // bytes of the work buffer's aux region for the recording
   bool recording = false;
   char* tape = nullptr;
   size_t tape_cap = 0, tape_used = 0;
@@ -653,7 +671,44 @@ lbm_status advance(lbm_ctx* c, int l, int s) {
   return LBM_OK;
 }
 
+// The operations of AdvanceLBM(l, s) in the order advance() runs them unfused.
+void plan(int L, int l, int s, std::vector<lbm_ctx::SchedOp>& out) {
+  if (l < L - 1) out.push_back({lbm_ctx::OP_DOWN, l, s});
+  out.push_back({lbm_ctx::OP_SC, l, s});
+  if (l < L - 1 && s == 2) out.push_back({lbm_ctx::OP_UP, l, s});
+  if (l > 0) {
+    plan(L, l - 1, 1, out);
+    plan(L, l - 1, 2, out);
+  }
+}
+
+// One finest-level step: the operations up to and including the next finest-level
+// stream-collide, then the upward transfers that follow it.
+lbm_status finest_step(lbm_ctx* c) {
+  const auto& q = c->sched;
+  bool done = false;
+  while (c->fine_cursor < q.size()) {
+    const lbm_ctx::SchedOp& op = q[c->fine_cursor];
+    if (done && op.kind != lbm_ctx::OP_UP) break;
+    lbm_status st = op.kind == lbm_ctx::OP_DOWN ? down_level(c, op.level, op.s)
+                    : op.kind == lbm_ctx::OP_UP ? up_level(c, op.level)
+                                                : sc_level(c, op.level, op.s);
+    if (st != LBM_OK) return st;
+    if (op.kind == lbm_ctx::OP_SC && op.level == 0) done = true;
+    ++c->fine_cursor;
+  }
+  if (c->fine_cursor == q.size()) c->fine_cursor = 0;
+  return LBM_OK;
+}
+
 bool level_ok(lbm_ctx* c, int level) { return c && level >= 0 && level < c->G.L; }
+
+// calls that need every level at the same time (a coarse-step boundary)
+lbm_status need_boundary(lbm_ctx* c) {
+  if (c->fine_cursor != 0)
+    return c->fail(LBM_ESTATE, "a coarse step is under way (lbm_step_finest): finish it with lbm_step_finest first");
+  return LBM_OK;
+}
 
 // ---- adjoint of one coarse step: reverse sweep over the undo log ----
 constexpr uint64_t kStateMagic = 0x4554415453424c4dull;  // "MLBSTATE"
@@ -677,7 +732,76 @@ size_t aux_bytes(const lbm_ctx* c) {
   return part_bytes(c) + round256((size_t)(c->cap + 1) * 4) + round256((size_t)(c->cap + 1));
 }
 
+// the aux region sized for any hierarchy the pool can hold (recordings with grid updates)
+size_t aux_bytes_cap(const lbm_ctx* c) {
+  return round256((size_t)c->cap * 2 * kMom * 125 * sizeof(float)) + round256((size_t)(c->cap + 1) * 4) +
+         round256((size_t)(c->cap + 1));
+}
+
+lbm_ctx::HierSave save_hier(const lbm_ctx* c) {
+  lbm_ctx::HierSave h;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    h.nblk[l] = c->nblk[l]; h.ngb[l] = c->ngb[l]; h.nib[l] = c->nib[l];
+    h.nob[l] = c->nob[l]; h.ntile[l] = c->ntile[l]; h.nbb[l] = c->nbb[l];
+  }
+  h.hier = c->hier;
+  h.rcur = c->rcur;
+  h.free_top = c->free_top;
+  h.generation = c->generation;
+  for (int l = 0; l < kMaxLevels; ++l) h.parity[l] = c->parity[l];
+  return h;
+}
+void load_hier(lbm_ctx* c, const lbm_ctx::HierSave& h) {
+  for (int l = 0; l < kMaxLevels; ++l) {
+    c->nblk[l] = h.nblk[l]; c->ngb[l] = h.ngb[l]; c->nib[l] = h.nib[l];
+    c->nob[l] = h.nob[l]; c->ntile[l] = h.ntile[l]; c->nbb[l] = h.nbb[l];
+  }
+  c->hier = h.hier;
+  c->rcur = h.rcur;
+  c->free_top = h.free_top;
+  c->generation = h.generation;
+}
+
 size_t slot_floats(const lbm_ctx* c) { return (size_t)(c->cap + 1) * kBlockStride; }
+
+// Grid update inside a recording: the meta buffer and both time levels of every block
+// go to the undo log first; if the update changes nothing (or is refused), the log
+// entry is dropped and the meta buffer, whose scratch parts the update used, is put
+// back, so that the tables of earlier recorded updates stay intact.
+lbm_status rebuild_recorded(lbm_ctx* c, const float* particles, int64_t n) {
+  hipStream_t s = c->stream;
+  const size_t bb = block_bytes(c);
+  int64_t nb = 0;
+  for (int l = 0; l < c->G.L; ++l) nb += c->nblk[l];
+  const size_t meta_bytes = round256(c->lay.total);
+  const size_t bytes = meta_bytes + (size_t)nb * 2 * bb;
+  if (c->tape_used + bytes > c->tape_cap) return c->fail(LBM_ECAPACITY, "adjoint tape too small for a grid update");
+  const size_t off = c->tape_used;
+  HIPCHK(c, hipMemcpyAsync(c->tape + off, c->meta, c->lay.total, hipMemcpyDeviceToDevice, s));
+  size_t o = off + meta_bytes;
+  for (int l = 0; l < c->G.L; ++l) {
+    HIPCHK(c, launch_gather_blocks2(c->cur(l), c->other(l), c->tape + o, c->blocks(l), (int32_t)c->nblk[l], bb, s));
+    o += (size_t)c->nblk[l] * 2 * bb;
+  }
+  const lbm_ctx::HierSave before = save_hier(c);
+  const uint64_t gen = c->generation;
+  lbm_status st = rebuild(c, particles, n, false);
+  if (st != LBM_OK || c->generation == gen) {
+    // nothing changed (or refused): the scratch parts of meta back, the entry dropped
+    HIPCHK(c, hipMemcpyAsync(c->meta, c->tape + off, c->lay.total, hipMemcpyDeviceToDevice, s));
+    return st;
+  }
+  lbm_ctx::TapeOp op;
+  op.kind = lbm_ctx::OP_REMESH;
+  op.level = op.s = op.pf = op.pc = 0;
+  op.off = off;
+  op.off2 = off + meta_bytes;
+  op.aux = (int)c->hier_saves.size();
+  c->hier_saves.push_back(before);
+  c->ops.push_back(op);
+  c->tape_used += bytes;
+  return LBM_OK;
+}
 constexpr size_t kAdjSlotBufs = 4;  // lam[2], mu[2]
 
 size_t tape_bytes(const lbm_ctx* c) {
@@ -719,10 +843,79 @@ struct AdjSweep {
 // adjoint of one recorded operation in the state right after it, then its undo
 // (folded into the adjoint kernels: each restores the nodes the operation wrote).
 // next: the operation the sweep takes after this one (recorded just before it).
+// per-slot tables of the downward transfer's adjoint for the current hierarchy
+lbm_status adjoint_tables(lbm_ctx* c, const AdjBufs& b) {
+  hipStream_t s = c->stream;
+  HIPCHK(c, launch_fill_u8(b.flags, 0, c->cap + 1, s));
+  HIPCHK(c, launch_fill_i32(b.gidx, -1, c->cap + 1, s));
+  for (int l = 0; l + 1 < c->G.L; ++l) {
+    AdjTransferLaunch t = adj_base(c, l);
+    t.blocks = c->gblocks(l);
+    t.nblocks = (int32_t)c->ngb[l];
+    t.flags = b.flags;
+    HIPCHK(c, launch_mark_gather(t, s));
+    HIPCHK(c, launch_ghost_index(c->gblocks(l), (int32_t)c->ngb[l], b.gidx, s));
+  }
+  return LBM_OK;
+}
+
+// Reverse of a recorded grid update (Sec. 6.3 new-node initialisation), in the state
+// right after it: the old state goes back into the old blocks' slots (it is what the
+// sampler read), the adjoint of every node the update wrote flows through the
+// transposed sampler into the old nodes, then the old tables and counts come back.
+// The time levels are those current at the update (the reverse sweep keeps the
+// context's parity at the end of the recording).
+lbm_status reverse_remesh(lbm_ctx* c, const lbm_ctx::TapeOp& op, const AdjBufs& b) {
+  hipStream_t s = c->stream;
+  const int L = c->G.L;
+  const lbm_ctx::HierSave& old = c->hier_saves[(size_t)op.aux];
+  const char* msnap = c->tape + op.off;
+  const size_t bb = block_bytes(c);
+  size_t o = op.off2;
+  for (int l = 0; l < L; ++l) {
+    const int32_t n = (int32_t)old.nblk[l];
+    const int32_t* blocks_old =
+        reinterpret_cast<const int32_t*>(msnap + c->lay.blocks) + c->lay.level_list_off[l];
+    HIPCHK(c, launch_scatter_blocks(c->tape + o, c->buf(l, old.parity[l]), blocks_old, n, bb, s));
+    HIPCHK(c, launch_scatter_blocks(c->tape + o + (size_t)n * bb, c->buf(l, 1 - old.parity[l]), blocks_old, n, bb,
+                                    s));
+    o += (size_t)n * 2 * bb;
+  }
+  for (int l = 0; l < L; ++l) {
+    InitAdjLaunch x;
+    std::memset(&x, 0, sizeof(x));
+    InitLaunch& a = x.f;
+    a.G = c->G;
+    a.level = l;
+    a.cells = c->lists(l, 0);
+    a.n = (int32_t)c->nblk[l];
+    a.dir_new = c->dir(c->hier);
+    a.dir_old = c->dir(1 - c->hier);
+    a.st_old = c->st(1 - c->hier);
+    a.role_new = c->role(c->rcur);
+    a.role_old = c->role(1 - c->rcur);
+    for (int k = 0; k < L; ++k) {
+      a.cur[k] = c->buf(k, old.parity[k]);
+      a.a_up[k] = (float)c->a_up[k];
+      a.a_down[k] = (float)c->a_down[k];
+      x.parity[k] = old.parity[k];
+    }
+    a.sc = c->sc;
+    a.storage = c->cfg.storage;
+    x.lam[0] = b.lam[0];
+    x.lam[1] = b.lam[1];
+    HIPCHK(c, launch_init_adj(x, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->meta, msnap, c->lay.total, hipMemcpyDeviceToDevice, s));
+  load_hier(c, old);
+  return adjoint_tables(c, b);
+}
+
 lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const lbm_ctx::TapeOp* next, const AdjBufs& b,
                       AdjSweep& sw) {
   const int l = op.level;
   hipStream_t s = c->stream;
+  if (op.kind == lbm_ctx::OP_REMESH) return reverse_remesh(c, op, b);
   if (op.kind == lbm_ctx::OP_SC) {
     const int p = op.pf;  // input time level; the sweep wrote 1 - p
     if (c->nob[l] > 0) {
@@ -734,7 +927,9 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const lbm_ctx::Tape
       t.undo_dst = c->buf(l, 1 - p);
       t.src_a = c->buf(l, p);  // the old time level (convective outflow)
       t.undo_tape = c->tape + op.off2;
+      const int k = c->tic(LBM_PROF_ADJ);
       HIPCHK(c, launch_outflow_adj(t, s));
+      c->toc(k);
     }
     AdjScLaunch a;
     std::memset(&a, 0, sizeof(a));
@@ -752,7 +947,11 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const lbm_ctx::Tape
     a.omega = (float)(1.0 / c->tau[l]);
     a.sc = c->sc;
     a.storage = c->cfg.storage;
-    if (!sw.mu_ready) HIPCHK(c, launch_sc_mu(a, s));
+    if (!sw.mu_ready) {
+      const int k = c->tic(LBM_PROF_ADJ);
+      HIPCHK(c, launch_sc_mu(a, s));
+      c->toc(k);
+    }
     // the next operation is the stream-collide of this level that wrote this one's
     // input (consecutive substeps of the finest level, or consecutive steps of a
     // single level), with no outflow adjoint before its first pass: the transpose
@@ -764,7 +963,9 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const lbm_ctx::Tape
       a.next_tape = c->tape + next->off;
       a.next_mu = b.mu[1 - sw.mu_cur];
     }
+    const int k = c->tic(fuse ? LBM_PROF_ADJ_SC_FUSED : LBM_PROF_ADJ_SC);
     HIPCHK(c, launch_sc_transpose(a, s));
+    c->toc(k);
     sw.mu_ready = fuse;
     if (fuse) sw.mu_cur = 1 - sw.mu_cur;
   } else if (op.kind == lbm_ctx::OP_DOWN) {
@@ -789,10 +990,12 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const lbm_ctx::Tape
     t.undo_dst2 = c->buf(l, 1 - op.pf);
     t.undo_tape = c->tape + op.off;
     t.undo_tape2 = c->tape + op.off2;
+    const int k = c->tic(LBM_PROF_ADJ);
     HIPCHK(c, launch_down_adj_lin(t, s));
     t.blocks = c->blocks(l + 1);
     t.nblocks = (int32_t)c->nblk[l + 1];
     HIPCHK(c, launch_down_adj_gather(t, s));
+    c->toc(k);
   } else {
     AdjTransferLaunch t = adj_base(c, l);
     t.blocks = c->iblocks(l + 1);
@@ -803,7 +1006,9 @@ lbm_status adjoint_op(lbm_ctx* c, const lbm_ctx::TapeOp& op, const lbm_ctx::Tape
     t.lam_coarse_a = b.lam[op.pc];
     t.undo_dst = c->buf(l + 1, op.pc);
     t.undo_tape = c->tape + op.off;
+    const int k = c->tic(LBM_PROF_ADJ);
     HIPCHK(c, launch_up_adj(t, s));
+    c->toc(k);
   }
   return LBM_OK;
 }
@@ -844,6 +1049,7 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
   c->pool = static_cast<char*>(cfg->pool);
   c->meta = static_cast<char*>(cfg->meta);
   c->solid = solid_fine;
+  plan(G.L, G.L - 1, 1, c->sched);
   for (int l = 0; l < G.L; ++l) {
     const double k = std::ldexp(1.0, l);
     c->tau[l] = cfg->tau0 / k + (k - 1.0) / (2.0 * k);  // tau_{l} from tau_0 (Sec. 5.2)
@@ -937,6 +1143,8 @@ lbm_status lbm_block_keys(lbm_ctx* ctx, int32_t level, int64_t* keys) {
 lbm_status lbm_set_block_moments(lbm_ctx* ctx, int32_t level, const int64_t* keys, const float* in, int64_t nb) {
   if (!level_ok(ctx, level)) return ctx ? ctx->fail(LBM_EINVAL, "bad level") : LBM_EINVAL;
   if (nb < 0 || (nb > 0 && (!keys || !in))) return ctx->fail(LBM_EINVAL, "bad block arrays");
+  if (lbm_status st = need_boundary(ctx)) return st;
+  if (ctx->rec_open) return ctx->fail(LBM_ESTATE, "a recording is open (lbm_record_end first)");
   if (nb == 0) return LBM_OK;
   ctx->rec_work = nullptr;
   int32_t* flag = ctx->m<int32_t>(ctx->lay.flag);
@@ -1023,11 +1231,33 @@ lbm_status lbm_scalar_advance(lbm_ctx* ctx, float dt, float D, const float* sour
 lbm_status lbm_step(lbm_ctx* ctx, int32_t n) {
   if (!ctx) return LBM_EINVAL;
   if (n < 0) return ctx->fail(LBM_EINVAL, "negative step count");
-  ctx->rec_work = nullptr;  // a recorded undo log no longer matches the state
+  if (lbm_status st = need_boundary(ctx)) return st;
+  if (!ctx->rec_open) ctx->rec_work = nullptr;  // a recorded undo log no longer matches the state
   for (int32_t i = 0; i < n; ++i) {
     lbm_status st = advance(ctx, ctx->G.L - 1, 1);
     if (st != LBM_OK) return st;
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_step_finest(lbm_ctx* ctx, int32_t n) {
+  if (!ctx) return LBM_EINVAL;
+  if (n < 0) return ctx->fail(LBM_EINVAL, "negative step count");
+  if (ctx->rec_open) return ctx->fail(LBM_ESTATE, "a recording is open (lbm_record_end first)");
+  ctx->rec_work = nullptr;
+  for (int32_t i = 0; i < n; ++i) {
+    lbm_status st = finest_step(ctx);
+    if (st != LBM_OK) return st;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_finest_phase(lbm_ctx* ctx, int32_t* out) {
+  if (!ctx || !out) return ctx ? ctx->fail(LBM_EINVAL, "null output") : LBM_EINVAL;
+  int32_t k = 0;
+  for (size_t i = 0; i < ctx->fine_cursor; ++i)
+    if (ctx->sched[i].kind == lbm_ctx::OP_SC && ctx->sched[i].level == 0) ++k;
+  *out = k;
   return LBM_OK;
 }
 
@@ -1041,9 +1271,15 @@ lbm_status lbm_advance_particles(lbm_ctx* ctx, float* particles, int64_t n, cons
 lbm_status lbm_remesh(lbm_ctx* ctx, const float* particles, int64_t n) {
   if (!ctx) return LBM_EINVAL;
   if (n < 0 || (n > 0 && !particles)) return ctx->fail(LBM_EINVAL, "bad particle array");
-  ctx->rec_work = nullptr;
+  if (lbm_status st = need_boundary(ctx)) return st;
   const int k = ctx->tic(LBM_PROF_REMESH);
-  lbm_status st = rebuild(ctx, particles, n, false);
+  lbm_status st;
+  if (ctx->rec_open) {
+    st = rebuild_recorded(ctx, particles, n);
+  } else {
+    ctx->rec_work = nullptr;
+    st = rebuild(ctx, particles, n, false);
+  }
   ctx->toc(k);
   return st;
 }
@@ -1132,6 +1368,7 @@ size_t lbm_state_bytes(const lbm_ctx* ctx) {
 
 lbm_status lbm_save(lbm_ctx* ctx, void* dst, size_t bytes) {
   if (!ctx) return LBM_EINVAL;
+  if (lbm_status st = need_boundary(ctx)) return st;
   if (!dst || bytes < lbm_state_bytes(ctx)) return ctx->fail(LBM_EINVAL, "state buffer missing or too small");
   Words8 w;
   std::memset(&w, 0, sizeof(w));
@@ -1152,6 +1389,8 @@ lbm_status lbm_save(lbm_ctx* ctx, void* dst, size_t bytes) {
 
 lbm_status lbm_load(lbm_ctx* ctx, const void* src, size_t bytes) {
   if (!ctx) return LBM_EINVAL;
+  if (lbm_status st = need_boundary(ctx)) return st;
+  if (ctx->rec_open) return ctx->fail(LBM_ESTATE, "a recording is open (lbm_record_end first)");
   if (!src || bytes < lbm_state_bytes(ctx)) return ctx->fail(LBM_EINVAL, "state buffer missing or too small");
   HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, src, 64, hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
@@ -1195,17 +1434,21 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, const void* state, size_t state_bytes
 
 lbm_status lbm_step_record(lbm_ctx* ctx, int32_t n_steps, void* work, size_t work_bytes) {
   if (!ctx) return LBM_EINVAL;
+  if (lbm_status st = need_boundary(ctx)) return st;
   if (ctx->cfg.coupling) return ctx->fail(LBM_EINVAL, "the adjoint does not cover coupling fields");
   if (n_steps < 1) return ctx->fail(LBM_EINVAL, "step count must be positive");
   if (!work) return ctx->fail(LBM_EINVAL, "null adjoint buffer");
   if (work_bytes < lbm_adjoint_work_bytes(ctx, n_steps)) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
+  if (ctx->rec_open) return ctx->fail(LBM_ESTATE, "a recording is open (lbm_record_end first)");
   const int L = ctx->G.L;
   const size_t sf = slot_floats(ctx);
   char* aux = reinterpret_cast<char*>(static_cast<float*>(work) + kAdjSlotBufs * sf);
-  ctx->tape = aux + aux_bytes(ctx);
-  ctx->tape_cap = work_bytes - kAdjSlotBufs * sf * sizeof(float) - aux_bytes(ctx);
+  ctx->rec_aux = aux_bytes(ctx);
+  ctx->tape = aux + ctx->rec_aux;
+  ctx->tape_cap = work_bytes - kAdjSlotBufs * sf * sizeof(float) - ctx->rec_aux;
   ctx->tape_used = 0;
   ctx->ops.clear();
+  ctx->hier_saves.clear();
   ctx->pending_sc_tape = SIZE_MAX;
   ctx->rec_work = work;
   ctx->rec_generation = ctx->generation;
@@ -1227,12 +1470,14 @@ lbm_status lbm_step_record(lbm_ctx* ctx, int32_t n_steps, void* work, size_t wor
 
 lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_out, void* work, size_t work_bytes) {
   if (!ctx) return LBM_EINVAL;
+  if (lbm_status st = need_boundary(ctx)) return st;
   if (!lam_next || !lam_out || !work) return ctx->fail(LBM_EINVAL, "null adjoint buffer");
+  if (ctx->rec_open) return ctx->fail(LBM_ESTATE, "a recording is open (lbm_record_end first)");
   if (ctx->rec_work == nullptr || ctx->ops.empty() || work != ctx->rec_work)
     return ctx->fail(LBM_ESTATE, "no recorded steps for this work buffer");
   if (ctx->rec_generation != ctx->generation)
     return ctx->fail(LBM_ESTATE, "the block hierarchy changed since the steps were recorded");
-  if (work_bytes < kAdjSlotBufs * slot_floats(ctx) * sizeof(float) + aux_bytes(ctx) + ctx->tape_used)
+  if (work_bytes < kAdjSlotBufs * slot_floats(ctx) * sizeof(float) + ctx->rec_aux + ctx->tape_used)
     return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
   hipStream_t s = ctx->stream;
   const int L = ctx->G.L;
@@ -1243,25 +1488,23 @@ lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_o
   b.mu[0] = b.lam[1] + sf;
   b.mu[1] = b.mu[0] + sf;
   char* aux = reinterpret_cast<char*>(b.mu[1] + sf);
+  // the partials take what the gidx and flag tables (sized by the capacity) leave
+  const size_t tables = round256((size_t)(ctx->cap + 1) * 4) + round256((size_t)(ctx->cap + 1));
   b.part = reinterpret_cast<float*>(aux);
-  b.gidx = reinterpret_cast<int32_t*>(aux + part_bytes(ctx));
-  b.flags = reinterpret_cast<uint8_t*>(aux + part_bytes(ctx) + round256((size_t)(ctx->cap + 1) * 4));
-  ctx->tape = aux + aux_bytes(ctx);
+  b.gidx = reinterpret_cast<int32_t*>(aux + ctx->rec_aux - tables);
+  b.flags = reinterpret_cast<uint8_t*>(aux + ctx->rec_aux - tables + round256((size_t)(ctx->cap + 1) * 4));
+  ctx->tape = aux + ctx->rec_aux;
   lbm_status st = LBM_OK;
   {
     // adjoint of the state after the steps: lam_next at the state nodes of the current time level
     for (int k = 0; k < 2; ++k)
       HIPCHK(ctx, launch_fill_i32(reinterpret_cast<int32_t*>(b.mu[k] + (size_t)ctx->cap * kBlockStride), 0, kBlockStride, s));
-    HIPCHK(ctx, launch_fill_u8(b.flags, 0, ctx->cap + 1, s));
-    HIPCHK(ctx, launch_fill_i32(b.gidx, -1, ctx->cap + 1, s));
-    for (int l = 0; l + 1 < L; ++l) {
-      AdjTransferLaunch t = adj_base(ctx, l);
-      t.blocks = ctx->gblocks(l);
-      t.nblocks = (int32_t)ctx->ngb[l];
-      t.flags = b.flags;
-      HIPCHK(ctx, launch_mark_gather(t, s));
-      HIPCHK(ctx, launch_ghost_index(ctx->gblocks(l), (int32_t)ctx->ngb[l], b.gidx, s));
-    }
+    if ((st = adjoint_tables(ctx, b)) != LBM_OK) return st;
+    // with grid updates in the log, blocks of earlier hierarchies receive adjoint too:
+    // every slot starts at zero
+    if (!ctx->hier_saves.empty())
+      for (int k = 0; k < 2; ++k)
+        HIPCHK(ctx, launch_fill_i32(reinterpret_cast<int32_t*>(b.lam[k]), 0, (int64_t)sf, s));
     size_t off = 0;
     for (int l = 0; l < L; ++l) {
       const int32_t n = (int32_t)ctx->nblk[l];
@@ -1277,6 +1520,7 @@ lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_o
     st = adjoint_op(ctx, ctx->ops[i], i > 0 ? &ctx->ops[i - 1] : nullptr, b, sw);
   for (int l = 0; l < L; ++l) ctx->parity[l] = ctx->rec_parity[l];
   ctx->ops.clear();
+  ctx->hier_saves.clear();
   ctx->rec_work = nullptr;
   ctx->tape = nullptr;
   ctx->tape_cap = 0;
@@ -1288,6 +1532,46 @@ lbm_status lbm_adjoint_reverse(lbm_ctx* ctx, const float* lam_next, float* lam_o
                                      kBlockStride * sizeof(float), s));
     off += (size_t)n * kBlockStride;
   }
+  return LBM_OK;
+}
+
+size_t lbm_record_work_bytes(const lbm_ctx* ctx, int32_t n_steps, int32_t n_updates) {
+  if (!ctx || n_steps < 0 || n_updates < 0) return 0;
+  const size_t state = (size_t)total_blocks(ctx) * 2 * block_bytes(ctx);
+  return kAdjSlotBufs * slot_floats(ctx) * sizeof(float) + aux_bytes_cap(ctx) + (size_t)n_steps * tape_bytes(ctx) +
+         (size_t)n_updates * (round256(ctx->lay.total) + state);
+}
+
+lbm_status lbm_record_begin(lbm_ctx* ctx, void* work, size_t work_bytes) {
+  if (!ctx) return LBM_EINVAL;
+  if (lbm_status st = need_boundary(ctx)) return st;
+  if (ctx->cfg.coupling) return ctx->fail(LBM_EINVAL, "the adjoint does not cover coupling fields");
+  if (ctx->rec_open) return ctx->fail(LBM_ESTATE, "a recording is already open");
+  if (!work) return ctx->fail(LBM_EINVAL, "null adjoint buffer");
+  const size_t fixed = kAdjSlotBufs * slot_floats(ctx) * sizeof(float) + aux_bytes_cap(ctx);
+  if (work_bytes < fixed) return ctx->fail(LBM_EINVAL, "adjoint work buffer too small");
+  char* aux = reinterpret_cast<char*>(static_cast<float*>(work) + kAdjSlotBufs * slot_floats(ctx));
+  ctx->rec_aux = aux_bytes_cap(ctx);
+  ctx->tape = aux + ctx->rec_aux;
+  ctx->tape_cap = work_bytes - fixed;
+  ctx->tape_used = 0;
+  ctx->ops.clear();
+  ctx->hier_saves.clear();
+  ctx->pending_sc_tape = SIZE_MAX;
+  ctx->rec_work = work;
+  for (int l = 0; l < ctx->G.L; ++l) ctx->rec_parity[l] = ctx->parity[l];
+  ctx->recording = true;
+  ctx->rec_open = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_record_end(lbm_ctx* ctx) {
+  if (!ctx) return LBM_EINVAL;
+  if (!ctx->rec_open) return ctx->fail(LBM_ESTATE, "no recording is open");
+  ctx->recording = false;
+  ctx->rec_open = false;
+  ctx->rec_generation = ctx->generation;
+  if (ctx->ops.empty()) ctx->rec_work = nullptr;
   return LBM_OK;
 }
 

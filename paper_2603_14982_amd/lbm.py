@@ -54,13 +54,14 @@ class LBMConfig(ctypes.Structure):
 
 EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm_num_blocks", "lbm_block_keys",
            "lbm_set_block_moments", "lbm_step", "lbm_advance_particles", "lbm_remesh", "lbm_get_moments",
-           "lbm_get_roles", "lbm_reduce_f64", "lbm_reduce_f64_noalloc", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
+           "lbm_get_roles", "lbm_reduce_f64", "lbm_reduce_f64_noalloc", "lbm_step_finest", "lbm_finest_phase", "lbm_record_work_bytes", "lbm_record_begin", "lbm_record_end", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
            "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
            "lbm_step_record", "lbm_adjoint_reverse",
            "lbm_loss_ke_grad", "lbm_set_option", "lbm_set_coupling",
            "lbm_scalar_set", "lbm_scalar_get", "lbm_scalar_advance", "lbm_last_error"]
 _SIZE_QUERIES = ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_state_bytes", "lbm_adjoint_work_bytes", "lbm_last_error")
-PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh", "sc_pair"]
+PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh", "sc_pair",
+                  "adj_sc", "adj_sc_fused", "adj"]
 OPTIONS = {"tile_min_blocks": 0, "fuse_substeps": 1}
 
 _lib = None
@@ -85,6 +86,12 @@ def lib():
         L.lbm_block_keys.argtypes = [vp, i32, vp]
         L.lbm_set_block_moments.argtypes = [vp, i32, vp, vp, i64]
         L.lbm_step.argtypes = [vp, i32]
+        L.lbm_step_finest.argtypes = [vp, i32]
+        L.lbm_record_work_bytes.restype = sz
+        L.lbm_record_work_bytes.argtypes = [vp, i32, i32]
+        L.lbm_record_begin.argtypes = [vp, vp, sz]
+        L.lbm_record_end.argtypes = [vp]
+        L.lbm_finest_phase.argtypes = [vp, ctypes.POINTER(i32)]
         L.lbm_advance_particles.argtypes = [vp, vp, i64, vp]
         L.lbm_remesh.argtypes = [vp, vp, i64]
         L.lbm_get_moments.argtypes = [vp, i32, vp, vp]
@@ -233,6 +240,16 @@ class Sim:
     def step(self, n=1):
         self._check(lib().lbm_step(self.h, int(n)))
 
+    def step_finest(self, n=1):
+        """n finest-level steps (Alg. 1 stopped after each finest stream-collide)."""
+        self._check(lib().lbm_step_finest(self.h, int(n)))
+
+    def finest_phase(self):
+        """Finest steps taken since the last coarse-step boundary."""
+        v = ctypes.c_int32()
+        self._check(lib().lbm_finest_phase(self.h, ctypes.byref(v)))
+        return v.value
+
     def advance_particles(self, particles, d):
         dd = (ctypes.c_float * 3)(*[float(v) for v in d])
         self._check(lib().lbm_advance_particles(self.h, _dptr(particles), particles.shape[0], dd))
@@ -380,15 +397,31 @@ class Sim:
 
     def step_record(self, n_steps, work):
         """`n_steps` coarse steps that keep their undo log in `work` (adjoint_work(n_steps))."""
+        self._rec_blocks = self.total_blocks()
         self._check(lib().lbm_step_record(self.h, int(n_steps), _dptr(work), work.numel()))
 
+    def record_work(self, n_steps, n_updates):
+        """A work buffer for a recording of n_steps coarse steps and n_updates grid updates."""
+        nbytes = int(lib().lbm_record_work_bytes(self.h, int(n_steps), int(n_updates)))
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def record_begin(self, work):
+        """Opens a recording (steps and grid updates) for adjoint_reverse."""
+        self._rec_blocks = self.total_blocks()
+        self._check(lib().lbm_record_begin(self.h, _dptr(work), work.numel()))
+
+    def record_end(self):
+        self._check(lib().lbm_record_end(self.h))
+
     def adjoint_reverse(self, lam_next, lam_out=None, work=None):
-        """Adjoint through the steps recorded by step_record; returns the simulation to
-        the state before them."""
+        """Adjoint through the recorded steps (and grid updates); returns the simulation
+        to the state (and hierarchy) before them. lam_out has the block count of that
+        hierarchy."""
+        nb0 = getattr(self, "_rec_blocks", None) or self.total_blocks()
         if lam_out is None:
-            lam_out = torch.empty_like(lam_next)
+            lam_out = torch.empty((nb0, 10, 512), dtype=torch.float32, device=self.device)
         assert lam_next.dtype == torch.float32 and lam_next.is_contiguous()
-        assert lam_next.shape == (self.total_blocks(), 10, 512) and lam_out.shape == lam_next.shape
+        assert lam_next.shape == (self.total_blocks(), 10, 512) and lam_out.shape[1:] == (10, 512)
         self._check(lib().lbm_adjoint_reverse(self.h, _dptr(lam_next), _dptr(lam_out), _dptr(work), work.numel()))
         return lam_out
 

@@ -1,7 +1,9 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same
 seeded inputs. FP32 storage bar: relative L2 <= 1e-5 per moment group
-(rho-1, u, S) over all owned nodes of all levels; block sets and node roles
-bit-exact."""
+(rho-1, u, S) over all owned nodes of all levels and over each node class
+(computed, upward-interface, next to ghosts, inflow/outflow), and no owned node
+off by more than 10x that bar relative to the group's RMS; block sets and node
+roles bit-exact."""
 import numpy as np
 import pytest
 import torch
@@ -39,10 +41,36 @@ def setup_pair(levels, n, bc, tau0, init, uin=(0.0, 0.0, 0.0), solid=None, parti
     return gpu, ora
 
 
-def compare(gpu, ora, tol=TOL, label=""):
+# Node classes checked on their own, so that errors on the few interface nodes are
+# not diluted by the bulk: computed nodes, upward-interface nodes (written by the
+# upward transfer), computed nodes of blocks that hold ghost nodes (next to the
+# values the downward transfer writes), inflow and outflow nodes.
+CLASSES = ("computed", "interface", "next to ghosts", "boundary")
+
+
+def _classes(roles):
+    has_ghost = (roles == O.R_GHOST).any(axis=1)
+    return {"computed": roles == O.R_INTERIOR,
+            "interface": roles == O.R_IU,
+            "next to ghosts": (roles == O.R_INTERIOR) & has_ghost[:, None],
+            "boundary": (roles == O.R_INFLOW) | (roles == O.R_OUTFLOW)}
+
+
+def compare(gpu, ora, tol=TOL, label="", point=None):
+    """Relative L2 per moment group over all owned nodes of all levels (<= tol). With
+    the FP32 bar (tol <= 1e-5) also per node class (each <= tol; the class's norm is
+    floored at the group's RMS over all owned nodes times the root of its size) and
+    pointwise: no owned node may differ by more than `point` (default 10) times tol
+    times the group's RMS.
+    With 16-bit storage the per-class figures are printed only: the two sides differ by
+    rounding flips of one unit in the last place, which gather where values are
+    interpolated (next to ghost nodes), so the bound is held over all owned nodes."""
     torch.cuda.synchronize()
-    worst = {}
+    per_class = tol <= TOL
+    if point is None and per_class:
+        point = 10.0
     A, B = [], []
+    cls = {c: [] for c in CLASSES}
     for l in range(ora.levels):
         ko, vo = ora.get_block_moments(l)
         kg, vg = gpu.get_moments(l)
@@ -54,14 +82,32 @@ def compare(gpu, ora, tol=TOL, label=""):
         own = (ro != O.R_GHOST)
         A.append(vg.cpu().numpy().astype(np.float64).transpose(1, 0, 2)[:, own])
         B.append(vo.transpose(1, 0, 2)[:, own])
+        for c, m in _classes(ro).items():
+            cls[c].append(m[own])
     a = np.concatenate(A, axis=1)
     b = np.concatenate(B, axis=1)
-    errs = {}
+    masks = {c: np.concatenate(v) for c, v in cls.items()}
+    errs, worst = {}, {}
     for name, sl in {"rho-1": slice(0, 1), "u": slice(1, 4), "S": slice(4, 10)}.items():
-        errs[name] = float(np.linalg.norm(a[sl] - b[sl]) / np.linalg.norm(b[sl]))
-    print(f"{label} rel L2: {errs}", flush=True)
+        d = a[sl] - b[sl]
+        errs[name] = float(np.linalg.norm(d) / np.linalg.norm(b[sl]))
+        rms = float(np.sqrt(np.mean(b[sl] ** 2)))
+        worst[name] = float(np.abs(d).max() / rms)
+        for c, m in masks.items():
+            if m.any():
+                # a class whose values are near zero (nodes still at rest, where the
+                # FP64 oracle carries rounding noise and the GPU exact zeros) is
+                # measured against the group's RMS over all owned nodes
+                ref = max(float(np.linalg.norm(b[sl][:, m])), rms * np.sqrt(d[:, m].size))
+                errs[f"{name} {c}"] = float(np.linalg.norm(d[:, m]) / ref)
+    print(f"{label} rel L2: " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    print(f"{label} max |gpu - oracle| / rms: " + ", ".join(f"{k} {v:.2e}" for k, v in worst.items()), flush=True)
     for k, v in errs.items():
-        assert v <= tol, (label, k, v)
+        if per_class or k in ("rho-1", "u", "S"):
+            assert v <= tol, (label, k, v)
+    if point is not None:
+        for k, v in worst.items():
+            assert v <= point * tol, (label, "pointwise", k, v)
     return errs
 
 

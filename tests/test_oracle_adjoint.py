@@ -95,3 +95,48 @@ def test_complex_step_matches_central_difference(kind):
     print(f"{kind}: loss {base:.6e}, complex step {d_cs:.10e}, central differences {fd}")
     assert abs(fd[0] - fd[1]) <= 1e-6 * abs(d_cs)
     assert abs(d_cs - fd[1]) <= 1e-6 * abs(d_cs)
+
+
+def _remesh_loss(x, v, h, moves):
+    """Loss after coarse steps with a grid update after each that moves the refined
+    region (new fine blocks on one side, coarsened ones on the other), and a last
+    coarse step; with h > 0 in the complex instance along direction v."""
+    c = _config("periodic")
+    p = c["particles"].copy()
+    if h:
+        sim = O.OracleSimComplex(2, N, c["bc"], 0.6, particles=p)
+        for l in range(2):
+            sim.set_block_moments(l, sim.block_keys(l), x[l], h * v[l])
+    else:
+        sim = O.OracleSim(2, N, c["bc"], 0.6, particles=p)
+        for l in range(2):
+            sim.set_block_moments(l, sim.block_keys(l), x[l])
+    for d in moves:
+        sim.step(1)
+        O.advance_particles(p, np.array(d, dtype=np.float32))
+        sim.remesh(p)
+    sim.step(1)
+    return sim.kinetic_energy(0, *BOX) + sim.kinetic_energy(1, *BOX)
+
+
+def test_complex_step_through_grid_updates_matches_central_difference():
+    # the refined region moves by two level-0 blocks along x, then by two along y and
+    # back along z: every update creates and deletes blocks on both levels (72 and 1,
+    # then 120 and 1 each way), so new nodes are sampled downward (refinement) and
+    # upward (coarsening)
+    c = _config("periodic")
+    probe = O.OracleSim(2, N, c["bc"], 0.6, particles=c["particles"])
+    x, v = _fields(probe, 13)
+    moves = [(16.0, 0.0, 0.0), (0.0, 16.0, -16.0)]
+    base = _remesh_loss(x, None, 0.0, moves)
+    cs = _remesh_loss(x, v, 1e-30, moves)
+    assert abs(cs.real - base) <= 1e-13 * abs(base)
+    d_cs = cs.imag / 1e-30
+    fd = []
+    for eps in (1e-5, 1e-6):
+        xp = [a + eps * b for a, b in zip(x, v)]
+        xm = [a - eps * b for a, b in zip(x, v)]
+        fd.append((_remesh_loss(xp, None, 0.0, moves) - _remesh_loss(xm, None, 0.0, moves)) / (2 * eps))
+    print(f"through grid updates: loss {base:.6e}, complex step {d_cs:.10e}, central differences {fd}")
+    assert abs(fd[0] - fd[1]) <= 1e-6 * abs(d_cs)
+    assert abs(d_cs - fd[1]) <= 1e-6 * abs(d_cs)

@@ -274,6 +274,9 @@ def main():
                     help="print only the adjoint/forward measurement (for profiling the adjoint kernels)")
     ap.add_argument("--storage", choices=["f32", "bf16", "f16"], default="f32",
                     help="moment storage format (FP32 arithmetic in every case)")
+    ap.add_argument("--separate-calls", action="store_true",
+                    help="step, particle advance and grid update as three calls (each update then waits for "
+                         "the step before it)")
     ap.add_argument("--no-adjoint-slab", action="store_true",
                     help="skip the adjoint/forward ratio on the benchmark's (fixed) hierarchy")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -309,9 +312,13 @@ def main():
     d = (wl["v_fine"][0] * sub, wl["v_fine"][1] * sub, wl["v_fine"][2] * sub)
 
     def coarse_step():
-        sim.step(1)
-        sim.advance_particles(particles, d)
-        sim.remesh(particles)
+        if args.separate_calls:
+            sim.step(1)
+            sim.advance_particles(particles, d)
+            sim.remesh(particles)
+        else:
+            # the same three operations, the particle work overlapping the step
+            sim.step_remesh(1, particles, d)
 
     for _ in range(args.warmup):
         coarse_step()

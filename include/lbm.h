@@ -194,6 +194,18 @@ lbm_status lbm_advance_particles(lbm_ctx* ctx, float* particles, int64_t n, cons
  * (block counts), twice when the block set changes. */
 lbm_status lbm_remesh(lbm_ctx* ctx, const float* particles, int64_t n);
 
+/* n coarse steps of a run whose grid follows prescribed particle motion, each one
+ * lbm_step(1), lbm_advance_particles(particles, d) and lbm_remesh(particles) in that
+ * order, with the same results. The particle advance and the check whether the
+ * level-0 target set changed (the grid update's first stage, Sec. 6.3) run on a
+ * second stream of the context, concurrently with the step, after everything issued
+ * on cfg.stream before the call; the host waits for that check only, not for the
+ * step, and runs the rest of the grid update on cfg.stream when the targets changed.
+ * particles: device float [np][3]; d: host float[3]. Synchronises with the check
+ * (once per step) and as lbm_remesh when the block set changes. Inside a recording
+ * (lbm_record_begin) the three calls run in order on cfg.stream. */
+lbm_status lbm_step_remesh(lbm_ctx* ctx, int32_t n, float* particles, int64_t np, const float d[3]);
+
 /* Current moments of a level (decoded to f32): keys_out device int64 [nb] (may be
  * NULL), out device f32 [nb][10][512], blocks in key order. */
 lbm_status lbm_get_moments(lbm_ctx* ctx, int32_t level, int64_t* keys_out, float* out);

@@ -314,8 +314,16 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   if (threadIdx.x == 0) r.blocks[blockIdx.x] = slot;
   if (threadIdx.x < 6) s_box[threadIdx.x] = threadIdx.x < 3 ? 7 : 0;
   __syncthreads();
+  // a block whose 26 neighbour positions all hold active blocks of the level, with no
+  // solid field (inside the domain on every side, so no boundary face either): every
+  // node is computed, with no bounce-back neighbour
+  bool inner = r.solid == nullptr;
+#pragma unroll 1
+  for (int d = 0; d < 27 && inner; ++d) inner = s_st[d] == ST_ACTIVE;
   uint8_t sum = 0;
-  for (int node = threadIdx.x; node < kNodes; node += 256) {
+  if (inner)
+    for (int node = threadIdx.x; node < kNodes; node += 256) r.role[(size_t)slot * kNodes + node] = ROLE_COMPUTED;
+  for (int node = threadIdx.x; node < kNodes && !inner; node += 256) {
     const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
     const int gc[3] = {b[0] * kEdge + lc[0], b[1] * kEdge + lc[1], b[2] * kEdge + lc[2]};
     uint8_t role = 255;

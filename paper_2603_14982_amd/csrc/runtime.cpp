@@ -158,6 +158,10 @@ struct lbm_ctx {
   Geom G;
   Layout lay;
   hipStream_t stream = nullptr;
+  // lbm_step_remesh: the particle advance and the target-set check run on `side`
+  // (default priority) while the step runs on `stream`
+  hipStream_t side = nullptr;
+  hipEvent_t ev_before = nullptr, ev_side = nullptr;
   int64_t cap = 0;
   double tau[kMaxLevels], a_up[kMaxLevels], a_down[kMaxLevels];
   int parity[kMaxLevels];
@@ -1120,9 +1124,13 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
 lbm_status lbm_destroy(lbm_ctx* ctx) {
   if (!ctx) return LBM_EINVAL;
   // teardown: release what can be released; a device error here has no remedy
-  const bool synced = hipStreamSynchronize(ctx->stream) == hipSuccess;
+  bool synced = hipStreamSynchronize(ctx->stream) == hipSuccess;
+  if (ctx->side) synced = hipStreamSynchronize(ctx->side) == hipSuccess && synced;
   ctx->collect();
   for (hipEvent_t e : ctx->spare) (void)hipEventDestroy(e);
+  if (ctx->ev_before) (void)hipEventDestroy(ctx->ev_before);
+  if (ctx->ev_side) (void)hipEventDestroy(ctx->ev_side);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   (void)hipHostFree(ctx->host_counts);
   delete ctx;
   return synced ? LBM_OK : LBM_EDEVICE;
@@ -1282,6 +1290,63 @@ lbm_status lbm_remesh(lbm_ctx* ctx, const float* particles, int64_t n) {
   }
   ctx->toc(k);
   return st;
+}
+
+lbm_status lbm_step_remesh(lbm_ctx* ctx, int32_t n, float* particles, int64_t np, const float d[3]) {
+  if (!ctx) return LBM_EINVAL;
+  if (n < 0) return ctx->fail(LBM_EINVAL, "negative step count");
+  if (np < 0 || (np > 0 && (!particles || !d))) return ctx->fail(LBM_EINVAL, "bad particle arguments");
+  if (lbm_status st = need_boundary(ctx)) return st;
+  if (ctx->rec_open) {
+    // a recording logs the three calls in their order
+    for (int32_t i = 0; i < n; ++i) {
+      lbm_status st;
+      if ((st = lbm_step(ctx, 1)) != LBM_OK || (st = lbm_advance_particles(ctx, particles, np, d)) != LBM_OK ||
+          (st = lbm_remesh(ctx, particles, np)) != LBM_OK)
+        return st;
+    }
+    return LBM_OK;
+  }
+  if (!ctx->side) {
+    HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_before, hipEventDisableTiming));
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->ev_side, hipEventDisableTiming));
+  }
+  ctx->rec_work = nullptr;
+  const Geom& G = ctx->G;
+  int32_t* flag = ctx->m<int32_t>(ctx->lay.counts) + 63;
+  for (int32_t i = 0; i < n; ++i) {
+    // everything issued before this step (the caller's writes to the particles too)
+    HIPCHK(ctx, hipEventRecord(ctx->ev_before, ctx->stream));
+    lbm_status st = advance(ctx, G.L - 1, 1);
+    if (st != LBM_OK) return st;
+    // meanwhile, on the side stream: particles forward, then the level-0 target set
+    // compared with the one the hierarchy was built from (the step reads neither)
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_before, 0));
+    HIPCHK(ctx, launch_advance_particles(particles, np, d[0], d[1], d[2], ctx->side));
+    HierLaunch h;
+    h.G = G;
+    h.t0 = ctx->m<uint8_t>(ctx->lay.t0);
+    h.t0_static = ctx->m<uint8_t>(ctx->lay.t0s);
+    h.flags = ctx->m<uint8_t>(ctx->lay.flags);
+    h.st_new = ctx->st(1 - ctx->hier);
+    h.st_old = ctx->st(ctx->hier);
+    HIPCHK(ctx, launch_targets(h, particles, np, ctx->side));
+    HIPCHK(ctx, launch_diff_flag(h.t0, ctx->m<uint8_t>(ctx->lay.t0p), G.lv[0].ncell, flag, ctx->side));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->side));
+    HIPCHK(ctx, hipEventRecord(ctx->ev_side, ctx->side));
+    // later work on the context's stream sees the new particle positions
+    HIPCHK(ctx, hipStreamWaitEvent(ctx->stream, ctx->ev_side, 0));
+    HIPCHK(ctx, hipEventSynchronize(ctx->ev_side));
+    if (ctx->host_counts[0] != 0) {
+      // the targets changed: the grid update proper, after the step, on the context's stream
+      const int k = ctx->tic(LBM_PROF_REMESH);
+      st = rebuild(ctx, particles, np, false);
+      ctx->toc(k);
+      if (st != LBM_OK) return st;
+    }
+  }
+  return LBM_OK;
 }
 
 lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t on) {

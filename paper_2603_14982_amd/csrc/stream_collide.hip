@@ -901,7 +901,7 @@ struct Pair {
   static constexpr int HALFA = CXA * 4;         // x-pass input [kind][half][col 0..19][4]
   static constexpr int KINDA = 2 * HALFA;
   static constexpr int KINDB = CA * 10;         // y-pass input [kind][col 0..17][10]
-  static constexpr int ROWA = 3 * KINDB + 20;   // 560 floats, 16 banks off a multiple of 32
+  static constexpr int ROWA = 3 * KINDB + 24;   // 564 floats, 20 banks off a multiple of 32 (measured best)
   // Phases run on whole waves (a wave with no lane in a phase skips it): A source on
   // waves 0..6, A x pass, A y/z pass and B source on 0..5, B x pass on 0..4, B y/z pass
   // on 4..7.

@@ -54,7 +54,7 @@ class LBMConfig(ctypes.Structure):
 
 EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm_num_blocks", "lbm_block_keys",
            "lbm_set_block_moments", "lbm_step", "lbm_advance_particles", "lbm_remesh", "lbm_get_moments",
-           "lbm_get_roles", "lbm_reduce_f64", "lbm_reduce_f64_noalloc", "lbm_step_finest", "lbm_finest_phase", "lbm_record_work_bytes", "lbm_record_begin", "lbm_record_end", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
+           "lbm_get_roles", "lbm_reduce_f64", "lbm_reduce_f64_noalloc", "lbm_step_finest", "lbm_finest_phase", "lbm_step_remesh", "lbm_record_work_bytes", "lbm_record_begin", "lbm_record_end", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
            "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
            "lbm_step_record", "lbm_adjoint_reverse",
            "lbm_loss_ke_grad", "lbm_set_option", "lbm_set_coupling",
@@ -87,6 +87,7 @@ def lib():
         L.lbm_set_block_moments.argtypes = [vp, i32, vp, vp, i64]
         L.lbm_step.argtypes = [vp, i32]
         L.lbm_step_finest.argtypes = [vp, i32]
+        L.lbm_step_remesh.argtypes = [vp, i32, vp, i64, vp]
         L.lbm_record_work_bytes.restype = sz
         L.lbm_record_work_bytes.argtypes = [vp, i32, i32]
         L.lbm_record_begin.argtypes = [vp, vp, sz]
@@ -249,6 +250,12 @@ class Sim:
         v = ctypes.c_int32()
         self._check(lib().lbm_finest_phase(self.h, ctypes.byref(v)))
         return v.value
+
+    def step_remesh(self, n, particles, d):
+        """n times: step(1), advance_particles(particles, d), remesh(particles), the particle
+        work overlapped with the step on a second stream."""
+        dd = (ctypes.c_float * 3)(*[float(v) for v in d])
+        self._check(lib().lbm_step_remesh(self.h, int(n), _dptr(particles), particles.shape[0], dd))
 
     def advance_particles(self, particles, d):
         dd = (ctypes.c_float * 3)(*[float(v) for v in d])

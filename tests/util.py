@@ -89,15 +89,13 @@ def canonical_sets(levels, nblk0, periodic, t0):
 
 
 # ---- composite conservation sums over a multi-level state --------------------
-def composite_sums(levels, keys, vals, roles):
-    """FP64 sums over the composite grid: every owned node (not ghost, not solid)
-    of level l weighs 8^l fine-node volumes, and a node of level l+1 counts only if
-    level l does not own the node at the same position (coarse node q sits on fine
-    node 2q), so the overlap of two levels is counted once, on the finer one.
-    keys[l]: sorted block keys; vals[l]: [nb, 10, 512] moments with rho - 1 in slot 0;
-    roles[l]: [nb, 512]. Returns {"volume", "mass_excess" (sum w (rho - 1)),
-    "momentum" (sum w rho u, 3)}."""
-    out = {"volume": 0.0, "mass_excess": 0.0, "momentum": np.zeros(3)}
+def composite_weights(levels, keys, roles):
+    """Per level [nb, 512] weights of the composite grid: every owned node (not ghost,
+    not solid) of level l weighs 8^l fine-node volumes, and a node of level l+1 counts
+    only if level l does not own the node at the same position (coarse node q sits on
+    fine node 2q), so the overlap of two levels is counted once, on the finer one.
+    keys[l]: sorted block keys; roles[l]: [nb, 512]."""
+    out = []
     node = np.arange(512)
     nx, ny, nz = node & 7, (node >> 3) & 7, node >> 6
     for l in range(levels):
@@ -117,6 +115,18 @@ def composite_sums(levels, keys, vals, roles):
                 fr = roles[l - 1][idx, np.broadcast_to(fn[None], fk.shape)]
                 covered = hit & (fr != 1) & (fr != 3)
             own = own & ~covered
+        out.append(own)
+    return out
+
+
+def composite_sums(levels, keys, vals, roles, counted=None):
+    """FP64 sums over the composite grid (composite_weights): {"volume", "mass_excess"
+    (sum w (rho - 1)), "momentum" (sum w rho u, 3)}. vals[l]: [nb, 10, 512] moments with
+    rho - 1 in slot 0; counted: composite_weights of the same hierarchy, if at hand."""
+    out = {"volume": 0.0, "mass_excess": 0.0, "momentum": np.zeros(3)}
+    counted = composite_weights(levels, keys, roles) if counted is None else counted
+    for l in range(levels):
+        own = counted[l]
         w = float(8 ** l)
         v = np.asarray(vals[l], dtype=np.float64)
         r = v[:, 0][own]

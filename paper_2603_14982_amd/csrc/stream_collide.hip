@@ -62,65 +62,78 @@ template <class S> struct ScArgs {
 // With coupling fields c4 = (eps, F) (CPL) the node relaxes at omega / eps (tau
 // scaled by the fluid fraction) and the force enters in Guo's moment form: S gains
 // (1 - om/2)(u F + F u)/rho, and the carried velocity is u + F/(2 rho).
+//
+// Every product that meets an addition is fused or not as written here (contraction
+// by the compiler is off in this function): the kernels that reconstruct a node in
+// different code (one substep per sweep, two substeps per sweep) round it the same
+// way, so they agree bit for bit.
 template <bool CPL>
 __device__ __forceinline__ void source_pops(const float q[kMom], float omega, const float c4[4], float p[24]) {
+#pragma clang fp contract(off)
   const float drho = q[0];
   const float rho = 1.0f + drho;
   float ux = q[1], uy = q[2], uz = q[3];
   const float om = CPL ? omega / c4[0] : omega;
   // collision: S relaxes to u u
-  float sxx = q[4] + om * (ux * ux - q[4]);
-  float syy = q[5] + om * (uy * uy - q[5]);
-  float szz = q[6] + om * (uz * uz - q[6]);
-  float sxy = q[7] + om * (ux * uy - q[7]);
-  float sxz = q[8] + om * (ux * uz - q[8]);
-  float syz = q[9] + om * (uy * uz - q[9]);
+  float sxx = __builtin_fmaf(om, __builtin_fmaf(ux, ux, -q[4]), q[4]);
+  float syy = __builtin_fmaf(om, __builtin_fmaf(uy, uy, -q[5]), q[5]);
+  float szz = __builtin_fmaf(om, __builtin_fmaf(uz, uz, -q[6]), q[6]);
+  float sxy = __builtin_fmaf(om, __builtin_fmaf(ux, uy, -q[7]), q[7]);
+  float sxz = __builtin_fmaf(om, __builtin_fmaf(ux, uz, -q[8]), q[8]);
+  float syz = __builtin_fmaf(om, __builtin_fmaf(uy, uz, -q[9]), q[9]);
   if (CPL) {
     const float g = (1.0f - 0.5f * om) / rho;
     const float fx = c4[1], fy = c4[2], fz = c4[3];
-    sxx += g * (ux * fx + fx * ux);
-    syy += g * (uy * fy + fy * uy);
-    szz += g * (uz * fz + fz * uz);
-    sxy += g * (ux * fy + fx * uy);
-    sxz += g * (ux * fz + fx * uz);
-    syz += g * (uy * fz + fy * uz);
+    sxx = __builtin_fmaf(g, 2.0f * (ux * fx), sxx);
+    syy = __builtin_fmaf(g, 2.0f * (uy * fy), syy);
+    szz = __builtin_fmaf(g, 2.0f * (uz * fz), szz);
+    sxy = __builtin_fmaf(g, __builtin_fmaf(ux, fy, fx * uy), sxy);
+    sxz = __builtin_fmaf(g, __builtin_fmaf(ux, fz, fx * uz), sxz);
+    syz = __builtin_fmaf(g, __builtin_fmaf(uy, fz, fy * uz), syz);
     const float h = 0.5f / rho;
-    ux += h * fx;
-    uy += h * fy;
-    uz += h * fz;
+    ux = __builtin_fmaf(h, fx, ux);
+    uy = __builtin_fmaf(h, fy, uy);
+    uz = __builtin_fmaf(h, fz, uz);
   }
   // third-order terms Gamma_aab = S_aa u_b + 2 S_ab u_a - 2 u_a^2 u_b
   //                             = u_b (S_aa - 2 u_a^2) + 2 S_ab u_a
-  const float tx = sxx - 2.0f * (ux * ux), ty = syy - 2.0f * (uy * uy), tz = szz - 2.0f * (uz * uz);
+  const float tx = __builtin_fmaf(-2.0f * ux, ux, sxx);
+  const float ty = __builtin_fmaf(-2.0f * uy, uy, syy);
+  const float tz = __builtin_fmaf(-2.0f * uz, uz, szz);
   const float s2xy = 2.0f * sxy, s2xz = 2.0f * sxz, s2yz = 2.0f * syz;
-  const float gxxy = uy * tx + s2xy * ux;
-  const float gyyx = ux * ty + s2xy * uy;
-  const float gxxz = uz * tx + s2xz * ux;
-  const float gzzx = ux * tz + s2xz * uz;
-  const float gyyz = uz * ty + s2yz * uy;
-  const float gzzy = uy * tz + s2yz * uz;
-  const float gxyz = sxy * uz + sxz * uy + syz * ux - 2.0f * (ux * uy) * uz;
-  // tensor-basis coefficients (Eq. three_order_f in the p0/p1/p2' basis)
+  const float gxxy = __builtin_fmaf(uy, tx, s2xy * ux);
+  const float gyyx = __builtin_fmaf(ux, ty, s2xy * uy);
+  const float gxxz = __builtin_fmaf(uz, tx, s2xz * ux);
+  const float gzzx = __builtin_fmaf(ux, tz, s2xz * uz);
+  const float gyyz = __builtin_fmaf(uz, ty, s2yz * uy);
+  const float gzzy = __builtin_fmaf(uy, tz, s2yz * uz);
+  const float gxyz = __builtin_fmaf(sxy, uz, __builtin_fmaf(sxz, uy, __builtin_fmaf(syz, ux, (-2.0f * (ux * uy)) * uz)));
+  // tensor-basis coefficients (Eq. three_order_f in the p0/p1/p2' basis); per
+  // (my, mz) group with coefficients (a0, a1, a2) along x:
+  //   P(+-1) = (a0 + 2 a2) +- a1,  P(0) = 4 (a0 - a2)
+  // a1 enters fused; a0 and a2 are rounded once (each is used twice)
   const float r3 = 3.0f * rho, r15 = 1.5f * rho, r9 = 9.0f * rho, r45 = 4.5f * rho, r27 = 27.0f * rho;
-  const float a100 = r3 * ux, a010 = r3 * uy, a001 = r3 * uz;
+  const float a010 = r3 * uy, a001 = r3 * uz;
   const float a200 = r15 * sxx, a020 = r15 * syy, a002 = r15 * szz;
-  const float a110 = r9 * sxy, a101 = r9 * sxz, a011 = r9 * syz;
-  const float a210 = r45 * gxxy, a120 = r45 * gyyx, a201 = r45 * gxxz;
-  const float a102 = r45 * gzzx, a021 = r45 * gyyz, a012 = r45 * gzzy;
-  const float a111 = r27 * gxyz;
+  const float a011 = r9 * syz;
+  const float a210 = r45 * gxxy, a201 = r45 * gxxz;
+  const float a021 = r45 * gyyz, a012 = r45 * gzzy;
   float e;
   // (my,mz) = (0,0): (a000, a100, a200)
-  e = drho + 2.0f * a200;  p[0] = e + a100;  p[1] = 4.0f * (drho - a200);  p[2] = e - a100;
+  e = __builtin_fmaf(2.0f, a200, drho);
+  p[0] = __builtin_fmaf(r3, ux, e);  p[1] = 4.0f * (drho - a200);  p[2] = __builtin_fmaf(-r3, ux, e);
   // (1,0): (a010, a110, a210)
-  e = a010 + 2.0f * a210;  p[3] = e + a110;  p[4] = 4.0f * (a010 - a210);  p[5] = e - a110;
+  e = __builtin_fmaf(2.0f, a210, a010);
+  p[3] = __builtin_fmaf(r9, sxy, e);  p[4] = 4.0f * (a010 - a210);  p[5] = __builtin_fmaf(-r9, sxy, e);
   // (0,1): (a001, a101, a201)
-  e = a001 + 2.0f * a201;  p[6] = e + a101;  p[7] = 4.0f * (a001 - a201);  p[8] = e - a101;
+  e = __builtin_fmaf(2.0f, a201, a001);
+  p[6] = __builtin_fmaf(r9, sxz, e);  p[7] = 4.0f * (a001 - a201);  p[8] = __builtin_fmaf(-r9, sxz, e);
   // (2,0): (a020, a120, 0)
-  p[9] = a020 + a120;  p[10] = 4.0f * a020;  p[11] = a020 - a120;
+  p[9] = __builtin_fmaf(r45, gyyx, a020);  p[10] = 4.0f * a020;  p[11] = __builtin_fmaf(-r45, gyyx, a020);
   // (0,2): (a002, a102, 0)
-  p[12] = a002 + a102;  p[13] = 4.0f * a002;  p[14] = a002 - a102;
+  p[12] = __builtin_fmaf(r45, gzzx, a002);  p[13] = 4.0f * a002;  p[14] = __builtin_fmaf(-r45, gzzx, a002);
   // (1,1): (a011, a111, 0)
-  p[15] = a011 + a111;  p[16] = 4.0f * a011;  p[17] = a011 - a111;
+  p[15] = __builtin_fmaf(r27, gxyz, a011);  p[16] = 4.0f * a011;  p[17] = __builtin_fmaf(-r27, gxyz, a011);
   // (2,1): (a021, 0, 0)
   p[18] = a021;  p[19] = 4.0f * a021;  p[20] = a021;
   // (1,2): (a012, 0, 0)
@@ -648,14 +661,10 @@ __device__ __forceinline__ void st8_at(float* lds, int off, const float v[8]) {
   st8_h<Tile<TX>::HALF>(lds, off, v);
 }
 
-// x pass for one row of a plane buffer (x-pass input at `base`, kinds KINDA apart,
-// 4 floats per column, halves HALF apart), output column x (input columns x, x+1, x+2)
-template <int HALF, int KINDA>
-__device__ __forceinline__ void x_pass_row(const float* lds, int base, int x, float yb[27]) {
-  float pp[8], pz[8], pm[8];
-  ld8_h<HALF>(lds, base + 0 * KINDA + x * 4, pp);        // P+ of column x-1
-  ld8_h<HALF>(lds, base + 1 * KINDA + (x + 1) * 4, pz);  // P0 of column x
-  ld8_h<HALF>(lds, base + 2 * KINDA + (x + 2) * 4, pm);  // P- of column x+1
+// x pass of one output column from the eight P+ of column x - 1, the eight P0 of
+// column x and the eight P- of column x + 1: back-map the 8 groups after the shift,
+// then forward-map along y for the 9 (qx, mz) triples
+__device__ __forceinline__ void x_pass_vals(const float pp[8], const float pz[8], const float pm[8], float yb[27]) {
   float B[3][3][3];  // [qx][my][mz]
 #pragma unroll
   for (int g = 0; g < 8; ++g) {
@@ -673,6 +682,40 @@ __device__ __forceinline__ void x_pass_row(const float* lds, int base, int x, fl
       const int t = 3 * qx + mz;
       fwd3(B[qx][0][mz], B[qx][1][mz], b2, yb[t], yb[9 + t], yb[18 + t]);
     }
+}
+
+// x pass for one row of a plane buffer (x-pass input at `base`, kinds KINDA apart,
+// 4 floats per column, halves HALF apart), output column x (input columns x, x+1, x+2)
+template <int HALF, int KINDA>
+__device__ __forceinline__ void x_pass_row(const float* lds, int base, int x, float yb[27]) {
+  float pp[8], pz[8], pm[8];
+  ld8_h<HALF>(lds, base + 0 * KINDA + x * 4, pp);        // P+ of column x-1
+  ld8_h<HALF>(lds, base + 1 * KINDA + (x + 1) * 4, pz);  // P0 of column x
+  ld8_h<HALF>(lds, base + 2 * KINDA + (x + 2) * 4, pm);  // P- of column x+1
+  x_pass_vals(pp, pz, pm, yb);
+}
+
+// Cross-lane moves of a wave (data-parallel primitives): lane i receives the value
+// of lane i - 1 (lane_prev) or lane i + 1 (lane_next); the lanes at the ends of the
+// wave receive zero. All 64 lanes must be active.
+__device__ __forceinline__ float lane_prev(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// x pass of the lane's column when the lanes before and after it hold the columns
+// x - 1 and x + 1 of the same row (p: the lane's own x-populations)
+__device__ __forceinline__ void x_pass_lanes(const float p[24], float yb[27]) {
+  float pp[8], pz[8], pm[8];
+#pragma unroll
+  for (int g = 0; g < 8; ++g) {
+    pp[g] = lane_prev(p[3 * g]);
+    pz[g] = p[3 * g + 1];
+    pm[g] = lane_next(p[3 * g + 2]);
+  }
+  x_pass_vals(pp, pz, pm, yb);
 }
 
 // x pass for tile row `row` (plane row row - 1), tile column x
@@ -881,10 +924,15 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
 // both. Substep A runs on the tile plus a one-node ring (18 x 18 columns, planes -1 to
 // 16) from the input with a two-node halo (20 x 20 points, planes -2 to 17); substep B
 // runs on the tile from A's results, one plane behind. A's result never leaves the
-// chip: column p of A (the B source point p of the 18 x 18 plane) belongs to the lane
-// that feeds point p into B's source stage, so A's moments go from its z pass straight
-// into B. The input is read once (with a two-node halo) and the output written once
-// for two updates of every node.
+// chip: the lane that finishes A's column p is the lane that feeds point p into B's
+// source stage. The input is read once (with a two-node halo) and the output written
+// once for two updates of every node.
+// Each wave holds whole rows of a plane in consecutive lanes (three rows of 20 source
+// points, three rows of 18 A columns, four rows of 16 B columns), so both x passes
+// take their neighbours' populations by cross-lane moves; only the y passes go
+// through LDS, with separate buffers for A and B. Per plane: phase 1 (A source and x
+// pass of plane z; B y and z pass of the plane B got in the previous iteration),
+// barrier, phase 2 (A y and z pass, B source and x pass), barrier.
 // Nodes of A's ring that A does not compute take what the second substep reads
 // otherwise: zero for solid nodes and missing blocks, the value already in the output
 // time level for ghost and inflow nodes (never written by either substep). Outflow
@@ -892,23 +940,18 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
 // node's own intermediate moments) are not handled: levels that have them run the two
 // substeps as two sweeps.
 struct Pair {
-  static constexpr int THREADS = 512;           // eight waves: one A point / column per lane
-  static constexpr int CXA = 20;                // A source plane: 20 x 20 points
-  static constexpr int PTSA = CXA * CXA;
-  static constexpr int CA = 18;                 // A columns: 18 x 18 (= B source points)
-  static constexpr int COLSA = CA * CA;
-  static constexpr int XA = CXA * CA;           // A x-pass outputs: 20 rows x 18 columns
-  static constexpr int HALFA = CXA * 4;         // x-pass input [kind][half][col 0..19][4]
-  static constexpr int KINDA = 2 * HALFA;
-  static constexpr int KINDB = CA * 10;         // y-pass input [kind][col 0..17][10]
-  static constexpr int ROWA = 3 * KINDB + 24;   // 564 floats, 20 banks off a multiple of 32 (measured best)
-  // Phases run on whole waves (a wave with no lane in a phase skips it): A source on
-  // waves 0..6, A x pass, A y/z pass and B source on 0..5, B x pass on 0..4, B y/z pass
-  // on 4..7.
-  static constexpr int BWAVE0 = 4;              // waves 4..7 run B's y and z passes
-  static_assert(3 * KINDA <= ROWA, "x-pass input must fit in a row");
-  static_assert(CXA * ROWA >= Tile<2>::CY * Tile<2>::ROW, "substep B's plane must fit");
-  static_assert(PTSA <= THREADS && XA <= THREADS && COLSA <= THREADS && Tile<2>::CY * 16 <= THREADS, "one round");
+  static constexpr int THREADS = 512;
+  static constexpr int CXA = 20;               // A source plane: 20 x 20 points
+  static constexpr int CA = 18;                // A columns (= B source points): 18 x 18
+  static constexpr int KA = CA * 10;           // A y-pass input [row 0..19][kind][col 0..17][10]
+  static constexpr int ROWA = 3 * KA + 24;     // 564 floats: 20 banks past a multiple of 32
+  static constexpr int KB = 16 * 10;           // B y-pass input [row 0..17][kind][col 0..15][10]
+  static constexpr int ROWB = 3 * KB;          // 480 floats: a multiple of 32 banks
+  // Work of each wave, 4 bits per wave (wave w at bits 4w, 0xf: none), spread so that
+  // the two waves of each SIMD (w, w + 4) carry similar loads over a plane:
+  static constexpr uint32_t SRC = 0xf6325410u;  // source rows 3s .. 3s + 2 (s = 0..6)
+  static constexpr uint32_t COL = 0xff325410u;  // A column rows 3c .. 3c + 2 (c = 0..5)
+  static constexpr uint32_t BCO = 0x32ff10ffu;  // B column rows 4b .. 4b + 3 (b = 0..3)
 };
 
 // role code of an A node: the role byte, or kPairZero for the all-zero slot
@@ -916,14 +959,14 @@ constexpr uint32_t kPairZero = 0xffu;
 
 template <class S>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_stream_collide_pair(ScArgs<S> a) {
-  typedef Tile<2> G;  // substep B: the tile kernel's plane layout
   typedef Pair P;
   typedef typename S::type T;
-  __shared__ __align__(16) float lds[P::CXA * P::ROWA];
+  __shared__ __align__(16) float lda[P::CXA * P::ROWA];
+  __shared__ __align__(16) float ldb[P::CA * P::ROWB];
   __shared__ int s_src[64];  // blocks (qx - 1 .. qx + 2) x (qy - 1 .. qy + 2) x (qz - 1 .. qz + 2)
   __shared__ int s_mem[8];   // the tile's blocks (or -1), x fastest
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
+  const int lane = tid & 63;
   const int4 c0 = a.coord[a.tiles[xcd_remap(blockIdx.x, a.ntiles)]];
   const int qx = c0.x & ~1, qy = c0.y & ~1, qz = c0.z & ~1;
   if (tid < 64) {
@@ -947,173 +990,56 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
   __syncthreads();
 
-  // A source point (20 x 20) and A column (18 x 18, also B source point) of the lane
-  const bool shas = tid < P::PTSA;
-  const int spx = tid % P::CXA - 2, spy = tid / P::CXA - 2;
-  const bool chas = tid < P::COLSA;
-  const int cx = tid % P::CA - 1, cy = tid / P::CA - 1;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int ss = (P::SRC >> (4 * wave)) & 0xf;
+  const int cs = (P::COL >> (4 * wave)) & 0xf;
+  const int bs = (P::BCO >> (4 * wave)) & 0xf;
+  // A source point (20 x 20 plane, two-node halo); the lanes at row positions 1..18
+  // write A's x-pass output of column position - 1
+  const bool swave = ss != 0xf;
+  const int sr = swave ? 3 * ss + lane / P::CXA : 0, sx = lane % P::CXA;
+  const bool shas = swave && lane < 3 * P::CXA && sr < P::CXA;
+  const bool swr = shas && sx >= 1 && sx <= P::CA;
+  const int spx = sx - 2, spy = sr - 2;
+  // A column (18 x 18: tile columns -1 .. 16), also B's source point; the lanes at
+  // row positions 1..16 write B's x-pass output of column position - 1
+  const bool cwave = cs != 0xf;
+  const bool chas = cwave && lane < 3 * P::CA;
+  const int cr = chas ? 3 * cs + lane / P::CA : 0, cxl = chas ? lane % P::CA : 0;
+  const bool cwr = chas && cxl >= 1 && cxl <= 16;
+  const int cx = cxl - 1, cy = cr - 1;
   const int cnode = (cx & 7) + 8 * (cy & 7);
   const int cblk = ((cx + 8) >> 3) + 4 * ((cy + 8) >> 3);
-  // B output column: waves 4..7, one block column of the tile each
-  const bool bout = wave >= P::BWAVE0;
-  const int bw = wave & 3;
-  const int ox = lane & 7, oy = lane >> 3;
-  const int tx = (bw & 1) * 8 + ox, ty = (bw >> 1) * 8 + oy;
+  // B output column (16 x 16)
+  const bool bwave = bs != 0xf;
+  const int tx = lane & 15, ty = 4 * (bwave ? bs : 0) + (lane >> 4);
+  const int bq = (tx >> 3) + 2 * (ty >> 3);
+  const int bnode = (tx & 7) + 8 * (ty & 7);
 
   T nxt[kMom];
+#pragma unroll
+  for (int m = 0; m < kMom; ++m) nxt[m] = T(0);
   if (shas) fetch_tile<S, 2>(a, s_src, spx, spy, -2, nxt);
 
-  float azp1[6], azp2[6], az0[6];  // A's z window (the lane's column)
-  float bzp1[6], bzp2[6], bz0[6];  // B's z window
+  float azp1[6], azp2[6], az0[6];  // A's z window (the lane's A column)
+  float bzp1[6], bzp2[6], bz0[6];  // B's z window (the lane's B column)
 #pragma unroll
   for (int k = 0; k < 6; ++k) azp1[k] = azp2[k] = az0[k] = bzp1[k] = bzp2[k] = bz0[k] = 0.0f;
-  uint32_t arole = kPairZero;  // role code of the column's node at A's output plane
+  uint32_t arole = kPairZero;  // role code of the A column's node at A's output plane
+  int bslot = -1;              // block and role of the B column's node at B's next output plane
+  uint32_t brole = ROLE_GHOST;
 
-  for (int z = -2; z <= 17; ++z) {
-    const int zi = z - 1;  // A's output plane of this iteration (B's source plane)
-    const int zo = z - 2;  // B's output plane
-    // ---- role of B's output node (used at the end of the iteration)
-    const int bslot = bout && zo >= 0 ? s_mem[bw + (zo >= 8 ? 4 : 0)] : -1;
-    uint32_t brole = ROLE_GHOST;
-    if (bslot >= 0) brole = a.role[(size_t)bslot * kNodes + ox + 8 * oy + 64 * (zo & 7)];
-    // ---- A source: input plane z (+ two-node halo) -> x-populations
-    T cur[kMom];
-#pragma unroll
-    for (int m = 0; m < kMom; ++m) cur[m] = nxt[m];
-    if (shas && z < 17) fetch_tile<S, 2>(a, s_src, spx, spy, z + 1, nxt);
-    if (shas) {
-      float q[kMom];
-#pragma unroll
-      for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(cur[m], a.sc.inv[m]);
-      float p[24];
-      source_pops(q, a.omega, p);
-      float v[8];
-      const int off = (spy + 2) * P::ROWA + (spx + 2) * 4;
-#pragma unroll
-      for (int kind = 0; kind < 3; ++kind) {
-#pragma unroll
-        for (int g = 0; g < 8; ++g) v[g] = p[3 * g + kind];
-        st8_h<P::HALFA>(lds, off + kind * P::KINDA, v);
-      }
-    }
-    // ---- value of A's output node if A does not compute it (ghost, inflow node)
-    T pv[kMom];
-    const uint32_t rk = arole & ROLE_MASK;
-    const bool pass = chas && zi >= -1 && arole != kPairZero && rk != ROLE_COMPUTED && rk != ROLE_SOLID;
-    if (pass) {
-      const int ns = s_src[cblk + 16 * ((zi + 8) >> 3)];
-      const T* src = a.out + (size_t)ns * kBlockStride + cnode + 64 * (zi & 7);
-#pragma unroll
-      for (int m = 0; m < kMom; ++m) pv[m] = src[m * kNodes];
-    }
-    // ---- role code of the next output plane (plane z)
-    uint32_t nrole = kPairZero;
-    if (chas && z >= -1 && z <= 16) {
-      const int ns = s_src[cblk + 16 * ((z + 8) >> 3)];
-      if (ns != a.zero_slot) nrole = a.role[(size_t)ns * kNodes + cnode + 64 * (z & 7)];
-    }
-    __syncthreads();
-
-    // ---- A x pass: 20 rows x 18 columns on the first six waves, each row overwritten
-    // by its y-pass input once all its reads are done (lanes past the 360 outputs
-    // repeat output 0 and do not store)
-    {
-      const bool act = tid < P::XA;
-      const int t = act ? tid : 0;
-      const int row = t / P::CA, x = t % P::CA;
-      float yb[27];
-      if (wave < (P::XA + 63) / 64) {
-        x_pass_row<P::HALFA, P::KINDA>(lds, row * P::ROWA, x, yb);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 27; ++k) yb[k] = 0.0f;
-      }
-      __syncthreads();
-      if (act) {
-        st9(lds, row * P::ROWA + 0 * P::KINDB + x * 10, yb);
-        st9(lds, row * P::ROWA + 1 * P::KINDB + x * 10, yb + 9);
-        st9(lds, row * P::ROWA + 2 * P::KINDB + x * 10, yb + 18);
-      }
-    }
-    __syncthreads();
-
-    // ---- A y pass and z pass of the lane's column: output plane zi
-    float qa[kMom];
-    if (chas) {
-      float zpp[6], zpz[6], zpm[6];
-      y_pass_col<P::ROWA, P::KINDB>(lds, cy + 1, cx + 1, zpp, zpz, zpm);
-      if (zi >= -1) {
-        if (arole != kPairZero && rk == ROLE_COMPUTED) {
-          float M[10];
-          z_back(azp2, az0, zpm, M);
-          float v[kMom];
-          finish_moments(M, v);
-          // what the second substep would read back from memory
-#pragma unroll
-          for (int m = 0; m < kMom; ++m) qa[m] = Codec<S>::load(Codec<S>::store(v[m], a.sc.s[m]), a.sc.inv[m]);
-        } else if (pass) {
-#pragma unroll
-          for (int m = 0; m < kMom; ++m) qa[m] = Codec<S>::load(pv[m], a.sc.inv[m]);
-        } else {
-#pragma unroll
-          for (int m = 0; m < kMom; ++m) qa[m] = 0.0f;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 6; ++k) {
-        azp2[k] = azp1[k];
-        azp1[k] = zpp[k];
-        az0[k] = zpz[k];
-      }
-    }
-    arole = nrole;
-    __syncthreads();
-
-    if (zi >= -1) {
-      // ---- B source: A's plane zi -> x-populations (B layout)
-      if (chas) {
-        float p[24];
-        source_pops(qa, a.omega, p);
-        float v[8];
-        const int off = (cy + 1) * G::ROW + (cx + 1) * 4;
-#pragma unroll
-        for (int kind = 0; kind < 3; ++kind) {
-#pragma unroll
-          for (int g = 0; g < 8; ++g) v[g] = p[3 * g + kind];
-          st8_at<2>(lds, off + kind * G::KINDA, v);
-        }
-      }
-      __syncthreads();
-
-      // ---- B x pass: 18 rows x 16 columns on the first five waves
-      {
-        const bool act = tid < G::CY * G::NX;
-        const int t = act ? tid : 0;
-        const int row = t / G::NX, x = t % G::NX;
-        float yb[27];
-        if (wave < (G::CY * G::NX + 63) / 64) {
-          x_pass_tile<2>(lds, row, x, yb);
-        } else {
-#pragma unroll
-          for (int k = 0; k < 27; ++k) yb[k] = 0.0f;
-        }
-        __syncthreads();
-        if (act) {
-          st9(lds, row * G::ROW + 0 * G::KINDB + x * 10, yb);
-          st9(lds, row * G::ROW + 1 * G::KINDB + x * 10, yb + 9);
-          st9(lds, row * G::ROW + 2 * G::KINDB + x * 10, yb + 18);
-        }
-      }
-      __syncthreads();
-
-      // ---- B y pass, z pass: output plane zo = zi - 1
-      if (bout) {
+  for (int z = -2; z <= 18; ++z) {
+    const int zi = z - 1;  // A's output plane (B's source plane) of this iteration
+    // ---- phase 1: B y and z pass of B's source plane z - 2 (output plane z - 3)
+    if (bwave) {
+      if (z >= 1) {
         float zpp[6], zpz[6], zpm[6];
-        y_pass_col<G::ROW, G::KINDB>(lds, ty, tx, zpp, zpz, zpm);
+        y_pass_col<P::ROWB, P::KB>(ldb, ty, tx, zpp, zpz, zpm);
         if (bslot >= 0) {
           float M[10];
           z_back(bzp2, bz0, zpm, M);
-          T* dst = a.out + (size_t)bslot * kBlockStride + ox + 8 * oy + 64 * (zo & 7);
+          T* dst = a.out + (size_t)bslot * kBlockStride + bnode + 64 * ((z - 3) & 7);
           if ((brole & ROLE_MASK) == ROLE_COMPUTED) {
             float v[kMom];
             finish_moments(M, v);
@@ -1131,8 +1057,91 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
           bz0[k] = zpz[k];
         }
       }
-      __syncthreads();
+      // block and role of the next output plane z - 2
+      const int zo = z - 2;
+      bslot = zo >= 0 && zo <= 15 ? s_mem[bq + (zo >= 8 ? 4 : 0)] : -1;
+      brole = bslot >= 0 ? a.role[(size_t)bslot * kNodes + bnode + 64 * (zo & 7)] : ROLE_GHOST;
     }
+    // ---- phase 1: A source and x pass of input plane z
+    if (swave && z <= 17) {
+      T cur[kMom];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) cur[m] = nxt[m];
+      if (shas && z < 17) fetch_tile<S, 2>(a, s_src, spx, spy, z + 1, nxt);
+      float q[kMom];
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(cur[m], a.sc.inv[m]);
+      float p[24];
+      source_pops(q, a.omega, p);
+      float yb[27];
+      x_pass_lanes(p, yb);
+      if (swr) {
+        const int off = sr * P::ROWA + (sx - 1) * 10;
+        st9(lda, off + 0 * P::KA, yb);
+        st9(lda, off + 1 * P::KA, yb + 9);
+        st9(lda, off + 2 * P::KA, yb + 18);
+      }
+    }
+    // value of A's output node (plane zi) where A does not compute it (ghost, inflow),
+    // and the role code of the next output plane (plane z)
+    T pv[kMom];
+    const uint32_t rk = arole & ROLE_MASK;
+    const bool pass = chas && zi >= -1 && zi <= 16 && arole != kPairZero && rk != ROLE_COMPUTED &&
+                      rk != ROLE_SOLID;
+    if (pass) {
+      const int ns = s_src[cblk + 16 * ((zi + 8) >> 3)];
+      const T* src = a.out + (size_t)ns * kBlockStride + cnode + 64 * (zi & 7);
+#pragma unroll
+      for (int m = 0; m < kMom; ++m) pv[m] = src[m * kNodes];
+    }
+    uint32_t nrole = kPairZero;
+    if (chas && z >= -1 && z <= 16) {
+      const int ns = s_src[cblk + 16 * ((z + 8) >> 3)];
+      if (ns != a.zero_slot) nrole = a.role[(size_t)ns * kNodes + cnode + 64 * (z & 7)];
+    }
+    __syncthreads();
+
+    // ---- phase 2: A y and z pass (output plane zi), B source and x pass of plane zi
+    if (cwave && z <= 17) {
+      float zpp[6], zpz[6], zpm[6];
+      y_pass_col<P::ROWA, P::KA>(lda, cr, cxl, zpp, zpz, zpm);
+      if (zi >= -1) {
+        float qa[kMom];
+        if (chas && arole != kPairZero && rk == ROLE_COMPUTED) {
+          float M[10];
+          z_back(azp2, az0, zpm, M);
+          float v[kMom];
+          finish_moments(M, v);
+          // what the second substep would read back from memory
+#pragma unroll
+          for (int m = 0; m < kMom; ++m) qa[m] = Codec<S>::load(Codec<S>::store(v[m], a.sc.s[m]), a.sc.inv[m]);
+        } else if (pass) {
+#pragma unroll
+          for (int m = 0; m < kMom; ++m) qa[m] = Codec<S>::load(pv[m], a.sc.inv[m]);
+        } else {
+#pragma unroll
+          for (int m = 0; m < kMom; ++m) qa[m] = 0.0f;
+        }
+        float p[24];
+        source_pops(qa, a.omega, p);
+        float yb[27];
+        x_pass_lanes(p, yb);
+        if (cwr) {
+          const int off = cr * P::ROWB + cx * 10;
+          st9(ldb, off + 0 * P::KB, yb);
+          st9(ldb, off + 1 * P::KB, yb + 9);
+          st9(ldb, off + 2 * P::KB, yb + 18);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        azp2[k] = azp1[k];
+        azp1[k] = zpp[k];
+        az0[k] = zpz[k];
+      }
+    }
+    arole = nrole;
+    __syncthreads();
   }
 }
 

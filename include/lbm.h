@@ -268,8 +268,8 @@ lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t 
  * LBM_OPT_FUSE_SUBSTEPS: 2 runs the two substeps of every parent step of the
  *   finest level (Alg. 1, levels >= 2) in one tiled sweep when that level is
  *   tiled and has no outflow or bounce-back nodes, and the step is not being
- *   recorded for the adjoint; 1 (default) does so with LBM_F32 storage only (with
- *   16-bit storage two sweeps are faster); 0 always runs them as two sweeps.
+ *   recorded for the adjoint (default: one sweep is faster with every storage
+ *   format); 1 does so with LBM_F32 storage only; 0 always runs them as two sweeps.
  * LBM_EINVAL for an unknown option or a value out of range. */
 enum { LBM_OPT_TILE_MIN_BLOCKS = 0, LBM_OPT_FUSE_SUBSTEPS = 1 };
 lbm_status lbm_set_option(lbm_ctx* ctx, int32_t option, int64_t value);

@@ -273,10 +273,24 @@ __device__ inline bool solid_at(const Geom& G, const uint8_t* solid, int l, int 
   return solid[x + (int64_t)G.N[0] * (y + (int64_t)G.N[1] * z)] != 0;
 }
 
+// The 27 block positions around a block, d = (ox + 1) + 3 (oy + 1) + 9 (oz + 1), as bits
+// of a mask. The 26 neighbours of a node fall in the positions ox in {-1, 0} if its local
+// x is 0, {0} if it is 1..6, {0, 1} if it is 7 (likewise y, z): reach_mask gives them.
+__device__ __forceinline__ uint32_t reach_axis(int c) { return c == 0 ? 3u : (c == kEdge - 1 ? 6u : 2u); }
+__device__ __forceinline__ uint32_t reach_mask(int lx, int ly, int lz) {
+  const uint32_t ax = reach_axis(lx), ay = reach_axis(ly), az = reach_axis(lz);
+  const uint32_t xm = ((ax & 1u) ? 0x1249249u : 0u) | ((ax & 2u) ? 0x2492492u : 0u) | ((ax & 4u) ? 0x4924924u : 0u);
+  const uint32_t row = 0x7u | (0x7u << 9) | (0x7u << 18);  // positions with oy = -1
+  const uint32_t ym = ((ay & 1u) ? row : 0u) | ((ay & 2u) ? row << 3 : 0u) | ((ay & 4u) ? row << 6 : 0u);
+  const uint32_t zm = ((az & 1u) ? 0x1ffu : 0u) | ((az & 2u) ? 0x1ffu << 9 : 0u) | ((az & 4u) ? 0x1ffu << 18 : 0u);
+  return xm & ym & zm & ~(1u << 13);
+}
+
 __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   __shared__ uint8_t s_st[27];    // state of the 27 surrounding block positions (255 = outside)
   __shared__ uint8_t s_wall[27];  // outside the domain across wall faces only
   __shared__ int s_box[6];        // ghost-node bounding box: lo x, lo y, lo z, hi x, hi y, hi z
+  __shared__ int s_changed;       // a block position around the block changed state
   const Geom& G = r.G;
   const int l = r.level;
   const LevelGeom& g = G.lv[l];
@@ -284,6 +298,8 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   const int32_t slot = r.dir[g.off + cell];
   if (slot < 0) return;  // every active cell holds a slot; never write out of bounds
   const int b[3] = {cell % g.nb[0], (cell / g.nb[0]) % g.nb[1], cell / (g.nb[0] * g.nb[1])};
+  if (threadIdx.x == 0) s_changed = 0;
+  __syncthreads();
   if (threadIdx.x < 27) {
     const int d = threadIdx.x;
     int h[3] = {b[0] + d % 3 - 1, b[1] + (d / 3) % 3 - 1, b[2] + d / 9 - 1};
@@ -304,6 +320,7 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
       const int64_t hc = g.off + cell_lin(g, h[0], h[1], h[2]);
       stv = r.st[hc];
       if (stv == ST_ACTIVE) ns = r.dir[hc];
+      if (r.st_old[hc] != stv) s_changed = 1;
     } else if (wall) {
       ns = NBR_WALL;
     }
@@ -323,7 +340,57 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   uint8_t sum = 0;
   if (inner)
     for (int node = threadIdx.x; node < kNodes; node += 256) r.role[(size_t)slot * kNodes + node] = ROLE_COMPUTED;
-  for (int node = threadIdx.x; node < kNodes && !inner; node += 256) {
+  // without a solid field a node's role follows from the states of the block positions
+  // its neighbours fall in (and its own position on a domain face): the same decisions
+  // as the per-neighbour test below, on 27-bit masks
+  const bool masks = !inner && r.solid == nullptr;
+  if (masks) {
+    uint32_t absent = 0, deleted = 0, wall = 0;
+#pragma unroll 1
+    for (int d = 0; d < 27; ++d) {
+      absent |= (s_st[d] == ST_ABSENT ? 1u : 0u) << d;
+      deleted |= (s_st[d] == ST_DELETED ? 1u : 0u) << d;
+      wall |= (uint32_t)s_wall[d] << d;
+    }
+    int lo[3] = {kEdge, kEdge, kEdge}, hi[3] = {-1, -1, -1};  // this thread's ghost nodes
+    for (int node = threadIdx.x; node < kNodes; node += 256) {
+      const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
+      uint8_t role = 255;
+      for (int a = 0; a < 3 && role == 255; ++a) {
+        if (G.periodic[a]) continue;
+        const int gc = b[a] * kEdge + lc[a];
+        int kind = -1;
+        if (gc == 0) kind = G.bc[2 * a];
+        else if (gc == g.nn[a] - 1) kind = G.bc[2 * a + 1];
+        if (kind == BC_INFLOW) role = ROLE_INFLOW;
+        else if (is_outflow_bc(kind)) role = ROLE_OUTFLOW;
+      }
+      if (role == 255) {
+        const uint32_t m = reach_mask(lc[0], lc[1], lc[2]);
+        role = (absent & m) ? ROLE_GHOST
+                            : ((deleted & m) ? ROLE_IU : (uint8_t)(ROLE_COMPUTED | ((wall & m) ? ROLE_BB : 0)));
+      }
+      r.role[(size_t)slot * kNodes + node] = role;
+      const uint8_t rk = role & ROLE_MASK;
+      if (rk == ROLE_GHOST) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          lo[a] = min(lo[a], lc[a]);
+          hi[a] = max(hi[a], lc[a]);
+        }
+      }
+      sum |= rk == ROLE_GHOST ? SUM_GHOST : (rk == ROLE_IU ? SUM_IU : (rk == ROLE_OUTFLOW ? SUM_OUTFLOW : 0));
+      if (role & ROLE_BB) sum |= SUM_BB;
+    }
+    if (hi[0] >= 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        atomicMin(&s_box[a], lo[a]);
+        atomicMax(&s_box[3 + a], hi[a]);
+      }
+    }
+  }
+  for (int node = threadIdx.x; node < kNodes && !inner && !masks; node += 256) {
     const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
     const int gc[3] = {b[0] * kEdge + lc[0], b[1] * kEdge + lc[1], b[2] * kEdge + lc[2]};
     uint8_t role = 255;
@@ -394,7 +461,7 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
         start = false;
     }
     r.summary[slot] = (any_g ? SUM_GHOST : 0) | (any_i ? SUM_IU : 0) | (any_o ? SUM_OUTFLOW : 0) |
-                      (start ? SUM_TILE : 0) | (any_b ? SUM_BB : 0);
+                      (start ? SUM_TILE : 0) | (any_b ? SUM_BB : 0) | (s_changed ? SUM_FRESH : 0);
     r.gbox[slot] = s_box[0] | s_box[3] << 3 | s_box[1] << 6 | s_box[4] << 9 | s_box[2] << 12 | s_box[5] << 15;
   }
 }
@@ -503,7 +570,13 @@ __device__ inline bool fresh_node(const InitLaunch& a, bool new_block, int32_t s
 template <class S>
 __global__ __launch_bounds__(256) void k_init(InitLaunch a) {
   const LevelGeom& g = a.G.lv[a.level];
-  const int32_t cell = a.cells[blockIdx.x];
+  int32_t cell;
+  if (a.cells) {
+    cell = a.cells[blockIdx.x];
+  } else {
+    const int4 q = a.coord[a.slots[blockIdx.x]];
+    cell = (int32_t)cell_lin(g, q.x, q.y, q.z);
+  }
   const int32_t slot = a.dir_new[g.off + cell];
   if (slot < 0) return;  // every active cell holds a slot; never write out of bounds
   const bool new_block = a.create || a.st_old[g.off + cell] != ST_ACTIVE;

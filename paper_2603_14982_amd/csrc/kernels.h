@@ -124,6 +124,7 @@ struct RoleLaunch {
   int32_t n;
   const int32_t* dir;        // new directory
   const uint8_t* st;         // new states
+  const uint8_t* st_old;     // old states (a block whose 27 positions kept their states keeps its roles)
   const uint8_t* solid;      // fine solid field or null
   uint8_t* role;             // [slot][512] new roles
   uint8_t* summary;          // [slot]
@@ -136,7 +137,9 @@ hipError_t launch_roles(const RoleLaunch& r, hipStream_t s);
 struct InitLaunch {
   Geom G;
   int level;
-  const int32_t* cells;      // active cells of the level (new hierarchy)
+  const int32_t* cells;      // active cells of the level (new hierarchy), or null: slots
+  const int32_t* slots;      // with cells null: the level's blocks that may hold new nodes
+  const int4* coord;         // block coordinates by slot (with slots)
   int32_t n;
   const int32_t* dir_new;
   const uint8_t* st_old;

@@ -175,7 +175,7 @@ struct lbm_ctx {
   int64_t nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels], ntile[kMaxLevels];
   int64_t nbb[kMaxLevels];          // blocks holding bounce-back nodes
   int64_t tile_min_blocks = 16384;  // LBM_OPT_TILE_MIN_BLOCKS
-  int fuse_substeps = 1;            // LBM_OPT_FUSE_SUBSTEPS: 0 never, 1 with FP32 storage, 2 always
+  int fuse_substeps = 2;            // LBM_OPT_FUSE_SUBSTEPS: 0 never, 1 with FP32 storage, 2 always
   int32_t free_top = 0;
   int32_t* host_counts = nullptr;  // pinned
   double* noalloc_partial = nullptr;  // this GPU's static reduction partials (lbm_reduce_f64_noalloc)
@@ -407,6 +407,7 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     r.n = (int32_t)nact[l];
     r.dir = dir_new;
     r.st = h.st_new;
+    r.st_old = h.st_old;
     r.solid = c->solid;
     r.role = role_new;
     r.summary = summary;
@@ -415,13 +416,50 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     r.nbr = c->m<int32_t>(c->lay.nbr);
     HIPCHK(c, launch_roles(r, s));
   }
+  c->hier = nh;
+  c->rcur = 1 - c->rcur;
+  c->free_top = top;
+  c->generation++;
+  HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
+  for (int l = 0; l < L; ++l) {
+    CompactOut o;
+    o.out[0] = c->gblocks(l);
+    o.out[1] = c->iblocks(l);
+    o.out[2] = c->oblocks(l);
+    o.count = counts + 3 * l;
+    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, 0, wave, o, s));
+    CompactOut t;
+    t.out[0] = c->tblocks(l);
+    t.out[1] = nullptr;
+    t.out[2] = c->lists(l, 1);  // blocks that may hold new nodes (SUM_FRESH)
+    t.count = counts + 32 + 3 * l;
+    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, SUM_TILE_SHIFT, wave, t, s));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 48 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int l = 0; l < L; ++l) {
+    c->nblk[l] = nact[l];
+    c->ngb[l] = c->host_counts[3 * l];
+    c->nib[l] = c->host_counts[3 * l + 1];
+    c->nob[l] = c->host_counts[3 * l + 2];
+    c->ntile[l] = c->host_counts[32 + 3 * l];
+    c->nbb[l] = c->host_counts[33 + 3 * l];
+  }
+  // new nodes: on a first build every block starts at rest; after that only blocks whose
+  // 27 surrounding block positions changed state can hold nodes the update makes owned
   for (int l = 0; l < L; ++l) {
     InitLaunch a;
     std::memset(&a, 0, sizeof(a));
     a.G = G;
     a.level = l;
-    a.cells = c->lists(l, 0);
-    a.n = (int32_t)nact[l];
+    if (create) {
+      a.cells = c->lists(l, 0);
+      a.n = (int32_t)nact[l];
+    } else {
+      a.slots = c->lists(l, 1);
+      a.coord = coord;
+      a.n = c->host_counts[34 + 3 * l];
+    }
     a.dir_new = dir_new;
     a.st_old = h.st_old;
     a.dir_old = dir_old;
@@ -440,34 +478,6 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     a.cpl = l == 0 ? c->cpl() : nullptr;
     a.phi = l == 0 ? c->phi(0) : nullptr;
     HIPCHK(c, launch_init(a, s));
-  }
-  c->hier = nh;
-  c->rcur = 1 - c->rcur;
-  c->free_top = top;
-  c->generation++;
-  HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
-  for (int l = 0; l < L; ++l) {
-    CompactOut o;
-    o.out[0] = c->gblocks(l);
-    o.out[1] = c->iblocks(l);
-    o.out[2] = c->oblocks(l);
-    o.count = counts + 3 * l;
-    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, 0, wave, o, s));
-    CompactOut t;
-    t.out[0] = c->tblocks(l);
-    t.out[1] = t.out[2] = nullptr;
-    t.count = counts + 32 + 3 * l;
-    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, SUM_TILE_SHIFT, wave, t, s));
-  }
-  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 48 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
-  for (int l = 0; l < L; ++l) {
-    c->nblk[l] = nact[l];
-    c->ngb[l] = c->host_counts[3 * l];
-    c->nib[l] = c->host_counts[3 * l + 1];
-    c->nob[l] = c->host_counts[3 * l + 2];
-    c->ntile[l] = c->host_counts[32 + 3 * l];
-    c->nbb[l] = c->host_counts[33 + 3 * l];
   }
   return LBM_OK;
 }

@@ -332,7 +332,7 @@ class Sim:
     def set_option(self, name, value):
         """Execution options: "tile_min_blocks" (blocks a level needs for the tiled
         stream-collide, default 16384) and "fuse_substeps" (2: the finest level's two
-        substeps per parent step in one sweep where allowed, 1 (default): the same
+        substeps per parent step in one sweep where allowed (default), 1: the same
         with FP32 storage only, 0: always two sweeps)."""
         self._check(lib().lbm_set_option(self.h, OPTIONS[name], int(value)))
 

@@ -55,7 +55,7 @@ def _slab_run(levels, storage="f32", fuse=True, steps=6, oracle=False):
             gpu.set_block_moments(l, keys, init(l, keys).astype(np.float32))
         ora = None
     gpu.set_option("tile_min_blocks", 0)
-    if fuse is not None:  # None: the default (one sweep with FP32 storage only)
+    if fuse is not None:  # None: the default (one sweep with every storage format)
         gpu.set_option("fuse_substeps", 2 if fuse else 0)
     gpu.set_profiling(True)
     pg = torch.as_tensor(p).cuda()
@@ -94,12 +94,21 @@ def test_pair_half_precision_matches_two_sweeps(storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_default_fuses_substeps_with_f32_storage_only(storage):
+def test_default_fuses_substeps_with_every_storage(storage):
     _, _, prof = _slab_run(2, storage=storage, fuse=None, steps=2)
-    if storage == "f32":
-        assert prof["sc_pair"][1] == 2 and prof["sc0"][1] == 0, prof
-    else:
-        assert prof["sc_pair"][1] == 0 and prof["sc0"][1] == 4, prof
+    assert prof["sc_pair"][1] == 2 and prof["sc0"][1] == 0, prof
+
+
+def test_fuse_option_one_fuses_with_f32_storage_only():
+    lbm = pytest.importorskip("paper_2603_14982_amd.lbm")
+    sim = lbm.Sim(2, (64, 64, 64), (P,) * 6, 0.6, particles=W.slab_particles(300, 5, (8.0, 8.0, 8.0), (56.0, 56.0, 24.0)),
+                  storage="bf16", scale=[64.0, 8.0, 8.0, 8.0, 64.0, 64.0, 64.0, 64.0, 64.0, 64.0])
+    sim.set_option("tile_min_blocks", 0)
+    sim.set_option("fuse_substeps", 1)
+    sim.set_profiling(True)
+    sim.step(1)
+    prof = sim.profile()
+    assert prof["sc_pair"][1] == 0 and prof["sc0"][1] == 2, prof
 
 
 def test_pair_not_used_with_bounce_back_or_outflow():

@@ -204,27 +204,40 @@ __global__ void k_summary_scatter(const int32_t* blocks, int32_t n, const uint8_
   }
 }
 
-// exclusive scan of three arrays of nw wave counts (in place), totals to count[3]
+// exclusive scan of three arrays of nw wave counts (in place), totals to count[3]:
+// chunks of 1024 values, each scanned within its 16 waves by cross-lane shifts, the 16
+// wave totals by one wave, with a carry from chunk to chunk
+__device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
 __global__ __launch_bounds__(1024) void k_scan3(int32_t* w, int64_t nw, int32_t* count) {
-  __shared__ int32_t part[1024];
+  __shared__ int32_t wsum[16];
   __shared__ int32_t carry;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int k = 0; k < 3; ++k) {
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int64_t base = 0; base < nw; base += 1024) {
       const int64_t i = base + threadIdx.x;
       const int32_t v = i < nw ? w[k * nw + i] : 0;
-      part[threadIdx.x] = v;
+      const int32_t inc = wave_inclusive_scan(v, lane);
+      if (lane == 63) wsum[wave] = inc;
       __syncthreads();
-      for (int off = 1; off < 1024; off <<= 1) {
-        const int32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += add;
-        __syncthreads();
+      if (wave == 0) {
+        const int32_t t = lane < 16 ? wsum[lane] : 0;
+        const int32_t ti = wave_inclusive_scan(t, lane);
+        if (lane < 16) wsum[lane] = ti - t;  // exclusive prefix of the wave totals
       }
-      if (i < nw) w[k * nw + i] = carry + part[threadIdx.x] - v;
       __syncthreads();
-      if (threadIdx.x == 1023) carry += part[1023];
+      const int32_t c0 = carry;
+      if (i < nw) w[k * nw + i] = c0 + wsum[wave] + inc - v;
+      __syncthreads();
+      if (threadIdx.x == 1023) carry = c0 + wsum[15] + inc;
       __syncthreads();
     }
     if (threadIdx.x == 0) count[k] = carry;
@@ -286,22 +299,105 @@ __device__ __forceinline__ uint32_t reach_mask(int lx, int ly, int lz) {
   return xm & ym & zm & ~(1u << 13);
 }
 
+// Role of a node from its own position on a domain face (inflow, outflow) and from the
+// block positions its 26 neighbours fall in (without a solid field): a neighbour in an
+// absent block makes it a ghost node, one in a deleted block an interface node, one
+// outside the domain across a wall a bounce-back node.
+__device__ inline uint8_t mask_role(const Geom& G, const LevelGeom& g, const int b[3], int lx, int ly, int lz,
+                                    uint32_t absent, uint32_t deleted, uint32_t wall) {
+  const int lc[3] = {lx, ly, lz};
+  for (int a = 0; a < 3; ++a) {
+    if (G.periodic[a]) continue;
+    const int gc = b[a] * kEdge + lc[a];
+    int kind = -1;
+    if (gc == 0) kind = G.bc[2 * a];
+    else if (gc == g.nn[a] - 1) kind = G.bc[2 * a + 1];
+    if (kind == BC_INFLOW) return ROLE_INFLOW;
+    if (is_outflow_bc(kind)) return ROLE_OUTFLOW;
+  }
+  const uint32_t m = reach_mask(lx, ly, lz);
+  if (absent & m) return ROLE_GHOST;
+  if (deleted & m) return ROLE_IU;
+  return (uint8_t)(ROLE_COMPUTED | ((wall & m) ? ROLE_BB : 0));
+}
+
+// Role of a node by testing each of its 26 neighbours (with a solid field)
+__device__ inline uint8_t test_role(const RoleLaunch& r, const LevelGeom& g, const int b[3], int node,
+                                    const uint8_t* s_st, const uint8_t* s_wall) {
+  const Geom& G = r.G;
+  const int l = r.level;
+  const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
+  const int gc[3] = {b[0] * kEdge + lc[0], b[1] * kEdge + lc[1], b[2] * kEdge + lc[2]};
+  if (solid_at(G, r.solid, l, gc[0], gc[1], gc[2])) return ROLE_SOLID;
+  for (int a = 0; a < 3; ++a) {
+    if (G.periodic[a]) continue;
+    int kind = -1;
+    if (gc[a] == 0) kind = G.bc[2 * a];
+    else if (gc[a] == g.nn[a] - 1) kind = G.bc[2 * a + 1];
+    if (kind == BC_INFLOW) return ROLE_INFLOW;
+    if (is_outflow_bc(kind)) return ROLE_OUTFLOW;
+  }
+  bool ghost = false, iu = false, bb = false;
+  for (int d = 0; d < 27; ++d) {
+    if (d == 13) continue;
+    const int dd[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
+    int h[3], o[3];
+    bool outside = false;
+    for (int a = 0; a < 3; ++a) {
+      const int v = lc[a] + dd[a];
+      o[a] = v < 0 ? 0 : (v > 7 ? 2 : 1);
+      h[a] = gc[a] + dd[a];
+      if (h[a] < 0 || h[a] >= g.nn[a]) {
+        if (G.periodic[a]) h[a] = h[a] < 0 ? h[a] + g.nn[a] : h[a] - g.nn[a];
+        else outside = true;
+      }
+    }
+    const int nd = o[0] + 3 * o[1] + 9 * o[2];
+    if (outside) {
+      if (s_wall[nd]) bb = true;
+      continue;
+    }
+    const uint8_t stv = s_st[nd];
+    if (stv == ST_ABSENT) ghost = true;
+    else if (stv == ST_DELETED) iu = true;
+    if (solid_at(G, r.solid, l, h[0], h[1], h[2])) bb = true;
+  }
+  return ghost ? ROLE_GHOST : (iu ? ROLE_IU : (uint8_t)(ROLE_COMPUTED | (bb ? ROLE_BB : 0)));
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// One 64-lane wave per block, four blocks per workgroup. Lanes 0..26 look up the 27
+// surrounding block positions (neighbour table, states); ballots turn their states into
+// masks. Lane i owns the 8 nodes of row (y, z) = (i & 7, i >> 3) and writes them as one
+// 8-byte word.
 __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
-  __shared__ uint8_t s_st[27];    // state of the 27 surrounding block positions (255 = outside)
-  __shared__ uint8_t s_wall[27];  // outside the domain across wall faces only
-  __shared__ int s_box[6];        // ghost-node bounding box: lo x, lo y, lo z, hi x, hi y, hi z
-  __shared__ int s_changed;       // a block position around the block changed state
+  __shared__ uint8_t s_st_w[4][32];    // per wave: state of the 27 positions (255 = outside)
+  __shared__ uint8_t s_wall_w[4][32];  // per wave: outside the domain across wall faces only
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Geom& G = r.G;
   const int l = r.level;
   const LevelGeom& g = G.lv[l];
-  const int32_t cell = r.cells[blockIdx.x];
-  const int32_t slot = r.dir[g.off + cell];
-  if (slot < 0) return;  // every active cell holds a slot; never write out of bounds
+  const int64_t bi = (int64_t)blockIdx.x * 4 + wv;
+  uint8_t* s_st = s_st_w[wv];
+  uint8_t* s_wall = s_wall_w[wv];
+  const int32_t cell = bi < r.n ? r.cells[bi] : 0;
+  const int32_t slot = bi < r.n ? r.dir[g.off + cell] : -1;
+  const bool valid = slot >= 0;  // every active cell holds a slot; never write out of bounds
   const int b[3] = {cell % g.nb[0], (cell / g.nb[0]) % g.nb[1], cell / (g.nb[0] * g.nb[1])};
-  if (threadIdx.x == 0) s_changed = 0;
-  __syncthreads();
-  if (threadIdx.x < 27) {
-    const int d = threadIdx.x;
+  uint8_t stv = 255;
+  bool wallpos = false, changed = false;
+  if (valid && lane < 27) {
+    const int d = lane;
     int h[3] = {b[0] + d % 3 - 1, b[1] + (d / 3) % 3 - 1, b[2] + d / 9 - 1};
     bool inside = true, wall = true;
     for (int a = 0; a < 3; ++a) {
@@ -315,141 +411,80 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
       }
     }
     int32_t ns = NBR_NONE;
-    uint8_t stv = 255;
     if (inside) {
       const int64_t hc = g.off + cell_lin(g, h[0], h[1], h[2]);
       stv = r.st[hc];
       if (stv == ST_ACTIVE) ns = r.dir[hc];
-      if (r.st_old[hc] != stv) s_changed = 1;
+      changed = r.st_old[hc] != stv;
     } else if (wall) {
       ns = NBR_WALL;
     }
+    wallpos = !inside && wall;
     s_st[d] = stv;
-    s_wall[d] = (!inside && wall) ? 1 : 0;
+    s_wall[d] = wallpos ? 1 : 0;
     r.nbr[(size_t)slot * 27 + d] = ns;
   }
-  if (threadIdx.x == 0) r.blocks[blockIdx.x] = slot;
-  if (threadIdx.x < 6) s_box[threadIdx.x] = threadIdx.x < 3 ? 7 : 0;
-  __syncthreads();
-  // a block whose 26 neighbour positions all hold active blocks of the level, with no
-  // solid field (inside the domain on every side, so no boundary face either): every
-  // node is computed, with no bounce-back neighbour
-  bool inner = r.solid == nullptr;
-#pragma unroll 1
-  for (int d = 0; d < 27 && inner; ++d) inner = s_st[d] == ST_ACTIVE;
-  uint8_t sum = 0;
-  if (inner)
-    for (int node = threadIdx.x; node < kNodes; node += 256) r.role[(size_t)slot * kNodes + node] = ROLE_COMPUTED;
-  // without a solid field a node's role follows from the states of the block positions
-  // its neighbours fall in (and its own position on a domain face): the same decisions
-  // as the per-neighbour test below, on 27-bit masks
-  const bool masks = !inner && r.solid == nullptr;
-  if (masks) {
-    uint32_t absent = 0, deleted = 0, wall = 0;
-#pragma unroll 1
-    for (int d = 0; d < 27; ++d) {
-      absent |= (s_st[d] == ST_ABSENT ? 1u : 0u) << d;
-      deleted |= (s_st[d] == ST_DELETED ? 1u : 0u) << d;
-      wall |= (uint32_t)s_wall[d] << d;
-    }
-    int lo[3] = {kEdge, kEdge, kEdge}, hi[3] = {-1, -1, -1};  // this thread's ghost nodes
-    for (int node = threadIdx.x; node < kNodes; node += 256) {
-      const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
-      uint8_t role = 255;
-      for (int a = 0; a < 3 && role == 255; ++a) {
-        if (G.periodic[a]) continue;
-        const int gc = b[a] * kEdge + lc[a];
-        int kind = -1;
-        if (gc == 0) kind = G.bc[2 * a];
-        else if (gc == g.nn[a] - 1) kind = G.bc[2 * a + 1];
-        if (kind == BC_INFLOW) role = ROLE_INFLOW;
-        else if (is_outflow_bc(kind)) role = ROLE_OUTFLOW;
-      }
-      if (role == 255) {
-        const uint32_t m = reach_mask(lc[0], lc[1], lc[2]);
-        role = (absent & m) ? ROLE_GHOST
-                            : ((deleted & m) ? ROLE_IU : (uint8_t)(ROLE_COMPUTED | ((wall & m) ? ROLE_BB : 0)));
-      }
-      r.role[(size_t)slot * kNodes + node] = role;
-      const uint8_t rk = role & ROLE_MASK;
-      if (rk == ROLE_GHOST) {
+  __syncthreads();  // the per-wave position tables (read by the per-neighbour test)
+  if (!valid) return;
+  if (lane == 0) r.blocks[bi] = slot;
+  const uint32_t active = (uint32_t)__ballot(lane < 27 && stv == ST_ACTIVE);
+  const uint32_t absent = (uint32_t)__ballot(lane < 27 && stv == ST_ABSENT);
+  const uint32_t deleted = (uint32_t)__ballot(lane < 27 && stv == ST_DELETED);
+  const uint32_t wall = (uint32_t)__ballot(lane < 27 && wallpos);
+  const bool any_changed = __ballot(lane < 27 && changed) != 0ull;
+
+  const int ly = lane & 7, lz = lane >> 3;
+  uint8_t rl[8];
+  if (r.solid == nullptr) {
+    // a block whose 26 neighbour positions all hold active blocks has only computed
+    // nodes; otherwise nodes 1..6 of the row share one role
+    if (active == 0x7ffffffu) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          lo[a] = min(lo[a], lc[a]);
-          hi[a] = max(hi[a], lc[a]);
-        }
-      }
-      sum |= rk == ROLE_GHOST ? SUM_GHOST : (rk == ROLE_IU ? SUM_IU : (rk == ROLE_OUTFLOW ? SUM_OUTFLOW : 0));
-      if (role & ROLE_BB) sum |= SUM_BB;
-    }
-    if (hi[0] >= 0) {
+      for (int i = 0; i < 8; ++i) rl[i] = ROLE_COMPUTED;
+    } else {
+      const uint8_t r0 = mask_role(G, g, b, 0, ly, lz, absent, deleted, wall);
+      const uint8_t r1 = mask_role(G, g, b, 1, ly, lz, absent, deleted, wall);
+      const uint8_t r7 = mask_role(G, g, b, 7, ly, lz, absent, deleted, wall);
+      rl[0] = r0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        atomicMin(&s_box[a], lo[a]);
-        atomicMax(&s_box[3 + a], hi[a]);
-      }
+      for (int i = 1; i < 7; ++i) rl[i] = r1;
+      rl[7] = r7;
     }
+  } else {
+#pragma unroll 1
+    for (int i = 0; i < 8; ++i) rl[i] = test_role(r, g, b, 8 * lane + i, s_st, s_wall);
   }
-  for (int node = threadIdx.x; node < kNodes && !inner && !masks; node += 256) {
-    const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
-    const int gc[3] = {b[0] * kEdge + lc[0], b[1] * kEdge + lc[1], b[2] * kEdge + lc[2]};
-    uint8_t role = 255;
-    if (solid_at(G, r.solid, l, gc[0], gc[1], gc[2])) role = ROLE_SOLID;
-    if (role == 255) {
-      for (int a = 0; a < 3 && role == 255; ++a) {
-        if (G.periodic[a]) continue;
-        int kind = -1;
-        if (gc[a] == 0) kind = G.bc[2 * a];
-        else if (gc[a] == g.nn[a] - 1) kind = G.bc[2 * a + 1];
-        if (kind == BC_INFLOW) role = ROLE_INFLOW;
-        else if (is_outflow_bc(kind)) role = ROLE_OUTFLOW;
-      }
-    }
-    if (role == 255) {
-      bool ghost = false, iu = false, bb = false;
-      for (int d = 0; d < 27; ++d) {
-        if (d == 13) continue;
-        const int dd[3] = {d % 3 - 1, (d / 3) % 3 - 1, d / 9 - 1};
-        int h[3], o[3];
-        bool outside = false;
-        for (int a = 0; a < 3; ++a) {
-          const int v = lc[a] + dd[a];
-          o[a] = v < 0 ? 0 : (v > 7 ? 2 : 1);
-          h[a] = gc[a] + dd[a];
-          if (h[a] < 0 || h[a] >= g.nn[a]) {
-            if (G.periodic[a]) h[a] = h[a] < 0 ? h[a] + g.nn[a] : h[a] - g.nn[a];
-            else outside = true;
-          }
-        }
-        const int nd = o[0] + 3 * o[1] + 9 * o[2];
-        if (outside) {
-          if (s_wall[nd]) bb = true;
-          continue;
-        }
-        const uint8_t stv = s_st[nd];
-        if (stv == ST_ABSENT) ghost = true;
-        else if (stv == ST_DELETED) iu = true;
-        if (solid_at(G, r.solid, l, h[0], h[1], h[2])) bb = true;
-      }
-      role = ghost ? ROLE_GHOST : (iu ? ROLE_IU : (uint8_t)(ROLE_COMPUTED | (bb ? ROLE_BB : 0)));
-    }
-    r.role[(size_t)slot * kNodes + node] = role;
-    const uint8_t rk = role & ROLE_MASK;
+  uint64_t word = 0;
+  uint8_t sum = 0;
+  int lo[3] = {kEdge, kEdge, kEdge}, hi[3] = {-1, -1, -1};
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    word |= (uint64_t)rl[i] << (8 * i);
+    const uint8_t rk = rl[i] & ROLE_MASK;
     if (rk == ROLE_GHOST) {
+      const int lc[3] = {i, ly, lz};
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        atomicMin(&s_box[a], lc[a]);
-        atomicMax(&s_box[3 + a], lc[a]);
+        lo[a] = min(lo[a], lc[a]);
+        hi[a] = max(hi[a], lc[a]);
       }
     }
     sum |= rk == ROLE_GHOST ? SUM_GHOST : (rk == ROLE_IU ? SUM_IU : (rk == ROLE_OUTFLOW ? SUM_OUTFLOW : 0));
-    if (role & ROLE_BB) sum |= SUM_BB;
+    if (rl[i] & ROLE_BB) sum |= SUM_BB;
   }
-  const int any_g = __syncthreads_or(sum & SUM_GHOST);
-  const int any_i = __syncthreads_or(sum & SUM_IU);
-  const int any_o = __syncthreads_or(sum & SUM_OUTFLOW);
-  const int any_b = __syncthreads_or(sum & SUM_BB);
-  if (threadIdx.x == 0) {
+  *reinterpret_cast<uint64_t*>(r.role + (size_t)slot * kNodes + 8 * lane) = word;
+  const bool any_g = __ballot(sum & SUM_GHOST) != 0ull;
+  const bool any_i = __ballot(sum & SUM_IU) != 0ull;
+  const bool any_o = __ballot(sum & SUM_OUTFLOW) != 0ull;
+  const bool any_b = __ballot(sum & SUM_BB) != 0ull;
+  // ghost-node bounding box (all-ghost-free blocks keep lo 7, hi 0)
+  int box[6];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    box[a] = min(wave_min(lo[a]), 7);
+    box[3 + a] = max(wave_max(hi[a]), 0);
+  }
+  if (lane == 0) {
     // one representative per stream-collide tile of kTileX x 2 x 2 blocks: the
     // active member with the lowest index (x fastest); members are never wrapped
     const int c = (b[0] & (kTileX - 1)) + kTileX * ((b[1] & 1) + 2 * (b[2] & 1));
@@ -461,8 +496,8 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
         start = false;
     }
     r.summary[slot] = (any_g ? SUM_GHOST : 0) | (any_i ? SUM_IU : 0) | (any_o ? SUM_OUTFLOW : 0) |
-                      (start ? SUM_TILE : 0) | (any_b ? SUM_BB : 0) | (s_changed ? SUM_FRESH : 0);
-    r.gbox[slot] = s_box[0] | s_box[3] << 3 | s_box[1] << 6 | s_box[4] << 9 | s_box[2] << 12 | s_box[5] << 15;
+                      (start ? SUM_TILE : 0) | (any_b ? SUM_BB : 0) | (any_changed ? SUM_FRESH : 0);
+    r.gbox[slot] = box[0] | box[3] << 3 | box[1] << 6 | box[4] << 9 | box[2] << 12 | box[5] << 15;
   }
 }
 
@@ -779,7 +814,7 @@ hipError_t launch_fill_u8(uint8_t* dst, uint8_t v, int64_t n, hipStream_t s) {
 }
 hipError_t launch_roles(const RoleLaunch& r, hipStream_t s) {
   if (r.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_roles, dim3(r.n), dim3(256), 0, s, r);
+  hipLaunchKernelGGL(k_roles, dim3((r.n + 3) / 4), dim3(256), 0, s, r);
   return hipGetLastError();
 }
 hipError_t launch_init(const InitLaunch& a, hipStream_t s) {

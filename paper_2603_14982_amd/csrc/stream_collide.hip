@@ -699,10 +699,10 @@ __device__ __forceinline__ void x_pass_row(const float* lds, int base, int x, fl
 // of lane i - 1 (lane_prev) or lane i + 1 (lane_next); the lanes at the ends of the
 // wave receive zero. All 64 lanes must be active.
 __device__ __forceinline__ float lane_prev(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float lane_next(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
 // x pass of the lane's column when the lanes before and after it hold the columns

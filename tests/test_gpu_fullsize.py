@@ -192,23 +192,6 @@ def _composite(sim, cache):
     return np.array([c["volume"], c["mass_excess"], *c["momentum"]]), sm, sp
 
 
-@pytest.mark.skipif(os.path.exists(os.path.join(GOLDEN, "slab512_oracle_run.npz")) or
-                    not os.path.exists(os.path.join(GOLDEN, "slab512_oracle_sample.npz")),
-                    reason="the stored oracle run covers the first 20 steps")
-def test_slab512_full_size_against_oracle_sample():
-    wl = W.workload("slab512")
-    g = np.load(os.path.join(GOLDEN, "slab512_oracle_sample.npz"), allow_pickle=False)
-    steps = int(g["steps"])
-    print(f"slab512: {steps} coarse steps with grid updates", flush=True)
-    sim, p, d = _slab_sim(wl)
-    for _ in range(steps):
-        sim.step(1)
-        sim.advance_particles(p, d)
-        sim.remesh(p)
-    torch.cuda.synchronize()
-    _compare_sample(sim, os.path.join(GOLDEN, "slab512_oracle_sample.npz"), 1e-5)
-
-
 @pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN, "slab512_oracle_run.npz")),
                     reason="stored oracle run not generated")
 def test_slab512_full_run_against_oracle():
@@ -236,7 +219,8 @@ def test_slab512_full_run_against_oracle():
         got, sm, sp = _composite(sim, cache)
         ref = sums_at[step]
         assert got[0] == ref[0], (step, "composite volume", got[0], ref[0])
-        em = abs(got[1] - ref[1]) / sm
+        # at step 0 every node is at rest density (sm = 0): the sums must then agree exactly
+        em = abs(got[1] - ref[1]) / sm if sm > 0 else (0.0 if got[1] == ref[1] else float("inf"))
         ep = float(np.abs(got[2:] - ref[2:]).max()) / sp
         print(f"step {step}: mass excess {got[1]:.6e} (oracle {ref[1]:.6e}, diff/scale {em:.1e}), momentum "
               f"{got[2:]} (oracle {ref[2:]}, diff/scale {ep:.1e})", flush=True)
@@ -276,41 +260,3 @@ def test_slab512_full_run_against_oracle():
     assert 0.95 < ratio < 0.995, ratio
 
 
-@pytest.mark.skipif(os.path.exists(os.path.join(GOLDEN, "slab512_oracle_run.npz")),
-                    reason="the stored oracle run covers the full run")
-def test_slab512_full_run_hierarchy_and_invariants():
-    wl = W.workload("slab512")
-    print("slab512: 200 coarse steps", flush=True)
-    sim, p, d = _slab_sim(wl)
-    host = W.slab_particles(wl["particles"], wl["seed"], wl["lo"], wl["hi"])
-    dd = np.array(d, dtype=np.float32)
-    ke0 = sim.reduce(2, (0, 0, 0), (512, 512, 256))[4]
-    changes = 0
-    prev = None
-    for step in range(wl["steps"]):
-        sim.step(1)
-        sim.advance_particles(p, d)
-        sim.remesh(p)
-        host = host + dd  # float32 add, the same rounding as the device
-        counts = tuple(sim.num_blocks(l) for l in range(3))
-        if counts != prev:
-            changes += 1
-            prev = counts
-            assert np.array_equal(p.cpu().numpy(), host)
-            t0 = {tuple(b) for b in np.unique(np.floor(host * np.float32(0.125)).astype(np.int64) % 64, axis=0)}
-            active, _ = canonical_sets(3, (64, 64, 64), (True, True, True), t0)
-            for l in range(3):
-                bx, by, bz = W.morton_decode(sim.block_keys(l).cpu().numpy())
-                assert set(zip(bx.tolist(), by.tolist(), bz.tolist())) == active[l], (step, l)
-            print(f"step {step + 1}: hierarchy {counts} matches the canonical sets", flush=True)
-    torch.cuda.synchronize()
-    assert changes >= 2
-    assert sim.check_finite()
-    # viscous decay of the vortex in the bottom half, which stays on the coarsest
-    # level: linear Taylor-Green decay exp(-6 nu k^2 t) with nu = (tau0 - 1/2)/3 in
-    # fine units over 4 fine steps per coarse step (0.976), nonlinear transfer and
-    # the start from S = u u allowed for by the band
-    ke1 = sim.reduce(2, (0, 0, 0), (512, 512, 256))[4]
-    ratio = ke1 / ke0
-    print(f"kinetic energy ratio (z < 256) after {wl['steps']} coarse steps: {ratio:.5f}", flush=True)
-    assert 0.95 < ratio < 0.995, ratio

@@ -26,7 +26,6 @@ constexpr int32_t NBR_NONE = -1;
 constexpr int32_t NBR_WALL = -2;
 // per-block summary bits
 constexpr uint8_t SUM_GHOST = 1, SUM_IU = 2, SUM_OUTFLOW = 4, SUM_TILE = 8, SUM_BB = 16, SUM_FRESH = 32;
-constexpr int SUM_TILE_SHIFT = 3;  // SUM_TILE, SUM_BB and SUM_FRESH compacted (or counted) together
 // stream-collide tiles of large levels: kTileX x 2 x 2 blocks (kTileX a power of two)
 constexpr int kTileX = 2;
 

@@ -174,6 +174,9 @@ __global__ void k_cells_scatter(Geom G, int l, const uint8_t* st_new, const uint
   }
 }
 
+// per block of a level list: predicates = bits shift .. shift + NP - 1 of its summary
+// byte; per wave the count of each predicate, then the scatter of the slots
+template <int NP>
 __global__ void k_summary_count(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
                                 int32_t* wcount) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -181,14 +184,15 @@ __global__ void k_summary_count(const int32_t* blocks, int32_t n, const uint8_t*
   const int64_t nw = ((int64_t)n + 63) >> 6;
   const int64_t wave = t >> 6;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < NP; ++k) {
     const uint64_t m = __ballot((bits >> k) & 1u);
     if ((threadIdx.x & 63) == 0 && wave < nw) wcount[k * nw + wave] = __popcll(m);
   }
 }
 
+template <int NP>
 __global__ void k_summary_scatter(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
-                                  const int32_t* woff, CompactOut o) {
+                                  const int32_t* woff, CompactOut6 o) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t slot = t < n ? blocks[t] : -1;
   const uint32_t bits = t < n ? (uint32_t)summary[slot] >> shift : 0u;
@@ -197,14 +201,14 @@ __global__ void k_summary_scatter(const int32_t* blocks, int32_t n, const uint8_
   const int lane = threadIdx.x & 63;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < NP; ++k) {
     const bool p = (bits >> k) & 1u;
     const uint64_t m = __ballot(p);
     if (p && o.out[k]) o.out[k][woff[k * nw + wave] + __popcll(m & below)] = slot;
   }
 }
 
-// exclusive scan of three arrays of nw wave counts (in place), totals to count[3]:
+// exclusive scan of nk (<= 6) arrays of nw wave counts (in place), totals to c0[0..2], then c1[0..2]:
 // chunks of 1024 values, each scanned within its 16 waves by cross-lane shifts, the 16
 // wave totals by one wave, with a carry from chunk to chunk
 __device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v, int lane) {
@@ -215,11 +219,11 @@ __device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v, int lane) {
   }
   return v;
 }
-__global__ __launch_bounds__(1024) void k_scan3(int32_t* w, int64_t nw, int32_t* count) {
+__global__ __launch_bounds__(1024) void k_scan(int32_t* w, int64_t nw, int nk, int32_t* c0, int32_t* c1) {
   __shared__ int32_t wsum[16];
   __shared__ int32_t carry;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < nk; ++k) {
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int64_t base = 0; base < nw; base += 1024) {
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(1024) void k_scan3(int32_t* w, int64_t nw, int32_t*
       if (threadIdx.x == 1023) carry = c0 + wsum[15] + inc;
       __syncthreads();
     }
-    if (threadIdx.x == 0) count[k] = carry;
+    if (threadIdx.x == 0) (k < 3 ? c0 : c1)[k % 3] = carry;
     __syncthreads();
   }
 }
@@ -768,20 +772,20 @@ hipError_t launch_compact_cells(const Geom& G, int l, const uint8_t* st_new, con
   const int64_t nitems = (int64_t)1 << (3 * G.lv[l].mbits);
   const int64_t nw = (nitems + 63) >> 6;
   hipLaunchKernelGGL(k_cells_count, dim3(grid1(nitems, 256)), dim3(256), 0, s, G, l, st_new, st_old, nitems, wave_scratch);
-  hipLaunchKernelGGL(k_scan3, dim3(1), dim3(1024), 0, s, wave_scratch, nw, o.count);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, wave_scratch, nw, 3, o.count, o.count);
   hipLaunchKernelGGL(k_cells_scatter, dim3(grid1(nitems, 256)), dim3(256), 0, s, G, l, st_new, st_old, nitems,
                      (const int32_t*)wave_scratch, o);
   return hipGetLastError();
 }
 
-hipError_t launch_compact_summary(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
-                                  int32_t* wave_scratch, const CompactOut& o, hipStream_t s) {
+hipError_t launch_compact_summary6(const int32_t* blocks, int32_t n, const uint8_t* summary, int32_t* wave_scratch,
+                                   const CompactOut6& o, hipStream_t s) {
   const int64_t nw = ((int64_t)n + 63) >> 6;
   if (n > 0)
-    hipLaunchKernelGGL(k_summary_count, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, shift, wave_scratch);
-  hipLaunchKernelGGL(k_scan3, dim3(1), dim3(1024), 0, s, wave_scratch, nw, o.count);
+    hipLaunchKernelGGL(k_summary_count<6>, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, 0, wave_scratch);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, wave_scratch, nw, 6, o.count[0], o.count[1]);
   if (n > 0)
-    hipLaunchKernelGGL(k_summary_scatter, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, shift,
+    hipLaunchKernelGGL(k_summary_scatter<6>, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, 0,
                        (const int32_t*)wave_scratch, o);
   return hipGetLastError();
 }

@@ -97,8 +97,14 @@ struct CompactOut {
 hipError_t launch_compact_cells(const Geom& G, int level, const uint8_t* st_new, const uint8_t* st_old,
                                 int32_t* wave_scratch, const CompactOut& o, hipStream_t s);
 // predicates: bits shift .. shift+2 of the block's summary byte
-hipError_t launch_compact_summary(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
-                                  int32_t* wave_scratch, const CompactOut& o, hipStream_t s);
+// the six summary predicates of a level's blocks (bits 0..5 of the summary byte:
+// SUM_GHOST, SUM_IU, SUM_OUTFLOW, SUM_TILE, SUM_BB, SUM_FRESH) in one pass
+struct CompactOut6 {
+  int32_t* out[6];           // compacted slots per predicate (may be null)
+  int32_t* count[2];         // device: totals of predicates 0..2, then 3..5
+};
+hipError_t launch_compact_summary6(const int32_t* blocks, int32_t n, const uint8_t* summary, int32_t* wave_scratch,
+                                   const CompactOut6& o, hipStream_t s);
 
 struct AllocLaunch {
   const int32_t* cells;      // new cells of one level

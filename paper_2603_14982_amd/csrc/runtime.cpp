@@ -124,7 +124,7 @@ Layout make_layout(const lbm_config* c, const Geom& G) {
   L.dir[0] = take(ncell * 4);
   L.dir[1] = take(ncell * 4);
   L.lists = take(3 * ncell * 4);
-  L.wave = take(3 * L.wave_cap * 4);
+  L.wave = take(6 * L.wave_cap * 4);
   L.counts = take(64 * 4);
   L.coord = take(cap * 16);
   L.nbr = take(cap * 27 * 4);
@@ -312,7 +312,9 @@ IoLaunch io_of(const lbm_ctx* c, int level) {
 
 // Grid update: H(Phi) for the particles (plus static solid blocks), new nodes
 // initialised from the old hierarchy (or at rest when creating).
-lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
+// targets_ready: the level-0 target set is already in place and known to differ from
+// the one the hierarchy was built from (lbm_step_remesh checks it on its side stream).
+lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, bool targets_ready = false) {
   const Geom& G = c->G;
   hipStream_t s = c->stream;
   const int L = G.L;
@@ -324,31 +326,24 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
   h.flags = c->m<uint8_t>(c->lay.flags);
   h.st_new = c->st(nh);
   h.st_old = c->st(c->hier);
-  HIPCHK(c, launch_targets(h, particles, n, s));
+  if (!targets_ready) HIPCHK(c, launch_targets(h, particles, n, s));
   int32_t* counts = c->m<int32_t>(c->lay.counts);
   int32_t* wave = c->m<int32_t>(c->lay.wave);
   uint8_t* t0_prev = c->m<uint8_t>(c->lay.t0p);
   int64_t ncell = 0;
   for (int l = 0; l < L; ++l) ncell += G.lv[l].ncell;
-  if (!create) {
-    // fast paths: H(Phi) depends on the level-0 target set T0 alone. If T0 equals a
-    // target set the current hierarchy is built from, nothing changes; otherwise the
-    // new block states are compared with the current ones.
+  if (!create && !targets_ready) {
+    // fast path: H(Phi) depends on the level-0 target set T0 alone. If T0 equals a
+    // target set the current hierarchy is built from, nothing changes.
     HIPCHK(c, launch_diff_flag(h.t0, t0_prev, G.lv[0].ncell, counts + 63, s));
     HIPCHK(c, hipMemcpyAsync(c->host_counts, counts + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     if (c->host_counts[0] == 0) return LBM_OK;
-    HIPCHK(c, launch_states(h, s));
-    HIPCHK(c, launch_diff_flag(h.st_new, h.st_old, ncell, counts + 63, s));
-    HIPCHK(c, hipMemcpyAsync(c->host_counts, counts + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    if (c->host_counts[0] == 0) {
-      HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
-      return LBM_OK;
-    }
-  } else {
-    HIPCHK(c, launch_states(h, s));
   }
+  HIPCHK(c, launch_states(h, s));
+  // otherwise the new block states are compared with the current ones; the flag comes
+  // back with the compaction counts (one synchronisation for both)
+  if (!create) HIPCHK(c, launch_diff_flag(h.st_new, h.st_old, ncell, counts + 63, s));
   for (int l = 0; l < L; ++l) {
     CompactOut o;
     o.out[0] = c->lists(l, 0);
@@ -357,8 +352,12 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
     o.count = counts + 3 * l;
     HIPCHK(c, launch_compact_cells(G, l, h.st_new, h.st_old, wave, o, s));
   }
-  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 3 * L * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 64 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  if (!create && c->host_counts[63] == 0) {
+    HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
+    return LBM_OK;
+  }
   int64_t nact[kMaxLevels], nnew[kMaxLevels], nrem[kMaxLevels];
   int64_t tot_new = 0, tot_act = 0;
   for (int l = 0; l < L; ++l) {
@@ -422,18 +421,16 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create) {
   c->generation++;
   HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
   for (int l = 0; l < L; ++l) {
-    CompactOut o;
+    CompactOut6 o;
     o.out[0] = c->gblocks(l);
     o.out[1] = c->iblocks(l);
     o.out[2] = c->oblocks(l);
-    o.count = counts + 3 * l;
-    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, 0, wave, o, s));
-    CompactOut t;
-    t.out[0] = c->tblocks(l);
-    t.out[1] = nullptr;
-    t.out[2] = c->lists(l, 1);  // blocks that may hold new nodes (SUM_FRESH)
-    t.count = counts + 32 + 3 * l;
-    HIPCHK(c, launch_compact_summary(c->blocks(l), (int32_t)nact[l], summary, SUM_TILE_SHIFT, wave, t, s));
+    o.out[3] = c->tblocks(l);
+    o.out[4] = nullptr;         // bounce-back blocks: counted only
+    o.out[5] = c->lists(l, 1);  // blocks that may hold new nodes (SUM_FRESH)
+    o.count[0] = counts + 3 * l;
+    o.count[1] = counts + 32 + 3 * l;
+    HIPCHK(c, launch_compact_summary6(c->blocks(l), (int32_t)nact[l], summary, wave, o, s));
   }
   HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 48 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
@@ -1351,7 +1348,7 @@ lbm_status lbm_step_remesh(lbm_ctx* ctx, int32_t n, float* particles, int64_t np
     if (ctx->host_counts[0] != 0) {
       // the targets changed: the grid update proper, after the step, on the context's stream
       const int k = ctx->tic(LBM_PROF_REMESH);
-      st = rebuild(ctx, particles, np, false);
+      st = rebuild(ctx, particles, np, false, true);
       ctx->toc(k);
       if (st != LBM_OK) return st;
     }

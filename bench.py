@@ -11,15 +11,17 @@ the particle advance and one grid update.
 
 Prints one JSON line. `value` is MLUPS (computed-node updates per second over
 the whole step, grid update included). The roofline object is the dominant
-kernel, level 0's stream-collide on 2 x 2 x 2 block tiles: with FP32 storage both
-substeps of a level-1 step in one launch (2 launches per coarse step), otherwise
-one substep per launch (4 per coarse step). `achieved` is its algorithmic bytes
-(80 B per computed-node update: 10 f32 moments read and written, counted per
-update, so a launch of two updates counts 160 B per node) over its HIP-event-timed
-average launch duration; `hbm_achieved` is the HBM traffic the counters measured
-for that launch (`traffic`, when the stored counter run matches the kernel source)
-over the same duration. The same figures over every stream-collide launch of all
-levels are given beside it.
+kernel, level 0's stream-collide on 2 x 2 x 2 block tiles: both substeps of a
+level-1 step in one launch (2 launches per coarse step; with --no-fuse one substep
+per launch, 4 per coarse step). `achieved` is its algorithmic bytes (80 B per
+computed-node update with FP32 moments: 10 moments read and written, counted per
+update, so a launch of two updates counts 160 B per node) over its average launch
+duration, timed with HIP events around those launches in the timed region (no other
+launch is bracketed there: each timed launch costs two event records); `hbm_achieved`
+is the HBM traffic the counters measured for that launch (`traffic`, when the
+stored counter run matches the kernel source) over the same duration. Every phase is
+timed over --breakdown-steps further steps (`phase_ms_per_step`, and the figures over
+every stream-collide launch of all levels given beside the roofline).
 """
 import argparse
 import hashlib
@@ -279,6 +281,8 @@ def main():
                          "the step before it)")
     ap.add_argument("--no-adjoint-slab", action="store_true",
                     help="skip the adjoint/forward ratio on the benchmark's (fixed) hierarchy")
+    ap.add_argument("--breakdown-steps", type=int, default=10,
+                    help="coarse steps after the timed ones with every phase timed (phase_ms_per_step)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this size three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -327,8 +331,11 @@ def main():
     blocks_before = [sim.num_blocks(l) for l in range(sim.levels)]
     print(f"[bench] warm-up done; blocks {blocks_before}, computed nodes {nodes_before}", file=sys.stderr, flush=True)
 
+    # the timed region brackets only the finest level's stream-collide launches with
+    # events (each timed launch costs two event records between dependent launches);
+    # every phase is timed over a few further steps afterwards
     sim.profile()
-    sim.set_profiling(True)
+    sim.set_profiling(True, phases=["sc_pair", "sc0"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -337,6 +344,11 @@ def main():
     elapsed = time.perf_counter() - t0
     sim.set_profiling(False)
     prof = sim.profile()
+    sim.set_profiling(True)
+    for i in range(args.breakdown_steps):
+        coarse_step()
+    sim.set_profiling(False)
+    prof_all = sim.profile()
     nodes_after = computed_nodes(sim)
     blocks_after = [sim.num_blocks(l) for l in range(sim.levels)]
     print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s; blocks {blocks_after}", file=sys.stderr, flush=True)
@@ -375,9 +387,10 @@ def main():
                 valu = {"wave_instructions_per_launch": insts,
                         "lane_instructions_per_update": round(insts * 64 / launch_updates, 1),
                         "issue_frac": round(insts / (VALU_CUS * VALU_CLOCK_HZ * sc_avg_s), 4)}
-    all_ms = sum(prof[f"sc{l}"][0] for l in range(sim.levels)) + prof["sc_pair"][0]
-    all_n = sum(prof[f"sc{l}"][1] for l in range(sim.levels)) + prof["sc_pair"][1]
-    sc_updates = sum(per_level[l] * (1 << (sim.levels - 1 - l)) for l in range(sim.levels)) * args.steps
+    # all stream-collide launches of all levels, over the breakdown steps
+    all_ms = sum(prof_all[f"sc{l}"][0] for l in range(sim.levels)) + prof_all["sc_pair"][0]
+    all_n = sum(prof_all[f"sc{l}"][1] for l in range(sim.levels)) + prof_all["sc_pair"][1]
+    sc_updates = sum(per_level[l] * (1 << (sim.levels - 1 - l)) for l in range(sim.levels)) * args.breakdown_steps
     all_bytes = BYTES_PER_UPDATE[args.storage] * sc_updates / all_n
     all_avg_s = all_ms / all_n / 1e3
     out = {
@@ -424,7 +437,7 @@ def main():
         "effective_mlups": round(fine_equiv * args.steps / elapsed / 1e6, 1),
         "stream_collide_mlups": round(sc_updates / (all_ms / 1e3) / 1e6, 1),
         "adjoint_forward_ratio": None,  # filled below
-        "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]},
+        "phase_ms_per_step": {k: round(v[0] / args.breakdown_steps, 4) for k, v in prof_all.items() if v[1]},
     }
     out["remesh_block_change"] = remesh_change(sim, particles, torch, ms_per_step)
     if args.calibrate_copy_mib > 0:

@@ -258,6 +258,12 @@ enum {
   LBM_PROFILE_PHASES = 13
 };
 lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t on);
+/* Phase timers for a subset of the phases: bit p of mask times phase p; 0 turns
+ * profiling off, and lbm_set_profiling(ctx, 1) is the mask of all phases. Every timed
+ * launch costs two event records on the stream (a few microseconds each between
+ * dependent launches), so timing only the phase of interest keeps that cost off the
+ * others. LBM_EINVAL for a bit at or above LBM_PROFILE_PHASES. */
+lbm_status lbm_set_profiling_phases(lbm_ctx* ctx, uint32_t mask);
 lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t count[LBM_PROFILE_PHASES]);
 
 /* Execution options (they change how a step is scheduled on the GPU, not what it

@@ -187,6 +187,7 @@ struct lbm_ctx {
   std::string err;
   // phase timers (HIP events around launches, enabled on request)
   bool profiling = false;
+  uint32_t prof_mask = 0;  // phases timed while profiling
   struct Timed { int phase; hipEvent_t a, b; };
   std::vector<Timed> timed;
   std::vector<hipEvent_t> spare;
@@ -252,7 +253,7 @@ struct lbm_ctx {
   // open a timed region of a phase; returns its index or -1 (timing is best effort:
   // a region whose events cannot be created or recorded is left out)
   int tic(int phase) {
-    if (!profiling) return -1;
+    if (!profiling || !((prof_mask >> phase) & 1u)) return -1;
     Timed t{phase, take_event(), take_event()};
     if (!t.a || !t.b || hipEventRecord(t.a, stream) != hipSuccess) {
       if (t.a) spare.push_back(t.a);
@@ -1357,9 +1358,15 @@ lbm_status lbm_step_remesh(lbm_ctx* ctx, int32_t n, float* particles, int64_t np
 }
 
 lbm_status lbm_set_profiling(lbm_ctx* ctx, int32_t on) {
+  return lbm_set_profiling_phases(ctx, on ? (1u << LBM_PROFILE_PHASES) - 1u : 0u);
+}
+
+lbm_status lbm_set_profiling_phases(lbm_ctx* ctx, uint32_t mask) {
   if (!ctx) return LBM_EINVAL;
+  if (mask >> LBM_PROFILE_PHASES) return ctx->fail(LBM_EINVAL, "profiling mask names an unknown phase");
   ctx->collect();
-  ctx->profiling = on != 0;
+  ctx->profiling = mask != 0;
+  ctx->prof_mask = mask;
   return LBM_OK;
 }
 

@@ -54,7 +54,7 @@ class LBMConfig(ctypes.Structure):
 
 EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm_num_blocks", "lbm_block_keys",
            "lbm_set_block_moments", "lbm_step", "lbm_advance_particles", "lbm_remesh", "lbm_get_moments",
-           "lbm_get_roles", "lbm_reduce_f64", "lbm_reduce_f64_noalloc", "lbm_step_finest", "lbm_finest_phase", "lbm_step_remesh", "lbm_record_work_bytes", "lbm_record_begin", "lbm_record_end", "lbm_check_finite", "lbm_set_profiling", "lbm_get_profile",
+           "lbm_get_roles", "lbm_reduce_f64", "lbm_reduce_f64_noalloc", "lbm_step_finest", "lbm_finest_phase", "lbm_step_remesh", "lbm_record_work_bytes", "lbm_record_begin", "lbm_record_end", "lbm_check_finite", "lbm_set_profiling", "lbm_set_profiling_phases", "lbm_get_profile",
            "lbm_state_bytes", "lbm_save", "lbm_load", "lbm_adjoint_work_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
            "lbm_step_record", "lbm_adjoint_reverse",
            "lbm_loss_ke_grad", "lbm_set_option", "lbm_set_coupling",
@@ -101,6 +101,7 @@ def lib():
         L.lbm_reduce_f64_noalloc.argtypes = [vp, i32, vp, vp, vp]
         L.lbm_check_finite.argtypes = [vp]
         L.lbm_set_profiling.argtypes = [vp, i32]
+        L.lbm_set_profiling_phases.argtypes = [vp, ctypes.c_uint32]
         L.lbm_get_profile.argtypes = [vp, vp, vp]
         L.lbm_state_bytes.restype = sz
         L.lbm_state_bytes.argtypes = [vp]
@@ -336,8 +337,16 @@ class Sim:
         with FP32 storage only, 0: always two sweeps)."""
         self._check(lib().lbm_set_option(self.h, OPTIONS[name], int(value)))
 
-    def set_profiling(self, on=True):
-        self._check(lib().lbm_set_profiling(self.h, 1 if on else 0))
+    def set_profiling(self, on=True, phases=None):
+        """Phase timers on or off; with `phases` (names from PROFILE_PHASES) only those
+        phases are timed (each timed launch costs two event records on the stream)."""
+        if phases is None:
+            self._check(lib().lbm_set_profiling(self.h, 1 if on else 0))
+        else:
+            mask = 0
+            for name in phases:
+                mask |= 1 << PROFILE_PHASES.index(name)
+            self._check(lib().lbm_set_profiling_phases(self.h, mask if on else 0))
 
     def profile(self):
         """Summed ms and launch counts per phase since the last call (synchronises)."""

@@ -142,3 +142,21 @@ def test_options_rejected_values():
     with pytest.raises(lbm.LBMError):
         sim.set_option("fuse_substeps", 3)
     assert lbm.lib().lbm_set_option(sim.h, 7, 0) == -1  # unknown option
+
+
+def test_profiling_phase_mask():
+    # timing only the fused finest-level launches leaves every other phase untimed
+    lbm = pytest.importorskip("paper_2603_14982_amd.lbm")
+    p = W.slab_particles(300, 5, (8.0, 8.0, 8.0), (56.0, 56.0, 24.0))
+    sim = lbm.Sim(2, (64, 64, 64), (P,) * 6, 0.6, particles=p)
+    sim.set_option("tile_min_blocks", 0)
+    sim.set_profiling(True, phases=["sc_pair"])
+    sim.step(2)
+    prof = sim.profile()
+    assert prof["sc_pair"][1] == 2, prof
+    assert all(n == 0 for k, (_, n) in prof.items() if k != "sc_pair"), prof
+    sim.set_profiling(True)
+    sim.step(1)
+    prof = sim.profile()
+    assert prof["sc_pair"][1] == 1 and prof["sc1"][1] == 1, prof
+    assert lbm.lib().lbm_set_profiling_phases(sim.h, 1 << len(lbm.PROFILE_PHASES)) == -1

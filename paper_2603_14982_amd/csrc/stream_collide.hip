@@ -917,6 +917,55 @@ __global__ __launch_bounds__(64 * 2 * TX) void k_stream_collide_tile(ScArgs<S> a
 }
 
 
+// The next plane's source moments of a point, held while the current plane is
+// processed: one register per moment in FP32, two 16-bit moments per register with
+// 16-bit storage (the prefetch then holds 5 registers instead of 10).
+template <class S> struct Prefetch {
+  typename S::type v[kMom];
+  __device__ void zero() {
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) v[m] = typename S::type(0);
+  }
+  __device__ void fetch(const ScArgs<S>& a, const int* s_src, int px, int py, int pz) {
+    fetch_tile<S, 2>(a, s_src, px, py, pz, v);
+  }
+  __device__ void load(const typename S::type* src) {  // the ten moments of one node
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) v[m] = src[m * kNodes];
+  }
+  __device__ float get(int m, float inv) const { return Codec<S>::load(v[m], inv); }
+};
+template <class S> struct Prefetch16 {
+  uint32_t w[kMom / 2];
+  __device__ void zero() {
+#pragma unroll
+    for (int k = 0; k < kMom / 2; ++k) w[k] = 0u;
+  }
+  __device__ void fetch(const ScArgs<S>& a, const int* s_src, int px, int py, int pz) {
+    uint16_t raw[kMom];
+    fetch_tile<S, 2>(a, s_src, px, py, pz, raw);
+    pack(raw);
+  }
+  __device__ void load(const uint16_t* src) {
+    uint16_t raw[kMom];
+#pragma unroll
+    for (int m = 0; m < kMom; ++m) raw[m] = src[m * kNodes];
+    pack(raw);
+  }
+  __device__ void pack(const uint16_t raw[kMom]) {
+#pragma unroll
+    for (int k = 0; k < kMom / 2; ++k) w[k] = (uint32_t)raw[2 * k] | ((uint32_t)raw[2 * k + 1] << 16);
+  }
+  __device__ float get(int m, float inv) const {
+    const uint16_t b = (uint16_t)((m & 1) ? (w[m >> 1] >> 16) : (w[m >> 1] & 0xffffu));
+    return Codec<S>::load(b, inv);
+  }
+};
+// the ring values (loaded for a few lanes only, read in the same plane) are held packed
+template <class S> struct Packed : Prefetch<S> {};
+template <> struct Packed<StoreBF16> : Prefetch16<StoreBF16> {};
+template <> struct Packed<StoreF16> : Prefetch16<StoreF16> {};
+
 // ---- two substeps of the finest level in one sweep ----------------------------------
 // The finest level takes its two substeps of a parent step back to back (Alg. 1):
 // between them only its ghost nodes change, and their values for the second substep
@@ -1017,10 +1066,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int bq = (tx >> 3) + 2 * (ty >> 3);
   const int bnode = (tx & 7) + 8 * (ty & 7);
 
-  T nxt[kMom];
-#pragma unroll
-  for (int m = 0; m < kMom; ++m) nxt[m] = T(0);
-  if (shas) fetch_tile<S, 2>(a, s_src, spx, spy, -2, nxt);
+  Prefetch<S> nxt;
+  nxt.zero();
+  if (shas) nxt.fetch(a, s_src, spx, spy, -2);
 
   float azp1[6], azp2[6], az0[6];  // A's z window (the lane's A column)
   float bzp1[6], bzp2[6], bz0[6];  // B's z window (the lane's B column)
@@ -1034,13 +1082,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int zi = z - 1;  // A's output plane (B's source plane) of this iteration
     // ---- phase 1: A source and x pass of input plane z
     if (swave && z <= 17) {
-      T cur[kMom];
-#pragma unroll
-      for (int m = 0; m < kMom; ++m) cur[m] = nxt[m];
-      if (shas && z < 17) fetch_tile<S, 2>(a, s_src, spx, spy, z + 1, nxt);
+      const Prefetch<S> cur = nxt;
+      if (shas && z < 17) nxt.fetch(a, s_src, spx, spy, z + 1);
       float q[kMom];
 #pragma unroll
-      for (int m = 0; m < kMom; ++m) q[m] = Codec<S>::load(cur[m], a.sc.inv[m]);
+      for (int m = 0; m < kMom; ++m) q[m] = cur.get(m, a.sc.inv[m]);
       float p[24];
       source_pops(q, a.omega, p);
       float yb[27];
@@ -1085,15 +1131,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     // value of A's output node (plane zi) where A does not compute it (ghost, inflow),
     // and the role code of the next output plane (plane z)
-    T pv[kMom];
+    Packed<S> pv;
     const uint32_t rk = arole & ROLE_MASK;
     const bool pass = chas && zi >= -1 && zi <= 16 && arole != kPairZero && rk != ROLE_COMPUTED &&
                       rk != ROLE_SOLID;
     if (pass) {
       const int ns = s_src[cblk + 16 * ((zi + 8) >> 3)];
-      const T* src = a.out + (size_t)ns * kBlockStride + cnode + 64 * (zi & 7);
-#pragma unroll
-      for (int m = 0; m < kMom; ++m) pv[m] = src[m * kNodes];
+      pv.load(a.out + (size_t)ns * kBlockStride + cnode + 64 * (zi & 7));
     }
     uint32_t nrole = kPairZero;
     if (chas && z >= -1 && z <= 16) {
@@ -1118,7 +1162,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
           for (int m = 0; m < kMom; ++m) qa[m] = Codec<S>::load(Codec<S>::store(v[m], a.sc.s[m]), a.sc.inv[m]);
         } else if (pass) {
 #pragma unroll
-          for (int m = 0; m < kMom; ++m) qa[m] = Codec<S>::load(pv[m], a.sc.inv[m]);
+          for (int m = 0; m < kMom; ++m) qa[m] = pv.get(m, a.sc.inv[m]);
         } else {
 #pragma unroll
           for (int m = 0; m < kMom; ++m) qa[m] = 0.0f;

@@ -276,8 +276,14 @@ lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t 
  *   tiled and has no outflow or bounce-back nodes, and the step is not being
  *   recorded for the adjoint (default: one sweep is faster with every storage
  *   format); 1 does so with LBM_F32 storage only; 0 always runs them as two sweeps.
+ * LBM_OPT_GRAPHS: 1 replays each coarse step of lbm_step and lbm_step_remesh as a
+ *   HIP graph, captured once per launch state (buffer parities, hierarchy, options)
+ *   on a stream of the context's own and launched on cfg.stream; not while
+ *   profiling or recording. 0 (default) launches every kernel itself: the replay
+ *   was no faster (the steps are bound by the kernels and the gaps between them on
+ *   the device, not by host launches).
  * LBM_EINVAL for an unknown option or a value out of range. */
-enum { LBM_OPT_TILE_MIN_BLOCKS = 0, LBM_OPT_FUSE_SUBSTEPS = 1 };
+enum { LBM_OPT_TILE_MIN_BLOCKS = 0, LBM_OPT_FUSE_SUBSTEPS = 1, LBM_OPT_GRAPHS = 2 };
 lbm_status lbm_set_option(lbm_ctx* ctx, int32_t option, int64_t value);
 
 /* ---- states and the adjoint (gradient of a loss of the final moments with

@@ -176,6 +176,23 @@ struct lbm_ctx {
   int64_t nbb[kMaxLevels];          // blocks holding bounce-back nodes
   int64_t tile_min_blocks = 16384;  // LBM_OPT_TILE_MIN_BLOCKS
   int fuse_substeps = 2;            // LBM_OPT_FUSE_SUBSTEPS: 0 never, 1 with FP32 storage, 2 always
+  int use_graphs = 0;               // LBM_OPT_GRAPHS
+  // Coarse steps replayed as HIP graphs: the launch arguments of a coarse step follow
+  // from the host state in LaunchKey alone (buffer parities, hierarchy and role-table
+  // selectors, list lengths, options), so a graph captured for one key replays any
+  // later step that starts from the same key.
+  struct LaunchKey {
+    int32_t hier, rcur, fuse, parity[kMaxLevels];
+    int64_t tile_min, nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels], ntile[kMaxLevels],
+        nbb[kMaxLevels];
+  };
+  struct StepGraph {
+    LaunchKey key;
+    int32_t parity_after[kMaxLevels];
+    hipGraphExec_t exec;
+  };
+  std::vector<StepGraph> graphs;
+  hipStream_t gstream = nullptr;    // capture stream (the caller's may be the null stream)
   int32_t free_top = 0;
   int32_t* host_counts = nullptr;  // pinned
   double* noalloc_partial = nullptr;  // this GPU's static reduction partials (lbm_reduce_f64_noalloc)
@@ -683,6 +700,69 @@ lbm_status advance(lbm_ctx* c, int l, int s) {
   return LBM_OK;
 }
 
+lbm_ctx::LaunchKey launch_key(const lbm_ctx* c) {
+  lbm_ctx::LaunchKey k;
+  std::memset(&k, 0, sizeof(k));
+  k.hier = c->hier;
+  k.rcur = c->rcur;
+  k.fuse = c->fuse_substeps;
+  k.tile_min = c->tile_min_blocks;
+  for (int l = 0; l < c->G.L; ++l) {
+    k.parity[l] = c->parity[l];
+    k.nblk[l] = c->nblk[l];
+    k.ngb[l] = c->ngb[l];
+    k.nib[l] = c->nib[l];
+    k.nob[l] = c->nob[l];
+    k.ntile[l] = c->ntile[l];
+    k.nbb[l] = c->nbb[l];
+  }
+  return k;
+}
+
+// One coarse step (Alg. 1 from the coarsest level). Outside profiling and recording
+// the step's launches are captured once per launch state into a HIP graph (on a
+// stream of the context's own) and replayed on the context's stream; the host-side
+// parities advance as the launches would have advanced them.
+lbm_status coarse_step(lbm_ctx* c) {
+  const int L = c->G.L;
+  if (!c->use_graphs || c->profiling || c->recording) return advance(c, L - 1, 1);
+  const lbm_ctx::LaunchKey key = launch_key(c);
+  for (const auto& g : c->graphs)
+    if (std::memcmp(&g.key, &key, sizeof(key)) == 0) {
+      HIPCHK(c, hipGraphLaunch(g.exec, c->stream));
+      for (int l = 0; l < L; ++l) c->parity[l] = g.parity_after[l];
+      return LBM_OK;
+    }
+  if (!c->gstream) HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+  hipStream_t user = c->stream;
+  HIPCHK(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+  c->stream = c->gstream;
+  const lbm_status st = advance(c, L - 1, 1);
+  c->stream = user;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->gstream, &graph);
+  if (st != LBM_OK) {
+    if (e == hipSuccess && graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  HIPCHK(c, e);
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(c, ei);
+  if (c->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  lbm_ctx::StepGraph g;
+  g.key = key;
+  for (int l = 0; l < kMaxLevels; ++l) g.parity_after[l] = l < L ? c->parity[l] : 0;
+  g.exec = exec;
+  c->graphs.push_back(g);
+  HIPCHK(c, hipGraphLaunch(exec, c->stream));
+  return LBM_OK;
+}
+
 // The operations of AdvanceLBM(l, s) in the order advance() runs them unfused.
 void plan(int L, int l, int s, std::vector<lbm_ctx::SchedOp>& out) {
   if (l < L - 1) out.push_back({lbm_ctx::OP_DOWN, l, s});
@@ -1139,6 +1219,8 @@ lbm_status lbm_destroy(lbm_ctx* ctx) {
   if (ctx->ev_before) (void)hipEventDestroy(ctx->ev_before);
   if (ctx->ev_side) (void)hipEventDestroy(ctx->ev_side);
   if (ctx->side) (void)hipStreamDestroy(ctx->side);
+  for (auto& g : ctx->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
   (void)hipHostFree(ctx->host_counts);
   delete ctx;
   return synced ? LBM_OK : LBM_EDEVICE;
@@ -1250,7 +1332,7 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t n) {
   if (lbm_status st = need_boundary(ctx)) return st;
   if (!ctx->rec_open) ctx->rec_work = nullptr;  // a recorded undo log no longer matches the state
   for (int32_t i = 0; i < n; ++i) {
-    lbm_status st = advance(ctx, ctx->G.L - 1, 1);
+    lbm_status st = coarse_step(ctx);
     if (st != LBM_OK) return st;
   }
   return LBM_OK;
@@ -1326,7 +1408,7 @@ lbm_status lbm_step_remesh(lbm_ctx* ctx, int32_t n, float* particles, int64_t np
   for (int32_t i = 0; i < n; ++i) {
     // everything issued before this step (the caller's writes to the particles too)
     HIPCHK(ctx, hipEventRecord(ctx->ev_before, ctx->stream));
-    lbm_status st = advance(ctx, G.L - 1, 1);
+    lbm_status st = coarse_step(ctx);
     if (st != LBM_OK) return st;
     // meanwhile, on the side stream: particles forward, then the level-0 target set
     // compared with the one the hierarchy was built from (the step reads neither)
@@ -1380,6 +1462,10 @@ lbm_status lbm_set_option(lbm_ctx* ctx, int32_t option, int64_t value) {
     case LBM_OPT_FUSE_SUBSTEPS:
       if (value < 0 || value > 2) return ctx->fail(LBM_EINVAL, "LBM_OPT_FUSE_SUBSTEPS takes 0, 1 or 2");
       ctx->fuse_substeps = (int)value;
+      return LBM_OK;
+    case LBM_OPT_GRAPHS:
+      if (value < 0 || value > 1) return ctx->fail(LBM_EINVAL, "LBM_OPT_GRAPHS takes 0 or 1");
+      ctx->use_graphs = (int)value;
       return LBM_OK;
   }
   return ctx->fail(LBM_EINVAL, "unknown option");

@@ -62,7 +62,7 @@ EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm
 _SIZE_QUERIES = ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_state_bytes", "lbm_adjoint_work_bytes", "lbm_last_error")
 PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh", "sc_pair",
                   "adj_sc", "adj_sc_fused", "adj"]
-OPTIONS = {"tile_min_blocks": 0, "fuse_substeps": 1}
+OPTIONS = {"tile_min_blocks": 0, "fuse_substeps": 1, "graphs": 2}
 
 _lib = None
 
@@ -334,7 +334,9 @@ class Sim:
         """Execution options: "tile_min_blocks" (blocks a level needs for the tiled
         stream-collide, default 16384) and "fuse_substeps" (2: the finest level's two
         substeps per parent step in one sweep where allowed (default), 1: the same
-        with FP32 storage only, 0: always two sweeps)."""
+        with FP32 storage only, 0: always two sweeps) and "graphs" (1: coarse steps
+        replayed as HIP graphs outside profiling and recording, 0: every kernel
+        launched by itself (default))."""
         self._check(lib().lbm_set_option(self.h, OPTIONS[name], int(value)))
 
     def set_profiling(self, on=True, phases=None):

@@ -141,6 +141,8 @@ def test_options_rejected_values():
         sim.set_option("tile_min_blocks", -1)
     with pytest.raises(lbm.LBMError):
         sim.set_option("fuse_substeps", 3)
+    with pytest.raises(lbm.LBMError):
+        sim.set_option("graphs", 2)
     assert lbm.lib().lbm_set_option(sim.h, 7, 0) == -1  # unknown option
 
 

@@ -282,8 +282,14 @@ lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t 
  *   profiling or recording. 0 (default) launches every kernel itself: the replay
  *   was no faster (the steps are bound by the kernels and the gaps between them on
  *   the device, not by host launches).
+ * LBM_OPT_PAIR_RUN: 1 .. 6 (default 4): the one-sweep form of the finest level's
+ *   two substeps gives each workgroup a run of up to this many 2 x 2 x 2-block
+ *   tiles stacked along z (runs break below a missing tile and at tile positions
+ *   z = 0 mod the value), longest runs launched first; the planes at the shared
+ *   faces of a run's tiles are read and recomputed once. The results do not depend
+ *   on it (bit for bit). LBM_ESTATE inside a recording.
  * LBM_EINVAL for an unknown option or a value out of range. */
-enum { LBM_OPT_TILE_MIN_BLOCKS = 0, LBM_OPT_FUSE_SUBSTEPS = 1, LBM_OPT_GRAPHS = 2 };
+enum { LBM_OPT_TILE_MIN_BLOCKS = 0, LBM_OPT_FUSE_SUBSTEPS = 1, LBM_OPT_GRAPHS = 2, LBM_OPT_PAIR_RUN = 3 };
 lbm_status lbm_set_option(lbm_ctx* ctx, int32_t option, int64_t value);
 
 /* ---- states and the adjoint (gradient of a loss of the final moments with

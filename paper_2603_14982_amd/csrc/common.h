@@ -28,6 +28,9 @@ constexpr int32_t NBR_WALL = -2;
 constexpr uint8_t SUM_GHOST = 1, SUM_IU = 2, SUM_OUTFLOW = 4, SUM_TILE = 8, SUM_BB = 16, SUM_FRESH = 32;
 // stream-collide tiles of large levels: kTileX x 2 x 2 blocks (kTileX a power of two)
 constexpr int kTileX = 2;
+// the two-substep sweep of the finest level takes runs of up to kRunMax tiles stacked
+// along z (class k of the run lists: runs of k + 1 tiles)
+constexpr int kRunMax = 6;
 
 struct LevelGeom {
   int nb[3];       // blocks per axis

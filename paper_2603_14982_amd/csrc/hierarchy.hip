@@ -505,6 +505,41 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   }
 }
 
+// ---------------------------------------------------------------- z runs of tiles
+// The two-substep sweep of the finest level (Alg. 1, both fine substeps of a parent
+// step in one pass) reads every plane of a tile with a two-node halo and recomputes a
+// one-node ring of the first substep; a workgroup that sweeps several tiles stacked
+// along z reads and recomputes the planes at their shared faces once. Runs break below
+// a missing tile and at tile positions z = 0 (mod run_max), so that a run is found from
+// its first tile alone.
+__device__ bool tile_exists(const LevelGeom& g, const uint8_t* st, int tx, int ty, int tz) {
+  if (tz < 0 || 2 * tz >= g.nb[2]) return false;
+  for (int m = 0; m < 4 * kTileX; ++m) {
+    const int x = tx * kTileX + m % kTileX, y = 2 * ty + (m / kTileX) % 2, z = 2 * tz + m / (2 * kTileX);
+    if (x < g.nb[0] && y < g.nb[1] && z < g.nb[2] && st[g.off + cell_lin(g, x, y, z)] == ST_ACTIVE) return true;
+  }
+  return false;
+}
+
+__global__ void k_tile_runs(Geom G, int level, const int32_t* blocks, int32_t n, const uint8_t* summary,
+                            const uint8_t* st, const int4* coord, int run_max, uint8_t* run_class) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int32_t slot = blocks[t];
+  uint8_t cls = 0;
+  if (summary[slot] & SUM_TILE) {
+    const LevelGeom& g = G.lv[level];
+    const int4 c = coord[slot];
+    const int tx = c.x / kTileX, ty = c.y >> 1, tz = c.z >> 1;
+    if (tz % run_max == 0 || !tile_exists(g, st, tx, ty, tz - 1)) {
+      int h = 1;
+      while (h < run_max && (tz + h) % run_max != 0 && tile_exists(g, st, tx, ty, tz + h)) ++h;
+      cls = (uint8_t)(1u << (h - 1));
+    }
+  }
+  run_class[slot] = cls;
+}
+
 // ---------------------------------------------------------------- new-node initialisation
 // Value of level-l node g in the old hierarchy, as a linear combination in
 // (rho-1, u, S^neq) of old owned nodes with weight w and S^neq factor sf: the node's
@@ -787,6 +822,15 @@ hipError_t launch_compact_summary6(const int32_t* blocks, int32_t n, const uint8
   if (n > 0)
     hipLaunchKernelGGL(k_summary_scatter<6>, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, 0,
                        (const int32_t*)wave_scratch, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_runs(const Geom& G, int level, const int32_t* blocks, int32_t n, const uint8_t* summary,
+                            const uint8_t* st, const int4* coord, int run_max, uint8_t* run_class, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (run_max < 1 || run_max > kRunMax) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tile_runs, dim3(grid1(n, 256)), dim3(256), 0, s, G, level, blocks, n, summary, st, coord,
+                     run_max, run_class);
   return hipGetLastError();
 }
 

@@ -27,6 +27,11 @@ struct ScLaunch {
   LevelGeom lg;
   int periodic[3];
   const float* cpl;          // finest level with coupling fields: [slot][4][512] (eps, F); else null
+  // two-substep sweep: runs of k + 1 tiles stacked along z, class k at runs + k * run_stride
+  // (first tile's first block, key order), nrun[k] of them
+  const int32_t* runs;
+  int64_t run_stride;
+  int32_t nrun[kRunMax];
 };
 hipError_t launch_stream_collide(const ScLaunch& a, hipStream_t s);
 // both substeps of a parent step of the finest level, in -> out (tiles required; the
@@ -105,6 +110,11 @@ struct CompactOut6 {
 };
 hipError_t launch_compact_summary6(const int32_t* blocks, int32_t n, const uint8_t* summary, int32_t* wave_scratch,
                                    const CompactOut6& o, hipStream_t s);
+// run class of every tile of a level for the two-substep sweep: the first tile of each
+// run of up to `run_max` tiles stacked along z gets bit (h - 1) for the run's height h;
+// runs break below a missing tile and at tile positions z = 0 (mod run_max)
+hipError_t launch_tile_runs(const Geom& G, int level, const int32_t* blocks, int32_t n, const uint8_t* summary,
+                            const uint8_t* st, const int4* coord, int run_max, uint8_t* run_class, hipStream_t s);
 
 struct AllocLaunch {
   const int32_t* cells;      // new cells of one level

@@ -22,7 +22,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
   size_t t0, t0s, t0p, flags, st[2], dir[2], lists, wave, counts, coord, nbr, role[2], summary, gbox, free_stack, blocks,
-      gblocks, iblocks, oblocks, tblocks, red_partial, red_out, flag, cpl, phi;
+      gblocks, iblocks, oblocks, tblocks, runs, run_class, red_partial, red_out, flag, cpl, phi;
   size_t total;
   int64_t level_list_off[kMaxLevels];  // offset (elements) of each level's segment in blocks / g/i/o lists
   int64_t level_list_cap[kMaxLevels];
@@ -138,6 +138,10 @@ Layout make_layout(const lbm_config* c, const Geom& G) {
   L.iblocks = take(nlist * 4);
   L.oblocks = take(nlist * 4);
   L.tblocks = take(nlist * 4);
+  // z runs of level-0 tiles by height (class k: runs of k + 1 tiles), and every level-0
+  // block's run class
+  L.runs = take((size_t)kRunMax * L.level_list_cap[0] * 4);
+  L.run_class = take(cap);
   L.red_partial = take(cap * 5 * 8);
   L.red_out = take(8 * 8);
   L.flag = take(64);
@@ -177,6 +181,8 @@ struct lbm_ctx {
   int64_t tile_min_blocks = 16384;  // LBM_OPT_TILE_MIN_BLOCKS
   int fuse_substeps = 2;            // LBM_OPT_FUSE_SUBSTEPS: 0 never, 1 with FP32 storage, 2 always
   int use_graphs = 0;               // LBM_OPT_GRAPHS
+  int pair_run = 4;                 // LBM_OPT_PAIR_RUN: tiles per run of the two-substep sweep
+  int64_t nrun[kRunMax] = {0};      // level-0 runs of k + 1 tiles
   // Coarse steps replayed as HIP graphs: the launch arguments of a coarse step follow
   // from the host state in LaunchKey alone (buffer parities, hierarchy and role-table
   // selectors, list lengths, options), so a graph captured for one key replays any
@@ -184,7 +190,7 @@ struct lbm_ctx {
   struct LaunchKey {
     int32_t hier, rcur, fuse, parity[kMaxLevels];
     int64_t tile_min, nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels], ntile[kMaxLevels],
-        nbb[kMaxLevels];
+        nbb[kMaxLevels], nrun[kRunMax];
   };
   struct StepGraph {
     LaunchKey key;
@@ -219,7 +225,7 @@ struct lbm_ctx {
   struct TapeOp { int kind, level, s, pf, pc; size_t off, off2; int aux = -1; };
   struct HierSave {
     int64_t nblk[kMaxLevels], ngb[kMaxLevels], nib[kMaxLevels], nob[kMaxLevels], ntile[kMaxLevels],
-        nbb[kMaxLevels];
+        nbb[kMaxLevels], nrun[kRunMax];
     int hier, rcur;
     int32_t free_top;
     uint64_t generation;
@@ -326,6 +332,21 @@ IoLaunch io_of(const lbm_ctx* c, int level) {
   a.sc = c->sc;
   a.storage = c->cfg.storage;
   return a;
+}
+
+// Level-0 tiles grouped into z runs of up to pair_run tiles (the two-substep sweep's
+// work items), compacted by height; the counts land in counts[48 .. 53].
+lbm_status build_runs(lbm_ctx* c, int64_t nb0) {
+  uint8_t* cls = c->m<uint8_t>(c->lay.run_class);
+  HIPCHK(c, launch_tile_runs(c->G, 0, c->blocks(0), (int32_t)nb0, c->m<uint8_t>(c->lay.summary), c->st(c->hier),
+                             c->m<int4>(c->lay.coord), c->pair_run, cls, c->stream));
+  int32_t* counts = c->m<int32_t>(c->lay.counts);
+  CompactOut6 o;
+  for (int k = 0; k < kRunMax; ++k) o.out[k] = c->m<int32_t>(c->lay.runs) + (size_t)k * c->lay.level_list_cap[0];
+  o.count[0] = counts + 48;
+  o.count[1] = counts + 51;
+  HIPCHK(c, launch_compact_summary6(c->blocks(0), (int32_t)nb0, cls, c->m<int32_t>(c->lay.wave), o, c->stream));
+  return LBM_OK;
 }
 
 // Grid update: H(Phi) for the particles (plus static solid blocks), new nodes
@@ -450,7 +471,11 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
     o.count[1] = counts + 32 + 3 * l;
     HIPCHK(c, launch_compact_summary6(c->blocks(l), (int32_t)nact[l], summary, wave, o, s));
   }
-  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 48 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  if (L >= 2) {
+    const lbm_status st = build_runs(c, nact[0]);
+    if (st != LBM_OK) return st;
+  }
+  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 54 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   for (int l = 0; l < L; ++l) {
     c->nblk[l] = nact[l];
@@ -460,6 +485,7 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
     c->ntile[l] = c->host_counts[32 + 3 * l];
     c->nbb[l] = c->host_counts[33 + 3 * l];
   }
+  for (int k = 0; k < kRunMax; ++k) c->nrun[k] = L >= 2 ? c->host_counts[48 + k] : 0;
   // new nodes: on a first build every block starts at rest; after that only blocks whose
   // 27 surrounding block positions changed state can hold nodes the update makes owned
   for (int l = 0; l < L; ++l) {
@@ -545,6 +571,9 @@ ScLaunch sc_base(lbm_ctx* c, int l) {
   a.lg = c->G.lv[l];
   for (int k = 0; k < 3; ++k) a.periodic[k] = c->G.periodic[k];
   a.cpl = l == 0 ? c->cpl() : nullptr;
+  a.runs = c->m<int32_t>(c->lay.runs);
+  a.run_stride = c->lay.level_list_cap[0];
+  for (int k = 0; k < kRunMax; ++k) a.nrun[k] = l == 0 ? (int32_t)c->nrun[k] : 0;
   return a;
 }
 
@@ -716,6 +745,7 @@ lbm_ctx::LaunchKey launch_key(const lbm_ctx* c) {
     k.ntile[l] = c->ntile[l];
     k.nbb[l] = c->nbb[l];
   }
+  for (int r = 0; r < kRunMax; ++r) k.nrun[r] = c->nrun[r];
   return k;
 }
 
@@ -836,6 +866,7 @@ lbm_ctx::HierSave save_hier(const lbm_ctx* c) {
     h.nblk[l] = c->nblk[l]; h.ngb[l] = c->ngb[l]; h.nib[l] = c->nib[l];
     h.nob[l] = c->nob[l]; h.ntile[l] = c->ntile[l]; h.nbb[l] = c->nbb[l];
   }
+  for (int k = 0; k < kRunMax; ++k) h.nrun[k] = c->nrun[k];
   h.hier = c->hier;
   h.rcur = c->rcur;
   h.free_top = c->free_top;
@@ -848,6 +879,7 @@ void load_hier(lbm_ctx* c, const lbm_ctx::HierSave& h) {
     c->nblk[l] = h.nblk[l]; c->ngb[l] = h.ngb[l]; c->nib[l] = h.nib[l];
     c->nob[l] = h.nob[l]; c->ntile[l] = h.ntile[l]; c->nbb[l] = h.nbb[l];
   }
+  for (int k = 0; k < kRunMax; ++k) c->nrun[k] = h.nrun[k];
   c->hier = h.hier;
   c->rcur = h.rcur;
   c->free_top = h.free_top;
@@ -1467,6 +1499,19 @@ lbm_status lbm_set_option(lbm_ctx* ctx, int32_t option, int64_t value) {
       if (value < 0 || value > 1) return ctx->fail(LBM_EINVAL, "LBM_OPT_GRAPHS takes 0 or 1");
       ctx->use_graphs = (int)value;
       return LBM_OK;
+    case LBM_OPT_PAIR_RUN: {
+      if (value < 1 || value > kRunMax) return ctx->fail(LBM_EINVAL, "LBM_OPT_PAIR_RUN takes 1 .. 6");
+      if (ctx->rec_open) return ctx->fail(LBM_ESTATE, "LBM_OPT_PAIR_RUN cannot change inside a recording");
+      ctx->pair_run = (int)value;
+      if (ctx->G.L < 2 || ctx->nblk[0] == 0) return LBM_OK;
+      // the run lists of the current hierarchy, regrouped
+      if (lbm_status st = build_runs(ctx, ctx->nblk[0])) return st;
+      HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, ctx->m<int32_t>(ctx->lay.counts) + 48, kRunMax * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, ctx->stream));
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      for (int k = 0; k < kRunMax; ++k) ctx->nrun[k] = ctx->host_counts[k];
+      return LBM_OK;
+    }
   }
   return ctx->fail(LBM_EINVAL, "unknown option");
 }

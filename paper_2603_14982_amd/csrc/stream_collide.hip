@@ -53,6 +53,13 @@ template <class S> struct ScArgs {
   const int4* coord;
   LevelGeom lg;
   int periodic[3];
+  // two-substep sweep: workgroups [run_off[c], run_off[c + 1]) take the runs of
+  // kRunMax - c tiles (list runs + (kRunMax - c - 1) * run_stride, run_n[c] of them; the
+  // range is padded to a multiple of 8 workgroups)
+  const int32_t* runs;
+  int64_t run_stride;
+  int32_t run_off[kRunMax + 1];
+  int32_t run_n[kRunMax];
 };
 
 // x-direction populations (times 6) of the 8 (my, mz) coefficient groups of a
@@ -728,7 +735,7 @@ __device__ __forceinline__ void x_pass_tile(const float* lds, int row, int x, fl
 template <class S, int TX>
 __device__ __forceinline__ void fetch_tile(const ScArgs<S>& a, const int* s_src, int px, int py, int pz,
                                            typename S::type raw[kMom]) {
-  // px in [-1, 8 TX], py, pz in [-1, 16] -> neighbourhood block per axis
+  // node coordinates from the tile origin (at least -8) -> neighbourhood block per axis
   constexpr int NXB = Tile<TX>::NXB;
   const int ns = s_src[((px + 8) >> 3) + NXB * ((py + 8) >> 3) + 4 * NXB * ((pz + 8) >> 3)];
   const int node = (px & 7) + 8 * (py & 7) + 64 * (pz & 7);
@@ -969,10 +976,13 @@ template <> struct Packed<StoreF16> : Prefetch16<StoreF16> {};
 // ---- two substeps of the finest level in one sweep ----------------------------------
 // The finest level takes its two substeps of a parent step back to back (Alg. 1):
 // between them only its ghost nodes change, and their values for the second substep
-// are written before the first. One workgroup takes a 2 x 2 x 2 block tile through
-// both. Substep A runs on the tile plus a one-node ring (18 x 18 columns, planes -1 to
-// 16) from the input with a two-node halo (20 x 20 points, planes -2 to 17); substep B
-// runs on the tile from A's results, one plane behind. A's result never leaves the
+// are written before the first. One workgroup takes a run of h 2 x 2 x 2 block tiles
+// stacked along z (16 x 16 columns, Z = 16 h planes) through both. Substep A runs on
+// the run plus a one-node ring (18 x 18 columns, planes -1 to Z) from the input with a
+// two-node halo (20 x 20 points, planes -2 to Z + 1); substep B runs on the run from
+// A's results, one plane behind. The halo and ring planes cost the same for any h, so
+// taller runs spend less of the sweep on them (the first substep's ring and the halo:
+// Z + 5 plane iterations for Z output planes). A's result never leaves the
 // chip: the lane that finishes A's column p is the lane that feeds point p into B's
 // source stage. The input is read once (with a two-node halo) and the output written
 // once for two updates of every node.
@@ -1013,13 +1023,22 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   typedef typename S::type T;
   __shared__ __align__(16) float lda[P::CXA * P::ROWA];
   __shared__ __align__(16) float ldb[P::CA * P::ROWB];
-  __shared__ int s_src[64];  // blocks (qx - 1 .. qx + 2) x (qy - 1 .. qy + 2) x (qz - 1 .. qz + 2)
-  __shared__ int s_mem[8];   // the tile's blocks (or -1), x fastest
+  __shared__ int s_src[16 * (2 * kRunMax + 2)];  // blocks (qx - 1 .. qx + 2) x (qy - 1 .. qy + 2) x (qz - 1 .. qz + 2h)
+  __shared__ int s_mem[8 * kRunMax];             // the run's blocks (or -1), x fastest
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int4 c0 = a.coord[a.tiles[xcd_remap(blockIdx.x, a.ntiles)]];
+  // the workgroup's run: height class, then the run within the class (consecutive runs
+  // on one XCD)
+  const int bid = blockIdx.x;
+  int cls = 0;
+  while (cls < kRunMax - 1 && bid >= a.run_off[cls + 1]) ++cls;
+  const int idx = xcd_remap(bid - a.run_off[cls], a.run_off[cls + 1] - a.run_off[cls]);
+  if (idx >= a.run_n[cls]) return;  // padding of the class's range
+  const int nt = kRunMax - cls;      // tiles in the run
+  const int Z = 16 * nt;             // output planes
+  const int4 c0 = a.coord[a.runs[(size_t)(nt - 1) * a.run_stride + idx]];
   const int qx = c0.x & ~1, qy = c0.y & ~1, qz = c0.z & ~1;
-  if (tid < 64) {
+  if (tid < 16 * (2 * nt + 2)) {
     const int ix = tid & 3, iy = (tid >> 2) & 3, iz = tid >> 4;
     int h[3] = {qx + ix - 1, qy + iy - 1, qz + iz - 1};
     bool inside = true;
@@ -1033,7 +1052,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
     const int ns = inside ? a.dir[a.lg.off + cell_lin(a.lg, h[0], h[1], h[2])] : -1;
     s_src[tid] = ns >= 0 ? ns : a.zero_slot;
-    if (ix >= 1 && ix <= 2 && iy >= 1 && iy <= 2 && iz >= 1 && iz <= 2) {
+    if (ix >= 1 && ix <= 2 && iy >= 1 && iy <= 2 && iz >= 1 && iz <= 2 * nt) {
       const bool own = qx + ix - 1 < a.lg.nb[0] && qy + iy - 1 < a.lg.nb[1] && qz + iz - 1 < a.lg.nb[2];
       s_mem[(ix - 1) + 2 * (iy - 1) + 4 * (iz - 1)] = own ? ns : -1;
     }
@@ -1078,12 +1097,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   int bslot = -1;              // block and role of the B column's node at B's next output plane
   uint32_t brole = ROLE_GHOST;
 
-  for (int z = -2; z <= 18; ++z) {
+  for (int z = -2; z <= Z + 2; ++z) {
     const int zi = z - 1;  // A's output plane (B's source plane) of this iteration
     // ---- phase 1: A source and x pass of input plane z
-    if (swave && z <= 17) {
+    if (swave && z <= Z + 1) {
       const Prefetch<S> cur = nxt;
-      if (shas && z < 17) nxt.fetch(a, s_src, spx, spy, z + 1);
+      if (shas && z < Z + 1) nxt.fetch(a, s_src, spx, spy, z + 1);
       float q[kMom];
 #pragma unroll
       for (int m = 0; m < kMom; ++m) q[m] = cur.get(m, a.sc.inv[m]);
@@ -1126,28 +1145,28 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
       }
       // block and role of the next output plane z - 2
       const int zo = z - 2;
-      bslot = zo >= 0 && zo <= 15 ? s_mem[bq + (zo >= 8 ? 4 : 0)] : -1;
+      bslot = zo >= 0 && zo < Z ? s_mem[bq + 4 * (zo >> 3)] : -1;
       brole = bslot >= 0 ? a.role[(size_t)bslot * kNodes + bnode + 64 * (zo & 7)] : ROLE_GHOST;
     }
     // value of A's output node (plane zi) where A does not compute it (ghost, inflow),
     // and the role code of the next output plane (plane z)
     Packed<S> pv;
     const uint32_t rk = arole & ROLE_MASK;
-    const bool pass = chas && zi >= -1 && zi <= 16 && arole != kPairZero && rk != ROLE_COMPUTED &&
+    const bool pass = chas && zi >= -1 && zi <= Z && arole != kPairZero && rk != ROLE_COMPUTED &&
                       rk != ROLE_SOLID;
     if (pass) {
       const int ns = s_src[cblk + 16 * ((zi + 8) >> 3)];
       pv.load(a.out + (size_t)ns * kBlockStride + cnode + 64 * (zi & 7));
     }
     uint32_t nrole = kPairZero;
-    if (chas && z >= -1 && z <= 16) {
+    if (chas && z >= -1 && z <= Z) {
       const int ns = s_src[cblk + 16 * ((z + 8) >> 3)];
       if (ns != a.zero_slot) nrole = a.role[(size_t)ns * kNodes + cnode + 64 * (z & 7)];
     }
     __syncthreads();
 
     // ---- phase 2: A y and z pass (output plane zi), B source and x pass of plane zi
-    if (cwave && z <= 17) {
+    if (cwave && z <= Z + 1) {
       float zpp[6], zpz[6], zpm[6];
       y_pass_col<P::ROWA, P::KA>(lda, cr, cxl, zpp, zpz, zpm);
       if (zi >= -1) {
@@ -1223,6 +1242,7 @@ template <class S> hipError_t launch_sc_t(const ScLaunch& l, hipStream_t s) {
 
 template <class S> hipError_t launch_pair_t(const ScLaunch& l, hipStream_t s) {
   if (!l.tiles || l.ntiles <= 0) return l.tiles ? hipSuccess : hipErrorInvalidValue;
+  if (!l.runs) return hipErrorInvalidValue;
   ScArgs<S> a;
   a.in = static_cast<const typename S::type*>(l.in);
   a.out = static_cast<typename S::type*>(l.out);
@@ -1241,7 +1261,23 @@ template <class S> hipError_t launch_pair_t(const ScLaunch& l, hipStream_t s) {
   for (int k = 0; k < 3; ++k) a.periodic[k] = l.periodic[k];
   a.cpl = nullptr;  // levels with coupling fields run two sweeps
   if (l.cpl) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_stream_collide_pair<S>, dim3(l.ntiles), dim3(Pair::THREADS), 0, s, a);
+  // tallest runs first (the short ones fill in at the end of the launch); each class's
+  // range of workgroups padded to a multiple of the 8 XCDs
+  a.runs = l.runs;
+  a.run_stride = l.run_stride;
+  int64_t total = 0, tiles = 0;
+  for (int c = 0; c < kRunMax; ++c) {
+    const int h = kRunMax - c;
+    const int32_t n = l.nrun[h - 1];
+    if (n < 0 || n > l.run_stride) return hipErrorInvalidValue;
+    a.run_off[c] = (int32_t)total;
+    a.run_n[c] = n;
+    total += (n + 7) / 8 * 8;
+    tiles += (int64_t)h * n;
+  }
+  a.run_off[kRunMax] = (int32_t)total;
+  if (tiles != l.ntiles) return hipErrorInvalidValue;  // the runs must cover the tiles
+  hipLaunchKernelGGL(k_stream_collide_pair<S>, dim3((unsigned)total), dim3(Pair::THREADS), 0, s, a);
   return hipGetLastError();
 }
 

@@ -62,7 +62,7 @@ EXPORTS = ["lbm_pool_bytes", "lbm_meta_bytes", "lbm_create", "lbm_destroy", "lbm
 _SIZE_QUERIES = ("lbm_pool_bytes", "lbm_meta_bytes", "lbm_state_bytes", "lbm_adjoint_work_bytes", "lbm_last_error")
 PROFILE_PHASES = ["sc0", "sc1", "sc2", "sc3", "sc4", "down", "up", "outflow", "remesh", "sc_pair",
                   "adj_sc", "adj_sc_fused", "adj"]
-OPTIONS = {"tile_min_blocks": 0, "fuse_substeps": 1, "graphs": 2}
+OPTIONS = {"tile_min_blocks": 0, "fuse_substeps": 1, "graphs": 2, "pair_run": 3}
 
 _lib = None
 

@@ -233,8 +233,11 @@ def test_slab512_full_run_against_oracle():
         sim.remesh(p)
         host = host + dd  # float32 add, the same rounding as the device
         keys = [sim.block_keys(l).cpu().numpy() for l in range(3)]
-        t0 = {tuple(b) for b in np.unique(np.floor(host * np.float32(0.125)).astype(np.int64) % 64, axis=0)}
-        if t0 != prev_t0:
+        cells = np.floor(host * np.float32(0.125)).astype(np.int64) % 64
+        occupied = np.bincount(cells[:, 0] + 64 * cells[:, 1] + 4096 * cells[:, 2], minlength=64 ** 3) > 0
+        if prev_t0 is None or not np.array_equal(occupied, prev_t0):
+            idx = np.flatnonzero(occupied)
+            t0 = set(zip((idx % 64).tolist(), (idx // 64 % 64).tolist(), (idx // 4096).tolist()))
             assert np.array_equal(p.cpu().numpy(), host)
             active, _ = canonical_sets(3, (64, 64, 64), (True, True, True), t0)
             for l in range(3):
@@ -242,7 +245,7 @@ def test_slab512_full_run_against_oracle():
                 assert set(zip(bx.tolist(), by.tolist(), bz.tolist())) == active[l], (step, l)
             if prev_keys is not None and any(not np.array_equal(a, b) for a, b in zip(keys, prev_keys)):
                 rebuilt += 1
-            prev_t0 = t0
+            prev_t0 = occupied
         else:
             assert all(np.array_equal(a, b) for a, b in zip(keys, prev_keys)), step
         prev_keys = keys

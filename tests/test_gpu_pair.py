@@ -40,10 +40,12 @@ def _agree(a, b, tol, label):
         assert e <= tol, f"{label}: {g} differs by {e:.3e}"
 
 
-def _slab_run(levels, storage="f32", fuse=True, steps=6, oracle=False):
+def _slab_run(levels, storage="f32", fuse=True, steps=6, oracle=False, pair_run=None, switch=None, zr=(72.0, 88.0)):
+    """pair_run: tiles per z run of the one-sweep form (None: the default); switch: the
+    value it takes from the middle coarse step on; zr: the slab's z extent"""
     lbm = pytest.importorskip("paper_2603_14982_amd.lbm")
     n = (128, 128, 128)
-    p = W.slab_particles(4000, 3, (24.0, 24.0, 72.0), (104.0, 104.0, 88.0))
+    p = W.slab_particles(4000, 3, (24.0, 24.0, zr[0]), (104.0, 104.0, zr[1]))
     init = lambda l, k: W.tgv3d_field(l, k, n, 0.05, pressure=True)
     scale = [64.0, 8.0, 8.0, 8.0, 64.0, 64.0, 64.0, 64.0, 64.0, 64.0] if storage != "f32" else None
     if oracle:
@@ -57,11 +59,15 @@ def _slab_run(levels, storage="f32", fuse=True, steps=6, oracle=False):
     gpu.set_option("tile_min_blocks", 0)
     if fuse is not None:  # None: the default (one sweep with every storage format)
         gpu.set_option("fuse_substeps", 2 if fuse else 0)
+    if pair_run is not None:
+        gpu.set_option("pair_run", pair_run)
     gpu.set_profiling(True)
     pg = torch.as_tensor(p).cuda()
     po = p.copy()
     d = np.array([0.0, 0.0, -1.25], dtype=np.float32)
     for it in range(steps):
+        if switch is not None and it == steps // 2:
+            gpu.set_option("pair_run", switch)  # regroups the current hierarchy's tiles
         gpu.step(1)
         gpu.advance_particles(pg, d)
         gpu.remesh(pg)
@@ -84,6 +90,18 @@ def test_pair_against_oracle_and_two_sweeps(levels):
     # the reconstruction fixes its own roundings (no contraction left to the compiler),
     # so both paths evaluate the same operations in the same order: bit-identical
     _agree(_moments(gpu), _moments(two), 0.0, f"pair vs two sweeps L={levels}")
+
+
+@pytest.mark.parametrize("run,switch", [(1, None), (2, None), (3, 6), (5, None), (6, 1)])
+def test_pair_z_runs_bit_identical(run, switch):
+    # a slab 80 nodes deep: columns of up to 6 tiles along z, cut into runs of up to
+    # `run` tiles (and regrouped halfway through); every grouping computes the same
+    # operations as two sweeps
+    zr = (24.0, 104.0)
+    a, _, pa = _slab_run(3, pair_run=run, switch=switch, zr=zr, steps=4)
+    b, _, pb = _slab_run(3, fuse=False, zr=zr, steps=4)
+    assert pa["sc_pair"][1] == 8 and pb["sc_pair"][1] == 0, (pa, pb)
+    _agree(_moments(a), _moments(b), 0.0, f"runs of {run} (then {switch})")
 
 
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
@@ -143,6 +161,9 @@ def test_options_rejected_values():
         sim.set_option("fuse_substeps", 3)
     with pytest.raises(lbm.LBMError):
         sim.set_option("graphs", 2)
+    for v in (0, 7):
+        with pytest.raises(lbm.LBMError):
+            sim.set_option("pair_run", v)
     assert lbm.lib().lbm_set_option(sim.h, 7, 0) == -1  # unknown option
 
 

@@ -282,7 +282,8 @@ lbm_status lbm_get_profile(lbm_ctx* ctx, double ms[LBM_PROFILE_PHASES], int64_t 
  *   profiling or recording. 0 (default) launches every kernel itself: the replay
  *   was no faster (the steps are bound by the kernels and the gaps between them on
  *   the device, not by host launches).
- * LBM_OPT_PAIR_RUN: 1 .. 6 (default 4): the one-sweep form of the finest level's
+ * LBM_OPT_PAIR_RUN: 1 .. 6 (default 4 with LBM_F32 storage, 2 with 16-bit storage,
+ *   each the fastest measured on the three-level slab): the one-sweep form of the finest level's
  *   two substeps gives each workgroup a run of up to this many 2 x 2 x 2-block
  *   tiles stacked along z (runs break below a missing tile and at tile positions
  *   z = 0 mod the value), longest runs launched first; the planes at the shared

@@ -181,7 +181,7 @@ struct lbm_ctx {
   int64_t tile_min_blocks = 16384;  // LBM_OPT_TILE_MIN_BLOCKS
   int fuse_substeps = 2;            // LBM_OPT_FUSE_SUBSTEPS: 0 never, 1 with FP32 storage, 2 always
   int use_graphs = 0;               // LBM_OPT_GRAPHS
-  int pair_run = 4;                 // LBM_OPT_PAIR_RUN: tiles per run of the two-substep sweep
+  int pair_run = 4;                 // LBM_OPT_PAIR_RUN: tiles per run of the two-substep sweep (4, 2 with 16-bit storage)
   int64_t nrun[kRunMax] = {0};      // level-0 runs of k + 1 tiles
   // Coarse steps replayed as HIP graphs: the launch arguments of a coarse step follow
   // from the host state in LaunchKey alone (buffer parities, hierarchy and role-table
@@ -1170,6 +1170,8 @@ lbm_status lbm_create(const lbm_config* cfg, const uint8_t* solid_fine, const fl
   c->stream = static_cast<hipStream_t>(cfg->stream);
   c->cap = cfg->max_blocks;
   c->elem = elem_bytes(cfg->storage);
+  // tiles per z run of the two-substep sweep: measured fastest on the benchmark with each format
+  c->pair_run = cfg->storage == LBM_F32 ? 4 : 2;
   c->pool = static_cast<char*>(cfg->pool);
   c->meta = static_cast<char*>(cfg->meta);
   c->solid = solid_fine;

@@ -99,21 +99,33 @@ __global__ void k_ring(Geom G, int l, uint8_t* flags_l) {
   if (ring) flags_l[cell] = F_B;
 }
 
-__global__ void k_state(Geom G, int l, const uint8_t* flags_l, const uint8_t* flags_up, uint8_t* st_l) {
-  const LevelGeom& g = G.lv[l];
-  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= g.ncell) return;
-  uint8_t s;
-  if (flags_l && (flags_l[cell] & F_D)) {
-    s = ST_DELETED;
-  } else if (l == G.L - 1) {
-    s = ST_ACTIVE;
-  } else {
-    const LevelGeom& u = G.lv[l + 1];
-    const int bx = (int)(cell % g.nb[0]), by = (int)((cell / g.nb[0]) % g.nb[1]), bz = (int)(cell / ((int64_t)g.nb[0] * g.nb[1]));
-    s = (flags_up[cell_lin(u, bx >> 1, by >> 1, bz >> 1)] & (F_D | F_B)) ? ST_ACTIVE : ST_ABSENT;
+// every cell of every level (all-level index gi): deleted if covered by finer blocks,
+// active on the coarsest level or where the parent position is covered or on a ring,
+// absent otherwise; with a flag, a wave holding a cell whose state changes writes tag
+__global__ void k_state(Geom G, const uint8_t* flags, uint8_t* st_new, const uint8_t* st_old, int64_t ntot,
+                        int32_t* flag, int32_t tag) {
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool changed = false;
+  if (gi < ntot) {
+    int l = 0;
+    while (l + 1 < G.L && gi >= G.lv[l + 1].off) ++l;
+    const LevelGeom& g = G.lv[l];
+    const int64_t cell = gi - g.off;
+    uint8_t s;
+    if (l >= 1 && (flags[gi] & F_D)) {
+      s = ST_DELETED;
+    } else if (l == G.L - 1) {
+      s = ST_ACTIVE;
+    } else {
+      const LevelGeom& u = G.lv[l + 1];
+      const int bx = (int)(cell % g.nb[0]), by = (int)((cell / g.nb[0]) % g.nb[1]),
+                bz = (int)(cell / ((int64_t)g.nb[0] * g.nb[1]));
+      s = (flags[u.off + cell_lin(u, bx >> 1, by >> 1, bz >> 1)] & (F_D | F_B)) ? ST_ACTIVE : ST_ABSENT;
+    }
+    st_new[gi] = s;
+    changed = flag && s != st_old[gi];
   }
-  st_l[cell] = s;
+  if (flag && __ballot(changed) != 0ull && (threadIdx.x & 63) == 0) *flag = tag;
 }
 
 // any block position of any level whose state changes -> flag = 1
@@ -124,9 +136,26 @@ __global__ void k_diff(const uint8_t* st_new, const uint8_t* st_old, int64_t n, 
 }
 
 // ---------------------------------------------------------------- compaction
-// Each wave evaluates up to three predicates on 64 consecutive items, counts
-// them with ballots, a single-workgroup scan turns the wave counts into offsets,
-// and the scatter pass writes every selected item at offset + rank-in-wave.
+// Each wave evaluates the predicates on 64 consecutive items of one segment, counts
+// them with ballots, a single-workgroup scan turns every segment's wave counts into
+// offsets, and the scatter pass writes every selected item at offset + rank-in-wave.
+// Segment s takes waves [wave0[s], wave0[s + 1]); its counts sit at NP wave0[s] +
+// k (wave0[s + 1] - wave0[s]) + wave for predicate k.
+struct SegWaves {
+  int nseg;
+  int64_t wave0[kMaxSegs + 1];
+  int64_t nitems[kMaxSegs];
+};
+struct SegCounts {
+  int32_t* c[kMaxSegs][2];  // totals of predicates 0..2, then 3..5
+};
+
+__device__ __forceinline__ int seg_of(const SegWaves& q, int64_t wave) {
+  int s = 0;
+  while (s + 1 < q.nseg && wave >= q.wave0[s + 1]) ++s;
+  return s;
+}
+
 __device__ inline void cell_preds(const Geom& G, int l, int64_t t, const uint8_t* st_new, const uint8_t* st_old,
                                   uint32_t& bits, int32_t& lin) {
   const LevelGeom& g = G.lv[l];
@@ -141,76 +170,80 @@ __device__ inline void cell_preds(const Geom& G, int l, int64_t t, const uint8_t
   bits = (a ? 1u : 0u) | ((a && !o) ? 2u : 0u) | ((o && !a) ? 4u : 0u);
 }
 
-__global__ void k_cells_count(Geom G, int l, const uint8_t* st_new, const uint8_t* st_old, int64_t nitems,
-                              int32_t* wcount) {
+__global__ void k_cells_count(CellSegs c, SegWaves q, int32_t* wcount) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t wave = t >> 6;
+  const int sg = seg_of(q, wave);
+  const int64_t i = t - 64 * q.wave0[sg];
   uint32_t bits = 0;
   int32_t lin;
-  if (t < nitems) cell_preds(G, l, t, st_new, st_old, bits, lin);
-  const int64_t wave = t >> 6;
-  const int64_t nw = (nitems + 63) >> 6;
+  if (i < q.nitems[sg]) cell_preds(c.G, c.level[sg], i, c.st_new, c.st_old, bits, lin);
+  const int64_t nw = q.wave0[sg + 1] - q.wave0[sg], w = wave - q.wave0[sg];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const uint64_t m = __ballot((bits >> k) & 1u);
-    if ((threadIdx.x & 63) == 0 && wave < nw) wcount[k * nw + wave] = __popcll(m);
+    if ((threadIdx.x & 63) == 0 && w < nw) wcount[3 * q.wave0[sg] + k * nw + w] = __popcll(m);
   }
 }
 
-__global__ void k_cells_scatter(Geom G, int l, const uint8_t* st_new, const uint8_t* st_old, int64_t nitems,
-                                const int32_t* woff, CompactOut o) {
+__global__ void k_cells_scatter(CellSegs c, SegWaves q, const int32_t* woff) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t wave = t >> 6;
+  const int sg = seg_of(q, wave);
+  const int64_t i = t - 64 * q.wave0[sg];
   uint32_t bits = 0;
   int32_t lin = -1;
-  if (t < nitems) cell_preds(G, l, t, st_new, st_old, bits, lin);
-  const int64_t wave = t >> 6;
-  const int64_t nw = (nitems + 63) >> 6;
+  if (i < q.nitems[sg]) cell_preds(c.G, c.level[sg], i, c.st_new, c.st_old, bits, lin);
+  const int64_t nw = q.wave0[sg + 1] - q.wave0[sg], w = wave - q.wave0[sg];
   const int lane = threadIdx.x & 63;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const bool p = (bits >> k) & 1u;
     const uint64_t m = __ballot(p);
-    if (p && o.out[k]) o.out[k][woff[k * nw + wave] + __popcll(m & below)] = lin;
+    int32_t* out = c.out[sg][k];
+    if (p && out) out[woff[3 * q.wave0[sg] + k * nw + w] + __popcll(m & below)] = lin;
   }
 }
 
-// per block of a level list: predicates = bits shift .. shift + NP - 1 of its summary
-// byte; per wave the count of each predicate, then the scatter of the slots
-template <int NP>
-__global__ void k_summary_count(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
-                                int32_t* wcount) {
+__global__ void k_bytes_count(ByteSegs b, SegWaves q, int32_t* wcount) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t bits = t < n ? (uint32_t)summary[blocks[t]] >> shift : 0u;
-  const int64_t nw = ((int64_t)n + 63) >> 6;
   const int64_t wave = t >> 6;
+  const int sg = seg_of(q, wave);
+  const int64_t i = t - 64 * q.wave0[sg];
+  const uint32_t bits = i < q.nitems[sg] ? (uint32_t)b.bytes[sg][b.items[sg][i]] : 0u;
+  const int64_t nw = q.wave0[sg + 1] - q.wave0[sg], w = wave - q.wave0[sg];
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
+  for (int k = 0; k < 6; ++k) {
     const uint64_t m = __ballot((bits >> k) & 1u);
-    if ((threadIdx.x & 63) == 0 && wave < nw) wcount[k * nw + wave] = __popcll(m);
+    if ((threadIdx.x & 63) == 0 && w < nw) wcount[6 * q.wave0[sg] + k * nw + w] = __popcll(m);
   }
 }
 
-template <int NP>
-__global__ void k_summary_scatter(const int32_t* blocks, int32_t n, const uint8_t* summary, int shift,
-                                  const int32_t* woff, CompactOut6 o) {
+__global__ void k_bytes_scatter(ByteSegs b, SegWaves q, const int32_t* woff) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t slot = t < n ? blocks[t] : -1;
-  const uint32_t bits = t < n ? (uint32_t)summary[slot] >> shift : 0u;
-  const int64_t nw = ((int64_t)n + 63) >> 6;
   const int64_t wave = t >> 6;
+  const int sg = seg_of(q, wave);
+  const int64_t i = t - 64 * q.wave0[sg];
+  const int32_t slot = i < q.nitems[sg] ? b.items[sg][i] : -1;
+  const uint32_t bits = i < q.nitems[sg] ? (uint32_t)b.bytes[sg][slot] : 0u;
+  const int64_t nw = q.wave0[sg + 1] - q.wave0[sg], w = wave - q.wave0[sg];
   const int lane = threadIdx.x & 63;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int k = 0; k < NP; ++k) {
+  for (int k = 0; k < 6; ++k) {
     const bool p = (bits >> k) & 1u;
     const uint64_t m = __ballot(p);
-    if (p && o.out[k]) o.out[k][woff[k * nw + wave] + __popcll(m & below)] = slot;
+    int32_t* out = b.out[sg][k];
+    if (p && out) out[woff[6 * q.wave0[sg] + k * nw + w] + __popcll(m & below)] = slot;
   }
 }
 
-// exclusive scan of nk (<= 6) arrays of nw wave counts (in place), totals to c0[0..2], then c1[0..2]:
-// chunks of 1024 values, each scanned within its 16 waves by cross-lane shifts, the 16
-// wave totals by one wave, with a carry from chunk to chunk
+// Exclusive scan (in place) of the NP arrays of wave counts of every segment; the totals
+// go to c[s][0][0..2], then c[s][1][0..2]. Each (segment, predicate) array is scanned by
+// one wave of the workgroup on its own, in chunks of 64 x 16 counts: each lane sums its
+// 16 consecutive counts, the lane sums are scanned by cross-lane shifts, and a carry
+// runs from chunk to chunk (no workgroup barrier: the waves share nothing).
 __device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v, int lane) {
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -219,33 +252,35 @@ __device__ __forceinline__ int32_t wave_inclusive_scan(int32_t v, int lane) {
   }
   return v;
 }
-__global__ __launch_bounds__(1024) void k_scan(int32_t* w, int64_t nw, int nk, int32_t* c0, int32_t* c1) {
-  __shared__ int32_t wsum[16];
-  __shared__ int32_t carry;
+template <int NP>
+__global__ __launch_bounds__(1024) void k_scan(int32_t* w, SegWaves q, SegCounts tot) {
+  constexpr int E = 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = 0; k < nk; ++k) {
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t base = 0; base < nw; base += 1024) {
-      const int64_t i = base + threadIdx.x;
-      const int32_t v = i < nw ? w[k * nw + i] : 0;
-      const int32_t inc = wave_inclusive_scan(v, lane);
-      if (lane == 63) wsum[wave] = inc;
-      __syncthreads();
-      if (wave == 0) {
-        const int32_t t = lane < 16 ? wsum[lane] : 0;
-        const int32_t ti = wave_inclusive_scan(t, lane);
-        if (lane < 16) wsum[lane] = ti - t;  // exclusive prefix of the wave totals
+  for (int job = wave; job < q.nseg * NP; job += 16) {
+    const int sg = job / NP, k = job % NP;
+    const int64_t nw = q.wave0[sg + 1] - q.wave0[sg];
+    int32_t* a = w + NP * q.wave0[sg] + k * nw;
+    int32_t carry = 0;
+    for (int64_t base = 0; base < nw; base += 64 * E) {
+      const int64_t i0 = base + (int64_t)lane * E;
+      int32_t v[E];
+      int32_t sum = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        v[e] = i0 + e < nw ? a[i0 + e] : 0;
+        sum += v[e];
       }
-      __syncthreads();
-      const int32_t c0 = carry;
-      if (i < nw) w[k * nw + i] = c0 + wsum[wave] + inc - v;
-      __syncthreads();
-      if (threadIdx.x == 1023) carry = c0 + wsum[15] + inc;
-      __syncthreads();
+      const int32_t inc = wave_inclusive_scan(sum, lane);
+      int32_t run = carry + inc - sum;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (i0 + e < nw) a[i0 + e] = run;
+        run += v[e];
+      }
+      carry += __shfl(inc, 63, 64);  // the chunk's total
     }
-    if (threadIdx.x == 0) (k < 3 ? c0 : c1)[k % 3] = carry;
-    __syncthreads();
+    int32_t* c = tot.c[sg][k / 3];
+    if (lane == 0 && c) c[k % 3] = carry;
   }
 }
 
@@ -326,10 +361,9 @@ __device__ inline uint8_t mask_role(const Geom& G, const LevelGeom& g, const int
 }
 
 // Role of a node by testing each of its 26 neighbours (with a solid field)
-__device__ inline uint8_t test_role(const RoleLaunch& r, const LevelGeom& g, const int b[3], int node,
+__device__ inline uint8_t test_role(const RoleLaunch& r, int l, const LevelGeom& g, const int b[3], int node,
                                     const uint8_t* s_st, const uint8_t* s_wall) {
   const Geom& G = r.G;
-  const int l = r.level;
   const int lc[3] = {node & 7, (node >> 3) & 7, node >> 6};
   const int gc[3] = {b[0] * kEdge + lc[0], b[1] * kEdge + lc[1], b[2] * kEdge + lc[2]};
   if (solid_at(G, r.solid, l, gc[0], gc[1], gc[2])) return ROLE_SOLID;
@@ -389,13 +423,15 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   __shared__ uint8_t s_wall_w[4][32];  // per wave: outside the domain across wall faces only
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const Geom& G = r.G;
-  const int l = r.level;
+  int l = 0;
+  while (l + 1 < G.L && (int32_t)blockIdx.x >= r.wg0[l + 1]) ++l;
   const LevelGeom& g = G.lv[l];
-  const int64_t bi = (int64_t)blockIdx.x * 4 + wv;
+  const int64_t bi = (int64_t)(blockIdx.x - r.wg0[l]) * 4 + wv;
   uint8_t* s_st = s_st_w[wv];
   uint8_t* s_wall = s_wall_w[wv];
-  const int32_t cell = bi < r.n ? r.cells[bi] : 0;
-  const int32_t slot = bi < r.n ? r.dir[g.off + cell] : -1;
+  const int32_t n = r.n[l];
+  const int32_t cell = bi < n ? r.cells[l][bi] : 0;
+  const int32_t slot = bi < n ? r.dir[g.off + cell] : -1;
   const bool valid = slot >= 0;  // every active cell holds a slot; never write out of bounds
   const int b[3] = {cell % g.nb[0], (cell / g.nb[0]) % g.nb[1], cell / (g.nb[0] * g.nb[1])};
   uint8_t stv = 255;
@@ -430,7 +466,7 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
   }
   __syncthreads();  // the per-wave position tables (read by the per-neighbour test)
   if (!valid) return;
-  if (lane == 0) r.blocks[bi] = slot;
+  if (lane == 0) r.blocks[l][bi] = slot;
   const uint32_t active = (uint32_t)__ballot(lane < 27 && stv == ST_ACTIVE);
   const uint32_t absent = (uint32_t)__ballot(lane < 27 && stv == ST_ABSENT);
   const uint32_t deleted = (uint32_t)__ballot(lane < 27 && stv == ST_DELETED);
@@ -456,7 +492,7 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
     }
   } else {
 #pragma unroll 1
-    for (int i = 0; i < 8; ++i) rl[i] = test_role(r, g, b, 8 * lane + i, s_st, s_wall);
+    for (int i = 0; i < 8; ++i) rl[i] = test_role(r, l, g, b, 8 * lane + i, s_st, s_wall);
   }
   uint64_t word = 0;
   uint8_t sum = 0;
@@ -642,13 +678,13 @@ __device__ inline bool fresh_node(const InitLaunch& a, bool new_block, int32_t s
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void k_init(InitLaunch a) {
+__device__ void init_block(const InitLaunch& a, int32_t item) {
   const LevelGeom& g = a.G.lv[a.level];
   int32_t cell;
   if (a.cells) {
-    cell = a.cells[blockIdx.x];
+    cell = a.cells[item];
   } else {
-    const int4 q = a.coord[a.slots[blockIdx.x]];
+    const int4 q = a.coord[a.slots[item]];
     cell = (int32_t)cell_lin(g, q.x, q.y, q.z);
   }
   const int32_t slot = a.dir_new[g.off + cell];
@@ -694,6 +730,21 @@ __global__ __launch_bounds__(256) void k_init(InitLaunch a) {
       cur[m * kNodes + node] = v;
       oth[m * kNodes + node] = v;
     }
+  }
+}
+
+// the blocks of every level's list, the grid striding over each (a list's length read
+// from the device where a.n_dev is set)
+struct InitLevels {
+  InitLaunch a[kMaxLevels];
+  int nlev;
+};
+template <class S>
+__global__ __launch_bounds__(256) void k_init(InitLevels x) {
+  for (int l = 0; l < x.nlev; ++l) {
+    const InitLaunch& a = x.a[l];
+    const int32_t n = a.n_dev ? *a.n_dev : a.n;
+    for (int32_t i = blockIdx.x; i < n; i += gridDim.x) init_block<S>(a, i);
   }
 }
 
@@ -778,7 +829,7 @@ hipError_t launch_targets(const HierLaunch& h, const float* p, int64_t n, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_states(const HierLaunch& h, hipStream_t s) {
+hipError_t launch_states(const HierLaunch& h, int32_t* flag, int32_t tag, hipStream_t s) {
   const Geom& G = h.G;
   for (int l = 1; l < G.L; ++l) {
     const LevelGeom& g = G.lv[l];
@@ -787,12 +838,10 @@ hipError_t launch_states(const HierLaunch& h, hipStream_t s) {
     hipLaunchKernelGGL(k_deleted, dim3(grid1(g.ncell, 256)), dim3(256), 0, s, G, l, finer, mask, h.flags + g.off);
     hipLaunchKernelGGL(k_ring, dim3(grid1(g.ncell, 256)), dim3(256), 0, s, G, l, h.flags + g.off);
   }
-  for (int l = 0; l < G.L; ++l) {
-    const LevelGeom& g = G.lv[l];
-    const uint8_t* fl = (l >= 1) ? h.flags + g.off : nullptr;
-    const uint8_t* fu = (l + 1 < G.L) ? h.flags + G.lv[l + 1].off : nullptr;
-    hipLaunchKernelGGL(k_state, dim3(grid1(g.ncell, 256)), dim3(256), 0, s, G, l, fl, fu, h.st_new + g.off);
-  }
+  int64_t ntot = 0;
+  for (int l = 0; l < G.L; ++l) ntot += G.lv[l].ncell;
+  hipLaunchKernelGGL(k_state, dim3(grid1(ntot, 256)), dim3(256), 0, s, G, (const uint8_t*)h.flags, h.st_new,
+                     h.st_old, ntot, flag, tag);
   return hipGetLastError();
 }
 
@@ -802,26 +851,68 @@ hipError_t launch_diff_flag(const uint8_t* st_new, const uint8_t* st_old, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_compact_cells(const Geom& G, int l, const uint8_t* st_new, const uint8_t* st_old,
-                                int32_t* wave_scratch, const CompactOut& o, hipStream_t s) {
-  const int64_t nitems = (int64_t)1 << (3 * G.lv[l].mbits);
-  const int64_t nw = (nitems + 63) >> 6;
-  hipLaunchKernelGGL(k_cells_count, dim3(grid1(nitems, 256)), dim3(256), 0, s, G, l, st_new, st_old, nitems, wave_scratch);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, wave_scratch, nw, 3, o.count, o.count);
-  hipLaunchKernelGGL(k_cells_scatter, dim3(grid1(nitems, 256)), dim3(256), 0, s, G, l, st_new, st_old, nitems,
-                     (const int32_t*)wave_scratch, o);
+// the segments' wave ranges; false if they need more than `wave_ints` counts
+static bool seg_waves(int nseg, const int64_t* nitems, int np, int64_t wave_ints, SegWaves& q) {
+  if (nseg < 1 || nseg > kMaxSegs) return false;
+  q.nseg = nseg;
+  int64_t w = 0;
+  for (int k = 0; k < nseg; ++k) {
+    if (nitems[k] < 0) return false;
+    q.wave0[k] = w;
+    q.nitems[k] = nitems[k];
+    w += (nitems[k] + 63) >> 6;
+  }
+  for (int k = nseg; k <= kMaxSegs; ++k) q.wave0[k] = w;
+  return w * np <= wave_ints;
+}
+
+static int64_t morton_items(const LevelGeom& g) { return (int64_t)1 << (3 * g.mbits); }
+
+int64_t compact_cells_ints(const Geom& G) {
+  int64_t w = 0;
+  for (int l = 0; l < G.L; ++l) w += (morton_items(G.lv[l]) + 63) >> 6;
+  return 3 * w;
+}
+int64_t compact_bytes_ints(int64_t list_items) { return 6 * ((list_items + 63) / 64 + kMaxSegs); }
+
+hipError_t launch_compact_cells(const CellSegs& c, int32_t* wave_scratch, int64_t wave_ints, hipStream_t s) {
+  if (c.nseg > kMaxLevels) return hipErrorInvalidValue;
+  int64_t nitems[kMaxSegs];
+  SegCounts tot;
+  for (int k = 0; k < c.nseg; ++k) {
+    nitems[k] = morton_items(c.G.lv[c.level[k]]);
+    tot.c[k][0] = c.count[k];
+    tot.c[k][1] = nullptr;
+  }
+  SegWaves q;
+  if (!seg_waves(c.nseg, nitems, 3, wave_ints, q)) return hipErrorInvalidValue;
+  const int64_t threads = 64 * q.wave0[c.nseg];
+  if (threads > 0)
+    hipLaunchKernelGGL(k_cells_count, dim3(grid1(threads, 256)), dim3(256), 0, s, c, q, wave_scratch);
+  hipLaunchKernelGGL(k_scan<3>, dim3(1), dim3(1024), 0, s, wave_scratch, q, tot);
+  if (threads > 0)
+    hipLaunchKernelGGL(k_cells_scatter, dim3(grid1(threads, 256)), dim3(256), 0, s, c, q,
+                       (const int32_t*)wave_scratch);
   return hipGetLastError();
 }
 
-hipError_t launch_compact_summary6(const int32_t* blocks, int32_t n, const uint8_t* summary, int32_t* wave_scratch,
-                                   const CompactOut6& o, hipStream_t s) {
-  const int64_t nw = ((int64_t)n + 63) >> 6;
-  if (n > 0)
-    hipLaunchKernelGGL(k_summary_count<6>, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, 0, wave_scratch);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, wave_scratch, nw, 6, o.count[0], o.count[1]);
-  if (n > 0)
-    hipLaunchKernelGGL(k_summary_scatter<6>, dim3(grid1(n, 256)), dim3(256), 0, s, blocks, n, summary, 0,
-                       (const int32_t*)wave_scratch, o);
+hipError_t launch_compact_bytes(const ByteSegs& b, int32_t* wave_scratch, int64_t wave_ints, hipStream_t s) {
+  int64_t nitems[kMaxSegs];
+  SegCounts tot;
+  for (int k = 0; k < b.nseg && k < kMaxSegs; ++k) {
+    nitems[k] = b.n[k];
+    tot.c[k][0] = b.count[k][0];
+    tot.c[k][1] = b.count[k][1];
+  }
+  SegWaves q;
+  if (!seg_waves(b.nseg, nitems, 6, wave_ints, q)) return hipErrorInvalidValue;
+  const int64_t threads = 64 * q.wave0[b.nseg];
+  if (threads > 0)
+    hipLaunchKernelGGL(k_bytes_count, dim3(grid1(threads, 256)), dim3(256), 0, s, b, q, wave_scratch);
+  hipLaunchKernelGGL(k_scan<6>, dim3(1), dim3(1024), 0, s, wave_scratch, q, tot);
+  if (threads > 0)
+    hipLaunchKernelGGL(k_bytes_scatter, dim3(grid1(threads, 256)), dim3(256), 0, s, b, q,
+                       (const int32_t*)wave_scratch);
   return hipGetLastError();
 }
 
@@ -860,17 +951,35 @@ hipError_t launch_fill_u8(uint8_t* dst, uint8_t v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u8, dim3(grid1(n, 256)), dim3(256), 0, s, dst, v, n);
   return hipGetLastError();
 }
-hipError_t launch_roles(const RoleLaunch& r, hipStream_t s) {
-  if (r.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_roles, dim3((r.n + 3) / 4), dim3(256), 0, s, r);
+hipError_t launch_roles(const RoleLaunch& r0, hipStream_t s) {
+  RoleLaunch r = r0;
+  int32_t wg = 0;
+  for (int l = 0; l < r.G.L; ++l) {
+    if (r.n[l] < 0) return hipErrorInvalidValue;
+    r.wg0[l] = wg;
+    wg += (r.n[l] + 3) / 4;
+  }
+  for (int l = r.G.L; l <= kMaxLevels; ++l) r.wg0[l] = wg;
+  if (wg == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_roles, dim3(wg), dim3(256), 0, s, r);
   return hipGetLastError();
 }
-hipError_t launch_init(const InitLaunch& a, hipStream_t s) {
-  if (a.n <= 0) return hipSuccess;
-  switch (a.storage) {
-    case 0: hipLaunchKernelGGL(k_init<StoreF32>, dim3(a.n), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(k_init<StoreBF16>, dim3(a.n), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_init<StoreF16>, dim3(a.n), dim3(256), 0, s, a); break;
+hipError_t launch_init(const InitLaunch* a, int nlev, hipStream_t s) {
+  if (nlev < 1 || nlev > kMaxLevels) return hipErrorInvalidValue;
+  InitLevels x;
+  x.nlev = nlev;
+  int32_t grid = 0;
+  for (int l = 0; l < nlev; ++l) {
+    if (a[l].storage != a[0].storage) return hipErrorInvalidValue;
+    x.a[l] = a[l];
+    grid = a[l].n > grid ? a[l].n : grid;  // n: the list length, or its bound
+  }
+  if (grid <= 0) return hipSuccess;
+  grid = grid < 2048 ? grid : 2048;
+  switch (a[0].storage) {
+    case 0: hipLaunchKernelGGL(k_init<StoreF32>, dim3(grid), dim3(256), 0, s, x); break;
+    case 1: hipLaunchKernelGGL(k_init<StoreBF16>, dim3(grid), dim3(256), 0, s, x); break;
+    case 2: hipLaunchKernelGGL(k_init<StoreF16>, dim3(grid), dim3(256), 0, s, x); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -88,28 +88,45 @@ struct HierLaunch {
 };
 hipError_t launch_mark_static(const Geom& G, const uint8_t* solid, uint8_t* t0_static, hipStream_t s);
 hipError_t launch_targets(const HierLaunch& h, const float* particles, int64_t n, hipStream_t s);
-hipError_t launch_states(const HierLaunch& h, hipStream_t s);
+// the new block state of every cell of every level (one pass over all levels after
+// the per-level flag passes); with `flag` non-null, any cell whose state differs from
+// st_old sets *flag = tag (tag never 0 or 1: a stale value cannot read as a change)
+hipError_t launch_states(const HierLaunch& h, int32_t* flag, int32_t tag, hipStream_t s);
 // flag = 1 if any of the n all-level block states differ
 hipError_t launch_diff_flag(const uint8_t* st_new, const uint8_t* st_old, int64_t n, int32_t* flag, hipStream_t s);
 
-// generic order-preserving compaction (ballot + device prefix scan) over up to
-// three predicates; items are cells visited in Morton order of a level, or the
-// entries of an int32 list
-struct CompactOut {
-  int32_t* out[3];           // compacted values per predicate (may be null)
-  int32_t* count;            // device: three totals
+// Order-preserving compaction (ballot + device prefix scan) of several segments in
+// three launches: per wave the count of every predicate, one single-workgroup scan over
+// every segment's wave counts, then the scatter. Each segment's items start on a wave.
+constexpr int kMaxSegs = 8;
+// cells of levels in Morton order; predicates: active now, new (active now, not
+// before), removed (active before, not now); outputs are the cells' level-linear indices
+struct CellSegs {
+  Geom G;
+  const uint8_t* st_new;
+  const uint8_t* st_old;
+  int nseg;
+  int level[kMaxLevels];
+  int32_t* out[kMaxLevels][3];   // compacted cells per predicate (may be null)
+  int32_t* count[kMaxLevels];    // device: the segment's three totals
 };
-hipError_t launch_compact_cells(const Geom& G, int level, const uint8_t* st_new, const uint8_t* st_old,
-                                int32_t* wave_scratch, const CompactOut& o, hipStream_t s);
-// predicates: bits shift .. shift+2 of the block's summary byte
-// the six summary predicates of a level's blocks (bits 0..5 of the summary byte:
-// SUM_GHOST, SUM_IU, SUM_OUTFLOW, SUM_TILE, SUM_BB, SUM_FRESH) in one pass
-struct CompactOut6 {
-  int32_t* out[6];           // compacted slots per predicate (may be null)
-  int32_t* count[2];         // device: totals of predicates 0..2, then 3..5
+// entries of int32 lists (block slots) with a predicate byte per slot (bits 0..5)
+struct ByteSegs {
+  int nseg;
+  const int32_t* items[kMaxSegs];
+  const uint8_t* bytes[kMaxSegs];
+  int32_t n[kMaxSegs];
+  int32_t* out[kMaxSegs][6];     // compacted slots per predicate (may be null)
+  int32_t* count[kMaxSegs][2];   // device: totals of predicates 0..2, then 3..5
 };
-hipError_t launch_compact_summary6(const int32_t* blocks, int32_t n, const uint8_t* summary, int32_t* wave_scratch,
-                                   const CompactOut6& o, hipStream_t s);
+// wave_ints: capacity of the wave scratch (int32 entries); a segment set that needs
+// more is refused (hipErrorInvalidValue)
+hipError_t launch_compact_cells(const CellSegs& c, int32_t* wave_scratch, int64_t wave_ints, hipStream_t s);
+hipError_t launch_compact_bytes(const ByteSegs& b, int32_t* wave_scratch, int64_t wave_ints, hipStream_t s);
+// wave scratch entries the two need at most: all levels' cells, and block lists of
+// `list_items` entries in total over at most kMaxSegs segments
+int64_t compact_cells_ints(const Geom& G);
+int64_t compact_bytes_ints(int64_t list_items);
 // run class of every tile of a level for the two-substep sweep: the first tile of each
 // run of up to `run_max` tiles stacked along z gets bit (h - 1) for the run's height h;
 // runs break below a missing tile and at tile positions z = 0 (mod run_max)
@@ -133,11 +150,14 @@ hipError_t launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStrea
 hipError_t launch_fill_i32(int32_t* dst, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u8(uint8_t* dst, uint8_t v, int64_t n, hipStream_t s);
 
+// every level in one launch: workgroups [wg0[l], wg0[l + 1]) take level l's cells, four
+// per workgroup (the launcher fills wg0)
 struct RoleLaunch {
   Geom G;
-  int level;
-  const int32_t* cells;      // active cells of the level (new hierarchy), Morton order
-  int32_t n;
+  const int32_t* cells[kMaxLevels];  // active cells of each level (new hierarchy), Morton order
+  int32_t n[kMaxLevels];
+  int32_t* blocks[kMaxLevels];       // out: each level's slots in key order
+  int32_t wg0[kMaxLevels + 1];
   const int32_t* dir;        // new directory
   const uint8_t* st;         // new states
   const uint8_t* st_old;     // old states (a block whose 27 positions kept their states keeps its roles)
@@ -145,7 +165,6 @@ struct RoleLaunch {
   uint8_t* role;             // [slot][512] new roles
   uint8_t* summary;          // [slot]
   int32_t* gbox;             // [slot] bounding box of the ghost nodes (3 bits per bound: lo x, hi x, lo y, ...)
-  int32_t* blocks;           // out: slots in key order
   int32_t* nbr;              // out: [slot][27]
 };
 hipError_t launch_roles(const RoleLaunch& r, hipStream_t s);
@@ -156,7 +175,8 @@ struct InitLaunch {
   const int32_t* cells;      // active cells of the level (new hierarchy), or null: slots
   const int32_t* slots;      // with cells null: the level's blocks that may hold new nodes
   const int4* coord;         // block coordinates by slot (with slots)
-  int32_t n;
+  int32_t n;                 // list length, or with n_dev an upper bound of it
+  const int32_t* n_dev;      // device: the list length (read by the kernel), or null
   const int32_t* dir_new;
   const uint8_t* st_old;
   const int32_t* dir_old;
@@ -173,7 +193,8 @@ struct InitLaunch {
   float* cpl;                // finest level with coupling fields: reset for new blocks; else null
   float* phi;                // finest level with a powder-snow field: zero for new blocks; else null
 };
-hipError_t launch_init(const InitLaunch& a, hipStream_t s);
+// the levels' initialisations (a[0 .. nlev - 1], one storage format) in one launch
+hipError_t launch_init(const InitLaunch* a, int nlev, hipStream_t s);
 // adjoint of launch_init over the same cells: lam[p] is the adjoint of time level p
 // (f32 slot layout), parity[k] the current time level of level k
 struct InitAdjLaunch {

@@ -26,7 +26,7 @@ struct Layout {
   size_t total;
   int64_t level_list_off[kMaxLevels];  // offset (elements) of each level's segment in blocks / g/i/o lists
   int64_t level_list_cap[kMaxLevels];
-  int64_t wave_cap;                    // int32 entries per predicate in the wave scratch
+  int64_t wave_ints;                   // int32 entries of the compactions' wave scratch
 };
 
 bool make_geom(const lbm_config* c, Geom& G, std::string& err) {
@@ -102,17 +102,16 @@ Layout make_layout(const lbm_config* c, const Geom& G) {
   Layout L;
   std::memset(&L, 0, sizeof(L));
   const int64_t cap = c->max_blocks;
-  int64_t ncell = 0, nlist = 0, maxw = 0;
+  int64_t ncell = 0, nlist = 0;
   for (int l = 0; l < G.L; ++l) {
     ncell += G.lv[l].ncell;
     L.level_list_off[l] = nlist;
     L.level_list_cap[l] = G.lv[l].ncell < cap ? G.lv[l].ncell : cap;
     nlist += L.level_list_cap[l];
-    const int64_t nw = ((int64_t(1) << (3 * G.lv[l].mbits)) + 63) / 64;
-    maxw = nw > maxw ? nw : maxw;
   }
-  const int64_t nwb = (cap + 63) / 64 + 1;
-  L.wave_cap = maxw > nwb ? maxw : nwb;
+  // all levels' cells in one compaction; all block lists plus the level-0 runs in another
+  const int64_t wc = compact_cells_ints(G), wb = compact_bytes_ints(nlist + L.level_list_cap[0]);
+  L.wave_ints = wc > wb ? wc : wb;
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes, 256); return r; };
   L.t0 = take(G.lv[0].ncell);
@@ -124,7 +123,7 @@ Layout make_layout(const lbm_config* c, const Geom& G) {
   L.dir[0] = take(ncell * 4);
   L.dir[1] = take(ncell * 4);
   L.lists = take(3 * ncell * 4);
-  L.wave = take(6 * L.wave_cap * 4);
+  L.wave = take(L.wave_ints * 4);
   L.counts = take(64 * 4);
   L.coord = take(cap * 16);
   L.nbr = take(cap * 27 * 4);
@@ -183,6 +182,7 @@ struct lbm_ctx {
   int use_graphs = 0;               // LBM_OPT_GRAPHS
   int pair_run = 4;                 // LBM_OPT_PAIR_RUN: tiles per run of the two-substep sweep (4, 2 with 16-bit storage)
   int64_t nrun[kRunMax] = {0};      // level-0 runs of k + 1 tiles
+  uint32_t state_tag = 0;           // grid updates that compared block states (tags their flag)
   // Coarse steps replayed as HIP graphs: the launch arguments of a coarse step follow
   // from the host state in LaunchKey alone (buffer parities, hierarchy and role-table
   // selectors, list lengths, options), so a graph captured for one key replays any
@@ -335,17 +335,29 @@ IoLaunch io_of(const lbm_ctx* c, int level) {
 }
 
 // Level-0 tiles grouped into z runs of up to pair_run tiles (the two-substep sweep's
-// work items), compacted by height; the counts land in counts[48 .. 53].
-lbm_status build_runs(lbm_ctx* c, int64_t nb0) {
-  uint8_t* cls = c->m<uint8_t>(c->lay.run_class);
+// work items): the run class of every level-0 block, then (as segment k of a byte
+// compaction) the runs by height, counts in counts[48 .. 53].
+lbm_status tile_runs(lbm_ctx* c, int64_t nb0) {
   HIPCHK(c, launch_tile_runs(c->G, 0, c->blocks(0), (int32_t)nb0, c->m<uint8_t>(c->lay.summary), c->st(c->hier),
-                             c->m<int4>(c->lay.coord), c->pair_run, cls, c->stream));
+                             c->m<int4>(c->lay.coord), c->pair_run, c->m<uint8_t>(c->lay.run_class), c->stream));
+  return LBM_OK;
+}
+void runs_segment(lbm_ctx* c, int64_t nb0, ByteSegs& b, int k) {
   int32_t* counts = c->m<int32_t>(c->lay.counts);
-  CompactOut6 o;
-  for (int k = 0; k < kRunMax; ++k) o.out[k] = c->m<int32_t>(c->lay.runs) + (size_t)k * c->lay.level_list_cap[0];
-  o.count[0] = counts + 48;
-  o.count[1] = counts + 51;
-  HIPCHK(c, launch_compact_summary6(c->blocks(0), (int32_t)nb0, cls, c->m<int32_t>(c->lay.wave), o, c->stream));
+  b.items[k] = c->blocks(0);
+  b.bytes[k] = c->m<uint8_t>(c->lay.run_class);
+  b.n[k] = (int32_t)nb0;
+  for (int r = 0; r < kRunMax; ++r) b.out[k][r] = c->m<int32_t>(c->lay.runs) + (size_t)r * c->lay.level_list_cap[0];
+  b.count[k][0] = counts + 48;
+  b.count[k][1] = counts + 51;
+}
+lbm_status build_runs(lbm_ctx* c, int64_t nb0) {
+  if (lbm_status st = tile_runs(c, nb0)) return st;
+  ByteSegs b;
+  std::memset(&b, 0, sizeof(b));
+  b.nseg = 1;
+  runs_segment(c, nb0, b, 0);
+  HIPCHK(c, launch_compact_bytes(b, c->m<int32_t>(c->lay.wave), c->lay.wave_ints, c->stream));
   return LBM_OK;
 }
 
@@ -379,21 +391,28 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
     HIPCHK(c, hipStreamSynchronize(s));
     if (c->host_counts[0] == 0) return LBM_OK;
   }
-  HIPCHK(c, launch_states(h, s));
-  // otherwise the new block states are compared with the current ones; the flag comes
-  // back with the compaction counts (one synchronisation for both)
-  if (!create) HIPCHK(c, launch_diff_flag(h.st_new, h.st_old, ncell, counts + 63, s));
-  for (int l = 0; l < L; ++l) {
-    CompactOut o;
-    o.out[0] = c->lists(l, 0);
-    o.out[1] = c->lists(l, 1);
-    o.out[2] = c->lists(l, 2);
-    o.count = counts + 3 * l;
-    HIPCHK(c, launch_compact_cells(G, l, h.st_new, h.st_old, wave, o, s));
+  // otherwise the new block states are compared with the current ones (a change writes
+  // this update's tag into the flag); the flag comes back with the compaction counts
+  // (one synchronisation for both)
+  const int32_t tag = (int32_t)(0x40000000u | (++c->state_tag & 0x3fffffffu));
+  HIPCHK(c, launch_states(h, create ? nullptr : counts + 63, tag, s));
+  {
+    CellSegs cs;
+    std::memset(&cs, 0, sizeof(cs));
+    cs.G = G;
+    cs.st_new = h.st_new;
+    cs.st_old = h.st_old;
+    cs.nseg = L;
+    for (int l = 0; l < L; ++l) {
+      cs.level[l] = l;
+      for (int k = 0; k < 3; ++k) cs.out[l][k] = c->lists(l, k);
+      cs.count[l] = counts + 3 * l;
+    }
+    HIPCHK(c, launch_compact_cells(cs, wave, c->lay.wave_ints, s));
   }
   HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 64 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  if (!create && c->host_counts[63] == 0) {
+  if (!create && c->host_counts[63] != tag) {
     HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
     return LBM_OK;
   }
@@ -437,12 +456,15 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
   uint8_t* role_old = c->role(c->rcur);
   uint8_t* role_new = c->role(1 - c->rcur);
   uint8_t* summary = c->m<uint8_t>(c->lay.summary);
-  for (int l = 0; l < L; ++l) {
+  {
     RoleLaunch r;
+    std::memset(&r, 0, sizeof(r));
     r.G = G;
-    r.level = l;
-    r.cells = c->lists(l, 0);
-    r.n = (int32_t)nact[l];
+    for (int l = 0; l < L; ++l) {
+      r.cells[l] = c->lists(l, 0);
+      r.n[l] = (int32_t)nact[l];
+      r.blocks[l] = c->blocks(l);
+    }
     r.dir = dir_new;
     r.st = h.st_new;
     r.st_old = h.st_old;
@@ -450,7 +472,6 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
     r.role = role_new;
     r.summary = summary;
     r.gbox = c->m<int32_t>(c->lay.gbox);
-    r.blocks = c->blocks(l);
     r.nbr = c->m<int32_t>(c->lay.nbr);
     HIPCHK(c, launch_roles(r, s));
   }
@@ -459,37 +480,38 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
   c->free_top = top;
   c->generation++;
   HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
-  for (int l = 0; l < L; ++l) {
-    CompactOut6 o;
-    o.out[0] = c->gblocks(l);
-    o.out[1] = c->iblocks(l);
-    o.out[2] = c->oblocks(l);
-    o.out[3] = c->tblocks(l);
-    o.out[4] = nullptr;         // bounce-back blocks: counted only
-    o.out[5] = c->lists(l, 1);  // blocks that may hold new nodes (SUM_FRESH)
-    o.count[0] = counts + 3 * l;
-    o.count[1] = counts + 32 + 3 * l;
-    HIPCHK(c, launch_compact_summary6(c->blocks(l), (int32_t)nact[l], summary, wave, o, s));
-  }
+  // the level-0 tiles' z runs (their class bytes), then one compaction of every level's
+  // blocks by summary bit and of the runs by height
   if (L >= 2) {
-    const lbm_status st = build_runs(c, nact[0]);
+    const lbm_status st = tile_runs(c, nact[0]);
     if (st != LBM_OK) return st;
   }
-  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 54 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIPCHK(c, hipStreamSynchronize(s));
-  for (int l = 0; l < L; ++l) {
-    c->nblk[l] = nact[l];
-    c->ngb[l] = c->host_counts[3 * l];
-    c->nib[l] = c->host_counts[3 * l + 1];
-    c->nob[l] = c->host_counts[3 * l + 2];
-    c->ntile[l] = c->host_counts[32 + 3 * l];
-    c->nbb[l] = c->host_counts[33 + 3 * l];
+  {
+    ByteSegs b;
+    std::memset(&b, 0, sizeof(b));
+    b.nseg = L;
+    for (int l = 0; l < L; ++l) {
+      b.items[l] = c->blocks(l);
+      b.bytes[l] = summary;
+      b.n[l] = (int32_t)nact[l];
+      b.out[l][0] = c->gblocks(l);
+      b.out[l][1] = c->iblocks(l);
+      b.out[l][2] = c->oblocks(l);
+      b.out[l][3] = c->tblocks(l);
+      b.out[l][4] = nullptr;         // bounce-back blocks: counted only
+      b.out[l][5] = c->lists(l, 1);  // blocks that may hold new nodes (SUM_FRESH)
+      b.count[l][0] = counts + 3 * l;
+      b.count[l][1] = counts + 32 + 3 * l;
+    }
+    if (L >= 2) runs_segment(c, nact[0], b, b.nseg++);
+    HIPCHK(c, launch_compact_bytes(b, wave, c->lay.wave_ints, s));
   }
-  for (int k = 0; k < kRunMax; ++k) c->nrun[k] = L >= 2 ? c->host_counts[48 + k] : 0;
   // new nodes: on a first build every block starts at rest; after that only blocks whose
   // 27 surrounding block positions changed state can hold nodes the update makes owned
+  // (their count stays on the device: the launch strides over it), all levels in one launch
+  InitLaunch inits[kMaxLevels];
   for (int l = 0; l < L; ++l) {
-    InitLaunch a;
+    InitLaunch& a = inits[l];
     std::memset(&a, 0, sizeof(a));
     a.G = G;
     a.level = l;
@@ -499,7 +521,8 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
     } else {
       a.slots = c->lists(l, 1);
       a.coord = coord;
-      a.n = c->host_counts[34 + 3 * l];
+      a.n = (int32_t)nact[l];
+      a.n_dev = counts + 34 + 3 * l;
     }
     a.dir_new = dir_new;
     a.st_old = h.st_old;
@@ -518,8 +541,19 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
     a.storage = c->cfg.storage;
     a.cpl = l == 0 ? c->cpl() : nullptr;
     a.phi = l == 0 ? c->phi(0) : nullptr;
-    HIPCHK(c, launch_init(a, s));
   }
+  HIPCHK(c, launch_init(inits, L, s));
+  HIPCHK(c, hipMemcpyAsync(c->host_counts, counts, 54 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  for (int l = 0; l < L; ++l) {
+    c->nblk[l] = nact[l];
+    c->ngb[l] = c->host_counts[3 * l];
+    c->nib[l] = c->host_counts[3 * l + 1];
+    c->nob[l] = c->host_counts[3 * l + 2];
+    c->ntile[l] = c->host_counts[32 + 3 * l];
+    c->nbb[l] = c->host_counts[33 + 3 * l];
+  }
+  for (int k = 0; k < kRunMax; ++k) c->nrun[k] = L >= 2 ? c->host_counts[48 + k] : 0;
   return LBM_OK;
 }
 

@@ -127,6 +127,8 @@ def test_recording_guards():
     keys = sim.block_keys(0).cpu().numpy()[:1]
     with pytest.raises(lbm.LBMError):
         sim.set_block_moments(0, keys, np.zeros((1, 10, 512), dtype=np.float32))
+    with pytest.raises(lbm.LBMError):  # the run lists belong to the recorded hierarchy
+        sim.set_option("pair_run", 2)
     sim.step(1)
     sim.remesh(p)  # same particles: nothing changes, nothing is logged
     sim.record_end()

@@ -174,7 +174,7 @@ def _compare_classes(sim, g, step, tol=1e-5, point=10.0):
 
 def _composite(sim, cache):
     """Composite sums of the GPU state (tests/util.py), the weights cached per hierarchy,
-    and the scales they are judged on: sum w |rho - 1| and sum w |rho u|."""
+    and the scales they are measured against: sum w |rho - 1| and sum w |rho u|."""
     from tests.util import composite_sums, composite_weights
     keys = [sim.block_keys(l).cpu().numpy() for l in range(sim.levels)]
     tag = tuple(hash(k.tobytes()) for k in keys)

@@ -152,7 +152,8 @@ def remesh_change(sim, particles, torch, ms_per_step, reps=4):
 def adjoint_ratio(lbm, W, torch):
     """Two-level 128^3 adjoint case: time of the plain forward of its 200 coarse steps
     vs the backward pass of the checkpointed rollout (checkpoints every 20 steps; per
-    segment one replay that keeps the undo log, then the reverse sweep)."""
+    segment one replay that keeps the undo log, then the reverse sweep); medians of
+    three runs."""
     wl = W.workload("adjoint128")
     sim = lbm.Sim(2, wl["n"], wl["bc"], wl["tau0"], particles=wl["markers"])
     u0 = W.smooth_random_velocity(wl["n"], wl["seed"], wl["kmax"], wl["rms"])
@@ -166,23 +167,29 @@ def adjoint_ratio(lbm, W, torch):
     x = x0.clone().requires_grad_(True)
     lbm.rollout(sim, x, wl["checkpoint_every"], checkpoint_every=wl["checkpoint_every"]).backward(
         sim.loss_ke_grad(0, *wl["box"]))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    fwd = time.perf_counter() - t0
-    x = x0.clone().requires_grad_(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xt = lbm.rollout(sim, x, steps, checkpoint_every=wl["checkpoint_every"])
-    torch.cuda.synchronize()
-    fwd_ckpt = time.perf_counter() - t0
-    seed = sim.loss_ke_grad(0, *wl["box"])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    xt.backward(seed)
-    torch.cuda.synchronize()
-    bwd = time.perf_counter() - t0
+    # each figure is the median of three runs (single runs of these ~15-45 ms measurements
+    # vary by a few percent)
+    fwds, ckpts, bwds = [], [], []
+    for _ in range(3):
+        sim.set_all_moments(x0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        fwds.append(time.perf_counter() - t0)
+        x = x0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xt = lbm.rollout(sim, x, steps, checkpoint_every=wl["checkpoint_every"])
+        torch.cuda.synchronize()
+        ckpts.append(time.perf_counter() - t0)
+        seed = sim.loss_ke_grad(0, *wl["box"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xt.backward(seed)
+        torch.cuda.synchronize()
+        bwds.append(time.perf_counter() - t0)
+    fwd, fwd_ckpt, bwd = (sorted(v)[1] for v in (fwds, ckpts, bwds))
     # the same gradient with the whole undo log of the forward pass kept in HBM (no replay)
     x = x0.clone().requires_grad_(True)
     torch.cuda.synchronize()

@@ -38,21 +38,22 @@ __global__ void k_mark_static(Geom G, const uint8_t* solid, uint8_t* t0s) {
   if (threadIdx.x == 0) t0s[cell] = any ? 1 : 0;
 }
 
-__global__ void k_copy_or_clear(uint8_t* dst, const uint8_t* src, int64_t n) {
+// dst = src (or zero); with a flag, the flag is cleared too
+__global__ void k_copy_or_clear(uint8_t* dst, const uint8_t* src, int64_t n, int32_t* flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src ? src[i] : 0;
+  if (flag && i == 0) *flag = 0;
 }
 
-__global__ void k_mark_particles(Geom G, const float* p, int64_t n, uint8_t* t0) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// the level-0 block position of a particle into the target set (particles outside a
+// non-periodic domain mark nothing)
+__device__ __forceinline__ void mark_particle(const Geom& G, const float q[3], uint8_t* t0) {
   const LevelGeom& g = G.lv[0];
   int b[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float q = p[3 * i + a];
-    if (!G.periodic[a] && !(q >= 0.0f && q < (float)G.N[a])) return;
-    int v = (int)floorf(q * 0.125f);
+    if (!G.periodic[a] && !(q[a] >= 0.0f && q[a] < (float)G.N[a])) return;
+    int v = (int)floorf(q[a] * 0.125f);
     if (G.periodic[a]) {
       v %= g.nb[a];
       if (v < 0) v += g.nb[a];
@@ -60,6 +61,25 @@ __global__ void k_mark_particles(Geom G, const float* p, int64_t n, uint8_t* t0)
     b[a] = v;
   }
   t0[cell_lin(g, b[0], b[1], b[2])] = 1;
+}
+
+__global__ void k_mark_particles(Geom G, const float* p, int64_t n, uint8_t* t0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float q[3] = {p[3 * i], p[3 * i + 1], p[3 * i + 2]};
+  mark_particle(G, q, t0);
+}
+
+// the particles moved by d (rounded like the separate advance) and marked at their new
+// positions, in one pass
+__global__ void k_advance_mark(Geom G, float* p, int64_t n, float dx, float dy, float dz, uint8_t* t0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float q[3] = {__fadd_rn(p[3 * i], dx), __fadd_rn(p[3 * i + 1], dy), __fadd_rn(p[3 * i + 2], dz)};
+  p[3 * i] = q[0];
+  p[3 * i + 1] = q[1];
+  p[3 * i + 2] = q[2];
+  mark_particle(G, q, t0);
 }
 
 // D_l from the finer level: any child flagged (T_0 for l = 1, D|B for l > 1)
@@ -815,7 +835,7 @@ inline unsigned grid1(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 hipError_t launch_mark_static(const Geom& G, const uint8_t* solid, uint8_t* t0s, hipStream_t s) {
   if (!solid) {
     hipLaunchKernelGGL(k_copy_or_clear, dim3(grid1(G.lv[0].ncell, 256)), dim3(256), 0, s, t0s, (const uint8_t*)nullptr,
-                       G.lv[0].ncell);
+                       G.lv[0].ncell, (int32_t*)nullptr);
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_mark_static, dim3((unsigned)G.lv[0].ncell), dim3(256), 0, s, G, solid, t0s);
@@ -824,8 +844,19 @@ hipError_t launch_mark_static(const Geom& G, const uint8_t* solid, uint8_t* t0s,
 
 hipError_t launch_targets(const HierLaunch& h, const float* p, int64_t n, hipStream_t s) {
   const int64_t n0 = h.G.lv[0].ncell;
-  hipLaunchKernelGGL(k_copy_or_clear, dim3(grid1(n0, 256)), dim3(256), 0, s, h.t0, h.t0_static, n0);
+  hipLaunchKernelGGL(k_copy_or_clear, dim3(grid1(n0, 256)), dim3(256), 0, s, h.t0, h.t0_static, n0,
+                     (int32_t*)nullptr);
   if (p && n > 0) hipLaunchKernelGGL(k_mark_particles, dim3(grid1(n, 256)), dim3(256), 0, s, h.G, p, n, h.t0);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_targets(const HierLaunch& h, float* p, int64_t n, const float d[3], const uint8_t* t0_prev,
+                                  int32_t* flag, hipStream_t s) {
+  const int64_t n0 = h.G.lv[0].ncell;
+  hipLaunchKernelGGL(k_copy_or_clear, dim3(grid1(n0, 256)), dim3(256), 0, s, h.t0, h.t0_static, n0, flag);
+  if (p && n > 0)
+    hipLaunchKernelGGL(k_advance_mark, dim3(grid1(n, 256)), dim3(256), 0, s, h.G, p, n, d[0], d[1], d[2], h.t0);
+  hipLaunchKernelGGL(k_diff, dim3(grid1(n0, 256)), dim3(256), 0, s, (const uint8_t*)h.t0, t0_prev, n0, flag);
   return hipGetLastError();
 }
 

@@ -88,6 +88,10 @@ struct HierLaunch {
 };
 hipError_t launch_mark_static(const Geom& G, const uint8_t* solid, uint8_t* t0_static, hipStream_t s);
 hipError_t launch_targets(const HierLaunch& h, const float* particles, int64_t n, hipStream_t s);
+// particles moved by d, the level-0 target set of their new positions, and flag = 1 if
+// it differs from t0_prev (the flag cleared first), in three launches
+hipError_t launch_advance_targets(const HierLaunch& h, float* particles, int64_t n, const float d[3],
+                                  const uint8_t* t0_prev, int32_t* flag, hipStream_t s);
 // the new block state of every cell of every level (one pass over all levels after
 // the per-level flag passes); with `flag` non-null, any cell whose state differs from
 // st_old sets *flag = tag (tag never 0 or 1: a stale value cannot read as a change)

@@ -1481,7 +1481,6 @@ lbm_status lbm_step_remesh(lbm_ctx* ctx, int32_t n, float* particles, int64_t np
     // meanwhile, on the side stream: particles forward, then the level-0 target set
     // compared with the one the hierarchy was built from (the step reads neither)
     HIPCHK(ctx, hipStreamWaitEvent(ctx->side, ctx->ev_before, 0));
-    HIPCHK(ctx, launch_advance_particles(particles, np, d[0], d[1], d[2], ctx->side));
     HierLaunch h;
     h.G = G;
     h.t0 = ctx->m<uint8_t>(ctx->lay.t0);
@@ -1489,8 +1488,7 @@ lbm_status lbm_step_remesh(lbm_ctx* ctx, int32_t n, float* particles, int64_t np
     h.flags = ctx->m<uint8_t>(ctx->lay.flags);
     h.st_new = ctx->st(1 - ctx->hier);
     h.st_old = ctx->st(ctx->hier);
-    HIPCHK(ctx, launch_targets(h, particles, np, ctx->side));
-    HIPCHK(ctx, launch_diff_flag(h.t0, ctx->m<uint8_t>(ctx->lay.t0p), G.lv[0].ncell, flag, ctx->side));
+    HIPCHK(ctx, launch_advance_targets(h, particles, np, d, ctx->m<uint8_t>(ctx->lay.t0p), flag, ctx->side));
     HIPCHK(ctx, hipMemcpyAsync(ctx->host_counts, flag, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->side));
     HIPCHK(ctx, hipEventRecord(ctx->ev_side, ctx->side));
     // later work on the context's stream sees the new particle positions

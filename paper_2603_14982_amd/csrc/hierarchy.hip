@@ -380,6 +380,24 @@ __device__ inline uint8_t mask_role(const Geom& G, const LevelGeom& g, const int
   return (uint8_t)(ROLE_COMPUTED | ((wall & m) ? ROLE_BB : 0));
 }
 
+__device__ bool tile_exists(const LevelGeom& g, const uint8_t* st, int tx, int ty, int tz) {
+  if (tz < 0 || 2 * tz >= g.nb[2]) return false;
+  for (int m = 0; m < 4 * kTileX; ++m) {
+    const int x = tx * kTileX + m % kTileX, y = 2 * ty + (m / kTileX) % 2, z = 2 * tz + m / (2 * kTileX);
+    if (x < g.nb[0] && y < g.nb[1] && z < g.nb[2] && st[g.off + cell_lin(g, x, y, z)] == ST_ACTIVE) return true;
+  }
+  return false;
+}
+
+// run class of the tile at tile position (tx, ty, tz) if it starts a run: bit h - 1 for a
+// run of h tiles, 0 if the tile continues the run of the tile below
+__device__ uint8_t run_class_of(const LevelGeom& g, const uint8_t* st, int tx, int ty, int tz, int run_max) {
+  if (tz % run_max != 0 && tile_exists(g, st, tx, ty, tz - 1)) return 0;
+  int h = 1;
+  while (h < run_max && (tz + h) % run_max != 0 && tile_exists(g, st, tx, ty, tz + h)) ++h;
+  return (uint8_t)(1u << (h - 1));
+}
+
 // Role of a node by testing each of its 26 neighbours (with a solid field)
 __device__ inline uint8_t test_role(const RoleLaunch& r, int l, const LevelGeom& g, const int b[3], int node,
                                     const uint8_t* s_st, const uint8_t* s_wall) {
@@ -557,6 +575,9 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
     }
     r.summary[slot] = (any_g ? SUM_GHOST : 0) | (any_i ? SUM_IU : 0) | (any_o ? SUM_OUTFLOW : 0) |
                       (start ? SUM_TILE : 0) | (any_b ? SUM_BB : 0) | (any_changed ? SUM_FRESH : 0);
+    // the finest level's tiles: the z-run class of a tile head (two-substep sweep)
+    if (l == 0 && r.run_class)
+      r.run_class[slot] = start ? run_class_of(g, r.st, b[0] / kTileX, b[1] >> 1, b[2] >> 1, r.run_max) : 0;
     r.gbox[slot] = box[0] | box[3] << 3 | box[1] << 6 | box[4] << 9 | box[2] << 12 | box[5] << 15;
   }
 }
@@ -568,15 +589,6 @@ __global__ __launch_bounds__(256) void k_roles(RoleLaunch r) {
 // along z reads and recomputes the planes at their shared faces once. Runs break below
 // a missing tile and at tile positions z = 0 (mod run_max), so that a run is found from
 // its first tile alone.
-__device__ bool tile_exists(const LevelGeom& g, const uint8_t* st, int tx, int ty, int tz) {
-  if (tz < 0 || 2 * tz >= g.nb[2]) return false;
-  for (int m = 0; m < 4 * kTileX; ++m) {
-    const int x = tx * kTileX + m % kTileX, y = 2 * ty + (m / kTileX) % 2, z = 2 * tz + m / (2 * kTileX);
-    if (x < g.nb[0] && y < g.nb[1] && z < g.nb[2] && st[g.off + cell_lin(g, x, y, z)] == ST_ACTIVE) return true;
-  }
-  return false;
-}
-
 __global__ void k_tile_runs(Geom G, int level, const int32_t* blocks, int32_t n, const uint8_t* summary,
                             const uint8_t* st, const int4* coord, int run_max, uint8_t* run_class) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -584,14 +596,8 @@ __global__ void k_tile_runs(Geom G, int level, const int32_t* blocks, int32_t n,
   const int32_t slot = blocks[t];
   uint8_t cls = 0;
   if (summary[slot] & SUM_TILE) {
-    const LevelGeom& g = G.lv[level];
     const int4 c = coord[slot];
-    const int tx = c.x / kTileX, ty = c.y >> 1, tz = c.z >> 1;
-    if (tz % run_max == 0 || !tile_exists(g, st, tx, ty, tz - 1)) {
-      int h = 1;
-      while (h < run_max && (tz + h) % run_max != 0 && tile_exists(g, st, tx, ty, tz + h)) ++h;
-      cls = (uint8_t)(1u << (h - 1));
-    }
+    cls = run_class_of(G.lv[level], st, c.x / kTileX, c.y >> 1, c.z >> 1, run_max);
   }
   run_class[slot] = cls;
 }
@@ -842,10 +848,9 @@ hipError_t launch_mark_static(const Geom& G, const uint8_t* solid, uint8_t* t0s,
   return hipGetLastError();
 }
 
-hipError_t launch_targets(const HierLaunch& h, const float* p, int64_t n, hipStream_t s) {
+hipError_t launch_targets(const HierLaunch& h, const float* p, int64_t n, int32_t* flag, hipStream_t s) {
   const int64_t n0 = h.G.lv[0].ncell;
-  hipLaunchKernelGGL(k_copy_or_clear, dim3(grid1(n0, 256)), dim3(256), 0, s, h.t0, h.t0_static, n0,
-                     (int32_t*)nullptr);
+  hipLaunchKernelGGL(k_copy_or_clear, dim3(grid1(n0, 256)), dim3(256), 0, s, h.t0, h.t0_static, n0, flag);
   if (p && n > 0) hipLaunchKernelGGL(k_mark_particles, dim3(grid1(n, 256)), dim3(256), 0, s, h.G, p, n, h.t0);
   return hipGetLastError();
 }
@@ -876,9 +881,8 @@ hipError_t launch_states(const HierLaunch& h, int32_t* flag, int32_t tag, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_diff_flag(const uint8_t* st_new, const uint8_t* st_old, int64_t n, int32_t* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, flag, 0, (int64_t)1);
-  if (n > 0) hipLaunchKernelGGL(k_diff, dim3(grid1(n, 256)), dim3(256), 0, s, st_new, st_old, n, flag);
+hipError_t launch_diff(const uint8_t* a, const uint8_t* b, int64_t n, int32_t* flag, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_diff, dim3(grid1(n, 256)), dim3(256), 0, s, a, b, n, flag);
   return hipGetLastError();
 }
 

@@ -87,7 +87,8 @@ struct HierLaunch {
   const uint8_t* st_old;
 };
 hipError_t launch_mark_static(const Geom& G, const uint8_t* solid, uint8_t* t0_static, hipStream_t s);
-hipError_t launch_targets(const HierLaunch& h, const float* particles, int64_t n, hipStream_t s);
+// level-0 targets: the static ones, then the particles' positions (flag, if given, is cleared)
+hipError_t launch_targets(const HierLaunch& h, const float* particles, int64_t n, int32_t* flag, hipStream_t s);
 // particles moved by d, the level-0 target set of their new positions, and flag = 1 if
 // it differs from t0_prev (the flag cleared first), in three launches
 hipError_t launch_advance_targets(const HierLaunch& h, float* particles, int64_t n, const float d[3],
@@ -96,8 +97,8 @@ hipError_t launch_advance_targets(const HierLaunch& h, float* particles, int64_t
 // the per-level flag passes); with `flag` non-null, any cell whose state differs from
 // st_old sets *flag = tag (tag never 0 or 1: a stale value cannot read as a change)
 hipError_t launch_states(const HierLaunch& h, int32_t* flag, int32_t tag, hipStream_t s);
-// flag = 1 if any of the n all-level block states differ
-hipError_t launch_diff_flag(const uint8_t* st_new, const uint8_t* st_old, int64_t n, int32_t* flag, hipStream_t s);
+// *flag = 1 if any of the n bytes of a and b differ (left alone otherwise: clear it first)
+hipError_t launch_diff(const uint8_t* a, const uint8_t* b, int64_t n, int32_t* flag, hipStream_t s);
 
 // Order-preserving compaction (ballot + device prefix scan) of several segments in
 // three launches: per wave the count of every predicate, one single-workgroup scan over
@@ -170,6 +171,8 @@ struct RoleLaunch {
   uint8_t* summary;          // [slot]
   int32_t* gbox;             // [slot] bounding box of the ghost nodes (3 bits per bound: lo x, hi x, lo y, ...)
   int32_t* nbr;              // out: [slot][27]
+  uint8_t* run_class;        // out: [slot] z-run class of the finest level's tile heads (0 elsewhere), or null
+  int run_max;               // tiles per run at most
 };
 hipError_t launch_roles(const RoleLaunch& r, hipStream_t s);
 

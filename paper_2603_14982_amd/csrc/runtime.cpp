@@ -334,6 +334,8 @@ IoLaunch io_of(const lbm_ctx* c, int level) {
   return a;
 }
 
+int32_t* counts_flag(lbm_ctx* c) { return c->m<int32_t>(c->lay.counts) + 63; }
+
 // Level-0 tiles grouped into z runs of up to pair_run tiles (the two-substep sweep's
 // work items): the run class of every level-0 block, then (as segment k of a byte
 // compaction) the runs by height, counts in counts[48 .. 53].
@@ -377,7 +379,8 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
   h.flags = c->m<uint8_t>(c->lay.flags);
   h.st_new = c->st(nh);
   h.st_old = c->st(c->hier);
-  if (!targets_ready) HIPCHK(c, launch_targets(h, particles, n, s));
+  // (the target copy clears the change flag of the check below)
+  if (!targets_ready) HIPCHK(c, launch_targets(h, particles, n, counts_flag(c), s));
   int32_t* counts = c->m<int32_t>(c->lay.counts);
   int32_t* wave = c->m<int32_t>(c->lay.wave);
   uint8_t* t0_prev = c->m<uint8_t>(c->lay.t0p);
@@ -386,7 +389,7 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
   if (!create && !targets_ready) {
     // fast path: H(Phi) depends on the level-0 target set T0 alone. If T0 equals a
     // target set the current hierarchy is built from, nothing changes.
-    HIPCHK(c, launch_diff_flag(h.t0, t0_prev, G.lv[0].ncell, counts + 63, s));
+    HIPCHK(c, launch_diff(h.t0, t0_prev, G.lv[0].ncell, counts + 63, s));
     HIPCHK(c, hipMemcpyAsync(c->host_counts, counts + 63, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     if (c->host_counts[0] == 0) return LBM_OK;
@@ -473,6 +476,8 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
     r.summary = summary;
     r.gbox = c->m<int32_t>(c->lay.gbox);
     r.nbr = c->m<int32_t>(c->lay.nbr);
+    r.run_class = L >= 2 ? c->m<uint8_t>(c->lay.run_class) : nullptr;
+    r.run_max = c->pair_run;
     HIPCHK(c, launch_roles(r, s));
   }
   c->hier = nh;
@@ -480,12 +485,8 @@ lbm_status rebuild(lbm_ctx* c, const float* particles, int64_t n, bool create, b
   c->free_top = top;
   c->generation++;
   HIPCHK(c, hipMemcpyAsync(t0_prev, h.t0, (size_t)G.lv[0].ncell, hipMemcpyDeviceToDevice, s));
-  // the level-0 tiles' z runs (their class bytes), then one compaction of every level's
-  // blocks by summary bit and of the runs by height
-  if (L >= 2) {
-    const lbm_status st = tile_runs(c, nact[0]);
-    if (st != LBM_OK) return st;
-  }
+  // one compaction of every level's blocks by summary bit and of the level-0 tiles' z runs
+  // (their class bytes written by the role pass) by height
   {
     ByteSegs b;
     std::memset(&b, 0, sizeof(b));

@@ -104,13 +104,15 @@ def test_pair_z_runs_bit_identical(run, switch):
     _agree(_moments(a), _moments(b), 0.0, f"runs of {run} (then {switch})")
 
 
-@pytest.mark.parametrize("storage", ["bf16", "f16"])
-def test_pair_half_precision_matches_two_sweeps(storage):
-    # the intermediate moments go through the storage format as if stored and read back
-    a, _, pa = _slab_run(2, storage=storage, fuse=True, steps=4)
-    b, _, pb = _slab_run(2, storage=storage, fuse=False, steps=4)
+@pytest.mark.parametrize("storage,run", [("bf16", None), ("f16", None), ("bf16", 4), ("f16", 1)])
+def test_pair_half_precision_matches_two_sweeps(storage, run):
+    # the intermediate moments go through the storage format as if stored and read back;
+    # any run length (None: the default with 16-bit storage) gives the same result
+    zr = (24.0, 104.0) if run else (72.0, 88.0)
+    a, _, pa = _slab_run(2, storage=storage, fuse=True, steps=4, pair_run=run, zr=zr)
+    b, _, pb = _slab_run(2, storage=storage, fuse=False, steps=4, zr=zr)
     assert pa["sc_pair"][1] == 4 and pb["sc_pair"][1] == 0
-    _agree(_moments(a), _moments(b), 0.0, f"pair {storage}")
+    _agree(_moments(a), _moments(b), 0.0, f"pair {storage} runs of {run}")
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
